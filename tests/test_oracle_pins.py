@@ -1,0 +1,305 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage of section 2 ("Mathematical Development") or
+section 3 ("Results") it follows.  None of them retypes the oracle: they use
+a literal 1-based enumeration with exact rationals, the paper's own DP
+recurrence and FFT construction run through numpy, closed forms, planted
+shifts, statistics of the noise, and a hand-worked fixture.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._exact import f_exact, overlap_set
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ints(rng, m, n, lo=0, hi=50):
+    return rng.integers(lo, hi, size=(m, n)).astype(np.int64)
+
+
+# --- overlap set and its area (sec. 2, definition of D) -------------------
+
+def test_area_equals_literal_enumeration():
+    for m in range(1, 8):
+        for n in range(1, 8):
+            for s in range(-(m - 1), m):
+                for t in range(-(n - 1), n):
+                    lit = len(overlap_set(m, n, s, t))
+                    assert lit == (m - abs(s)) * (n - abs(t))
+                    assert oracle.area(m, n, s, t) == lit
+
+
+# --- the objective itself (sec. 2, objective f) ----------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_f_matches_exact_rationals_all_windows(seed):
+    rng = np.random.default_rng(seed)
+    m, n = int(rng.integers(1, 8)), int(rng.integers(1, 8))
+    a, b = _ints(rng, m, n, -20, 60), _ints(rng, m, n, -20, 60)
+    al, bl = a.tolist(), b.tolist()
+    for w in range(1, min(m, n) + 1):
+        surf = oracle.surface(a, b, w)
+        for s in range(-(w - 1), w):
+            for t in range(-(w - 1), w):
+                ex = f_exact(al, bl, s, t)
+                # integer data: oracle sums exactly, one rounding at the division
+                assert surf[s + w - 1, t + w - 1] == float(ex), (m, n, w, s, t)
+
+
+def test_hand_worked_fixture():
+    rows = {}
+    shifts = []
+    with open(os.path.join(GOLDEN, "hand_2x3_w2.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            k, *v = line.split()
+            if k in ("m", "n", "w"):
+                rows[k] = int(v[0])
+            elif k in ("a", "b"):
+                rows[k] = [float(x) for x in v]
+            elif k == "argmin":
+                rows["argmin"] = tuple(int(x) for x in v)
+            elif k == "gap":
+                rows["gap"] = int(v[0]) / int(v[1])
+            else:
+                shifts.append((int(k), int(v[0]), int(v[1]), int(v[2])))
+    m, n, w = rows["m"], rows["n"], rows["w"]
+    a = np.array(rows["a"]).reshape(m, n)
+    b = np.array(rows["b"]).reshape(m, n)
+    surf = oracle.surface(a, b, w)
+    assert len(shifts) == (2 * w - 1) ** 2
+    for s, t, tot, ar in shifts:
+        assert oracle.area(m, n, s, t) == ar
+        assert surf[s + w - 1, t + w - 1] == tot / ar
+    r = oracle.align(a[None], b, w, False)
+    assert tuple(r.shifts[0]) == rows["argmin"]
+    assert r.fmin[0] == 2.0
+    assert r.gap_c[0] == rows["gap"]
+
+
+# --- the energy split (sec. 2, Area*f = sum a^2 + sum b^2 - 2 sum ab) -------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_energy_split_identity_in_integers(seed):
+    rng = np.random.default_rng(100 + seed)
+    m, n = 9, 7
+    a, b = _ints(rng, m, n, 0, 1000), _ints(rng, m, n, 0, 1000)
+    for s in range(-3, 4):
+        for t in range(-3, 4):
+            A, B, h, ar = oracle.terms(a, b, s, t)
+            ex = f_exact(a.tolist(), b.tolist(), s, t)
+            assert ar == (m - abs(s)) * (n - abs(t))
+            assert int(A) + int(B) - 2 * int(h) == ex * int(ar)
+
+
+# --- the DP recurrence for the overlap energies (sec. 2, recurrence for g) --
+
+def _g_by_recurrence(a):
+    """g_{s,t} for s,t <= 0 from g_{s,t} = g_{s-1,t} + g_{s,t-1} - g_{s-1,t-1} + a_{m+s,n+t}^2,
+    with g = 0 when m+s = 0 or n+t = 0 (empty overlap); 1-based a as printed."""
+    m, n = a.shape
+    g = {}
+    for s in range(-m, 1):
+        for t in range(-n, 1):
+            if m + s == 0 or n + t == 0:
+                g[(s, t)] = 0
+            else:
+                g[(s, t)] = (g[(s - 1, t)] + g[(s, t - 1)] - g[(s - 1, t - 1)]
+                             + int(a[m + s - 1, n + t - 1]) ** 2)
+    return g
+
+
+@pytest.mark.parametrize("shape", [(6, 5), (4, 7), (8, 8)])
+def test_overlap_energy_matches_paper_recurrence(shape):
+    rng = np.random.default_rng(7)
+    a = _ints(rng, *shape, 0, 300)
+    b = _ints(rng, *shape, 0, 300)
+    m, n = shape
+    g = _g_by_recurrence(a)
+    for s in range(-(m - 1), 1):
+        for t in range(-(n - 1), 1):
+            A, _, _, _ = oracle.terms(a, b, s, t)
+            assert int(A) == g[(s, t)]
+    # other quadrants: the same recurrence on the mirrored image (s -> -s and/or t -> -t)
+    for fi, fj in ((True, False), (False, True), (True, True)):
+        am = a[::-1] if fi else a
+        am = am[:, ::-1] if fj else am
+        gm = _g_by_recurrence(np.ascontiguousarray(am))
+        for s in range(-(m - 1), 1):
+            for t in range(-(n - 1), 1):
+                ss, tt = (-s if fi else s), (-t if fj else t)
+                A, _, _, _ = oracle.terms(a, b, ss, tt)
+                assert int(A) == gm[(s, t)]
+
+
+# --- the FFT construction of h (sec. 2, padded transforms and ifft2) -------
+
+@pytest.mark.parametrize("shape,w", [((5, 7), 4), ((12, 9), 5), ((16, 16), 8)])
+def test_correlation_matches_paper_fft_construction(shape, w):
+    rng = np.random.default_rng(11)
+    m, n = shape
+    a = _ints(rng, m, n, 0, 500)
+    b = _ints(rng, m, n, 0, 500)
+    # paper's construction: rotate b by 180 degrees, pad both with w zero
+    # columns on the right and w zero rows below, multiply the transforms
+    bhat = b[::-1, ::-1]
+    pa = np.zeros((m + w, n + w)); pa[:m, :n] = a
+    pb = np.zeros((m + w, n + w)); pb[:m, :n] = bhat
+    c = np.real(np.fft.ifft2(np.fft.fft2(pa) * np.fft.fft2(pb)))
+    # the minimal-padding correlation form: any P >= m+w-1, Q >= n+w-1
+    P, Q = m + w - 1, n + w - 1
+    qa = np.zeros((P, Q)); qa[:m, :n] = a
+    qb = np.zeros((P, Q)); qb[:m, :n] = b
+    cc = np.real(np.fft.ifft2(np.fft.fft2(qa) * np.conj(np.fft.fft2(qb))))
+    for s in range(-(w - 1), w):
+        for t in range(-(w - 1), w):
+            _, _, h, _ = oracle.terms(a, b, s, t)
+            assert round(c[s + m - 1, t + n - 1]) == int(h)
+            assert round(cc[s % P, t % Q]) == int(h)
+
+
+# --- the search: argmin and sign (sec. 2), refine convention (sec. 2, last paragraph)
+
+def _blob_image(rng, m, n, k=12):
+    i = np.arange(m)[:, None]
+    j = np.arange(n)[None, :]
+    img = 1.0 + 0.3 * np.cos(2 * np.pi * i / m + 0.4) * np.cos(2 * np.pi * j / n + 1.1)
+    for _ in range(k):
+        ci, cj = rng.uniform(0, m), rng.uniform(0, n)
+        sg = rng.uniform(1.5, 3.5)
+        img = img + rng.uniform(0.5, 2.0) * np.exp(-((i - ci) ** 2 + (j - cj) ** 2) / (2 * sg * sg))
+    return img
+
+
+def test_planted_shifts_recovered_without_downsampling():
+    rng = np.random.default_rng(3)
+    m, n, w = 40, 36, 9
+    b = _blob_image(rng, m, n)
+    truth = [(0, 0), (3, -5), (-8, 8), (7, 1), (-2, -6), (8, -8)]
+    frames = np.stack([np.roll(b, st, axis=(0, 1)) + 1e-4 * rng.standard_normal((m, n))
+                       for st in truth])
+    r = oracle.align(frames, b, w, False)
+    assert [tuple(x) for x in r.shifts] == truth
+    assert [tuple(x) for x in r.coarse] == truth
+
+
+def test_planted_odd_and_even_shifts_refined_at_full_resolution():
+    rng = np.random.default_rng(5)
+    m, n, w = 64, 60, 8
+    b = _blob_image(rng, m, n, 20)
+    truth = [(7, -13), (6, 4), (-5, -1), (0, 0), (-14, 9), (1, 1), (13, -14)]
+    frames = np.stack([np.roll(b, st, axis=(0, 1)) for st in truth])
+    r = oracle.align(frames, b, w, True)
+    for k, (S, T) in enumerate(truth):
+        assert tuple(r.shifts[k]) == (S, T)
+        cs, ct = r.coarse[k]
+        assert S - 2 * cs in (-1, 0, 1) and T - 2 * ct in (-1, 0, 1)
+        # rolled, noise-free: wrapped pixels lie outside D, so f(S,T) is exactly 0
+        u, v = S - 2 * cs, T - 2 * ct
+        assert r.frefine[k, (u + 1) * 3 + (v + 1)] == 0.0
+
+
+def test_rolled_seam_gives_exact_zero():
+    rng = np.random.default_rng(9)
+    b = _blob_image(rng, 23, 29)
+    for S, T in [(4, -7), (-9, 2), (0, 11)]:
+        a = np.roll(b, (S, T), axis=(0, 1))
+        assert oracle.f(a, b, S, T) == 0.0
+        assert oracle.f(a, b, S + 1, T) > 0.0
+
+
+def test_zero_shift_normalisation_two_noisy_copies():
+    # f(0,0) of two independent noisy copies of one image estimates 2 sigma^2
+    rng = np.random.default_rng(21)
+    m = n = 128
+    base = _blob_image(rng, m, n, 40)
+    sig = 0.3
+    a = base + sig * rng.standard_normal((m, n))
+    b = base + sig * rng.standard_normal((m, n))
+    N = m * n
+    ratio = oracle.f(a, b, 0, 0) / (2 * sig * sig)
+    assert abs(ratio - 1.0) < 5 * math.sqrt(2.0 / N)
+
+
+def test_window_one_is_plain_mse():
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((31, 17))
+    b = rng.standard_normal((31, 17))
+    r = oracle.align(a[None], b, 1, False)
+    mse = math.fsum(((a - b) ** 2).ravel()) / a.size
+    assert tuple(r.shifts[0]) == (0, 0)
+    assert r.fmin[0] == pytest.approx(mse, rel=1e-14, abs=0)
+
+
+def test_swap_symmetry():
+    rng = np.random.default_rng(8)
+    a, b = _ints(rng, 11, 13, 0, 99), _ints(rng, 11, 13, 0, 99)
+    sab = oracle.surface(a, b, 5)
+    sba = oracle.surface(b, a, 5)
+    assert np.array_equal(sab, sba[::-1, ::-1])
+
+
+def test_downsample_is_box_mean():
+    rng = np.random.default_rng(12)
+    for m, n in [(8, 8), (9, 7), (5, 12)]:
+        x = rng.integers(0, 65536, size=(m, n)).astype(np.float64)
+        mc, nc = m // 2, n // 2
+        ref = x[:2 * mc, :2 * nc].reshape(mc, 2, nc, 2).mean((1, 3))
+        assert np.array_equal(oracle.downsample(x), ref)
+
+
+def test_tie_order_prefers_smallest_displacement():
+    # constant images: f == 0 at every shift, so the tie order alone decides
+    a = np.full((9, 9), 3.0)
+    r = oracle.align(a[None], a, 4, False)
+    assert tuple(r.shifts[0]) == (0, 0) and r.gap_c[0] == 0.0
+    # period-3 image: zero at every multiple of 3; the smallest is (0,0)
+    i = np.arange(12)[:, None]
+    j = np.arange(12)[None, :]
+    p = ((i % 3) * 7 + (j % 3) * 2).astype(float)
+    r = oracle.align(np.roll(p, (3, 0), axis=(0, 1))[None], p, 5, False)
+    assert tuple(r.shifts[0]) == (0, 0)
+    # two equal minima at the same ring: (-1, 0) wins over (0, -1)? ring 1, |s|+|t| 1, s smaller
+    a = np.zeros((5, 5))
+    b = np.zeros((5, 5))
+    r = oracle.align(a[None], b, 2, False)
+    assert tuple(r.shifts[0]) == (0, 0)
+
+
+def test_tie_order_lexicographic_within_ring():
+    # a and b both symmetric under transposition make f(s,t) == f(t,s) exactly
+    # (integer data); a = roll(b,(1,0)) + roll(b,(0,1)) against 2b puts the
+    # minimum on the pair (1,0)/(0,1), which the order (ring, |s|+|t|, s, t)
+    # resolves to (0,1)
+    i = np.arange(24)[:, None]
+    j = np.arange(24)[None, :]
+    b = np.zeros((24, 24))
+    for ci, cj, amp in [(6, 15, 40), (15, 6, 40), (12, 12, 70), (4, 4, 25), (19, 19, 25)]:
+        b += np.rint(amp * np.exp(-((i - ci) ** 2 + (j - cj) ** 2) / 8.0))
+        b += np.rint(amp * np.exp(-((i - cj) ** 2 + (j - ci) ** 2) / 8.0))
+    assert np.array_equal(b, b.T)
+    a = np.roll(b, (1, 0), axis=(0, 1)) + np.roll(b, (0, 1), axis=(0, 1))
+    surf = oracle.surface(a, 2 * b, 3)
+    assert surf[3, 2] == surf[2, 3]                   # f(1,0) == f(0,1)
+    assert surf[3, 2] == surf.min()
+    r = oracle.align(a[None], 2 * b, 3, False)
+    assert tuple(r.shifts[0]) == (0, 1)
+    assert r.gap_c[0] == 0.0
+
+
+def test_validation_rules():
+    assert oracle.validate(1, 8, 8, 8, 0)
+    assert not oracle.validate(1, 8, 8, 9, 0)       # w > m'
+    assert not oracle.validate(1, 8, 8, 5, 1)       # w > m/2
+    assert oracle.validate(0, 8, 8, 4, 1)           # T = 0 is valid
+    assert not oracle.validate(1, 1, 8, 1, 1)       # m' = 0
+    assert not oracle.validate(1, 8, 8, 0, 0)       # w < 1
+    assert not oracle.validate(1, 8, 8, 2, 2)       # ds not in {0,1}
+    assert not oracle.validate(-1, 8, 8, 2, 0)
