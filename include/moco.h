@@ -1,0 +1,157 @@
+/*
+ * moco.h -- C ABI of the MI355X (gfx950) translation-search library.
+ *
+ * The library computes, for every frame a of a stack and one template b, the
+ * integer translation (S,T) chosen by the search of Dubbs, Guevara, Peterka
+ * and Yuste, "moco: Fast Motion Correction for Calcium Imaging"
+ * (arXiv:1506.06039), section 2:
+ *
+ *   f_{s,t} = (1/Area(D_{s,t})) * sum over (i,j) in D_{s,t} of (a[i+s][j+t] - b[i][j])^2
+ *
+ * where D_{s,t} is the set of pixels (i,j) such that both (i,j) and
+ * (i+s,j+t) lie inside the m x n image (sec. 2, objective and overlap set).
+ * Every shift with max(|s|,|t|) < w is scored (sec. 2, first paragraph), on
+ * the 2x2-box-downsampled frame when `downsample` is set; the argmin is then
+ * multiplied by two and f_{2s+u,2t+v}, u,v in {-1,0,1}, is evaluated at full
+ * resolution and the minimum kept (sec. 2, last paragraph).
+ *
+ * Indices are 0-based.  Row shift s runs along m, column shift t along n.
+ * A frame made as np.roll(template, (S,T), axis=(0,1)) returns (S,T); the
+ * frame is corrected by shifting it by (-S,-T).
+ *
+ * Conventions for every entry point:
+ *   - Return value: MOCO_OK (0) or a negative moco_status.  Nothing throws,
+ *     aborts or exits across this boundary.  moco_last_error() returns a
+ *     thread-local message describing the last failure of the calling thread.
+ *   - Device pointers ("d_" prefix) are HIP device addresses on the context's
+ *     device, owned by the caller; the library never frees them.
+ *   - Work is ordered on the caller's HIP stream (`hip_stream`, a hipStream_t
+ *     passed as void*; NULL is the legacy default stream).  Outputs are valid
+ *     once that stream has synchronised.  Entry points return as soon as the
+ *     work is enqueued.
+ *   - A context is used by one host thread at a time.
+ *   - Layouts are row-major and contiguous.
+ */
+#ifndef MOCO_H
+#define MOCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MOCO_OK = 0,
+    MOCO_EINVAL = -1,    /* an argument is out of range, null or inconsistent */
+    MOCO_ENOMEM = -2,    /* device scratch beyond the context's budget, or allocation failure */
+    MOCO_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+    MOCO_EBUSY = -4,     /* serving: no free slot or memory right now (back-pressure) */
+    MOCO_ECANCELED = -5  /* serving: request cancelled by server destruction */
+} moco_status;
+
+typedef enum {
+    MOCO_U16 = 1,   /* uint16 pixels (photon counts) */
+    MOCO_F32 = 2    /* float32 pixels (must be finite) */
+} moco_dtype;
+
+/* How the correlation sum of a[i+s][j+t]*b[i][j] (the third term of the
+ * energy split of sec. 2) is computed.  Every form computes the same f. */
+typedef enum {
+    MOCO_FORM_AUTO = 0,       /* library choice: MOCO_FORM_INT8_MFMA for uint16 when it
+                                 applies, else MOCO_FORM_FP64_EXACT */
+    MOCO_FORM_FP64_EXACT = 3, /* direct FP64 sums on the vector ALUs; bit-exact f for uint16 */
+    MOCO_FORM_INT8_MFMA = 4   /* uint16 only: exact integer correlation on int8 matrix
+                                 cores (balanced base-256 limbs); bit-exact f */
+} moco_form;
+
+typedef struct moco_ctx moco_ctx;
+typedef struct moco_tmpl moco_tmpl;
+
+/* Outputs of one stack of T frames.  All are device pointers; only `shifts`
+ * is required.  W = 2w-1.
+ *   shifts  T x 2 int32   final (S,T) (after the x2 refine when downsampled)
+ *   fmin    T     double  f at the argmin of the searched (coarse) grid
+ *   fsurf   T x W x W double  every f of the searched grid, [frame][s+w-1][t+w-1]
+ *   frefine T x 9 double  f at (2s*+u, 2t*+v), [u+1][v+1]; NaN when not downsampled
+ *   coarse  T x 2 int32   argmin (s*,t*) on the searched grid
+ *   gaps    T x 2 double  (second-best minus best f on the searched grid,
+ *                          second-best minus best of the nine; +inf when n/a)
+ * f is in squared intensity units of the searched grid (box-mean units when
+ * downsampled). */
+typedef struct {
+    int32_t *shifts;
+    double *fmin;
+    double *fsurf;
+    double *frefine;
+    int32_t *coarse;
+    double *gaps;
+} moco_outputs;
+
+/* Create a context on HIP device `device`.  `scratch_budget_bytes` caps the
+ * device scratch the context may hold (0 = 1 GiB); larger stacks are processed
+ * in chunks that fit.  On success *out owns the context.
+ * Errors: MOCO_EINVAL (null out, bad device), MOCO_EDEVICE. */
+int moco_create(int device, size_t scratch_budget_bytes, moco_ctx **out);
+
+/* Release the context and its scratch.  Safe on NULL.  The caller must have
+ * synchronised every stream used with it. */
+void moco_destroy(moco_ctx *ctx);
+
+/* Prepare a template for search (sec. 2: b, its overlap energies sum b^2 for
+ * every shift of the window, computed once and kept resident).
+ * d_template: m x n pixels of `dtype` on the device, read on `hip_stream`
+ * during this call's enqueued work only (the library keeps its own copy).
+ * Errors: MOCO_EINVAL (validation as for moco_align), MOCO_ENOMEM, MOCO_EDEVICE. */
+int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype, int m, int n,
+                         int w, int downsample, void *hip_stream, moco_tmpl **out);
+
+/* Release a template.  Safe on NULL.  Pending work that uses it must have
+ * completed (synchronise its stream first). */
+void moco_template_destroy(moco_tmpl *tmpl);
+
+/* Align one stack: T frames of m x n pixels (d_frames, T*m*n elements of
+ * `dtype`) against a template prepared with the same (dtype, m, n, w,
+ * downsample).  T == 0 is a no-op.  Validation (MOCO_EINVAL): m,n >= 1 (>= 2
+ * when downsampling); downsample in {0,1}; 1 <= w <= min(m',n') where
+ * m' = m/2, n' = n/2 when downsampling (floor), else m, n; T >= 0; known dtype
+ * and form; non-null frames, template and out->shifts; template parameters
+ * equal to the call's.  MOCO_FORM_INT8_MFMA on float32 data is MOCO_EINVAL. */
+int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m, int n,
+               int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
+               void *hip_stream);
+
+/* Stage timing (tracing).  Stages of the pipeline, in launch order. */
+typedef enum {
+    MOCO_STAGE_COARSE = 0,   /* 2x2 box mean / conversion of the frames */
+    MOCO_STAGE_ENERGY = 1,   /* summed-area tables of squared grid values */
+    MOCO_STAGE_PREP = 2,     /* int8 form: limb split of the frames */
+    MOCO_STAGE_CORR = 3,     /* cross-correlation h */
+    MOCO_STAGE_COMBINE = 4,  /* f = (A+B-2h)/Area, argmin, gap */
+    MOCO_STAGE_REFINE = 5,   /* nine full-resolution evaluations */
+    MOCO_STAGE_COUNT = 6
+} moco_stage;
+
+/* Turn stage timing on (1) or off (0) for a context.  While on, every stage
+ * kernel launch is bracketed by a pair of HIP events recorded on the stream it
+ * is launched on.  Errors: MOCO_EINVAL (null ctx). */
+int moco_profile_enable(moco_ctx *ctx, int enable);
+
+/* Wait for the recorded events, add their durations into ms[MOCO_STAGE_COUNT]
+ * (milliseconds) and launches[MOCO_STAGE_COUNT] (kernel launches), and clear
+ * the record.  Arrays are host memory of MOCO_STAGE_COUNT elements, filled
+ * (not accumulated).  Errors: MOCO_EINVAL, MOCO_EDEVICE. */
+int moco_profile_read(moco_ctx *ctx, double *ms, int64_t *launches);
+
+/* Human-readable message of the calling thread's last failure ("" if none). */
+const char *moco_last_error(void);
+
+/* Library version string. */
+const char *moco_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOCO_H */

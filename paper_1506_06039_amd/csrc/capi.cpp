@@ -1,0 +1,389 @@
+// C ABI of the translation-search library: validation, context and scratch,
+// resident templates, and the per-stack pipeline that enqueues the stage
+// kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "moco_internal.h"
+
+struct ProfRec {
+    int stage;
+    hipEvent_t a, b;
+};
+
+struct moco_ctx {
+    int device = 0;
+    size_t budget = 0;
+    void *scratch = nullptr;
+    size_t scratch_size = 0;
+    bool profiling = false;
+    std::vector<ProfRec> prof;        // recorded, not yet read
+    std::vector<hipEvent_t> ev_pool;  // reusable events
+};
+
+struct moco_tmpl {
+    moco_ctx *ctx = nullptr;
+    moco::Tmpl t{};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(MOCO_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Validation shared by template creation and alignment.
+int validate(int m, int n, int w, int ds, moco_dtype dt, moco::Geom *g)
+{
+    if (dt != MOCO_U16 && dt != MOCO_F32) return fail(MOCO_EINVAL, "unknown dtype %d", (int)dt);
+    if (ds != 0 && ds != 1) return fail(MOCO_EINVAL, "downsample must be 0 or 1, got %d", ds);
+    if (m < 1 || n < 1) return fail(MOCO_EINVAL, "image size %dx%d must be positive", m, n);
+    if (ds && (m < 2 || n < 2))
+        return fail(MOCO_EINVAL, "downsampling needs m,n >= 2 (got %dx%d)", m, n);
+    int mg = ds ? m / 2 : m, ng = ds ? n / 2 : n;
+    if (w < 1 || w > mg || w > ng)
+        return fail(MOCO_EINVAL, "window w=%d must satisfy 1 <= w <= min(%d,%d)", w, mg, ng);
+    if ((long long)m * n > (1LL << 30)) return fail(MOCO_EINVAL, "image %dx%d too large", m, n);
+    if (2 * w - 1 > 1024) return fail(MOCO_EINVAL, "window w=%d too large (max 512)", w);
+    g->m = m;
+    g->n = n;
+    g->mg = mg;
+    g->ng = ng;
+    g->w = w;
+    g->W = 2 * w - 1;
+    g->ds = ds;
+    g->dtype = dt;
+    return MOCO_OK;
+}
+
+size_t dtype_size(moco_dtype dt) { return dt == MOCO_U16 ? 2 : 4; }
+
+// Ensure the context holds at least `bytes` of scratch.  Growing frees the old
+// block only after the stream has drained it.
+int ensure_scratch(moco_ctx *ctx, size_t bytes, hipStream_t st)
+{
+    if (bytes <= ctx->scratch_size) return MOCO_OK;
+    if (bytes > ctx->budget)
+        return fail(MOCO_ENOMEM, "scratch of %zu bytes exceeds the context budget %zu", bytes,
+                    ctx->budget);
+    if (ctx->scratch) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(ctx->scratch));
+        ctx->scratch = nullptr;
+        ctx->scratch_size = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->scratch, bytes);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        return fail(MOCO_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    ctx->scratch_size = bytes;
+    return MOCO_OK;
+}
+
+// Per-frame scratch of the FP64 exact form.
+struct ExactLayout {
+    size_t coarse, sat, h, cst, total_per_frame;
+};
+
+ExactLayout exact_layout(const moco::Geom &g)
+{
+    ExactLayout L;
+    L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
+    L.sat = align_up((size_t)(g.mg + 1) * (g.ng + 1) * sizeof(double), 256);
+    L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
+    L.cst = 2 * sizeof(int32_t);
+    L.total_per_frame = L.coarse + L.sat + L.h + L.cst;
+    return L;
+}
+
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev)
+    {
+        ok_ = hipGetDevice(&prev_) == hipSuccess;
+        if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+private:
+    int prev_ = 0;
+    bool ok_ = false;
+};
+
+hipEvent_t pool_event(moco_ctx *ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one stage launch with events when profiling is on.
+class StageTimer {
+public:
+    StageTimer(moco_ctx *ctx, int stage, hipStream_t st) : ctx_(ctx), st_(st)
+    {
+        if (!ctx->profiling) return;
+        rec_.stage = stage;
+        rec_.a = pool_event(ctx);
+        rec_.b = pool_event(ctx);
+        if (rec_.a && rec_.b && hipEventRecord(rec_.a, st) == hipSuccess) on_ = true;
+    }
+    ~StageTimer()
+    {
+        if (on_ && hipEventRecord(rec_.b, st_) == hipSuccess) ctx_->prof.push_back(rec_);
+    }
+
+private:
+    moco_ctx *ctx_;
+    hipStream_t st_;
+    ProfRec rec_{};
+    bool on_ = false;
+};
+
+void free_tmpl(moco::Tmpl &t)
+{
+    if (t.raw) (void)hipFree(t.raw);
+    if (t.coarse) (void)hipFree(t.coarse);
+    if (t.btab) (void)hipFree(t.btab);
+    if (t.limbs) (void)hipFree(t.limbs);
+    t.raw = nullptr;
+    t.coarse = nullptr;
+    t.btab = nullptr;
+    t.limbs = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *moco_last_error(void) { return g_err.c_str(); }
+
+const char *moco_version(void) { return "moco-mi355x 0.1"; }
+
+int moco_create(int device, size_t scratch_budget_bytes, moco_ctx **out)
+{
+    if (!out) return fail(MOCO_EINVAL, "moco_create: out is null");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(MOCO_EINVAL, "device %d out of range (%d devices)", device, count);
+    moco_ctx *ctx = new (std::nothrow) moco_ctx;
+    if (!ctx) return fail(MOCO_ENOMEM, "out of host memory");
+    ctx->device = device;
+    ctx->budget = scratch_budget_bytes ? scratch_budget_bytes : (size_t)1 << 30;
+    *out = ctx;
+    return MOCO_OK;
+}
+
+void moco_destroy(moco_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    for (auto &r : ctx->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int moco_profile_enable(moco_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(MOCO_EINVAL, "moco_profile_enable: null ctx");
+    ctx->profiling = enable != 0;
+    return MOCO_OK;
+}
+
+int moco_profile_read(moco_ctx *ctx, double *ms, int64_t *launches)
+{
+    if (!ctx || !ms || !launches) return fail(MOCO_EINVAL, "moco_profile_read: null argument");
+    DeviceGuard dg(ctx->device);
+    for (int k = 0; k < MOCO_STAGE_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : ctx->prof) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.stage] += t;
+        launches[r.stage] += 1;
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->prof.clear();
+    return MOCO_OK;
+}
+
+int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype, int m, int n,
+                         int w, int downsample, void *hip_stream, moco_tmpl **out)
+{
+    if (!ctx || !out || !d_template)
+        return fail(MOCO_EINVAL, "moco_template_create: null ctx, template or out");
+    *out = nullptr;
+    moco::Geom g;
+    int rc = validate(m, n, w, downsample, dtype, &g);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    moco_tmpl *tp = new (std::nothrow) moco_tmpl;
+    if (!tp) return fail(MOCO_ENOMEM, "out of host memory");
+    tp->ctx = ctx;
+    moco::Tmpl &t = tp->t;
+    t.g = g;
+    size_t raw_bytes = (size_t)m * n * dtype_size(dtype);
+    double *sat = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&](int code) {
+        if (sat) (void)hipStreamSynchronize(st), (void)hipFree(sat);
+        free_tmpl(t);
+        delete tp;
+        return code;
+    };
+    if ((e = hipMalloc(&t.raw, raw_bytes)) != hipSuccess ||
+        (e = hipMalloc(&t.coarse, (size_t)g.mg * g.ng * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&t.btab, (size_t)g.W * g.W * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&sat, (size_t)(g.mg + 1) * (g.ng + 1) * sizeof(double))) != hipSuccess)
+        return cleanup(fail(MOCO_ENOMEM, "template allocation failed: %s", hipGetErrorString(e)));
+    if ((e = hipMemcpyAsync(t.raw, d_template, raw_bytes, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess ||
+        (e = moco::launch_coarse(t.raw, dtype, 1, g, t.coarse, st)) != hipSuccess ||
+        (e = moco::launch_sat_sq(t.coarse, 1, g, sat, st)) != hipSuccess ||
+        (e = moco::launch_btab(sat, g, t.btab, st)) != hipSuccess)
+        return cleanup(fail(MOCO_EDEVICE, "template preparation failed: %s", hipGetErrorString(e)));
+    // the table of template energies is all that is kept of its SAT
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return cleanup(fail(MOCO_EDEVICE, "template preparation failed: %s", hipGetErrorString(e)));
+    (void)hipFree(sat);
+    sat = nullptr;
+    *out = tp;
+    return MOCO_OK;
+}
+
+void moco_template_destroy(moco_tmpl *tmpl)
+{
+    if (!tmpl) return;
+    DeviceGuard dg(tmpl->ctx->device);
+    free_tmpl(tmpl->t);
+    delete tmpl;
+}
+
+int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m, int n,
+               int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
+               void *hip_stream)
+{
+    if (!ctx || !tmpl || !out) return fail(MOCO_EINVAL, "moco_align: null ctx, template or outputs");
+    moco::Geom g;
+    int rc = validate(m, n, w, downsample, dtype, &g);
+    if (rc) return rc;
+    if (T < 0) return fail(MOCO_EINVAL, "T=%d must be >= 0", T);
+    const moco::Geom &tg = tmpl->t.g;
+    if (tg.m != m || tg.n != n || tg.w != w || tg.ds != downsample || tg.dtype != dtype)
+        return fail(MOCO_EINVAL,
+                    "template prepared for (m=%d n=%d w=%d ds=%d dtype=%d), call has "
+                    "(m=%d n=%d w=%d ds=%d dtype=%d)",
+                    tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
+    if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA)
+        return fail(MOCO_EINVAL, "unknown form %d", (int)form);
+    if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
+        return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
+    if (T == 0) return MOCO_OK;
+    if (!d_frames || !out->shifts) return fail(MOCO_EINVAL, "moco_align: null frames or shifts");
+    if (form == MOCO_FORM_INT8_MFMA)
+        return fail(MOCO_EINVAL, "the int8 matrix-core form is not available in this build");
+
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    ExactLayout L = exact_layout(g);
+    int C = (int)std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / L.total_per_frame));
+    C = std::min(C, 4096);
+    if (L.total_per_frame > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu",
+                    L.total_per_frame, ctx->budget);
+    rc = ensure_scratch(ctx, L.total_per_frame * (size_t)C, st);
+    if (rc) return rc;
+    char *base = (char *)ctx->scratch;
+    double *coarse = (double *)base;
+    double *sat = (double *)(base + L.coarse * C);
+    double *h = (double *)(base + (L.coarse + L.sat) * C);
+    int32_t *cst = (int32_t *)(base + (L.coarse + L.sat + L.h) * C);
+    const size_t fbytes = (size_t)m * n * dtype_size(dtype);
+    const int W = g.W;
+    for (int f0 = 0; f0 < T; f0 += C) {
+        int c = std::min(C, T - f0);
+        const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
+            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+            HIP_TRY(moco::launch_sat_sq(coarse, c, g, sat, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            HIP_TRY(moco::launch_corr_fp64(coarse, tmpl->t.coarse, c, g, h, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+            HIP_TRY(moco::launch_combine(sat, tmpl->t.btab, h, c, g,
+                                     out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
+                                     out->fmin ? out->fmin + f0 : nullptr,
+                                     out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
+                                     out->shifts + 2 * (size_t)f0,
+                                     out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
+                                     out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
+        }
+        if (g.ds) {
+            StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
+            HIP_TRY(moco::launch_refine(fr, tmpl->t.raw, c, g,
+                                        out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
+                                        out->shifts + 2 * (size_t)f0,
+                                        out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, st));
+        }
+    }
+    return MOCO_OK;
+}
+
+}  // extern "C"

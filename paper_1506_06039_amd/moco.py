@@ -1,0 +1,185 @@
+"""Python binding of libmoco.so (argument marshalling only).
+
+Every step of the search runs in the HIP kernels behind the C ABI declared in
+``include/moco.h``; this module only turns torch device tensors into pointers
+and the current torch stream into a ``hipStream_t``.  There is no CPU path:
+if the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmoco.so")
+
+MOCO_OK, MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE, MOCO_EBUSY, MOCO_ECANCELED = 0, -1, -2, -3, -4, -5
+MOCO_U16, MOCO_F32 = 1, 2
+FORMS = {"auto": 0, "fp64": 3, "int8": 4}
+
+
+class MocoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("moco error %d: %s" % (code, msg))
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmoco.so is not built (%s); run python -m paper_1506_06039_amd.build"
+                      % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class _Outputs(ctypes.Structure):
+    _fields_ = [("shifts", ctypes.c_void_p), ("fmin", ctypes.c_void_p),
+                ("fsurf", ctypes.c_void_p), ("frefine", ctypes.c_void_p),
+                ("coarse", ctypes.c_void_p), ("gaps", ctypes.c_void_p)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_lib.moco_create.argtypes = [_i, ctypes.c_size_t, ctypes.POINTER(_vp)]
+_lib.moco_create.restype = _i
+_lib.moco_destroy.argtypes = [_vp]
+_lib.moco_destroy.restype = None
+_lib.moco_template_create.argtypes = [_vp, _vp, _i, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]
+_lib.moco_template_create.restype = _i
+_lib.moco_template_destroy.argtypes = [_vp]
+_lib.moco_template_destroy.restype = None
+_lib.moco_align.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
+                            ctypes.POINTER(_Outputs), _vp]
+_lib.moco_align.restype = _i
+_lib.moco_last_error.argtypes = []
+_lib.moco_last_error.restype = ctypes.c_char_p
+_lib.moco_version.argtypes = []
+_lib.moco_version.restype = ctypes.c_char_p
+
+
+def _check(rc: int):
+    if rc != MOCO_OK:
+        raise MocoError(rc, _lib.moco_last_error().decode())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint16:
+        return MOCO_U16
+    if t.dtype == torch.float32:
+        return MOCO_F32
+    raise TypeError("frames must be uint16 or float32, got %s" % t.dtype)
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def version() -> str:
+    return _lib.moco_version().decode()
+
+
+def last_error() -> str:
+    return _lib.moco_last_error().decode()
+
+
+class Context:
+    """moco_create / moco_destroy."""
+
+    def __init__(self, device: int = 0, scratch_budget: int = 0):
+        h = _vp()
+        _check(_lib.moco_create(device, scratch_budget, ctypes.byref(h)))
+        self.handle = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _lib.moco_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Template:
+    """moco_template_create / moco_template_destroy."""
+
+    def __init__(self, ctx: Context, template: torch.Tensor, w: int, downsample: bool):
+        if not template.is_cuda or template.dim() != 2:
+            raise ValueError("template must be a 2-D device tensor")
+        template = template.contiguous()
+        m, n = template.shape
+        h = _vp()
+        _check(_lib.moco_template_create(ctx.handle, template.data_ptr(), _dtype_code(template),
+                                         m, n, w, int(bool(downsample)),
+                                         _stream_handle(template.device), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self.m, self.n, self.w, self.downsample = m, n, w, bool(downsample)
+        self.dtype = template.dtype
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.ctx.device)
+            _lib.moco_template_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Result:
+    shifts: torch.Tensor            # (T, 2) int32
+    fmin: torch.Tensor              # (T,) float64
+    frefine: torch.Tensor           # (T, 9) float64
+    coarse: torch.Tensor            # (T, 2) int32
+    gaps: torch.Tensor              # (T, 2) float64
+    fsurf: torch.Tensor | None      # (T, W, W) float64
+
+
+def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "auto",
+               surface: bool = False, out: Result | None = None) -> Result:
+    """Align frames (T, m, n) against a prepared template; enqueued on the current stream."""
+    if not frames.is_cuda or frames.dim() != 3:
+        raise ValueError("frames must be a 3-D device tensor")
+    if not frames.is_contiguous():
+        raise ValueError("frames must be contiguous")
+    T, m, n = frames.shape
+    W = 2 * tmpl.w - 1
+    dev = frames.device
+    if out is None:
+        out = Result(
+            shifts=torch.empty((T, 2), dtype=torch.int32, device=dev),
+            fmin=torch.empty(T, dtype=torch.float64, device=dev),
+            frefine=torch.empty((T, 9), dtype=torch.float64, device=dev),
+            coarse=torch.empty((T, 2), dtype=torch.int32, device=dev),
+            gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
+            fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None)
+    o = _Outputs(out.shifts.data_ptr(), out.fmin.data_ptr(),
+                 out.fsurf.data_ptr() if out.fsurf is not None else None,
+                 out.frefine.data_ptr(), out.coarse.data_ptr(), out.gaps.data_ptr())
+    _check(_lib.moco_align(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
+                           int(tmpl.downsample), _dtype_code(frames), FORMS[form],
+                           ctypes.byref(o), _stream_handle(dev)))
+    return out
+
+
+def align(frames: torch.Tensor, template: torch.Tensor, w: int, downsample: bool,
+          form: str = "auto", surface: bool = False) -> Result:
+    """One-shot convenience: context + template + align on the current stream."""
+    ctx = Context(frames.device.index or 0)
+    tp = Template(ctx, template, w, downsample)
+    r = moco_align(ctx, frames, tp, form=form, surface=surface)
+    torch.cuda.synchronize(frames.device)
+    tp.close()
+    ctx.close()
+    return r

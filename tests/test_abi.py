@@ -1,0 +1,76 @@
+"""The C-ABI library loads and exports every entry point its headers declare (CPU only)."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1506_06039_amd", "libmoco.so")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(moco_\w+)\s*\(", txt, re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1506_06039_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("moco_create", "moco_destroy", "moco_template_create", "moco_template_destroy",
+                 "moco_align", "moco_last_error"):
+        assert need in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", LIB]).decode()
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for name in sorted(_declared()):
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_version_and_error_string_without_gpu(lib):
+    lib.moco_version.restype = ctypes.c_char_p
+    lib.moco_last_error.restype = ctypes.c_char_p
+    assert lib.moco_version().decode().startswith("moco")
+    assert isinstance(lib.moco_last_error(), bytes)
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    lib.moco_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
+    assert lib.moco_create(0, 0, None) == -1
+    lib.moco_align.restype = ctypes.c_int
+    assert lib.moco_align(None, None, None, 1, 8, 8, 2, 0, 1, 0, None, None) == -1
+    lib.moco_last_error.restype = ctypes.c_char_p
+    assert b"null" in lib.moco_last_error()
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    # the product binding has no CPU path: without libmoco.so it refuses to import
+    code = ("import sys, importlib.util; sys.path.insert(0, %r);"
+            "import paper_1506_06039_amd.moco as m" % ROOT)
+    env = dict(os.environ)
+    # point the package at an empty copy of itself that has no library
+    pkg = tmp_path / "paper_1506_06039_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "moco.py"):
+        (pkg / f).write_text(open(os.path.join(ROOT, "paper_1506_06039_amd", f)).read())
+    code = "import sys; sys.path.insert(0, %r); import paper_1506_06039_amd.moco" % str(tmp_path)
+    r = subprocess.run(["python", "-c", code], capture_output=True, env=env)
+    assert r.returncode != 0
+    assert b"libmoco.so is not built" in r.stderr
