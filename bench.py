@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the moco translation search on one MI355X.
+
+Workload: a stack of 2000 synthetic 512x512 uint16 frames (Poisson photon
+counts, mean 200, ~300 flickering blobs, random-walk drift with jumps up to
+50 px), template = frame 0, 2x2 box downsample to 256x256, window w = 32 on
+the downsampled grid, +-1 refine at 512x512.  A step aligns the whole stack
+(every stage of the search); frames are resident in HBM before timing.
+
+Prints one JSON line: frames/s, the roofline position of the dominant kernel
+(HIP events around its launches on the stream it runs on), the FP64 oracle's
+throughput on the host cores on a bounded sample of the same frames, and a
+shift/f parity check of the timed run against that sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "poisson512_u16_ds_w32"
+M = N = 512
+W_WIN = 32
+DS = True
+STAGES = ["coarse", "energy", "prep", "corr", "combine", "refine"]
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_INT8_TOPS = 5000.0
+
+
+def useful_macs(mg: int, ng: int, w: int) -> int:
+    """Products a[i+s][j+t]*b[i][j] summed over all shifts of the window:
+    sum_s (mg-|s|) * sum_t (ng-|t|)."""
+    W = 2 * w - 1
+    return (W * mg - w * (w - 1)) * (W * ng - w * (w - 1))
+
+
+def kernel_source_sha(fname: str) -> str:
+    p = os.path.join(ROOT, "paper_1506_06039_amd", "csrc", fname)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, source: str, frames_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+    except (ValueError, OSError):
+        return None
+    if not rec or rec.get("source_sha256_16") != kernel_source_sha(source):
+        return None
+    per_frame = (rec["fetch_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) / \
+        rec["frames_per_dispatch"]
+    return per_frame * frames_per_launch
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", default="auto", choices=["auto", "fp64", "int8"])
+    ap.add_argument("--frames", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="frames for the oracle baseline (0: 4 per host thread)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-iters", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(frames are independent; see the design notes for how the stack would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    T = args.frames
+    scene = synth.poisson512_u16(T=T)
+    t0 = time.time()
+    frames_np = scene.frames(0, T, workers=synth.default_workers())
+    tmpl_np = frames_np[0].copy()
+    print("[bench] generated %d frames in %.1fs" % (T, time.time() - t0), file=sys.stderr,
+          flush=True)
+
+    import torch
+    from paper_1506_06039_amd import moco
+    dev = torch.device("cuda", 0)
+    frames = torch.from_numpy(frames_np).to(dev)
+    tmpl = torch.from_numpy(tmpl_np).to(dev)
+    ctx = moco.Context(0, scratch_budget=16 << 30)
+    tp = moco.Template(ctx, tmpl, W_WIN, DS)
+    Wn = 2 * W_WIN - 1
+    out = moco.Result(
+        shifts=torch.empty((T, 2), dtype=torch.int32, device=dev),
+        fmin=torch.empty(T, dtype=torch.float64, device=dev),
+        frefine=torch.empty((T, 9), dtype=torch.float64, device=dev),
+        coarse=torch.empty((T, 2), dtype=torch.int32, device=dev),
+        gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
+        fsurf=None)
+
+    for _ in range(args.warmup):
+        moco.moco_align(ctx, frames, tp, form=args.form, out=out)
+    torch.cuda.synchronize(dev)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    moco.profile_enable(ctx, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    t_start = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        moco.moco_align(ctx, frames, tp, form=args.form, out=out)
+    ev1.record()
+    torch.cuda.synchronize(dev)
+    t_end = time.perf_counter()
+    moco.profile_enable(ctx, False)
+    stage_ms, stage_launches = moco.profile_read(ctx)
+    wall_s = t_end - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1000.0 * wall_s / args.steps
+    fps = T * args.steps / wall_s
+    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr,
+          flush=True)
+
+    # which correlation form ran (AUTO resolves inside the library)
+    form_ran = moco.resolved_form(ctx, tp, args.form)
+    mg, ng = M // 2, N // 2
+    macs = useful_macs(mg, ng, W_WIN)
+    stages = {}
+    for k, name in enumerate(STAGES):
+        if stage_launches[k]:
+            stages[name] = {"ms_total": round(stage_ms[k], 4), "launches": int(stage_launches[k]),
+                            "us_per_launch": round(1000.0 * stage_ms[k] / stage_launches[k], 3)}
+    corr = STAGES.index("corr")
+    frames_per_launch = T * args.steps / max(1, stage_launches[corr])
+    avg_s = stage_ms[corr] / 1000.0 / max(1, stage_launches[corr])
+    if form_ran == "int8":
+        nprod = moco.int8_products(tp)
+        work = 2.0 * macs * nprod * frames_per_launch
+        roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAK_INT8_TOPS,
+                "unit": "TOP/s"}
+        kname, ksrc = "k_corr_int8", "corr_int8.hip"
+        dtype = "i8"
+    else:
+        work = 2.0 * macs * frames_per_launch
+        roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s"}
+        kname, ksrc = "k_corr_fp64", "kernels_basic.hip"
+        dtype = "f64"
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = load_traffic(kname, ksrc, frames_per_launch)
+    roof["kernel"] = kname
+    roof = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()}
+
+    # single-frame latency (submit -> result on host)
+    lat = []
+    one = moco.Result(shifts=out.shifts[:1], fmin=out.fmin[:1], frefine=out.frefine[:1],
+                      coarse=out.coarse[:1], gaps=out.gaps[:1], fsurf=None)
+    host = torch.empty((1, 2), dtype=torch.int32).pin_memory()
+    for k in range(args.latency_iters):
+        fr1 = frames[k % T: k % T + 1]
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        moco.moco_align(ctx, fr1, tp, form=args.form, out=one)
+        host.copy_(one.shifts, non_blocking=True)
+        torch.cuda.synchronize(dev)
+        lat.append(time.perf_counter() - t)
+    lat_us = np.array(lat) * 1e6
+
+    # rerun the stack once more for the parity sample (the timed outputs were overwritten by
+    # the latency loop's first rows)
+    moco.moco_align(ctx, frames, tp, form=args.form, out=out)
+    torch.cuda.synchronize(dev)
+    shifts = out.shifts.cpu().numpy()
+    fmin = out.fmin.cpu().numpy()
+    frefine = out.frefine.cpu().numpy()
+
+    result = {
+        "metric": "frames/s aligned (512x512 uint16, 2x downsample, w=32, +-1 refine)",
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "gpu_ms_per_step": round(gpu_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded Poisson blob movie; stands in for the paper's private videos)",
+        "config": {"workload": WORKLOAD, "frames": T, "m": M, "n": N, "w": W_WIN,
+                   "downsample": DS, "form": form_ran, "template": "frame 0"},
+        "roofline": roof,
+        "stages": stages,
+        "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 1),
+                       "p99": round(float(np.percentile(lat_us, 99)), 1),
+                       "frames": 1, "iters": args.latency_iters},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        nthr = oracle.threads()
+        ns = args.cpu_sample or max(8, 4 * nthr)
+        ns = min(ns, T)
+        t = time.perf_counter()
+        orc = oracle.align(frames_np[:ns], tmpl_np, W_WIN, DS)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {
+            "value": round(ns / dt, 3), "unit": "frames/s", "cores": nthr, "kind": "oracle",
+            "sample": "frames 0..%d of the same stack, FP64 brute force, %d OpenMP threads, "
+                      "%.1f s wall" % (ns - 1, nthr, dt)}
+        same_shift = int(np.sum(np.all(shifts[:ns] == orc.shifts, axis=1)))
+        exact_f = bool(np.array_equal(fmin[:ns], orc.fmin) and
+                       np.array_equal(frefine[:ns], orc.frefine))
+        result["parity"] = {"frames": ns, "shifts_equal": same_shift, "f_bit_exact": exact_f}
+
+    print(json.dumps(result), flush=True)
+    tp.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

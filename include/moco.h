@@ -122,6 +122,14 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
                int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
                void *hip_stream);
 
+/* The correlation form a call with `requested` runs for this template:
+ * MOCO_FORM_AUTO resolves to MOCO_FORM_INT8_MFMA when that form applies to the
+ * template (uint16 data, searched grid of fewer than 131072 pixels and at most
+ * 2048 columns, w <= 512, template grid values within two balanced base-256
+ * digits, i.e. |value| <= 32639), else to MOCO_FORM_FP64_EXACT.
+ * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
+int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
+
 /* Stage timing (tracing).  Stages of the pipeline, in launch order. */
 typedef enum {
     MOCO_STAGE_COARSE = 0,   /* 2x2 box mean / conversion of the frames */

@@ -29,7 +29,7 @@ struct moco_ctx {
 };
 
 struct moco_tmpl {
-    moco_ctx *ctx = nullptr;
+    int device = 0;     // its own copy: a template may outlive the context that made it
     moco::Tmpl t{};
 };
 
@@ -181,11 +181,129 @@ void free_tmpl(moco::Tmpl &t)
     if (t.raw) (void)hipFree(t.raw);
     if (t.coarse) (void)hipFree(t.coarse);
     if (t.btab) (void)hipFree(t.btab);
-    if (t.limbs) (void)hipFree(t.limbs);
+    if (t.i8.tp) (void)hipFree(t.i8.tp);
+    if (t.i8.atab) (void)hipFree(t.i8.atab);
     t.raw = nullptr;
     t.coarse = nullptr;
     t.btab = nullptr;
-    t.limbs = nullptr;
+    t.i8.tp = nullptr;
+    t.i8.atab = nullptr;
+}
+
+// Per-frame scratch of the int8 form.
+struct Int8Layout {
+    size_t limbs, nlimb, atab, edge, h, cst, total_per_frame;
+};
+
+Int8Layout int8_layout(const moco::Geom &g, int npad)
+{
+    Int8Layout L;
+    L.limbs = align_up((size_t)3 * g.mg * npad, 256);
+    L.nlimb = 256;
+    L.atab = align_up((size_t)g.W * g.W * sizeof(long long), 256);
+    L.edge = align_up((size_t)4 * (g.w - 1) * g.w * sizeof(long long), 256);
+    L.h = align_up((size_t)g.W * g.W * sizeof(long long), 256);
+    L.cst = 2 * sizeof(int32_t);
+    L.total_per_frame = L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst;
+    return L;
+}
+
+// Prepare the template side of the int8 form: digit planes, Toeplitz rows and
+// the exact energy table.  Leaves t.int8_ok false when the template needs a
+// third digit plane.
+int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
+{
+    const moco::Geom &g = t.g;
+    t.int8_ok = false;
+    if (!moco::int8_applicable(g)) return MOCO_OK;
+    moco::Int8Geom ig = moco::int8_geom(g);
+    Int8Layout L = int8_layout(g, ig.npad);
+    char *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, L.total_per_frame);
+    if (e != hipSuccess) return fail(MOCO_ENOMEM, "template scratch: %s", hipGetErrorString(e));
+    int8_t *limbs = (int8_t *)tmp;
+    int32_t *nl = (int32_t *)(tmp + L.limbs);
+    long long *atab = (long long *)(tmp + L.limbs + L.nlimb);
+    long long *edge = (long long *)(tmp + L.limbs + L.nlimb + L.atab);
+    int32_t nlimb = 0;
+    int rc = MOCO_OK;
+    t.i8.npad = ig.npad;
+    t.i8.padl = ig.padl;
+    t.i8.trow = ig.trow;
+    if ((e = moco::launch_prep_u16((const uint16_t *)t.raw, 1, g, ig.npad, limbs, nl, atab, edge,
+                                   st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&nlimb, nl, sizeof nlimb, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
+    } else if (nlimb == 2) {
+        if ((e = hipMalloc(&t.i8.tp, (size_t)2 * g.mg * ig.trow)) != hipSuccess ||
+            (e = hipMalloc(&t.i8.atab, (size_t)g.W * g.W * sizeof(long long))) != hipSuccess) {
+            rc = fail(MOCO_ENOMEM, "int8 template allocation: %s", hipGetErrorString(e));
+        } else if ((e = moco::launch_tpad(limbs, g, t.i8, st)) != hipSuccess ||
+                   (e = hipMemcpyAsync(t.i8.atab, atab, (size_t)g.W * g.W * sizeof(long long),
+                                       hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+                   (e = hipStreamSynchronize(st)) != hipSuccess) {
+            rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
+        } else {
+            t.int8_ok = true;
+        }
+    }
+    (void)hipFree(tmp);
+    return rc;
+}
+
+int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
+               const moco::Geom &g, const moco_outputs *out, void *hip_stream)
+{
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int npad = tt.i8.npad;
+    Int8Layout L = int8_layout(g, npad);
+    if (L.total_per_frame > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu",
+                    L.total_per_frame, ctx->budget);
+    int C = (int)std::min<size_t>((size_t)T, ctx->budget / L.total_per_frame);
+    C = std::min(C, 8192);
+    int rc = ensure_scratch(ctx, L.total_per_frame * (size_t)C, st);
+    if (rc) return rc;
+    char *base = (char *)ctx->scratch;
+    int8_t *limbs = (int8_t *)base;
+    int32_t *nl = (int32_t *)(base + L.limbs * C);
+    long long *atab = (long long *)(base + (L.limbs + L.nlimb) * C);
+    long long *edge = (long long *)(base + (L.limbs + L.nlimb + L.atab) * C);
+    long long *h = (long long *)(base + (L.limbs + L.nlimb + L.atab + L.edge) * C);
+    int32_t *cst = (int32_t *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h) * C);
+    const size_t fbytes = (size_t)g.m * g.n * sizeof(uint16_t);
+    const int W = g.W;
+    for (int f0 = 0; f0 < T; f0 += C) {
+        int c = std::min(C, T - f0);
+        const uint16_t *fr = (const uint16_t *)((const char *)d_frames + (size_t)f0 * fbytes);
+        int32_t *coarse = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
+        {
+            StageTimer tm(ctx, MOCO_STAGE_PREP, st);
+            HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, limbs, nl, atab, edge, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            HIP_TRY(moco::launch_corr_int8(limbs, nl, tt.i8, c, g, h, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+            HIP_TRY(moco::launch_combine_i64(
+                atab, tt.i8.atab, h, c, g, out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
+                out->fmin ? out->fmin + f0 : nullptr, coarse, out->shifts + 2 * (size_t)f0,
+                out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
+                out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
+        }
+        if (g.ds) {
+            StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
+            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, coarse, out->shifts + 2 * (size_t)f0,
+                                        out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, st));
+        }
+    }
+    return MOCO_OK;
 }
 
 }  // namespace
@@ -223,6 +341,26 @@ void moco_destroy(moco_ctx *ctx)
     }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved)
+{
+    if (!tmpl || !resolved) return fail(MOCO_EINVAL, "moco_template_form: null argument");
+    const moco::Tmpl &t = tmpl->t;
+    switch (requested) {
+    case MOCO_FORM_AUTO:
+        *resolved = t.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
+        return MOCO_OK;
+    case MOCO_FORM_FP64_EXACT:
+        *resolved = requested;
+        return MOCO_OK;
+    case MOCO_FORM_INT8_MFMA:
+        if (!t.int8_ok) return fail(MOCO_EINVAL, "the int8 matrix-core form does not apply");
+        *resolved = requested;
+        return MOCO_OK;
+    default:
+        return fail(MOCO_EINVAL, "unknown form %d", (int)requested);
+    }
 }
 
 int moco_profile_enable(moco_ctx *ctx, int enable)
@@ -267,7 +405,7 @@ int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype
     hipStream_t st = (hipStream_t)hip_stream;
     moco_tmpl *tp = new (std::nothrow) moco_tmpl;
     if (!tp) return fail(MOCO_ENOMEM, "out of host memory");
-    tp->ctx = ctx;
+    tp->device = ctx->device;
     moco::Tmpl &t = tp->t;
     t.g = g;
     size_t raw_bytes = (size_t)m * n * dtype_size(dtype);
@@ -295,6 +433,10 @@ int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype
         return cleanup(fail(MOCO_EDEVICE, "template preparation failed: %s", hipGetErrorString(e)));
     (void)hipFree(sat);
     sat = nullptr;
+    if (dtype == MOCO_U16) {
+        int rc8 = prepare_int8_template(t, st);
+        if (rc8) return cleanup(rc8);
+    }
     *out = tp;
     return MOCO_OK;
 }
@@ -302,7 +444,7 @@ int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype
 void moco_template_destroy(moco_tmpl *tmpl)
 {
     if (!tmpl) return;
-    DeviceGuard dg(tmpl->ctx->device);
+    DeviceGuard dg(tmpl->device);
     free_tmpl(tmpl->t);
     delete tmpl;
 }
@@ -316,6 +458,9 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     int rc = validate(m, n, w, downsample, dtype, &g);
     if (rc) return rc;
     if (T < 0) return fail(MOCO_EINVAL, "T=%d must be >= 0", T);
+    if (tmpl->device != ctx->device)
+        return fail(MOCO_EINVAL, "template lives on device %d, context on device %d", tmpl->device,
+                    ctx->device);
     const moco::Geom &tg = tmpl->t.g;
     if (tg.m != m || tg.n != n || tg.w != w || tg.ds != downsample || tg.dtype != dtype)
         return fail(MOCO_EINVAL,
@@ -328,9 +473,14 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
         return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
     if (T == 0) return MOCO_OK;
     if (!d_frames || !out->shifts) return fail(MOCO_EINVAL, "moco_align: null frames or shifts");
-    if (form == MOCO_FORM_INT8_MFMA)
-        return fail(MOCO_EINVAL, "the int8 matrix-core form is not available in this build");
-
+    const moco::Tmpl &tt = tmpl->t;
+    if (form == MOCO_FORM_INT8_MFMA && !tt.int8_ok)
+        return fail(MOCO_EINVAL,
+                    "the int8 matrix-core form does not apply to this template (needs uint16, "
+                    "grid area below 131072, grid width at most 2048 and template values "
+                    "within two base-256 digits)");
+    if (form == MOCO_FORM_AUTO) form = tt.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
+    if (form == MOCO_FORM_INT8_MFMA) return align_int8(ctx, d_frames, tt, T, g, out, hip_stream);
     DeviceGuard dg(ctx->device);
     if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)hip_stream;

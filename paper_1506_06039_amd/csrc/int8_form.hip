@@ -1,0 +1,622 @@
+// Exact integer form of the search for uint16 data on the gfx950 matrix cores.
+//
+// Grid values are integers X (2x2 box sums when downsampling, raw counts
+// otherwise).  The three sums of the energy split (sec. 2: Area*f = sum a^2 +
+// sum b^2 - 2 sum ab) are computed exactly:
+//
+//   * sum of squares over D_{s,t} (sec. 2, the recurrence for g): total energy
+//     minus excluded border rows and columns plus the excluded corner, all in
+//     int64, from row/column energies and corner prefix tables built while the
+//     frame streams in (k_prep_u16);
+//   * the correlation h_{s,t} = sum over D of a[i+s][j+t]*b[i][j] (sec. 2,
+//     definition of h) on int8 MFMA: each value is split into balanced base-256
+//     digits X = d0 + 256*d1 (+ 65536*d2), d in [-128,127], every digit product
+//     is exact in the int32 accumulators, and h = sum 256^(p+q) H_pq in int64
+//     (k_corr_int8).
+//
+// The correlation is a band contraction: for template row i and frame column
+// k, H[s][t] += A[i+s][k] * B[i][k-t].  M = s (frame rows i+s, read from a
+// per-wave ring of frame rows in LDS), N = t (the template row i laid out as a
+// Toeplitz operand, read from LDS at a per-lane byte offset and re-aligned
+// with v_alignbyte), K = k (32 columns per MFMA).
+#include <math.h>
+
+#include "moco_internal.h"
+
+namespace moco {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kBlock = 256;
+constexpr int kWaves = 4;
+constexpr int kStrip = 128;          // frame columns per strip
+constexpr int kRowStride = kStrip + 16;  // LDS bytes per ring row (bank offset)
+
+__device__ inline long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int lo = (int)(unsigned)(v & 0xffffffffLL);
+        int hi = (int)(v >> 32);
+        lo = __shfl_xor(lo, off);
+        hi = __shfl_xor(hi, off);
+        v += ((long long)hi << 32) | (unsigned)lo;
+    }
+    return v;
+}
+
+// balanced base-256 digit: returns d in [-128,127] with x - d divisible by 256
+__device__ inline int bdigit(int x) { return ((x + 128) & 255) - 128; }
+
+// ---------------------------------------------------------------------------
+// k_prep_u16: one block per frame.
+//   limbs  [frame][3][mg][npad] int8 (plane 2 written only when needed)
+//   nlimb  [frame]               2, or 3 when some |X| > 32639
+//   atab   [frame][W][W] int64   sum of X^2 over D_{s,t} (frame side)
+//   edge   [frame][2][2][w-1][w] int64 scratch: for the first (top) and last
+//          (bottom) w-1 rows, prefix sums of X^2 over the first q columns (LP)
+//          and over the last q columns (RS), q = 0..w-1
+template <bool DS>
+__device__ inline int grid_value(const uint16_t *a, int n, int i, int j)
+{
+    if (DS) {
+        const uint16_t *p = a + (size_t)(2 * i) * n + 2 * j;
+        return (int)p[0] + (int)p[1] + (int)p[n] + (int)p[n + 1];
+    }
+    return (int)a[(size_t)i * n + j];
+}
+
+template <bool DS>
+__global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
+                                                     int n, int mg, int ng, int w, int npad,
+                                                     int8_t *__restrict__ limbs,
+                                                     int32_t *__restrict__ nlimb,
+                                                     long long *__restrict__ atab,
+                                                     long long *__restrict__ edge)
+{
+    constexpr int kMaxCol4 = 8;                 // npad <= 2048
+    __shared__ long long colE[2048];
+    __shared__ long long rowbuf[kWaves][2][512];  // X^2 of the first / last w-1 columns of an edge row
+    __shared__ long long rT[512], rB[512], cL[512], cR[512];
+    __shared__ long long etot;
+    __shared__ int need3;
+
+    const int frame = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const uint16_t *a = raw + (size_t)frame * m * n;
+    const size_t plane = (size_t)mg * npad;
+    int8_t *L0 = limbs + (size_t)frame * 3 * plane;
+    int8_t *L1 = L0 + plane;
+    const int W = 2 * w - 1, we = w - 1;
+    long long *E = edge + (size_t)frame * 4 * we * w;
+    // E layout: [tb][lr][e][q]: tb 0 top / 1 bottom, lr 0 LP / 1 RS
+    auto eidx = [&](int tb, int lr, int e, int q) { return ((size_t)(tb * 2 + lr) * we + e) * w + q; };
+
+    for (int j = threadIdx.x; j < npad; j += blockDim.x) colE[j] = 0;
+    if (threadIdx.x == 0) {
+        etot = 0;
+        need3 = 0;
+    }
+    __syncthreads();
+
+    long long col[kMaxCol4][4];
+#pragma unroll
+    for (int c = 0; c < kMaxCol4; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) col[c][q] = 0;
+    long long my_etot = 0;
+    int my_need3 = 0;
+
+    for (int i = wave; i < mg; i += kWaves) {
+        const bool top = i < we, bot = i >= mg - we;
+        long long rpart = 0;
+#pragma unroll
+        for (int c = 0; c < kMaxCol4; ++c) {
+            int j0 = 4 * (lane + 64 * c);
+            if (j0 >= npad) break;
+            int d0p = 0, d1p = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int j = j0 + q;
+                int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
+                int d0 = bdigit(X);
+                int x1 = (X - d0) >> 8;
+                int d1 = bdigit(x1);
+                if (((x1 - d1) >> 8) != 0) my_need3 = 1;
+                d0p |= (d0 & 255) << (8 * q);
+                d1p |= (d1 & 255) << (8 * q);
+                long long x2 = (long long)X * X;
+                rpart += x2;
+                col[c][q] += x2;
+                if ((top || bot) && j < ng) {
+                    if (j < we) rowbuf[wave][0][j] = x2;
+                    if (j >= ng - we) rowbuf[wave][1][ng - 1 - j] = x2;
+                }
+            }
+            *(int *)(L0 + (size_t)i * npad + j0) = d0p;
+            *(int *)(L1 + (size_t)i * npad + j0) = d1p;
+        }
+        long long r = wave_sum_i64(rpart);
+        my_etot += r;
+        if (top || bot) {
+            if (lane == 0) {
+                if (top) rT[i] = r;
+                if (bot) rB[mg - 1 - i] = r;
+            }
+            // prefix sums of this row's X^2 over the first / last q columns
+            for (int q = lane; q < w; q += 64) {
+                long long lp = 0, rs = 0;
+                for (int j = 0; j < q; ++j) {
+                    lp += rowbuf[wave][0][j];
+                    rs += rowbuf[wave][1][j];
+                }
+                if (top) {
+                    E[eidx(0, 0, i, q)] = lp;
+                    E[eidx(0, 1, i, q)] = rs;
+                }
+                if (bot) {
+                    E[eidx(1, 0, mg - 1 - i, q)] = lp;
+                    E[eidx(1, 1, mg - 1 - i, q)] = rs;
+                }
+            }
+        }
+    }
+    // column energies and totals
+#pragma unroll
+    for (int c = 0; c < kMaxCol4; ++c) {
+        int j0 = 4 * (lane + 64 * c);
+        if (j0 >= npad) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (j0 + q < ng) atomicAdd((unsigned long long *)&colE[j0 + q], (unsigned long long)col[c][q]);
+    }
+    if (lane == 0) atomicAdd((unsigned long long *)&etot, (unsigned long long)my_etot);
+    if (my_need3) need3 = 1;
+    __syncthreads();
+    // cumulative border tables: rows excluded from the top / bottom, columns from left / right
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int s = 0; s < w; ++s) { cL[s] = acc; if (s < we) acc += colE[s]; }
+    }
+    if (threadIdx.x == 64) {
+        long long acc = 0;
+        for (int s = 0; s < w; ++s) { cR[s] = acc; if (s < we) acc += colE[ng - 1 - s]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // rT/rB become cumulative: rT[s] = sum of the first s row energies
+        long long acc = 0;
+        for (int s = 0; s < w; ++s) { long long v = (s < we) ? rT[s] : 0; rT[s] = acc; acc += v; }
+    }
+    if (threadIdx.x == 64) {
+        long long acc = 0;
+        for (int s = 0; s < w; ++s) { long long v = (s < we) ? rB[s] : 0; rB[s] = acc; acc += v; }
+    }
+    __syncthreads();
+    const long long Etot = etot;
+    long long *A = atab + (size_t)frame * W * W;
+    for (int tt = threadIdx.x; tt < W; tt += blockDim.x) {
+        const int t = tt - we, at = t < 0 ? -t : t;
+        const int lr = t > 0 ? 0 : 1;
+        const long long colex = t > 0 ? cL[at] : (t < 0 ? cR[at] : 0);
+        const long long base = Etot - colex;
+        A[(size_t)we * W + tt] = base;
+        long long ct = 0, cb = 0;
+        for (int s = 1; s < w; ++s) {
+            if (t != 0) {
+                ct += E[eidx(0, lr, s - 1, at)];
+                cb += E[eidx(1, lr, s - 1, at)];
+            }
+            A[(size_t)(we + s) * W + tt] = base - rT[s] + ct;   // shift +s excludes top rows
+            A[(size_t)(we - s) * W + tt] = base - rB[s] + cb;   // shift -s excludes bottom rows
+        }
+    }
+    // third digit plane, only for frames that need it
+    if (need3) {
+        int8_t *L2 = L0 + 2 * plane;
+        for (int i = wave; i < mg; i += kWaves)
+            for (int j0 = 4 * lane; j0 < npad; j0 += 256) {
+                int d2p = 0;
+                for (int q = 0; q < 4; ++q) {
+                    int j = j0 + q;
+                    int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
+                    int d0 = bdigit(X);
+                    int x1 = (X - d0) >> 8;
+                    int d1 = bdigit(x1);
+                    int d2 = (x1 - d1) >> 8;
+                    d2p |= (d2 & 255) << (8 * q);
+                }
+                *(int *)(L2 + (size_t)i * npad + j0) = d2p;
+            }
+    }
+    if (threadIdx.x == 0) nlimb[frame] = need3 ? 3 : 2;
+}
+
+// ---------------------------------------------------------------------------
+// Template rows as Toeplitz sources: TP[q][i][x] = digit q of Y[i][x - padl]
+// (zero outside 0..ng-1), q = 0,1.
+__global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, int mg, int ng,
+                                                 int npad, int trow, int padl,
+                                                 int8_t *__restrict__ tp)
+{
+    const size_t total = (size_t)2 * mg * trow;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        int x = (int)(idx % trow);
+        size_t r = idx / trow;
+        int i = (int)(r % mg), q = (int)(r / mg);
+        int j = x - padl;
+        tp[idx] = (j >= 0 && j < ng) ? tl[(size_t)q * mg * npad + (size_t)i * npad + j] : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_corr_int8: block = 4 waves = 4 frames (one per wave), one (s-group,
+// t-group) of NS x NT tiles of 32 shifts.  NPA digit planes of the frame
+// starting at PA0 (main pass: planes 0,1; extra pass: plane 2) times the two
+// template planes.  Every product is a separate exact int32 accumulator.
+template <int NS, int NT, int NPA, int PA0>
+__global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
+    const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
+    const int8_t *__restrict__ tp, int C, int mg, int npad, int trow, int padl, int w,
+    int tgroups, long long *__restrict__ hout)
+{
+    constexpr int RING = 32 * NS;
+    constexpr int NACC = NPA * 2;
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    int8_t *ring = (int8_t *)lds_raw;                                   // [wave][NPA][RING][kRowStride]
+    int8_t *tbuf = ring + (size_t)kWaves * NPA * RING * kRowStride;     // [2][2][trow]
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int rho = lane % 32, h = lane / 32;
+    const int frame = blockIdx.x * kWaves + wave;
+    const int sg = blockIdx.y / tgroups, tg = blockIdx.y % tgroups;
+    const int W = 2 * w - 1;
+    const int s_lo = -(w - 1) + 32 * NS * sg;
+    const int t_lo = -(w - 1) + 32 * NT * tg;
+    const int s_hi = min(s_lo + RING - 1, w - 1);
+    const int i_lo = max(0, -s_hi), i_hi = min(mg, mg - s_lo);
+    const size_t plane = (size_t)mg * npad;
+
+    // does this wave's frame take part in this pass?
+    bool live = frame < C;
+    if (PA0 > 0) live = live && nlimb[frame] > 2;
+    if (PA0 > 0) {
+        // skip the whole block when no frame of it needs the extra digit plane
+        int any = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            int f = blockIdx.x * kWaves + k;
+            if (f < C && nlimb[f] > 2) any = 1;
+        }
+        if (!any) return;
+    }
+    const int8_t *fl = limbs + (size_t)(live ? frame : 0) * 3 * plane + (size_t)PA0 * plane;
+    int8_t *my_ring = ring + (size_t)wave * NPA * RING * kRowStride;
+
+    v16i acc[NS][NT][NACC];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+#pragma unroll
+            for (int c = 0; c < NACC; ++c) acc[a][b][c] = v16i{0};
+
+    // ring row loader: lanes 0..31 plane 0, 32..63 plane 1 (NPA == 2); 4 bytes each
+    auto fetch_row = [&](int r, int ks, int sw) -> int {
+        int p = lane / 32, off = 4 * (lane % 32);
+        if (!live || p >= NPA || off >= sw || r < 0 || r >= mg) return 0;
+        return *(const int *)(fl + (size_t)p * plane + (size_t)r * npad + ks + off);
+    };
+    auto store_row = [&](int slot, int v, int sw) {
+        int p = lane / 32, off = 4 * (lane % 32);
+        if (p < NPA && off < sw) *(int *)(my_ring + ((size_t)p * RING + slot) * kRowStride + off) = v;
+    };
+    const int tb_words = (2 * trow) / 4;
+    const int *tp32 = (const int *)tp;
+
+    for (int ks = 0; ks < npad; ks += kStrip) {
+        const int sw = min(kStrip, npad - ks);
+        // fill the ring for i = i_lo: rows i_lo + s_lo + q
+        for (int q = 0; q < RING; ++q) {
+            int r = i_lo + s_lo + q;
+            int v = fetch_row(r, ks, sw);
+            store_row((r - s_lo) % RING, v, sw);
+        }
+        // template row i_lo into buffer 0
+        for (int k = threadIdx.x; k < tb_words; k += blockDim.x) {
+            int q = k / (trow / 4), x4 = k % (trow / 4);
+            ((int *)tbuf)[k] = tp32[((size_t)q * mg + i_lo) * (trow / 4) + x4];
+        }
+        __syncthreads();
+        for (int i = i_lo; i < i_hi; ++i) {
+            const int buf = (i - i_lo) & 1;
+            // prefetch: the ring row entering at i+1, and template row i+1
+            const int r_new = i + s_lo + RING;
+            int pf_row = fetch_row(r_new, ks, sw);
+            int pf_t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                int k = threadIdx.x + u * kBlock;
+                pf_t[u] = 0;
+                if (i + 1 < i_hi && k < tb_words) {
+                    int q = k / (trow / 4), x4 = k % (trow / 4);
+                    pf_t[u] = tp32[((size_t)q * mg + i + 1) * (trow / 4) + x4];
+                }
+            }
+            const int8_t *tb = tbuf + (size_t)buf * 2 * trow;
+#pragma unroll
+            for (int kc = 0; kc < kStrip / 32; ++kc) {
+                if (kc * 32 >= sw) break;
+                v4i av[NS][NPA];
+#pragma unroll
+                for (int st = 0; st < NS; ++st) {
+                    int slot = (i + 32 * st + rho) % RING;  // row i + s_lo + 32 st + rho
+#pragma unroll
+                    for (int p = 0; p < NPA; ++p)
+                        av[st][p] = *(const v4i *)(my_ring + ((size_t)p * RING + slot) * kRowStride +
+                                                   kc * 32 + 16 * h);
+                }
+                v4i bv[NT][2];
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt) {
+                    // template bytes B[i][k - t] for k = ks + kc*32 + 16h + e, t = t_lo + 32 tt + rho
+                    int x0 = ks + kc * 32 + 16 * h - (t_lo + 32 * tt + rho) + padl;
+                    int sh = x0 & 3, xa = x0 >> 2;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int *src = (const int *)(tb + (size_t)q * trow) + xa;
+                        int w0 = src[0], w1 = src[1], w2 = src[2], w3 = src[3], w4 = src[4];
+                        v4i b;
+                        b[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
+                        b[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
+                        b[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
+                        b[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
+                        bv[tt][q] = b;
+                    }
+                }
+#pragma unroll
+                for (int st = 0; st < NS; ++st)
+#pragma unroll
+                    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                        for (int p = 0; p < NPA; ++p)
+#pragma unroll
+                            for (int q = 0; q < 2; ++q)
+                                acc[st][tt][p * 2 + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    av[st][p], bv[tt][q], acc[st][tt][p * 2 + q], 0, 0, 0);
+            }
+            // row i + s_lo leaves the ring; row i + s_lo + RING takes its slot (own wave only)
+            store_row(i % RING, pf_row, sw);
+            if (i + 1 < i_hi) {
+                int8_t *nb = tbuf + (size_t)(buf ^ 1) * 2 * trow;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int k = threadIdx.x + u * kBlock;
+                    if (k < tb_words) ((int *)nb)[k] = pf_t[u];
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+
+    if (!live) return;
+    long long *H = hout + (size_t)frame * W * W;
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int s = s_lo + 32 * st + 8 * (r / 4) + 4 * h + (r % 4);
+                int t = t_lo + 32 * tt + rho;
+                if (s > w - 1 || t > w - 1) continue;
+                long long v = 0;
+#pragma unroll
+                for (int p = 0; p < NPA; ++p)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        v += (long long)acc[st][tt][p * 2 + q][r] * (1LL << (8 * (PA0 + p + q)));
+                size_t k = (size_t)(s + w - 1) * W + (t + w - 1);
+                if (PA0 == 0)
+                    H[k] = v;
+                else
+                    H[k] += v;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Combine with exact integer energies: E = A(s,t) + B(s,t) - 2h(s,t) is the
+// integer sum of squared differences over D; f = E*scale/Area.  B comes from
+// the template's own table at (-s,-t).
+struct CandI {
+    double f;
+    int s, t;
+    double second;
+};
+
+__device__ inline bool precedes_i(double f1, int s1, int t1, double f2, int s2, int t2)
+{
+    if (f1 != f2) return f1 < f2;
+    int r1 = max(abs(s1), abs(t1)), r2 = max(abs(s2), abs(t2));
+    if (r1 != r2) return r1 < r2;
+    int l1 = abs(s1) + abs(t1), l2 = abs(s2) + abs(t2);
+    if (l1 != l2) return l1 < l2;
+    if (s1 != s2) return s1 < s2;
+    return t1 < t2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_combine_i64(const long long *__restrict__ atab,
+                                                        const long long *__restrict__ btab_t,
+                                                        const long long *__restrict__ hbuf,
+                                                        int mg, int ng, int w, int ds,
+                                                        double scale, double *__restrict__ fsurf,
+                                                        double *__restrict__ fmin_out,
+                                                        int32_t *__restrict__ coarse_st,
+                                                        int32_t *__restrict__ shifts,
+                                                        double *__restrict__ gaps,
+                                                        double *__restrict__ frefine)
+{
+    const int W = 2 * w - 1;
+    const int frame = blockIdx.x;
+    const long long *A = atab + (size_t)frame * W * W;
+    const long long *Hh = hbuf + (size_t)frame * W * W;
+    CandI c{INFINITY, INT32_MIN, 0, INFINITY};
+    for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
+        int si = k / W, ti = k % W;
+        int s = si - (w - 1), t = ti - (w - 1);
+        long long B = btab_t[(size_t)(W - 1 - si) * W + (W - 1 - ti)];
+        long long E = A[k] + B - 2 * Hh[k];
+        double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+        double f = ((double)E * scale) / area;
+        if (fsurf) fsurf[(size_t)frame * W * W + k] = f;
+        if (c.s == INT32_MIN) {
+            c.f = f; c.s = s; c.t = t;
+        } else if (precedes_i(f, s, t, c.f, c.s, c.t)) {
+            c.second = fmin(c.second, c.f);
+            c.f = f; c.s = s; c.t = t;
+        } else {
+            c.second = fmin(c.second, f);
+        }
+    }
+    __shared__ double sf[kBlock], ss2[kBlock];
+    __shared__ int si_[kBlock], sj_[kBlock];
+    int tid = threadIdx.x;
+    sf[tid] = c.f; ss2[tid] = c.second; si_[tid] = c.s; sj_[tid] = c.t;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            int ys = si_[tid + off];
+            if (ys != INT32_MIN) {
+                int xs = si_[tid];
+                double xf = sf[tid], yf = sf[tid + off];
+                double sec = fmin(ss2[tid], ss2[tid + off]);
+                if (xs == INT32_MIN) {
+                    sf[tid] = yf; si_[tid] = ys; sj_[tid] = sj_[tid + off]; ss2[tid] = sec;
+                } else if (precedes_i(yf, ys, sj_[tid + off], xf, xs, sj_[tid])) {
+                    ss2[tid] = fmin(sec, xf);
+                    sf[tid] = yf; si_[tid] = ys; sj_[tid] = sj_[tid + off];
+                } else {
+                    ss2[tid] = fmin(sec, yf);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (fmin_out) fmin_out[frame] = sf[0];
+        coarse_st[2 * frame] = si_[0];
+        coarse_st[2 * frame + 1] = sj_[0];
+        if (gaps) gaps[2 * frame] = ss2[0] - sf[0];
+        if (!ds) {
+            shifts[2 * frame] = si_[0];
+            shifts[2 * frame + 1] = sj_[0];
+            if (gaps) gaps[2 * frame + 1] = INFINITY;
+        }
+    }
+    if (!ds && frefine && tid < 9) frefine[(size_t)frame * 9 + tid] = NAN;
+}
+
+template <int NS, int NT, int NPA, int PA0>
+hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
+                               int C, const Geom &g, long long *h, hipStream_t st)
+{
+    clear_stale_error();
+    const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
+    const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
+    size_t lds = (size_t)kWaves * NPA * 32 * NS * kRowStride + 2 * 2 * (size_t)tt.trow;
+    dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_corr_int8<NS, NT, NPA, PA0>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_corr_int8<NS, NT, NPA, PA0><<<grid, kBlock, lds, st>>>(limbs, nlimb, tt.tp, C, g.mg, tt.npad,
+                                                            tt.trow, tt.padl, g.w, tgroups, h);
+    return hipGetLastError();
+}
+
+int grid_for(size_t total)
+{
+    size_t gsz = (total + kBlock - 1) / kBlock;
+    if (gsz > 65535 * 4) gsz = 65535 * 4;
+    return (int)(gsz < 1 ? 1 : gsz);
+}
+
+}  // namespace
+
+Int8Geom int8_geom(const Geom &g)
+{
+    Int8Geom r;
+    r.npad = (g.ng + 31) / 32 * 32;
+    const int NT = g.W <= 32 ? 1 : 2;
+    const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
+    const int t_max = -(g.w - 1) + 32 * NT * tgroups - 1;
+    r.padl = (t_max > 0 ? t_max : 0) + 4;
+    r.trow = (r.padl + r.npad + g.w + 32 + 15) / 16 * 16;
+    return r;
+}
+
+bool int8_applicable(const Geom &g)
+{
+    // exact int32 accumulation needs fewer than 2^17 terms per shift; the
+    // prep kernel holds at most 2048 grid columns
+    return g.dtype == MOCO_U16 && (long long)g.mg * g.ng < 131072 && g.ng <= 2048 && g.w <= 512;
+}
+
+hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
+                           int8_t *limbs, int32_t *nlimb, long long *atab, long long *edge,
+                           hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.ds)
+        k_prep_u16<true><<<C, kBlock, 0, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                               nlimb, atab, edge);
+    else
+        k_prep_u16<false><<<C, kBlock, 0, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                                nlimb, atab, edge);
+    return hipGetLastError();
+}
+
+hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st)
+{
+    clear_stale_error();
+    k_tpad<<<grid_for((size_t)2 * g.mg * tt.trow), kBlock, 0, st>>>(tlimbs, g.mg, g.ng, tt.npad,
+                                                                   tt.trow, tt.padl, tt.tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
+                            const Geom &g, long long *h, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    hipError_t e;
+    if (g.W <= 32) {
+        if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, h, st)) != hipSuccess)
+            return e;
+        return launch_corr_variant<1, 1, 1, 2>(limbs, nlimb, tt, C, g, h, st);
+    }
+    if ((e = launch_corr_variant<2, 2, 2, 0>(limbs, nlimb, tt, C, g, h, st)) != hipSuccess) return e;
+    return launch_corr_variant<2, 2, 1, 2>(limbs, nlimb, tt, C, g, h, st);
+}
+
+hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
+                              int C, const Geom &g, double *fsurf, double *fmin,
+                              int32_t *coarse_st, int32_t *shifts, double *gaps, double *frefine,
+                              hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const double scale = g.ds ? 0.0625 : 1.0;
+    k_combine_i64<<<C, kBlock, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale, fsurf, fmin,
+                                        coarse_st, shifts, gaps, frefine);
+    return hipGetLastError();
+}
+
+}  // namespace moco

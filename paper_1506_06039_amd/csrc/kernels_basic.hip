@@ -385,6 +385,7 @@ int grid_for(size_t total)
 hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g, double *coarse,
                          hipStream_t st)
 {
+    clear_stale_error();
     size_t total = (size_t)C * g.mg * g.ng;
     if (total == 0) return hipSuccess;
     if (dt == MOCO_U16)
@@ -398,6 +399,7 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
 
 hipError_t launch_sat_sq(const double *coarse, int C, const Geom &g, double *sat, hipStream_t st)
 {
+    clear_stale_error();
     if (C == 0) return hipSuccess;
     k_sat_sq<<<C, kBlock, 0, st>>>(coarse, g.mg, g.ng, sat);
     return hipGetLastError();
@@ -405,6 +407,7 @@ hipError_t launch_sat_sq(const double *coarse, int C, const Geom &g, double *sat
 
 hipError_t launch_btab(const double *sat_b, const Geom &g, double *btab, hipStream_t st)
 {
+    clear_stale_error();
     k_btab<<<grid_for((size_t)g.W * g.W), kBlock, 0, st>>>(sat_b, g.mg, g.ng, g.w, btab);
     return hipGetLastError();
 }
@@ -412,6 +415,7 @@ hipError_t launch_btab(const double *sat_b, const Geom &g, double *btab, hipStre
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st)
 {
+    clear_stale_error();
     if (C == 0) return hipSuccess;
     int lanes_per_s = (g.W + TB - 1) / TB;
     int s_per_blk = kBlock / lanes_per_s;
@@ -434,6 +438,7 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st)
 {
+    clear_stale_error();
     if (C == 0) return hipSuccess;
     k_combine<<<C, kBlock, 0, st>>>(sat, btab, h, g.mg, g.ng, g.w, g.ds, fsurf, fmin, coarse_st,
                                     shifts, gaps, frefine);
@@ -444,6 +449,7 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, hipStream_t st)
 {
+    clear_stale_error();
     if (C == 0) return hipSuccess;
     if (g.dtype == MOCO_U16)
         k_refine<uint16_t><<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,

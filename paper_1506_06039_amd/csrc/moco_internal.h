@@ -17,23 +17,40 @@ struct Geom {
     moco_dtype dtype;
 };
 
+// Geometry of the int8 form: grid columns padded to a multiple of 32, and the
+// template rows laid out with `padl` leading zero bytes in rows of `trow`.
+struct Int8Geom {
+    int npad, padl, trow;
+};
+
+// Template side of the int8 form (device memory owned by the template).
+struct Int8Tmpl {
+    int8_t *tp = nullptr;          // [2][mg][trow] digit rows of the template
+    long long *atab = nullptr;     // [W][W] sum of Y^2 over the frame-side rows of D at (s,t);
+                                   // the template energy at (s,t) is this table at (-s,-t)
+    int npad = 0, padl = 0, trow = 0;
+};
+
 // Resident, prepared template.  All pointers are device memory owned by it.
 struct Tmpl {
     Geom g;
     void *raw;        // m x n pixels of g.dtype (full resolution, for the x2 refine)
     double *coarse;   // mg x ng FP64 (box mean when ds)
     double *btab;     // W x W: sum of b'^2 over D_{s,t}, [s+w-1][t+w-1]
-    int32_t bmin, bmax;   // range of the integer grid values (uint16 data): box sums or raw
-    int8_t *limbs;    // int8 MFMA form: packed template limbs (see corr_int8.hip), or null
-    size_t limbs_bytes;
-    int nlimb_b;      // number of base-256 limbs the template needs (int8 form)
-    int32_t center;   // common integer offset subtracted from frame and template (int8 form)
+    bool int8_ok;     // the int8 form applies (uint16, template digits fit two planes)
+    Int8Tmpl i8;
 };
 
 // Per-frame intermediate results of the coarse search (device).
 struct CoarseOut {
     int32_t s, t;     // argmin on the searched grid
 };
+
+// A failing HIP call made elsewhere in the process (by the caller, or by a
+// framework sharing the thread) leaves a non-sticky error in the thread's
+// last-error slot; launchers clear it first so that the status they return
+// belongs to their own launch.
+inline void clear_stale_error() { (void)hipGetLastError(); }
 
 // ---- launchers (kernels_basic.hip) -------------------------------------
 // All return hipSuccess or the launch error; they only enqueue.
@@ -49,5 +66,18 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, hipStream_t st);
+
+// ---- int8 form (int8_form.hip) -----------------------------------------
+Int8Geom int8_geom(const Geom &g);
+bool int8_applicable(const Geom &g);
+hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
+                           int32_t *nlimb, long long *atab, long long *edge, hipStream_t st);
+hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
+hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
+                            const Geom &g, long long *h, hipStream_t st);
+hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
+                              int C, const Geom &g, double *fsurf, double *fmin,
+                              int32_t *coarse_st, int32_t *shifts, double *gaps, double *frefine,
+                              hipStream_t st);
 
 }  // namespace moco

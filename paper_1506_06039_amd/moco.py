@@ -53,6 +53,13 @@ _lib.moco_template_destroy.restype = None
 _lib.moco_align.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
                             ctypes.POINTER(_Outputs), _vp]
 _lib.moco_align.restype = _i
+_lib.moco_profile_enable.argtypes = [_vp, _i]
+_lib.moco_profile_enable.restype = _i
+_lib.moco_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+_lib.moco_profile_read.restype = _i
+_lib.moco_template_form.argtypes = [_vp, _i, ctypes.POINTER(_i)]
+_lib.moco_template_form.restype = _i
 _lib.moco_last_error.argtypes = []
 _lib.moco_last_error.restype = ctypes.c_char_p
 _lib.moco_version.argtypes = []
@@ -183,3 +190,33 @@ def align(frames: torch.Tensor, template: torch.Tensor, w: int, downsample: bool
     tp.close()
     ctx.close()
     return r
+
+
+STAGE_COUNT = 6
+
+
+def profile_enable(ctx: Context, on: bool = True):
+    """moco_profile_enable: bracket every stage launch with HIP events."""
+    _check(_lib.moco_profile_enable(ctx.handle, int(bool(on))))
+
+
+def profile_read(ctx: Context):
+    """moco_profile_read: (milliseconds, launches) per stage since the last read."""
+    ms = (ctypes.c_double * STAGE_COUNT)()
+    n = (ctypes.c_int64 * STAGE_COUNT)()
+    _check(_lib.moco_profile_read(ctx.handle, ms, n))
+    return list(ms), list(n)
+
+
+def resolved_form(ctx: Context, tmpl: Template, form: str) -> str:
+    """moco_template_form: the correlation form a call with ``form`` runs for this template."""
+    r = _i()
+    _check(_lib.moco_template_form(tmpl.handle, FORMS[form], ctypes.byref(r)))
+    return {v: k for k, v in FORMS.items()}[r.value]
+
+
+def int8_products(tmpl: Template) -> int:
+    """int8 digit products per correlation term in the int8 form: two balanced
+    base-256 digits of the frame times two of the template (frames that need a
+    third digit add two more products)."""
+    return 4

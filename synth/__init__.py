@@ -157,10 +157,21 @@ class PoissonScene:
             return out
         bounds = np.linspace(k0, k1, workers * 4 + 1).astype(int)
         jobs = [(self, int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
-        with ProcessPoolExecutor(max_workers=workers) as ex:
+        with ProcessPoolExecutor(max_workers=workers, initializer=_one_blas_thread) as ex:
             for (_, a, b), chunk in zip(jobs, ex.map(_poisson_chunk, jobs)):
                 out[a - k0:b - k0] = chunk
         return out
+
+
+def _one_blas_thread():
+    # each worker process draws frames serially; a multi-threaded BLAS in every
+    # worker would oversubscribe the cores
+    try:
+        import threadpoolctl
+        global _TP_LIMIT
+        _TP_LIMIT = threadpoolctl.threadpool_limits(limits=1)
+    except ImportError:  # pragma: no cover
+        pass
 
 
 def _poisson_chunk(job):

@@ -54,12 +54,13 @@ def test_blobs128_f32_all_frames(gpu_lib):
     _say(st)
 
 
-def test_poisson512_u16_ds_first_frames_bit_exact(gpu_lib):
+@pytest.mark.parametrize("form", ["fp64", "int8"])
+def test_poisson512_u16_ds_first_frames_bit_exact(gpu_lib, form):
     sc = synth.poisson512_u16(T=2000)
     T = 24
     fr = sc.frames(0, T)
-    _say("case poisson512_u16 T=%d w=32 ds=1 form=fp64" % T)
-    res = _run(gpu_lib, fr, sc.template, 32, True, "fp64", surface=True)
+    _say("case poisson512_u16 T=%d w=32 ds=1 form=%s" % (T, form))
+    res = _run(gpu_lib, fr, sc.template, 32, True, form, surface=True)
     orc = oracle.align(fr, sc.template, 32, True, want_surface=True)
     st = check(res, orc, True, exact=True, label="poisson512")
     check_surface(res["fsurf"], orc.surf, exact=True, label="poisson512 surface")
@@ -78,9 +79,18 @@ RAGGED = [
 ]
 
 
-@pytest.mark.parametrize("case", RAGGED, ids=lambda c: "%dx%d_w%d_ds%d_%s" % c[:5])
+def _ragged_cases():
+    out = []
+    for c in RAGGED:
+        out.append(c + ("fp64",))
+        if c[4] == "u16":
+            out.append(c + ("int8",))
+    return out
+
+
+@pytest.mark.parametrize("case", _ragged_cases(), ids=lambda c: "%dx%d_w%d_ds%d_%s_%s" % (c[:5] + (c[6],)))
 def test_ragged_shapes(gpu_lib, case):
-    m, n, w, ds, dt, T = case
+    m, n, w, ds, dt, T, form = case
     rng = np.random.default_rng(m * 1000 + n)
     base = rng.uniform(0, 1, size=(m, n))
     if dt == "u16":
@@ -92,7 +102,7 @@ def test_ragged_shapes(gpu_lib, case):
         fr = np.stack([np.roll(base, (k % 3 - 1, k % 2), (0, 1)) + 0.05 * rng.standard_normal((m, n))
                        for k in range(T)]).astype(np.float32)
     _say("case ragged", case)
-    res = _run(gpu_lib, fr, tmpl, w, ds, "fp64", surface=True)
+    res = _run(gpu_lib, fr, tmpl, w, ds, form, surface=True)
     orc = oracle.align(fr, tmpl, w, ds, want_surface=True)
     check(res, orc, ds, exact=(dt == "u16"), label=str(case))
     check_surface(res["fsurf"], orc.surf, exact=(dt == "u16"), label=str(case))
@@ -133,13 +143,14 @@ def test_scratch_budget_too_small(gpu_lib):
     assert ei.value.code == gpu_lib.MOCO_ENOMEM
 
 
-def test_chunked_equals_unchunked(gpu_lib):
+@pytest.mark.parametrize("form,budget", [("fp64", 3 * 1200 * 1024), ("int8", 3 * 300 * 1024)])
+def test_chunked_equals_unchunked(gpu_lib, form, budget):
     # a small scratch budget forces several chunks; results must be identical
     sc = synth.poisson512_u16(T=40)
     fr = sc.frames(0, 12)
-    big = _run(gpu_lib, fr, sc.template, 32, True, "fp64")
-    ctx = gpu_lib.Context(0, scratch_budget=3 * 1200 * 1024)
-    small = _run(gpu_lib, fr, sc.template, 32, True, "fp64", ctx=ctx)
+    big = _run(gpu_lib, fr, sc.template, 32, True, form)
+    ctx = gpu_lib.Context(0, scratch_budget=budget)
+    small = _run(gpu_lib, fr, sc.template, 32, True, form, ctx=ctx)
     for k in big:
         assert np.array_equal(big[k], small[k], equal_nan=True), k
 
@@ -151,3 +162,77 @@ def test_deterministic_repeat(gpu_lib):
     b = _run(gpu_lib, fr, sc.template, 10, False, "fp64", surface=True)
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_int8_third_digit_plane_frames(gpu_lib):
+    # frames with box sums above 32639 need a third digit plane; the template does not
+    rng = np.random.default_rng(77)
+    m = n = 96
+    base = rng.uniform(0, 1, size=(m, n))
+    tmpl = rng.poisson(2000 * base + 100).astype(np.uint16)
+    frames = []
+    for k in range(6):
+        f = rng.poisson(np.roll(2000 * base + 100, (k - 3, 2 * k - 5), (0, 1))).astype(np.int64)
+        if k % 2 == 1:
+            f[10:30, 40:70] = 60000 + rng.integers(0, 5000, size=(20, 30))  # bright patch
+        frames.append(np.clip(f, 0, 65535).astype(np.uint16))
+    fr = np.stack(frames)
+    _say("case int8 third digit plane 96x96 w=12 ds=1")
+    res8 = _run(gpu_lib, fr, tmpl, 12, True, "int8", surface=True)
+    res64 = _run(gpu_lib, fr, tmpl, 12, True, "fp64", surface=True)
+    orc = oracle.align(fr, tmpl, 12, True, want_surface=True)
+    check(res8, orc, True, exact=True, label="int8 3 digits")
+    check_surface(res8["fsurf"], orc.surf, exact=True, label="int8 3 digits surface")
+    for k in res8:
+        assert np.array_equal(res8[k], res64[k], equal_nan=True), k
+
+
+def test_int8_bright_template_falls_back(gpu_lib):
+    # a template beyond two base-256 digits: the int8 form refuses it, AUTO uses FP64
+    rng = np.random.default_rng(5)
+    tmpl = rng.integers(50000, 65535, size=(64, 64)).astype(np.uint16)
+    fr = np.stack([np.roll(tmpl, (1, -2), (0, 1))]).astype(np.uint16)
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(tmpl), 8, True)
+    with pytest.raises(gpu_lib.MocoError) as ei:
+        gpu_lib.moco_align(ctx, _to_dev(fr), tp, form="int8")
+    assert ei.value.code == gpu_lib.MOCO_EINVAL
+    r = gpu_lib.moco_align(ctx, _to_dev(fr), tp, form="auto")
+    torch.cuda.synchronize()
+    assert r.shifts.cpu().numpy().tolist() == [[1, -2]]
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fp64"
+
+
+def test_auto_picks_int8_for_uint16(gpu_lib):
+    sc = synth.poisson512_u16(T=4)
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(sc.template), 32, True)
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "int8"
+    tf = gpu_lib.Template(ctx, _to_dev(sc.template.astype(np.float32)), 32, True)
+    assert gpu_lib.resolved_form(ctx, tf, "auto") == "fp64"
+
+
+def test_int8_equals_fp64_on_a_stack(gpu_lib):
+    sc = synth.poisson512_u16(T=64, seed=4)
+    fr = sc.frames(0, 64)
+    a = _run(gpu_lib, fr, sc.template, 32, True, "int8", surface=True)
+    b = _run(gpu_lib, fr, sc.template, 32, True, "fp64", surface=True)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    # partial last block of four frames
+    c = _run(gpu_lib, fr[:7], sc.template, 32, True, "int8", surface=True)
+    for k in c:
+        assert np.array_equal(c[k], a[k][:7], equal_nan=True), k
+
+
+def test_template_outlives_context(gpu_lib):
+    # destroying the context first must leave the template's own teardown sound
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(np.ones((32, 32), np.uint16)), 4, False)
+    ctx.close()
+    tp.close()
+    ctx2 = gpu_lib.Context(0)
+    tp2 = gpu_lib.Template(ctx2, _to_dev(np.ones((32, 32), np.uint16)), 4, False)
+    r = gpu_lib.moco_align(ctx2, _to_dev(np.ones((2, 32, 32), np.uint16)), tp2)
+    torch.cuda.synchronize()
+    assert r.shifts.cpu().numpy().tolist() == [[0, 0], [0, 0]]
