@@ -108,7 +108,7 @@ int ensure_scratch(moco_ctx *ctx, size_t bytes, hipStream_t st)
 
 // Per-frame scratch of the FP64 exact form.
 struct ExactLayout {
-    size_t coarse, sat, h, cst, total_per_frame;
+    size_t coarse, sat, h, cst, part, total_per_frame;
 };
 
 ExactLayout exact_layout(const moco::Geom &g)
@@ -118,7 +118,8 @@ ExactLayout exact_layout(const moco::Geom &g)
     L.sat = align_up((size_t)(g.mg + 1) * (g.ng + 1) * sizeof(double), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 2 * sizeof(int32_t);
-    L.total_per_frame = L.coarse + L.sat + L.h + L.cst;
+    L.part = align_up(moco::refine_partial_bytes(g), 8);
+    L.total_per_frame = L.coarse + L.sat + L.h + L.cst + L.part;
     return L;
 }
 
@@ -192,7 +193,7 @@ void free_tmpl(moco::Tmpl &t)
 
 // Per-frame scratch of the int8 form.
 struct Int8Layout {
-    size_t limbs, nlimb, atab, edge, h, cst, total_per_frame;
+    size_t limbs, nlimb, atab, edge, h, cst, part, total_per_frame;
 };
 
 Int8Layout int8_layout(const moco::Geom &g, int npad)
@@ -204,7 +205,8 @@ Int8Layout int8_layout(const moco::Geom &g, int npad)
     L.edge = align_up((size_t)4 * (g.w - 1) * g.w * sizeof(long long), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(long long), 256);
     L.cst = 2 * sizeof(int32_t);
-    L.total_per_frame = L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst;
+    L.part = align_up(moco::refine_partial_bytes(g), 8);
+    L.total_per_frame = L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst + L.part;
     return L;
 }
 
@@ -274,6 +276,7 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     long long *edge = (long long *)(base + (L.limbs + L.nlimb + L.atab) * C);
     long long *h = (long long *)(base + (L.limbs + L.nlimb + L.atab + L.edge) * C);
     int32_t *cst = (int32_t *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h) * C);
+    double *part = (double *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst) * C);
     const size_t fbytes = (size_t)g.m * g.n * sizeof(uint16_t);
     const int W = g.W;
     for (int f0 = 0; f0 < T; f0 += C) {
@@ -300,7 +303,8 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
             HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, coarse, out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
-                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, st));
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
+                                        st));
         }
     }
     return MOCO_OK;
@@ -497,6 +501,7 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     double *sat = (double *)(base + L.coarse * C);
     double *h = (double *)(base + (L.coarse + L.sat) * C);
     int32_t *cst = (int32_t *)(base + (L.coarse + L.sat + L.h) * C);
+    double *part = (double *)(base + (L.coarse + L.sat + L.h + L.cst) * C);
     const size_t fbytes = (size_t)m * n * dtype_size(dtype);
     const int W = g.W;
     for (int f0 = 0; f0 < T; f0 += C) {
@@ -530,7 +535,8 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
                                         out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
                                         out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
-                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, st));
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
+                                        st));
         }
     }
     return MOCO_OK;

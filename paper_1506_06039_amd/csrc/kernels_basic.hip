@@ -373,6 +373,234 @@ __global__ __launch_bounds__(kBlock) void k_refine(const T *__restrict__ frames,
     }
 }
 
+// Banded x2 step: block (band of template rows, frame).  The frame rows the
+// band touches, i0+2s*-1 .. i1+2s*, are staged in LDS; every thread walks
+// template pixels of the band and adds the nine squared differences with FP64
+// FMAs (exact for uint16: every square is below 2^32 and every partial sum
+// far below 2^53).  Partial sums go to [frame][band][9]; k_refine_finish adds
+// them in band order and takes the argmin.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_refine_band(const T *__restrict__ frames,
+                                                        const T *__restrict__ tmpl, int m, int n,
+                                                        int br, const int32_t *__restrict__ coarse_st,
+                                                        double *__restrict__ partial)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    T *rows = (T *)lds_raw;  // (br + 2) x n
+    const int frame = blockIdx.y, band = blockIdx.x, nband = gridDim.x;
+    const int i0 = band * br, i1 = min(m, i0 + br);
+    const int cs = coarse_st[2 * frame], ct = coarse_st[2 * frame + 1];
+    const int S0 = 2 * cs, T0 = 2 * ct;
+    const int rbase = i0 + S0 - 1;
+    const int nrows = i1 - i0 + 2;
+    const T *a = frames + (size_t)frame * m * n;
+    for (int idx = threadIdx.x; idx < nrows * n; idx += blockDim.x) {
+        int rr = idx / n, c = idx - (idx / n) * n;
+        int r = rbase + rr;
+        rows[idx] = (r >= 0 && r < m) ? a[(size_t)r * n + c] : (T)0;
+    }
+    __syncthreads();
+    double acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    const int total = (i1 - i0) * n;
+    for (int p = threadIdx.x; p < total; p += blockDim.x) {
+        int li = p / n, j = p - (p / n) * n;
+        int i = i0 + li;
+        double bv = (double)tmpl[(size_t)i * n + j];
+#pragma unroll
+        for (int u = -1; u <= 1; ++u) {
+            int r = i + S0 + u;
+            if (r < 0 || r >= m) continue;
+            const T *rowp = rows + (size_t)(li + u + 1) * n;
+#pragma unroll
+            for (int v = -1; v <= 1; ++v) {
+                int c = j + T0 + v;
+                if (c >= 0 && c < n) {
+                    double d = (double)rowp[c] - bv;
+                    acc[(u + 1) * 3 + (v + 1)] = fma(d, d, acc[(u + 1) * 3 + (v + 1)]);
+                }
+            }
+        }
+    }
+    // block reduction of the nine sums (fixed tree order)
+    __shared__ double red[9][kBlock];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 9)
+        partial[((size_t)frame * nband + band) * 9 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// uint16 x2 step in integers.  One block per frame; a thread owns four
+// template columns j0..j0+3 and a contiguous run of rows, and walks them with
+// a rolling window of the three frame rows i+2s*-1..i+2s*+1 held in registers
+// (the next row is fetched one step ahead).  Each frame row contributes the six
+// values at columns j0+2t*-1..j0+2t*+4.  Squares of differences (|d| <= 65535)
+// come from a 24-bit multiply (exact low 32 bits) and add into 64-bit sums;
+// the nine block sums go to partial[frame][9] as exact FP64 integers.
+struct Row6 {
+    int v[6];
+};
+
+__device__ inline Row6 load_row6(const uint16_t *__restrict__ a, int m, int n, int r, int c0,
+                                 bool vec)
+{
+    // columns c0 .. c0+5 of row r; zero where outside the image
+    Row6 o;
+    if (r < 0 || r >= m) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o.v[k] = 0;
+        return o;
+    }
+    const uint16_t *row = a + (size_t)r * n;
+    if (vec) {
+        // c0 - 1 is even and c0-1 .. c0+6 lie inside the row: four aligned pairs
+        const uint32_t *p = (const uint32_t *)(row + c0 - 1);
+        uint32_t q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+        o.v[0] = (int)(q0 >> 16);
+        o.v[1] = (int)(q1 & 0xffff);
+        o.v[2] = (int)(q1 >> 16);
+        o.v[3] = (int)(q2 & 0xffff);
+        o.v[4] = (int)(q2 >> 16);
+        o.v[5] = (int)(q3 & 0xffff);
+        return o;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int c = c0 + k;
+        o.v[k] = (c >= 0 && c < n) ? (int)row[c] : 0;
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restrict__ frames,
+                                                       const uint16_t *__restrict__ tmpl, int m,
+                                                       int n, const int32_t *__restrict__ coarse_st,
+                                                       double *__restrict__ partial)
+{
+    const int frame = blockIdx.x;
+    const int S0 = 2 * coarse_st[2 * frame], T0 = 2 * coarse_st[2 * frame + 1];
+    const uint16_t *a = frames + (size_t)frame * m * n;
+    const bool aligned = ((n & 1) == 0) && ((((uintptr_t)a) & 3) == 0);
+    unsigned long long acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0;
+    const int ncg = (n + 3) / 4;
+    const int ncgs = ncg < kBlock ? ncg : kBlock;
+    const int rg_count = kBlock / ncgs;
+    const int rg = threadIdx.x / ncgs;
+    if (rg < rg_count) {
+        const int rows_per = (m + rg_count - 1) / rg_count;
+        const int ia = rg * rows_per, ib = min(m, ia + rows_per);
+        for (int cg = threadIdx.x % ncgs; cg < ncg; cg += ncgs) {
+            const int j0 = 4 * cg;
+            const int c0 = j0 + T0 - 1;  // first frame column of the window
+            int kval = 0, qval = 0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (c0 + k >= 0 && c0 + k < n) kval |= 1 << k;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j0 + q < n) qval |= 1 << q;
+            const bool interior = kval == 63 && qval == 15;
+            const bool vec = aligned && c0 - 1 >= 0 && c0 + 6 < n;
+            const bool tvec = ((n & 3) == 0) && j0 + 3 < n;
+            if (ia >= ib) continue;
+            Row6 w0 = load_row6(a, m, n, ia + S0 - 1, c0, vec);
+            Row6 w1 = load_row6(a, m, n, ia + S0, c0, vec);
+            Row6 w2 = load_row6(a, m, n, ia + S0 + 1, c0, vec);
+            for (int i = ia; i < ib; ++i) {
+                // fetch one step ahead
+                Row6 w3 = load_row6(a, m, n, i + S0 + 2, c0, vec);
+                int b[4];
+                if (tvec) {
+                    uint2 t2 = *(const uint2 *)(tmpl + (size_t)i * n + j0);
+                    b[0] = (int)(t2.x & 0xffff);
+                    b[1] = (int)(t2.x >> 16);
+                    b[2] = (int)(t2.y & 0xffff);
+                    b[3] = (int)(t2.y >> 16);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        b[q] = (qval >> q & 1) ? (int)tmpl[(size_t)i * n + j0 + q] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    const int r = i + S0 + u - 1;
+                    if (r < 0 || r >= m) continue;
+                    const Row6 &f = u == 0 ? w0 : (u == 1 ? w1 : w2);
+#pragma unroll
+                    for (int v = 0; v < 3; ++v)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            int d = f.v[q + v] - b[q];
+                            if (!interior && !((kval >> (q + v) & 1) && (qval >> q & 1))) d = 0;
+                            acc[u * 3 + v] += (unsigned)__mul24(d, d);
+                        }
+                }
+                w0 = w1;
+                w1 = w2;
+                w2 = w3;
+            }
+        }
+    }
+    // wave sums, then the four waves in order
+    __shared__ unsigned long long red[kBlock / 64][9];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        unsigned long long v = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+            lo = __shfl_xor(lo, off);
+            hi = __shfl_xor(hi, off);
+            v += ((unsigned long long)hi << 32) | lo;
+        }
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
+        partial[(size_t)frame * 9 + threadIdx.x] = (double)t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restrict__ partial,
+                                                          int C, int nband, int m, int n,
+                                                          const int32_t *__restrict__ coarse_st,
+                                                          int32_t *__restrict__ shifts,
+                                                          double *__restrict__ frefine,
+                                                          double *__restrict__ gaps)
+{
+    const int frame = blockIdx.x * blockDim.x + threadIdx.x;
+    if (frame >= C) return;
+    const int cs = coarse_st[2 * frame], ct = coarse_st[2 * frame + 1];
+    Cand c{INFINITY, INT32_MIN, 0, INFINITY};
+    for (int q = 0; q < 9; ++q) {
+        double e = 0.0;
+        for (int b = 0; b < nband; ++b) e += partial[((size_t)frame * nband + b) * 9 + q];
+        int u = q / 3 - 1, v = q % 3 - 1;
+        int s = 2 * cs + u, t = 2 * ct + v;
+        double area = (double)(m - abs(s)) * (double)(n - abs(t));
+        double f = e / area;
+        if (frefine) frefine[(size_t)frame * 9 + q] = f;
+        cand_add(c, f, s, t);
+    }
+    shifts[2 * frame] = c.s;
+    shifts[2 * frame + 1] = c.t;
+    if (gaps) gaps[2 * frame + 1] = c.second - c.f;
+}
+
 int grid_for(size_t total)
 {
     size_t g = (total + kBlock - 1) / kBlock;
@@ -447,10 +675,41 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
 
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
-                         double *gaps, hipStream_t st)
+                         double *gaps, double *partial, hipStream_t st)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
+    const size_t esz = g.dtype == MOCO_U16 ? 2 : 4;
+    int br = refine_band_rows(g);
+    if (g.dtype == MOCO_U16) {
+        k_refine_u16<<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw, g.m,
+                                           g.n, coarse_st, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, 1, g.m, g.n,
+                                                                      coarse_st, shifts, frefine,
+                                                                      gaps);
+        return hipGetLastError();
+    }
+    if (br > 0) {
+        const int nband = (g.m + br - 1) / br;
+        const size_t lds = (size_t)(br + 2) * g.n * esz;
+        dim3 grid(nband, C);
+        if (g.dtype == MOCO_U16)
+            k_refine_band<uint16_t><<<grid, kBlock, lds, st>>>((const uint16_t *)frames,
+                                                               (const uint16_t *)traw, g.m, g.n, br,
+                                                               coarse_st, partial);
+        else
+            k_refine_band<float><<<grid, kBlock, lds, st>>>((const float *)frames,
+                                                            (const float *)traw, g.m, g.n, br,
+                                                            coarse_st, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, nband, g.m, g.n,
+                                                                      coarse_st, shifts, frefine,
+                                                                      gaps);
+        return hipGetLastError();
+    }
     if (g.dtype == MOCO_U16)
         k_refine<uint16_t><<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
                                                  g.m, g.n, coarse_st, shifts, frefine, gaps);
@@ -458,6 +717,25 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
         k_refine<float><<<C, kBlock, 0, st>>>((const float *)frames, (const float *)traw, g.m,
                                               g.n, coarse_st, shifts, frefine, gaps);
     return hipGetLastError();
+}
+
+int refine_band_rows(const Geom &g)
+{
+    // rows of LDS staging: uint16 rows carry a few halo columns
+    const size_t esz = g.dtype == MOCO_U16 ? 2 : 4;
+    const size_t row = (size_t)(g.n + 16) * esz;
+    if (3 * row > 40 * 1024) return 0;  // very wide frames: the unstaged kernel
+    int br = (int)(40 * 1024 / row) - 2;
+    const int cap = g.dtype == MOCO_U16 ? 32 : 16;
+    return br > cap ? cap : br;
+}
+
+size_t refine_partial_bytes(const Geom &g)
+{
+    if (g.dtype == MOCO_U16) return 9 * sizeof(double);
+    int br = refine_band_rows(g);
+    if (br <= 0) return 0;
+    return (size_t)((g.m + br - 1) / br) * 9 * sizeof(double);
 }
 
 }  // namespace moco

@@ -65,7 +65,9 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st);
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
-                         double *gaps, hipStream_t st);
+                         double *gaps, double *partial, hipStream_t st);
+int refine_band_rows(const Geom &g);
+size_t refine_partial_bytes(const Geom &g);   // per frame
 
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);
