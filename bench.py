@@ -78,7 +78,19 @@ def main():
                     help="frames for the oracle baseline (0: 4 per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (three times), the "
+                         "reference for HBM byte counters, and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(frames are independent; see the design notes for how the stack would shard)",
@@ -152,7 +164,7 @@ def main():
         work = 2.0 * macs * nprod * frames_per_launch
         roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": PEAK_INT8_TOPS,
                 "unit": "TOP/s"}
-        kname, ksrc = "k_corr_int8", "corr_int8.hip"
+        kname, ksrc = "k_corr_int8", "int8_form.hip"
         dtype = "i8"
     else:
         work = 2.0 * macs * frames_per_launch

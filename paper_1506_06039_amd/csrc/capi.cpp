@@ -238,7 +238,7 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
     } else if (nlimb == 2) {
-        if ((e = hipMalloc(&t.i8.tp, (size_t)2 * g.mg * ig.trow)) != hipSuccess ||
+        if ((e = hipMalloc(&t.i8.tp, moco::int8_template_bytes(g))) != hipSuccess ||
             (e = hipMalloc(&t.i8.atab, (size_t)g.W * g.W * sizeof(long long))) != hipSuccess) {
             rc = fail(MOCO_ENOMEM, "int8 template allocation: %s", hipGetErrorString(e));
         } else if ((e = moco::launch_tpad(limbs, g, t.i8, st)) != hipSuccess ||

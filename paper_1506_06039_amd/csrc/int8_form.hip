@@ -33,6 +33,8 @@ constexpr int kBlock = 256;
 constexpr int kWaves = 4;
 constexpr int kStrip = 128;          // frame columns per strip
 constexpr int kRowStride = kStrip + 16;  // LDS bytes per ring row (bank offset)
+constexpr int kPhases = 8;           // byte-phase copies of each template row
+constexpr int kMaxTrow = 1024;       // template row bytes held per phase and digit
 
 __device__ inline long long wave_sum_i64(long long v)
 {
@@ -235,19 +237,22 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Template rows as Toeplitz sources: TP[q][i][x] = digit q of Y[i][x - padl]
-// (zero outside 0..ng-1), q = 0,1.
+// Template rows as Toeplitz sources, in eight byte-phase copies so that every
+// operand read is 8-byte aligned: TP[i][q][phi][x] = digit q of
+// Y[i][x + phi - padl] (zero outside 0..ng-1), q = 0,1, phi = 0..7.
 __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, int mg, int ng,
                                                  int npad, int trow, int padl,
                                                  int8_t *__restrict__ tp)
 {
-    const size_t total = (size_t)2 * mg * trow;
+    const size_t total = (size_t)mg * 2 * kPhases * trow;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         int x = (int)(idx % trow);
         size_t r = idx / trow;
-        int i = (int)(r % mg), q = (int)(r / mg);
-        int j = x - padl;
+        int phi = (int)(r % kPhases);
+        r /= kPhases;
+        int q = (int)(r % 2), i = (int)(r / 2);
+        int j = x + phi - padl;
         tp[idx] = (j >= 0 && j < ng) ? tl[(size_t)q * mg * npad + (size_t)i * npad + j] : 0;
     }
 }
@@ -257,17 +262,28 @@ __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, 
 // t-group) of NS x NT tiles of 32 shifts.  NPA digit planes of the frame
 // starting at PA0 (main pass: planes 0,1; extra pass: plane 2) times the two
 // template planes.  Every product is a separate exact int32 accumulator.
+//
+// Per template row i and strip of 128 frame columns: each wave reads its A
+// operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
+// (template row i as a Toeplitz operand) from the shared template buffer, four
+// K-chunks of 32 columns, 16 MFMAs per chunk, operands of chunk k+1 loaded
+// before the MFMAs of chunk k.  Template row i+1 streams global -> LDS (no
+// registers) into the other of two statically distinct buffers while row i is
+// in use; the row loop is unrolled by two so that every LDS read provably
+// targets a buffer other than the one being filled.
 template <int NS, int NT, int NPA, int PA0>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
     const int8_t *__restrict__ tp, int C, int mg, int npad, int trow, int padl, int w,
     int tgroups, long long *__restrict__ hout)
 {
-    constexpr int RING = 32 * NS;
+    constexpr int RING = 32 * NS;     // frame rows an iteration reads
+    constexpr int RS = RING + 2;      // ring slots: two rows arrive ahead of use
     constexpr int NACC = NPA * 2;
-    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-    int8_t *ring = (int8_t *)lds_raw;                                   // [wave][NPA][RING][kRowStride]
-    int8_t *tbuf = ring + (size_t)kWaves * NPA * RING * kRowStride;     // [2][2][trow]
+    constexpr int KC = kStrip / 32;   // MFMA K-chunks per strip (npad is a multiple of kStrip)
+    __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * NPA * RS * kRowStride];
+    __shared__ __attribute__((aligned(16))) int8_t s_tA[2 * kPhases * kMaxTrow];
+    __shared__ __attribute__((aligned(16))) int8_t s_tB[2 * kPhases * kMaxTrow];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int rho = lane % 32, h = lane / 32;
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         if (!any) return;
     }
     const int8_t *fl = limbs + (size_t)(live ? frame : 0) * 3 * plane + (size_t)PA0 * plane;
-    int8_t *my_ring = ring + (size_t)wave * NPA * RING * kRowStride;
+    int8_t *my_ring = s_ring + (size_t)wave * NPA * RS * kRowStride;
 
     v16i acc[NS][NT][NACC];
 #pragma unroll
@@ -303,78 +319,96 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
 #pragma unroll
             for (int c = 0; c < NACC; ++c) acc[a][b][c] = v16i{0};
 
-    // ring row loader: lanes 0..31 plane 0, 32..63 plane 1 (NPA == 2); 4 bytes each
-    auto fetch_row = [&](int r, int ks, int sw) -> int {
-        int p = lane / 32, off = 4 * (lane % 32);
-        if (!live || p >= NPA || off >= sw || r < 0 || r >= mg) return 0;
-        return *(const int *)(fl + (size_t)p * plane + (size_t)r * npad + ks + off);
+    // Frame row r (columns ks..ks+127 of every digit plane) into ring slot
+    // (r - s_lo) mod RS: global -> LDS by eight lanes per plane when the row
+    // exists, zeros written directly otherwise.  Each wave fills its own ring.
+    auto ring_fill = [&](int r, int ks) {
+        const int slot = (r - s_lo) % RS;
+        if (live && r >= 0 && r < mg) {
+#pragma unroll
+            for (int p = 0; p < NPA; ++p)
+                if (lane < kStrip / 16)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(fl + (size_t)p * plane + (size_t)r * npad + ks + lane * 16),
+                        (__attribute__((address_space(3))) void *)(my_ring +
+                                                                   ((size_t)p * RS + slot) * kRowStride),
+                        16, 0, 0);
+        } else {
+            const int p = lane / 32, off = 4 * (lane % 32);
+            if (p < NPA && off < kStrip)
+                *(int *)(my_ring + ((size_t)p * RS + slot) * kRowStride + off) = 0;
+        }
     };
-    auto store_row = [&](int slot, int v, int sw) {
-        int p = lane / 32, off = 4 * (lane % 32);
-        if (p < NPA && off < sw) *(int *)(my_ring + ((size_t)p * RING + slot) * kRowStride + off) = v;
+    const int rowbytes = 2 * kPhases * trow;      // one template row: both digits, all phases
+    // template row ti into dst, global -> LDS, 1 KB per wave instruction
+    auto dma_row = [&](int ti, int8_t *dst) {
+        const int8_t *src = tp + (size_t)ti * rowbytes;
+        for (int c = wave; c * 1024 < rowbytes; c += kWaves) {
+            if (c * 1024 + lane * 16 < rowbytes)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(src + c * 1024 + lane * 16),
+                    (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
+        }
     };
-    const int tb_words = (2 * trow) / 4;
-    const int *tp32 = (const int *)tp;
 
     for (int ks = 0; ks < npad; ks += kStrip) {
-        const int sw = min(kStrip, npad - ks);
-        // fill the ring for i = i_lo: rows i_lo + s_lo + q
-        for (int q = 0; q < RING; ++q) {
-            int r = i_lo + s_lo + q;
-            int v = fetch_row(r, ks, sw);
-            store_row((r - s_lo) % RING, v, sw);
-        }
-        // template row i_lo into buffer 0
-        for (int k = threadIdx.x; k < tb_words; k += blockDim.x) {
-            int q = k / (trow / 4), x4 = k % (trow / 4);
-            ((int *)tbuf)[k] = tp32[((size_t)q * mg + i_lo) * (trow / 4) + x4];
-        }
-        __syncthreads();
-        for (int i = i_lo; i < i_hi; ++i) {
-            const int buf = (i - i_lo) & 1;
-            // prefetch: the ring row entering at i+1, and template row i+1
-            const int r_new = i + s_lo + RING;
-            int pf_row = fetch_row(r_new, ks, sw);
-            int pf_t[8];
+        // rows for i = i_lo and the two that follow: i_lo + s_lo + q, q < RING + 1
+        for (int q = 0; q <= RING; ++q) ring_fill(i_lo + s_lo + q, ks);
+        dma_row(i_lo, s_tA);
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+
+        // one template row: MFMAs with row i from tcur while template row i+1 and
+        // frame row i + s_lo + RING + 1 stream in
+        auto step = [&](int i, const int8_t *tcur, int8_t *tnext) {
+            if (i + 1 < i_hi) dma_row(i + 1, tnext);
+            ring_fill(i + s_lo + RING + 1, ks);
+
+            // operand addresses of K-chunk 0; chunk kc adds kc*32 bytes.  The byte
+            // phase of a template read does not depend on kc (32 is a multiple of 8).
+            const int8_t *abase[NS][NPA];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                int k = threadIdx.x + u * kBlock;
-                pf_t[u] = 0;
-                if (i + 1 < i_hi && k < tb_words) {
-                    int q = k / (trow / 4), x4 = k % (trow / 4);
-                    pf_t[u] = tp32[((size_t)q * mg + i + 1) * (trow / 4) + x4];
-                }
+            for (int st = 0; st < NS; ++st)
+#pragma unroll
+                for (int p = 0; p < NPA; ++p)
+                    abase[st][p] = my_ring +
+                                   ((size_t)p * RS + (i + 32 * st + rho) % RS) * kRowStride + 16 * h;
+            const int8_t *bbase[NT][2];
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) {
+                // template bytes B[i][k - t] for k = ks + kc*32 + 16h + e, t = t_lo + 32 tt + rho,
+                // read from the phase copy that makes them 8-byte aligned
+                int x0 = ks + 16 * h - (t_lo + 32 * tt + rho) + padl;
+                int phi = x0 & (kPhases - 1);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    bbase[tt][q] = tcur + ((size_t)q * kPhases + phi) * trow + (x0 - phi);
             }
-            const int8_t *tb = tbuf + (size_t)buf * 2 * trow;
+            auto load_a = [&](int kc, v4i (&av)[NS][NPA]) {
 #pragma unroll
-            for (int kc = 0; kc < kStrip / 32; ++kc) {
-                if (kc * 32 >= sw) break;
-                v4i av[NS][NPA];
+                for (int st = 0; st < NS; ++st)
 #pragma unroll
-                for (int st = 0; st < NS; ++st) {
-                    int slot = (i + 32 * st + rho) % RING;  // row i + s_lo + 32 st + rho
+                    for (int p = 0; p < NPA; ++p) av[st][p] = *(const v4i *)(abase[st][p] + kc * 32);
+            };
+            auto load_b = [&](int kc, v4i (&bv)[NT][2]) {
 #pragma unroll
-                    for (int p = 0; p < NPA; ++p)
-                        av[st][p] = *(const v4i *)(my_ring + ((size_t)p * RING + slot) * kRowStride +
-                                                   kc * 32 + 16 * h);
-                }
-                v4i bv[NT][2];
-#pragma unroll
-                for (int tt = 0; tt < NT; ++tt) {
-                    // template bytes B[i][k - t] for k = ks + kc*32 + 16h + e, t = t_lo + 32 tt + rho
-                    int x0 = ks + kc * 32 + 16 * h - (t_lo + 32 * tt + rho) + padl;
-                    int sh = x0 & 3, xa = x0 >> 2;
+                for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        const int *src = (const int *)(tb + (size_t)q * trow) + xa;
-                        int w0 = src[0], w1 = src[1], w2 = src[2], w3 = src[3], w4 = src[4];
-                        v4i b;
-                        b[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-                        b[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-                        b[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-                        b[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
-                        bv[tt][q] = b;
+                        const int2 *src = (const int2 *)(bbase[tt][q] + kc * 32);
+                        int2 lo = src[0], hi = src[1];
+                        bv[tt][q] = v4i{lo.x, lo.y, hi.x, hi.y};
                     }
+            };
+
+            v4i av[NS][NPA], bv[NT][2];
+            load_a(0, av);
+            load_b(0, bv);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                v4i an[NS][NPA], bn[NT][2];
+                if (kc + 1 < KC) {
+                    load_a(kc + 1, an);
+                    load_b(kc + 1, bn);
                 }
 #pragma unroll
                 for (int st = 0; st < NS; ++st)
@@ -386,20 +420,26 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                             for (int q = 0; q < 2; ++q)
                                 acc[st][tt][p * 2 + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                     av[st][p], bv[tt][q], acc[st][tt][p * 2 + q], 0, 0, 0);
-            }
-            // row i + s_lo leaves the ring; row i + s_lo + RING takes its slot (own wave only)
-            store_row(i % RING, pf_row, sw);
-            if (i + 1 < i_hi) {
-                int8_t *nb = tbuf + (size_t)(buf ^ 1) * 2 * trow;
+                if (kc + 1 < KC) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int k = threadIdx.x + u * kBlock;
-                    if (k < tb_words) ((int *)nb)[k] = pf_t[u];
+                    for (int st = 0; st < NS; ++st)
+#pragma unroll
+                        for (int p = 0; p < NPA; ++p) av[st][p] = an[st][p];
+#pragma unroll
+                    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) bv[tt][q] = bn[tt][q];
                 }
             }
-            __syncthreads();
+            // Both row transfers must have landed, and this wave's LDS reads of tcur
+            // must be done, before the barrier.  The asm also keeps the compiler from
+            // moving memory accesses across the barrier.
+            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        };
+        for (int i = i_lo; i < i_hi; i += 2) {
+            step(i, s_tA, s_tB);
+            if (i + 1 < i_hi) step(i + 1, s_tB, s_tA);
         }
-        __syncthreads();
     }
 
     if (!live) return;
@@ -523,20 +563,11 @@ template <int NS, int NT, int NPA, int PA0>
 hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
                                int C, const Geom &g, long long *h, hipStream_t st)
 {
-    clear_stale_error();
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
-    size_t lds = (size_t)kWaves * NPA * 32 * NS * kRowStride + 2 * 2 * (size_t)tt.trow;
     dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_corr_int8<NS, NT, NPA, PA0>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    k_corr_int8<NS, NT, NPA, PA0><<<grid, kBlock, lds, st>>>(limbs, nlimb, tt.tp, C, g.mg, tt.npad,
-                                                            tt.trow, tt.padl, g.w, tgroups, h);
+    k_corr_int8<NS, NT, NPA, PA0><<<grid, kBlock, 0, st>>>(
+        limbs, nlimb, tt.tp, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, h);
     return hipGetLastError();
 }
 
@@ -552,20 +583,34 @@ int grid_for(size_t total)
 Int8Geom int8_geom(const Geom &g)
 {
     Int8Geom r;
-    r.npad = (g.ng + 31) / 32 * 32;
+    r.npad = (g.ng + kStrip - 1) / kStrip * kStrip;
     const int NT = g.W <= 32 ? 1 : 2;
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int t_max = -(g.w - 1) + 32 * NT * tgroups - 1;
-    r.padl = (t_max > 0 ? t_max : 0) + 4;
-    r.trow = (r.padl + r.npad + g.w + 32 + 15) / 16 * 16;
+    // padl >= t_max keeps every read in the row; (padl + w) % 8 == 0 makes the
+    // first byte of lane rho's operand, padl - t_lo - rho + (multiple of 8), fall
+    // in 8-byte groups of eight consecutive lanes (rho = 8g..8g+7), so that each
+    // group reads eight distinct bank pairs of the eight phase copies
+    r.padl = ((t_max > 0 ? t_max : 0) + 4 + g.w + 7) / 8 * 8 - g.w;
+    // trow = 16 (mod 32): the eight phase copies of a row start 4 (mod 8) dwords
+    // apart, so eight lanes reading eight phases hit eight disjoint bank pairs
+    r.trow = (r.padl + r.npad + g.w + 40 + 31) / 32 * 32 + 16;
     return r;
 }
 
 bool int8_applicable(const Geom &g)
 {
     // exact int32 accumulation needs fewer than 2^17 terms per shift; the
-    // prep kernel holds at most 2048 grid columns
-    return g.dtype == MOCO_U16 && (long long)g.mg * g.ng < 131072 && g.ng <= 2048 && g.w <= 512;
+    // prep kernel holds at most 2048 grid columns; the correlation kernel holds
+    // template rows of at most kMaxTrow bytes
+    if (g.dtype != MOCO_U16 || (long long)g.mg * g.ng >= 131072 || g.ng > 2048 || g.w > 512)
+        return false;
+    return int8_geom(g).trow <= kMaxTrow;
+}
+
+size_t int8_template_bytes(const Geom &g)
+{
+    return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow;
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
@@ -586,7 +631,7 @@ hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npa
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st)
 {
     clear_stale_error();
-    k_tpad<<<grid_for((size_t)2 * g.mg * tt.trow), kBlock, 0, st>>>(tlimbs, g.mg, g.ng, tt.npad,
+    k_tpad<<<grid_for((size_t)2 * kPhases * g.mg * tt.trow), kBlock, 0, st>>>(tlimbs, g.mg, g.ng, tt.npad,
                                                                    tt.trow, tt.padl, tt.tp);
     return hipGetLastError();
 }

@@ -25,7 +25,7 @@ struct Int8Geom {
 
 // Template side of the int8 form (device memory owned by the template).
 struct Int8Tmpl {
-    int8_t *tp = nullptr;          // [2][mg][trow] digit rows of the template
+    int8_t *tp = nullptr;          // [mg][2][8][trow] digit rows of the template, 8 byte phases
     long long *atab = nullptr;     // [W][W] sum of Y^2 over the frame-side rows of D at (s,t);
                                    // the template energy at (s,t) is this table at (-s,-t)
     int npad = 0, padl = 0, trow = 0;
@@ -72,6 +72,7 @@ size_t refine_partial_bytes(const Geom &g);   // per frame
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);
 bool int8_applicable(const Geom &g);
+size_t int8_template_bytes(const Geom &g);
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
                            int32_t *nlimb, long long *atab, long long *edge, hipStream_t st);
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
