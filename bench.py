@@ -218,9 +218,9 @@ def main():
                    "downsample": DS, "form": form_ran, "template": "frame 0"},
         "roofline": roof,
         "stages": stages,
-        "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 1),
-                       "p99": round(float(np.percentile(lat_us, 99)), 1),
-                       "frames": 1, "iters": args.latency_iters},
+        "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
+                        "p99": round(float(np.percentile(lat_us, 99)), 1),
+                        "frames": 1, "iters": args.latency_iters} if lat_us.size else None),
     }
 
     if not args.no_cpu_baseline:

@@ -225,6 +225,7 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
     if (e != hipSuccess) return fail(MOCO_ENOMEM, "template scratch: %s", hipGetErrorString(e));
     int8_t *limbs = (int8_t *)tmp;
     int32_t *nl = (int32_t *)(tmp + L.limbs);
+    int32_t *vm = nl + 1;
     long long *atab = (long long *)(tmp + L.limbs + L.nlimb);
     long long *edge = (long long *)(tmp + L.limbs + L.nlimb + L.atab);
     int32_t nlimb = 0;
@@ -232,9 +233,11 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
     t.i8.npad = ig.npad;
     t.i8.padl = ig.padl;
     t.i8.trow = ig.trow;
-    if ((e = moco::launch_prep_u16((const uint16_t *)t.raw, 1, g, ig.npad, limbs, nl, atab, edge,
-                                   st)) != hipSuccess ||
+    int32_t vmaxv = 0;
+    if ((e = moco::launch_prep_u16((const uint16_t *)t.raw, 1, g, ig.npad, limbs, nl, vm, atab,
+                                   edge, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&nlimb, nl, sizeof nlimb, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&vmaxv, vm, sizeof vmaxv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
     } else if (nlimb == 2) {
@@ -248,6 +251,7 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
             rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
         } else {
             t.int8_ok = true;
+            t.i8.vmax = vmaxv == INT32_MAX ? -1 : vmaxv;
         }
     }
     (void)hipFree(tmp);
@@ -272,6 +276,7 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     char *base = (char *)ctx->scratch;
     int8_t *limbs = (int8_t *)base;
     int32_t *nl = (int32_t *)(base + L.limbs * C);
+    int32_t *vm = nl + C;   // the per-frame slot of L.nlimb bytes holds both arrays
     long long *atab = (long long *)(base + (L.limbs + L.nlimb) * C);
     long long *edge = (long long *)(base + (L.limbs + L.nlimb + L.atab) * C);
     long long *h = (long long *)(base + (L.limbs + L.nlimb + L.atab + L.edge) * C);
@@ -285,7 +290,7 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int32_t *coarse = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         {
             StageTimer tm(ctx, MOCO_STAGE_PREP, st);
-            HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, limbs, nl, atab, edge, st));
+            HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, limbs, nl, vm, atab, edge, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
@@ -304,7 +309,7 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, coarse, out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
                                         out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
-                                        st));
+                                        st, vm, tt.i8.vmax));
         }
     }
     return MOCO_OK;

@@ -70,24 +70,63 @@ __device__ inline int grid_value(const uint16_t *a, int n, int i, int j)
     return (int)a[(size_t)i * n + j];
 }
 
+// Four consecutive grid values j0..j0+3 of grid row i (zero beyond ng).  With
+// `vec`, the raw rows are read as 16-byte (box sums) or 8-byte vectors.
 template <bool DS>
+__device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int j0, bool vec,
+                                    int (&X)[4])
+{
+    if (vec && j0 + 3 < ng) {
+        if (DS) {
+            const uint4 r0 = *(const uint4 *)(a + (size_t)(2 * i) * n + 2 * j0);
+            const uint4 r1 = *(const uint4 *)(a + (size_t)(2 * i + 1) * n + 2 * j0);
+            const unsigned u0[4] = {r0.x, r0.y, r0.z, r0.w}, u1[4] = {r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                X[q] = (int)(u0[q] & 0xffff) + (int)(u0[q] >> 16) + (int)(u1[q] & 0xffff) +
+                       (int)(u1[q] >> 16);
+        } else {
+            const uint2 r0 = *(const uint2 *)(a + (size_t)i * n + j0);
+            X[0] = (int)(r0.x & 0xffff);
+            X[1] = (int)(r0.x >> 16);
+            X[2] = (int)(r0.y & 0xffff);
+            X[3] = (int)(r0.y >> 16);
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) X[q] = (j0 + q < ng) ? grid_value<DS>(a, n, i, j0 + q) : 0;
+}
+
+template <bool DS, int kMaxCol4>
 __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
                                                      int8_t *__restrict__ limbs,
                                                      int32_t *__restrict__ nlimb,
+                                                     int32_t *__restrict__ vmax,
                                                      long long *__restrict__ atab,
                                                      long long *__restrict__ edge)
 {
-    constexpr int kMaxCol4 = 8;                 // npad <= 2048
-    __shared__ long long colE[2048];
-    __shared__ long long rowbuf[kWaves][2][512];  // X^2 of the first / last w-1 columns of an edge row
-    __shared__ long long rT[512], rB[512], cL[512], cR[512];
-    __shared__ long long etot;
-    __shared__ int need3;
+    // dynamic LDS: colE[npad] | rowbuf[kWaves][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
+    extern __shared__ long long lds_prep[];
+    const int we1 = w > 1 ? w - 1 : 1;
+    long long *colE = lds_prep;
+    long long *rowbuf_base = colE + npad;   // X^2 of the first / last w-1 columns of an edge row
+    long long *rT = rowbuf_base + (size_t)kWaves * 2 * we1;
+    long long *rB = rT + w;
+    long long *cL = rB + w;
+    long long *cR = cL + w;
+    long long &etot = cR[w];
+    int &need3 = *(int *)(cR + w + 1);
+    int &xmax = *((int *)(cR + w + 1) + 1);
+    auto rowbuf = [&](int wv, int side) { return rowbuf_base + ((size_t)wv * 2 + side) * we1; };
 
     const int frame = blockIdx.x;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const uint16_t *a = raw + (size_t)frame * m * n;
+    // vector raw reads need aligned rows: 16 bytes (box sums) or 8 bytes
+    const bool vec = DS ? ((n % 8) == 0 && (((uintptr_t)a) & 15) == 0)
+                        : ((n % 4) == 0 && (((uintptr_t)a) & 7) == 0);
     const size_t plane = (size_t)mg * npad;
     int8_t *L0 = limbs + (size_t)frame * 3 * plane;
     int8_t *L1 = L0 + plane;
@@ -100,8 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
     if (threadIdx.x == 0) {
         etot = 0;
         need3 = 0;
+        xmax = 0;
     }
     __syncthreads();
+    int my_xmax = 0;
 
     long long col[kMaxCol4][4];
 #pragma unroll
@@ -119,10 +160,13 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
             int j0 = 4 * (lane + 64 * c);
             if (j0 >= npad) break;
             int d0p = 0, d1p = 0;
+            int Xs[4];
+            grid_values4<DS>(a, n, ng, i, j0, vec, Xs);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int j = j0 + q;
-                int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
+                int X = Xs[q];
+                my_xmax = max(my_xmax, X);
                 int d0 = bdigit(X);
                 int x1 = (X - d0) >> 8;
                 int d1 = bdigit(x1);
@@ -133,8 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
                 rpart += x2;
                 col[c][q] += x2;
                 if ((top || bot) && j < ng) {
-                    if (j < we) rowbuf[wave][0][j] = x2;
-                    if (j >= ng - we) rowbuf[wave][1][ng - 1 - j] = x2;
+                    if (j < we) rowbuf(wave, 0)[j] = x2;
+                    if (j >= ng - we) rowbuf(wave, 1)[ng - 1 - j] = x2;
                 }
             }
             *(int *)(L0 + (size_t)i * npad + j0) = d0p;
@@ -151,8 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
             for (int q = lane; q < w; q += 64) {
                 long long lp = 0, rs = 0;
                 for (int j = 0; j < q; ++j) {
-                    lp += rowbuf[wave][0][j];
-                    rs += rowbuf[wave][1][j];
+                    lp += rowbuf(wave, 0)[j];
+                    rs += rowbuf(wave, 1)[j];
                 }
                 if (top) {
                     E[eidx(0, 0, i, q)] = lp;
@@ -176,6 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
     }
     if (lane == 0) atomicAdd((unsigned long long *)&etot, (unsigned long long)my_etot);
     if (my_need3) need3 = 1;
+    atomicMax(&xmax, my_xmax);
     __syncthreads();
     // cumulative border tables: rows excluded from the top / bottom, columns from left / right
     if (threadIdx.x == 0) {
@@ -233,7 +278,12 @@ __global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict_
                 *(int *)(L2 + (size_t)i * npad + j0) = d2p;
             }
     }
-    if (threadIdx.x == 0) nlimb[frame] = need3 ? 3 : 2;
+    if (threadIdx.x == 0) {
+        nlimb[frame] = need3 ? 3 : 2;
+        // every pixel is a term of some grid value unless a side is odd when downsampling
+        const bool covers = !DS || ((m % 2) == 0 && (n % 2) == 0);
+        vmax[frame] = covers ? xmax : INT32_MAX;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -613,18 +663,39 @@ size_t int8_template_bytes(const Geom &g)
     return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow;
 }
 
+template <bool DS>
+void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
+                 int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, hipStream_t st)
+{
+    // 256 grid columns per chunk (64 lanes x 4 columns)
+    const int nc = (npad + 255) / 256;
+    const int we1 = g.w > 1 ? g.w - 1 : 1;
+    const size_t lds = ((size_t)npad + (size_t)kWaves * 2 * we1 + 4 * (size_t)g.w + 2) *
+                       sizeof(long long);
+    if (nc <= 1)
+        k_prep_u16<DS, 1><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                                  nlimb, vmax, atab, edge);
+    else if (nc <= 2)
+        k_prep_u16<DS, 2><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                                  nlimb, vmax, atab, edge);
+    else if (nc <= 4)
+        k_prep_u16<DS, 4><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                                  nlimb, vmax, atab, edge);
+    else
+        k_prep_u16<DS, 8><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
+                                                  nlimb, vmax, atab, edge);
+}
+
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
-                           int8_t *limbs, int32_t *nlimb, long long *atab, long long *edge,
-                           hipStream_t st)
+                           int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
+                           long long *edge, hipStream_t st)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     if (g.ds)
-        k_prep_u16<true><<<C, kBlock, 0, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                               nlimb, atab, edge);
+        prep_launch<true>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, st);
     else
-        k_prep_u16<false><<<C, kBlock, 0, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                                nlimb, atab, edge);
+        prep_launch<false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, st);
     return hipGetLastError();
 }
 

@@ -439,67 +439,67 @@ __global__ __launch_bounds__(kBlock) void k_refine_band(const T *__restrict__ fr
         partial[((size_t)frame * nband + band) * 9 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// uint16 x2 step in integers.  One block per frame; a thread owns four
-// template columns j0..j0+3 and a contiguous run of rows, and walks them with
-// a rolling window of the three frame rows i+2s*-1..i+2s*+1 held in registers
-// (the next row is fetched one step ahead).  Each frame row contributes the six
-// values at columns j0+2t*-1..j0+2t*+4.  Squares of differences (|d| <= 65535)
-// come from a 24-bit multiply (exact low 32 bits) and add into 64-bit sums;
-// the nine block sums go to partial[frame][9] as exact FP64 integers.
-struct Row6 {
-    int v[6];
-};
-
-__device__ inline Row6 load_row6(const uint16_t *__restrict__ a, int m, int n, int r, int c0,
-                                 bool vec)
-{
-    // columns c0 .. c0+5 of row r; zero where outside the image
-    Row6 o;
-    if (r < 0 || r >= m) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) o.v[k] = 0;
-        return o;
-    }
-    const uint16_t *row = a + (size_t)r * n;
-    if (vec) {
-        // c0 - 1 is even and c0-1 .. c0+6 lie inside the row: four aligned pairs
-        const uint32_t *p = (const uint32_t *)(row + c0 - 1);
-        uint32_t q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-        o.v[0] = (int)(q0 >> 16);
-        o.v[1] = (int)(q1 & 0xffff);
-        o.v[2] = (int)(q1 >> 16);
-        o.v[3] = (int)(q2 & 0xffff);
-        o.v[4] = (int)(q2 >> 16);
-        o.v[5] = (int)(q3 & 0xffff);
-        return o;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        int c = c0 + k;
-        o.v[k] = (c >= 0 && c < n) ? (int)row[c] : 0;
-    }
-    return o;
-}
+// uint16 x2 step in integers.  Block (band of kRefBand template rows, frame).
+// The frame rows the band touches, i0+2s*-1 .. i1+2s*, are copied into LDS with
+// 16-byte loads (one contiguous span of full rows); a thread then owns four
+// template columns j0..j0+3 and a run of the band's rows, reading for each row
+// the six frame values at columns j0+2t*-1..j0+2t*+4.
+//
+// pmax (may be null): per frame, an upper bound of its pixel values; tmax the
+// template's (-1: none).  With both, |d| <= M = max(pmax, tmax) and the nine
+// sums run in 32 bits (24-bit multiply-adds) while flush*4*M^2 < 2^32, then add
+// into 64-bit sums, so no 32-bit sum can wrap.  Without a bound every term goes
+// straight into 64 bits.  Partial sums go to [frame][band][9] as exact FP64
+// integers (far below 2^53).
+constexpr int kRefBand = 32;
 
 __global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restrict__ frames,
                                                        const uint16_t *__restrict__ tmpl, int m,
                                                        int n, const int32_t *__restrict__ coarse_st,
+                                                       const int32_t *__restrict__ pmax, int tmax,
                                                        double *__restrict__ partial)
 {
-    const int frame = blockIdx.x;
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    uint16_t *srow = (uint16_t *)lds_raw;  // 8 guard elements, (kRefBand + 2) rows of n, 8 guard
+    const int frame = blockIdx.y, band = blockIdx.x, nband = gridDim.x;
+    const int i0 = band * kRefBand, i1 = min(m, i0 + kRefBand), nb = i1 - i0;
     const int S0 = 2 * coarse_st[2 * frame], T0 = 2 * coarse_st[2 * frame + 1];
     const uint16_t *a = frames + (size_t)frame * m * n;
-    const bool aligned = ((n & 1) == 0) && ((((uintptr_t)a) & 3) == 0);
+    const int r0 = i0 + S0 - 1;  // frame row held in LDS row 0
+    {
+        const int ra = max(r0, 0), rb = min(r0 + nb + 2, m);
+        if (rb > ra) {
+            const uint16_t *src = a + (size_t)ra * n;
+            uint16_t *dst = srow + 8 + (size_t)(ra - r0) * n;
+            const size_t cnt = (size_t)(rb - ra) * n;
+            const bool v16 = ((n & 7) == 0) && ((((uintptr_t)src) & 15) == 0);
+            if (v16) {
+                const uint4 *s4 = (const uint4 *)src;
+                uint4 *d4 = (uint4 *)dst;  // 16 + 2*(ra-r0)*n bytes into the buffer: aligned
+                for (size_t k = threadIdx.x; k < cnt / 8; k += blockDim.x) d4[k] = s4[k];
+            } else {
+                for (size_t k = threadIdx.x; k < cnt; k += blockDim.x) dst[k] = src[k];
+            }
+        }
+    }
+    __syncthreads();
     unsigned long long acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0;
+    int flush = 0;  // rows between flushes of the 32-bit sums (0: 64-bit sums only)
+    if (pmax && tmax >= 0) {
+        const long long M = max((long long)pmax[frame], (long long)tmax);
+        const long long lim = M > 0 ? 0xffffffffLL / (4 * M * M) : (1LL << 30);
+        flush = (int)min(lim, (long long)(1 << 30));
+    }
+    const bool even = (n & 1) == 0;
     const int ncg = (n + 3) / 4;
     const int ncgs = ncg < kBlock ? ncg : kBlock;
     const int rg_count = kBlock / ncgs;
     const int rg = threadIdx.x / ncgs;
     if (rg < rg_count) {
-        const int rows_per = (m + rg_count - 1) / rg_count;
-        const int ia = rg * rows_per, ib = min(m, ia + rows_per);
+        const int rows_per = (nb + rg_count - 1) / rg_count;
+        const int la = rg * rows_per, lb = min(nb, la + rows_per);
         for (int cg = threadIdx.x % ncgs; cg < ncg; cg += ncgs) {
             const int j0 = 4 * cg;
             const int c0 = j0 + T0 - 1;  // first frame column of the window
@@ -511,15 +511,13 @@ __global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restric
             for (int q = 0; q < 4; ++q)
                 if (j0 + q < n) qval |= 1 << q;
             const bool interior = kval == 63 && qval == 15;
-            const bool vec = aligned && c0 - 1 >= 0 && c0 + 6 < n;
             const bool tvec = ((n & 3) == 0) && j0 + 3 < n;
-            if (ia >= ib) continue;
-            Row6 w0 = load_row6(a, m, n, ia + S0 - 1, c0, vec);
-            Row6 w1 = load_row6(a, m, n, ia + S0, c0, vec);
-            Row6 w2 = load_row6(a, m, n, ia + S0 + 1, c0, vec);
-            for (int i = ia; i < ib; ++i) {
-                // fetch one step ahead
-                Row6 w3 = load_row6(a, m, n, i + S0 + 2, c0, vec);
+            unsigned acc32[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc32[q] = 0;
+            int since = 0;
+            for (int li = la; li < lb; ++li) {
+                const int i = i0 + li;
                 int b[4];
                 if (tvec) {
                     uint2 t2 = *(const uint2 *)(tmpl + (size_t)i * n + j0);
@@ -536,20 +534,56 @@ __global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restric
                 for (int u = 0; u < 3; ++u) {
                     const int r = i + S0 + u - 1;
                     if (r < 0 || r >= m) continue;
-                    const Row6 &f = u == 0 ? w0 : (u == 1 ? w1 : w2);
+                    // LDS row li+u holds frame row r; the window is its columns c0 .. c0+5
+                    const uint16_t *row = srow + 8 + (size_t)(li + u) * n + (c0 - 1);
+                    int f[6];
+                    if (interior && even) {
+                        // c0-1 .. c0+6 lie within this row's neighbourhood of the buffer
+                        // (c0 >= 0, c0+5 < n, 8 guard elements at either end); c0-1 is even
+                        const uint32_t *p = (const uint32_t *)row;
+                        uint32_t q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+                        f[0] = (int)(q0 >> 16);
+                        f[1] = (int)(q1 & 0xffff);
+                        f[2] = (int)(q1 >> 16);
+                        f[3] = (int)(q2 & 0xffff);
+                        f[4] = (int)(q2 >> 16);
+                        f[5] = (int)(q3 & 0xffff);
+                    } else {
+                        // edge of the image: read only the columns that exist
 #pragma unroll
-                    for (int v = 0; v < 3; ++v)
+                        for (int k = 0; k < 6; ++k) f[k] = (kval >> k & 1) ? (int)row[k + 1] : 0;
+                    }
+                    if (flush > 0) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            int d = f.v[q + v] - b[q];
-                            if (!interior && !((kval >> (q + v) & 1) && (qval >> q & 1))) d = 0;
-                            acc[u * 3 + v] += (unsigned)__mul24(d, d);
-                        }
+                        for (int v = 0; v < 3; ++v)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                int d = f[q + v] - b[q];
+                                if (!interior && !((kval >> (q + v) & 1) && (qval >> q & 1))) d = 0;
+                                acc32[u * 3 + v] += (unsigned)__mul24(d, d);
+                            }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 3; ++v)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                int d = f[q + v] - b[q];
+                                if (!interior && !((kval >> (q + v) & 1) && (qval >> q & 1))) d = 0;
+                                acc[u * 3 + v] += (unsigned)__mul24(d, d);
+                            }
+                    }
                 }
-                w0 = w1;
-                w1 = w2;
-                w2 = w3;
+                if (flush > 0 && ++since >= flush) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        acc[q] += acc32[q];
+                        acc32[q] = 0;
+                    }
+                    since = 0;
+                }
             }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[q] += acc32[q];
         }
     }
     // wave sums, then the four waves in order
@@ -571,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restric
     if (threadIdx.x < 9) {
         unsigned long long t = 0;
         for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
-        partial[(size_t)frame * 9 + threadIdx.x] = (double)t;
+        partial[((size_t)frame * nband + band) * 9 + threadIdx.x] = (double)t;
     }
 }
 
@@ -675,18 +709,22 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
 
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
-                         double *gaps, double *partial, hipStream_t st)
+                         double *gaps, double *partial, hipStream_t st, const int32_t *pmax,
+                         int tmax)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     const size_t esz = g.dtype == MOCO_U16 ? 2 : 4;
     int br = refine_band_rows(g);
-    if (g.dtype == MOCO_U16) {
-        k_refine_u16<<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw, g.m,
-                                           g.n, coarse_st, partial);
+    if (g.dtype == MOCO_U16 && refine_u16_banded(g)) {
+        const int nband = (g.m + kRefBand - 1) / kRefBand;
+        const size_t lds = ((size_t)(kRefBand + 2) * g.n + 16) * sizeof(uint16_t);
+        dim3 grid(nband, C);
+        k_refine_u16<<<grid, kBlock, lds, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
+                                               g.m, g.n, coarse_st, pmax, tmax, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, 1, g.m, g.n,
+        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, nband, g.m, g.n,
                                                                       coarse_st, shifts, frefine,
                                                                       gaps);
         return hipGetLastError();
@@ -730,9 +768,15 @@ int refine_band_rows(const Geom &g)
     return br > cap ? cap : br;
 }
 
+bool refine_u16_banded(const Geom &g)
+{
+    return (size_t)(kRefBand + 2) * g.n * sizeof(uint16_t) + 32 <= 48 * 1024;
+}
+
 size_t refine_partial_bytes(const Geom &g)
 {
-    if (g.dtype == MOCO_U16) return 9 * sizeof(double);
+    if (g.dtype == MOCO_U16 && refine_u16_banded(g))
+        return (size_t)((g.m + kRefBand - 1) / kRefBand) * 9 * sizeof(double);
     int br = refine_band_rows(g);
     if (br <= 0) return 0;
     return (size_t)((g.m + br - 1) / br) * 9 * sizeof(double);

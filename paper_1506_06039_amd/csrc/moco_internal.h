@@ -26,6 +26,7 @@ struct Int8Geom {
 // Template side of the int8 form (device memory owned by the template).
 struct Int8Tmpl {
     int8_t *tp = nullptr;          // [mg][2][8][trow] digit rows of the template, 8 byte phases
+    int32_t vmax = -1;             // bound of the template's pixel values (-1: none)
     long long *atab = nullptr;     // [W][W] sum of Y^2 over the frame-side rows of D at (s,t);
                                    // the template energy at (s,t) is this table at (-s,-t)
     int npad = 0, padl = 0, trow = 0;
@@ -65,16 +66,22 @@ hipError_t launch_combine(const double *sat, const double *btab, const double *h
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st);
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
-                         double *gaps, double *partial, hipStream_t st);
+                         double *gaps, double *partial, hipStream_t st,
+                         const int32_t *pmax = nullptr, int tmax = -1);
 int refine_band_rows(const Geom &g);
+bool refine_u16_banded(const Geom &g);
 size_t refine_partial_bytes(const Geom &g);   // per frame
 
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);
 bool int8_applicable(const Geom &g);
 size_t int8_template_bytes(const Geom &g);
+// nlimb[frame]: digit planes (2 or 3); vmax[frame]: an upper bound of the frame's
+// pixel values (its largest grid value), or INT32_MAX when the grid does not
+// cover every pixel (odd sides when downsampling)
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
-                           int32_t *nlimb, long long *atab, long long *edge, hipStream_t st);
+                           int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge,
+                           hipStream_t st);
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st);

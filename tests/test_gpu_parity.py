@@ -236,3 +236,20 @@ def test_template_outlives_context(gpu_lib):
     r = gpu_lib.moco_align(ctx2, _to_dev(np.ones((2, 32, 32), np.uint16)), tp2)
     torch.cuda.synchronize()
     assert r.shifts.cpu().numpy().tolist() == [[0, 0], [0, 0]]
+
+
+@pytest.mark.parametrize("level", [3000, 7000])
+def test_refine_partial_sum_flushes(gpu_lib, level):
+    # bright frames make the 32-bit partial sums of the x2 step flush every few rows
+    # (level 3000: box sums near 13000, flush every ~6 rows; 7000: box sums near 29000,
+    # too large for even two rows of 32-bit sums, so every term goes to 64 bits)
+    rng = np.random.default_rng(level)
+    m = n = 128
+    base = rng.uniform(0.5, 1.0, size=(m, n))
+    tmpl = rng.poisson(level * base).astype(np.uint16)
+    fr = np.stack([rng.poisson(np.roll(level * base, (2 * k - 3, 3 - k), (0, 1)))
+                   for k in range(5)]).astype(np.uint16)
+    _say("case refine flush level", level)
+    res = _run(gpu_lib, fr, tmpl, 16, True, "int8")
+    orc = oracle.align(fr, tmpl, 16, True)
+    check(res, orc, True, exact=True, label="refine flush %d" % level)
