@@ -29,7 +29,9 @@
  *     passed as void*; NULL is the legacy default stream).  Outputs are valid
  *     once that stream has synchronised.  Entry points return as soon as the
  *     work is enqueued.
- *   - A context is used by one host thread at a time.
+ *   - A context is used by one host thread at a time.  Calls on one context
+ *     share its scratch memory: enqueue them on one stream, or synchronise
+ *     between calls made on different streams.
  *   - Layouts are row-major and contiguous.
  */
 #ifndef MOCO_H
@@ -121,6 +123,29 @@ void moco_template_destroy(moco_tmpl *tmpl);
 int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m, int n,
                int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
                void *hip_stream);
+
+/* One stack of a batch: moco_align's arguments as a record. */
+typedef struct {
+    const void *d_frames;
+    const moco_tmpl *tmpl;
+    int T, m, n, w, downsample;
+    moco_dtype dtype;
+    moco_outputs out;
+} moco_stack;
+
+/* Align a batch of stacks of uneven length, size and window (each frame of each
+ * stack exactly as moco_align would: the search of sec. 2, every frame
+ * independent of the others).  Work is ordered after everything enqueued on
+ * `hip_stream` before the call, and everything enqueued on it afterwards waits
+ * for the whole batch.  Internally the stacks run longest-first on up to
+ * `lanes` streams of the context (0: the library's choice, at most 8), each
+ * with its own slice of the context's scratch budget; results do not depend on
+ * the lanes, the order or the chunking.  All stacks are validated before any
+ * work is enqueued (MOCO_EINVAL names the first bad stack); `form` applies to
+ * every stack (MOCO_FORM_AUTO resolves per stack).  Errors: MOCO_EINVAL,
+ * MOCO_ENOMEM (a slice cannot hold one frame of some stack), MOCO_EDEVICE. */
+int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
+                     int lanes, void *hip_stream);
 
 /* The correlation form a call with `requested` runs for this template:
  * MOCO_FORM_AUTO resolves to MOCO_FORM_INT8_MFMA when that form applies to the

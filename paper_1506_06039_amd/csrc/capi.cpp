@@ -26,6 +26,8 @@ struct moco_ctx {
     bool profiling = false;
     std::vector<ProfRec> prof;        // recorded, not yet read
     std::vector<hipEvent_t> ev_pool;  // reusable events
+    std::vector<hipStream_t> lanes;   // internal streams of moco_align_batch (default priority)
+    std::vector<hipEvent_t> lane_ev;  // one join event per lane, plus one fork event
 };
 
 struct moco_tmpl {
@@ -258,22 +260,18 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
     return rc;
 }
 
-int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
-               const moco::Geom &g, const moco_outputs *out, void *hip_stream)
+// The int8 pipeline over one stack, in chunks that fit `sbytes` of scratch at
+// `sbase`; every launch goes to stream st.
+int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
+             const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
+             size_t sbytes)
 {
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
-    hipStream_t st = (hipStream_t)hip_stream;
     const int npad = tt.i8.npad;
     Int8Layout L = int8_layout(g, npad);
-    if (L.total_per_frame > ctx->budget)
-        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu",
-                    L.total_per_frame, ctx->budget);
-    int C = (int)std::min<size_t>((size_t)T, ctx->budget / L.total_per_frame);
+    int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
     C = std::min(C, 8192);
-    int rc = ensure_scratch(ctx, L.total_per_frame * (size_t)C, st);
-    if (rc) return rc;
-    char *base = (char *)ctx->scratch;
+    if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
+    char *base = sbase;
     int8_t *limbs = (int8_t *)base;
     int32_t *nl = (int32_t *)(base + L.limbs * C);
     int32_t *vm = nl + C;   // the per-frame slot of L.nlimb bytes holds both arrays
@@ -315,6 +313,111 @@ int align_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     return MOCO_OK;
 }
 
+// The FP64 exact pipeline over one stack, in chunks that fit `sbytes` of
+// scratch at `sbase`; every launch goes to stream st.
+int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
+              const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
+              size_t sbytes)
+{
+    ExactLayout L = exact_layout(g);
+    int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
+    C = std::min(C, 4096);
+    if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
+    char *base = sbase;
+    const moco_dtype dtype = g.dtype;
+    double *coarse = (double *)base;
+    double *sat = (double *)(base + L.coarse * C);
+    double *h = (double *)(base + (L.coarse + L.sat) * C);
+    int32_t *cst = (int32_t *)(base + (L.coarse + L.sat + L.h) * C);
+    double *part = (double *)(base + (L.coarse + L.sat + L.h + L.cst) * C);
+    const size_t fbytes = (size_t)g.m * g.n * dtype_size(dtype);
+    const int W = g.W;
+    for (int f0 = 0; f0 < T; f0 += C) {
+        int c = std::min(C, T - f0);
+        const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
+            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+            HIP_TRY(moco::launch_sat_sq(coarse, c, g, sat, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            HIP_TRY(moco::launch_corr_fp64(coarse, tt.coarse, c, g, h, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+            HIP_TRY(moco::launch_combine(sat, tt.btab, h, c, g,
+                                     out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
+                                     out->fmin ? out->fmin + f0 : nullptr,
+                                     out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
+                                     out->shifts + 2 * (size_t)f0,
+                                     out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
+                                     out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
+        }
+        if (g.ds) {
+            StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
+            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g,
+                                        out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
+                                        out->shifts + 2 * (size_t)f0,
+                                        out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
+                                        st));
+        }
+    }
+    return MOCO_OK;
+}
+
+size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &tt)
+{
+    return form == MOCO_FORM_INT8_MFMA ? int8_layout(g, tt.i8.npad).total_per_frame
+                                       : exact_layout(g).total_per_frame;
+}
+
+int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
+              const moco::Geom &g, moco_form form, const moco_outputs *out, hipStream_t st,
+              char *sbase, size_t sbytes)
+{
+    if (form == MOCO_FORM_INT8_MFMA) return run_int8(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
+    return run_exact(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
+}
+
+// Validation shared by moco_align and moco_align_batch; resolves AUTO.
+int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
+                int n, int w, int downsample, moco_dtype dtype, moco_form form,
+                const moco_outputs *out, moco::Geom *g, moco_form *resolved)
+{
+    if (!tmpl || !out) return fail(MOCO_EINVAL, "null template or outputs");
+    int rc = validate(m, n, w, downsample, dtype, g);
+    if (rc) return rc;
+    if (T < 0) return fail(MOCO_EINVAL, "T=%d must be >= 0", T);
+    if (tmpl->device != ctx->device)
+        return fail(MOCO_EINVAL, "template lives on device %d, context on device %d", tmpl->device,
+                    ctx->device);
+    const moco::Geom &tg = tmpl->t.g;
+    if (tg.m != m || tg.n != n || tg.w != w || tg.ds != downsample || tg.dtype != dtype)
+        return fail(MOCO_EINVAL,
+                    "template prepared for (m=%d n=%d w=%d ds=%d dtype=%d), call has "
+                    "(m=%d n=%d w=%d ds=%d dtype=%d)",
+                    tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
+    if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA)
+        return fail(MOCO_EINVAL, "unknown form %d", (int)form);
+    if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
+        return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
+    if (T > 0 && (!d_frames || !out->shifts)) return fail(MOCO_EINVAL, "null frames or shifts");
+    const moco::Tmpl &tt = tmpl->t;
+    if (form == MOCO_FORM_INT8_MFMA && !tt.int8_ok)
+        return fail(MOCO_EINVAL,
+                    "the int8 matrix-core form does not apply to this template (needs uint16, "
+                    "grid area below 131072, grid width at most 2048 and template values "
+                    "within two base-256 digits)");
+    if (form == MOCO_FORM_AUTO) form = tt.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
+    *resolved = form;
+    return MOCO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -349,6 +452,8 @@ void moco_destroy(moco_ctx *ctx)
         (void)hipEventDestroy(r.b);
     }
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : ctx->lane_ev) (void)hipEventDestroy(e);
+    for (auto l : ctx->lanes) (void)hipStreamDestroy(l);
     delete ctx;
 }
 
@@ -464,85 +569,98 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
 {
     if (!ctx || !tmpl || !out) return fail(MOCO_EINVAL, "moco_align: null ctx, template or outputs");
     moco::Geom g;
-    int rc = validate(m, n, w, downsample, dtype, &g);
+    int rc = check_stack(ctx, d_frames, tmpl, T, m, n, w, downsample, dtype, form, out, &g, &form);
     if (rc) return rc;
-    if (T < 0) return fail(MOCO_EINVAL, "T=%d must be >= 0", T);
-    if (tmpl->device != ctx->device)
-        return fail(MOCO_EINVAL, "template lives on device %d, context on device %d", tmpl->device,
-                    ctx->device);
-    const moco::Geom &tg = tmpl->t.g;
-    if (tg.m != m || tg.n != n || tg.w != w || tg.ds != downsample || tg.dtype != dtype)
-        return fail(MOCO_EINVAL,
-                    "template prepared for (m=%d n=%d w=%d ds=%d dtype=%d), call has "
-                    "(m=%d n=%d w=%d ds=%d dtype=%d)",
-                    tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
-    if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA)
-        return fail(MOCO_EINVAL, "unknown form %d", (int)form);
-    if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
-        return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
     if (T == 0) return MOCO_OK;
-    if (!d_frames || !out->shifts) return fail(MOCO_EINVAL, "moco_align: null frames or shifts");
     const moco::Tmpl &tt = tmpl->t;
-    if (form == MOCO_FORM_INT8_MFMA && !tt.int8_ok)
-        return fail(MOCO_EINVAL,
-                    "the int8 matrix-core form does not apply to this template (needs uint16, "
-                    "grid area below 131072, grid width at most 2048 and template values "
-                    "within two base-256 digits)");
-    if (form == MOCO_FORM_AUTO) form = tt.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
-    if (form == MOCO_FORM_INT8_MFMA) return align_int8(ctx, d_frames, tt, T, g, out, hip_stream);
     DeviceGuard dg(ctx->device);
     if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)hip_stream;
-    ExactLayout L = exact_layout(g);
-    int C = (int)std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / L.total_per_frame));
-    C = std::min(C, 4096);
-    if (L.total_per_frame > ctx->budget)
-        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu",
-                    L.total_per_frame, ctx->budget);
-    rc = ensure_scratch(ctx, L.total_per_frame * (size_t)C, st);
+    const size_t pf = per_frame_scratch(g, form, tt);
+    if (pf > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf,
+                    ctx->budget);
+    const size_t need = pf * std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / pf));
+    rc = ensure_scratch(ctx, need, st);
     if (rc) return rc;
+    return run_stack(ctx, d_frames, tt, T, g, form, out, st, (char *)ctx->scratch, need);
+    return MOCO_OK;
+}
+
+int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
+                     int lanes, void *hip_stream)
+{
+    if (!ctx || (nstacks > 0 && !stacks) || nstacks < 0)
+        return fail(MOCO_EINVAL, "moco_align_batch: null ctx or stacks, or nstacks < 0");
+    if (lanes < 0) return fail(MOCO_EINVAL, "lanes=%d must be >= 0", lanes);
+    // validate everything before enqueuing anything
+    std::vector<moco::Geom> geo(nstacks);
+    std::vector<moco_form> forms(nstacks);
+    std::vector<size_t> pf(nstacks);
+    std::vector<double> cost(nstacks);
+    size_t pf_max = 0;
+    for (int k = 0; k < nstacks; ++k) {
+        const moco_stack &sk = stacks[k];
+        int rc = check_stack(ctx, sk.d_frames, sk.tmpl, sk.T, sk.m, sk.n, sk.w, sk.downsample,
+                             sk.dtype, form, &sk.out, &geo[k], &forms[k]);
+        if (rc) return fail(rc, "stack %d: %s", k, moco_last_error());
+        pf[k] = per_frame_scratch(geo[k], forms[k], sk.tmpl->t);
+        if (sk.T > 0) pf_max = std::max(pf_max, pf[k]);
+        const moco::Geom &g = geo[k];
+        cost[k] = (double)sk.T * ((double)g.W * g.W * g.mg * g.ng + (double)g.m * g.n);
+    }
+    if (pf_max == 0) return MOCO_OK;  // nothing to align
+    if (pf_max > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf_max,
+                    ctx->budget);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    int nl = lanes ? std::min(lanes, 8) : 4;
+    nl = (int)std::min<size_t>((size_t)nl, ctx->budget / pf_max);
+    nl = std::max(1, std::min(nl, nstacks));
+    const size_t slice = ctx->budget / nl / 256 * 256;
+    int rc = ensure_scratch(ctx, slice * nl, st);
+    if (rc) return rc;
+    while ((int)ctx->lanes.size() < nl) {
+        hipStream_t l = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&l, hipStreamNonBlocking));
+        ctx->lanes.push_back(l);
+    }
+    while ((int)ctx->lane_ev.size() < nl + 1) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->lane_ev.push_back(e);
+    }
+    // longest first onto the least loaded lane
+    std::vector<int> order(nstacks);
+    for (int k = 0; k < nstacks; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nl, 0.0);
+    std::vector<std::vector<int>> plan(nl);
+    for (int k : order) {
+        if (stacks[k].T == 0) continue;
+        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        plan[best].push_back(k);
+        load[best] += cost[k];
+    }
+    // fork: every lane waits for the caller's stream
+    hipEvent_t fork = ctx->lane_ev[nl];
+    HIP_TRY(hipEventRecord(fork, st));
+    for (int l = 0; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(ctx->lanes[l], fork, 0));
     char *base = (char *)ctx->scratch;
-    double *coarse = (double *)base;
-    double *sat = (double *)(base + L.coarse * C);
-    double *h = (double *)(base + (L.coarse + L.sat) * C);
-    int32_t *cst = (int32_t *)(base + (L.coarse + L.sat + L.h) * C);
-    double *part = (double *)(base + (L.coarse + L.sat + L.h + L.cst) * C);
-    const size_t fbytes = (size_t)m * n * dtype_size(dtype);
-    const int W = g.W;
-    for (int f0 = 0; f0 < T; f0 += C) {
-        int c = std::min(C, T - f0);
-        const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
-        {
-            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
-            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+    for (int l = 0; l < nl; ++l) {
+        for (int k : plan[l]) {
+            const moco_stack &sk = stacks[k];
+            rc = run_stack(ctx, sk.d_frames, sk.tmpl->t, sk.T, geo[k], forms[k], &sk.out,
+                           ctx->lanes[l], base + slice * l, slice);
+            if (rc) return rc;
         }
-        {
-            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
-            HIP_TRY(moco::launch_sat_sq(coarse, c, g, sat, st));
-        }
-        {
-            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            HIP_TRY(moco::launch_corr_fp64(coarse, tmpl->t.coarse, c, g, h, st));
-        }
-        {
-            StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
-            HIP_TRY(moco::launch_combine(sat, tmpl->t.btab, h, c, g,
-                                     out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
-                                     out->fmin ? out->fmin + f0 : nullptr,
-                                     out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
-                                     out->shifts + 2 * (size_t)f0,
-                                     out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
-                                     out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
-        }
-        if (g.ds) {
-            StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
-            HIP_TRY(moco::launch_refine(fr, tmpl->t.raw, c, g,
-                                        out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
-                                        out->shifts + 2 * (size_t)f0,
-                                        out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
-                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
-                                        st));
-        }
+    }
+    // join: the caller's stream waits for every lane
+    for (int l = 0; l < nl; ++l) {
+        HIP_TRY(hipEventRecord(ctx->lane_ev[l], ctx->lanes[l]));
+        HIP_TRY(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
     }
     return MOCO_OK;
 }

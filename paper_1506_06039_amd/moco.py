@@ -58,6 +58,15 @@ _lib.moco_profile_enable.restype = _i
 _lib.moco_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]
 _lib.moco_profile_read.restype = _i
+class _Stack(ctypes.Structure):
+    _fields_ = [("d_frames", ctypes.c_void_p), ("tmpl", ctypes.c_void_p),
+                ("T", ctypes.c_int), ("m", ctypes.c_int), ("n", ctypes.c_int),
+                ("w", ctypes.c_int), ("downsample", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("out", _Outputs)]
+
+
+_lib.moco_align_batch.argtypes = [_vp, ctypes.POINTER(_Stack), _i, _i, _i, _vp]
+_lib.moco_align_batch.restype = _i
 _lib.moco_template_form.argtypes = [_vp, _i, ctypes.POINTER(_i)]
 _lib.moco_template_form.restype = _i
 _lib.moco_last_error.argtypes = []
@@ -178,6 +187,43 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
                            int(tmpl.downsample), _dtype_code(frames), FORMS[form],
                            ctypes.byref(o), _stream_handle(dev)))
     return out
+
+
+def _new_result(T: int, W: int, dev, surface: bool) -> Result:
+    return Result(
+        shifts=torch.empty((T, 2), dtype=torch.int32, device=dev),
+        fmin=torch.empty(T, dtype=torch.float64, device=dev),
+        frefine=torch.empty((T, 9), dtype=torch.float64, device=dev),
+        coarse=torch.empty((T, 2), dtype=torch.int32, device=dev),
+        gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
+        fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None)
+
+
+def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
+                     surface: bool = False):
+    """Align several stacks in one call.  items: list of (frames, Template) or
+    (frames, Template, Result).  Returns the list of Results (enqueued on the
+    current stream)."""
+    stacks = (_Stack * max(1, len(items)))()
+    results = []
+    dev = None
+    for k, it in enumerate(items):
+        frames, tmpl = it[0], it[1]
+        if not frames.is_cuda or frames.dim() != 3 or not frames.is_contiguous():
+            raise ValueError("stack %d: frames must be a contiguous 3-D device tensor" % k)
+        T, m, n = frames.shape
+        dev = frames.device
+        res = it[2] if len(it) > 2 and it[2] is not None else \
+            _new_result(T, 2 * tmpl.w - 1, dev, surface)
+        results.append(res)
+        o = _Outputs(res.shifts.data_ptr(), res.fmin.data_ptr(),
+                     res.fsurf.data_ptr() if res.fsurf is not None else None,
+                     res.frefine.data_ptr(), res.coarse.data_ptr(), res.gaps.data_ptr())
+        stacks[k] = _Stack(frames.data_ptr(), tmpl.handle.value, T, m, n, tmpl.w,
+                           int(tmpl.downsample), _dtype_code(frames), o)
+    stream = _stream_handle(dev if dev is not None else ctx.device)
+    _check(_lib.moco_align_batch(ctx.handle, stacks, len(items), FORMS[form], lanes, stream))
+    return results
 
 
 def align(frames: torch.Tensor, template: torch.Tensor, w: int, downsample: bool,

@@ -253,3 +253,47 @@ def test_refine_partial_sum_flushes(gpu_lib, level):
     res = _run(gpu_lib, fr, tmpl, 16, True, "int8")
     orc = oracle.align(fr, tmpl, 16, True)
     check(res, orc, True, exact=True, label="refine flush %d" % level)
+
+
+def test_batch_of_uneven_stacks_matches_single_calls_and_oracle(gpu_lib):
+    # uneven batch: frame sizes from {128^2, 256^2, 512^2, 512x796}, windows from
+    # {8,16,32,48}, downsampled iff a side exceeds 256; short stacks for test time
+    specs = synth.mixed_stacks(nstacks=8, seed=5, max_len=6, min_len=2)
+    ctx = gpu_lib.Context(0)
+    items, data = [], []
+    for sp in specs:
+        sc = sp["scene"]
+        fr = sc.frames(0, sp["T"])
+        tm = sc.template
+        tp = gpu_lib.Template(ctx, _to_dev(tm), sp["w"], sp["downsample"])
+        items.append((_to_dev(fr), tp))
+        data.append((fr, tm, sp))
+    _say("case batch of %d stacks" % len(items), [(d[2]["m"], d[2]["n"], d[2]["w"], d[2]["T"]) for d in data])
+    res = gpu_lib.moco_align_batch(ctx, items, surface=True, lanes=3)
+    torch.cuda.synchronize()
+    for (fr_dev, tp), r, (fr, tm, sp) in zip(items, res, data):
+        single = gpu_lib.moco_align(ctx, fr_dev, tp, surface=True)
+        torch.cuda.synchronize()
+        for k in ("shifts", "fmin", "frefine", "coarse", "gaps", "fsurf"):
+            a, b = getattr(r, k), getattr(single, k)
+            if a.dtype == torch.float64:   # bitwise, so that NaN equals NaN
+                a, b = a.view(torch.int64), b.view(torch.int64)
+            assert torch.equal(a, b), (k, sp["m"], sp["n"], sp["w"])
+        got = {k: getattr(r, k).cpu().numpy() for k in ("shifts", "fmin", "frefine", "coarse", "gaps")}
+        orc = oracle.align(fr[:2], tm, sp["w"], sp["downsample"])
+        got2 = {k: v[:2] for k, v in got.items()}
+        check(got2, orc, sp["downsample"], exact=True, label="batch %dx%d w%d" % (sp["m"], sp["n"], sp["w"]))
+
+
+def test_batch_validation_is_all_or_nothing(gpu_lib):
+    ctx = gpu_lib.Context(0)
+    good = gpu_lib.Template(ctx, _to_dev(np.ones((32, 32), np.uint16)), 4, False)
+    bad_frames = _to_dev(np.ones((2, 30, 32), np.uint16))   # size differs from its template's
+    ok_frames = _to_dev(np.ones((2, 32, 32), np.uint16))
+    marker = gpu_lib._new_result(2, 7, ok_frames.device, False)
+    marker.shifts.fill_(-99)
+    with pytest.raises(gpu_lib.MocoError) as ei:
+        gpu_lib.moco_align_batch(ctx, [(ok_frames, good, marker), (bad_frames, good)])
+    assert ei.value.code == gpu_lib.MOCO_EINVAL and "stack 1" in str(ei.value)
+    torch.cuda.synchronize()
+    assert int(marker.shifts.min()) == -99   # nothing was enqueued
