@@ -155,6 +155,62 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
 
+/* ---- Serving: single frames from many sources, continuous batching ----
+ *
+ * A server owns its own context on the device of `ctx`, a pool of `max_slots`
+ * request slots (pinned host staging plus device space for two batches in
+ * flight) and the prepared template of each source, resident on the device.
+ * Requests are single host frames; a worker thread takes every request waiting
+ * when the GPU can accept a batch (up to max_slots), runs the search of sec. 2 on
+ * the batch (frames of one source share a launch), and publishes one result per
+ * request.  Requests that arrive while batches are on the GPU are admitted as
+ * slots free up and go in the next batch.  Each frame's result is exactly what
+ * moco_align gives for that frame alone.  All server calls are thread-safe. */
+typedef struct moco_server moco_server;
+
+typedef struct {
+    uint64_t tag;          /* the caller's tag from moco_server_submit */
+    int source;            /* the source id */
+    int status;            /* MOCO_OK, MOCO_EDEVICE, or MOCO_ECANCELED */
+    int32_t shift[2];      /* final (S,T) */
+    int32_t coarse[2];     /* argmin on the searched grid */
+    double fmin;           /* f at the coarse argmin */
+    double frefine[9];     /* nine full-resolution values (NaN when not downsampled) */
+    double gaps[2];        /* as moco_outputs.gaps */
+    double latency_us;     /* submit -> result published */
+} moco_result;
+
+/* Create a server.  device_budget_bytes caps the device memory it may hold (0 =
+ * 1 GiB); max_slots (>= 1) caps the requests admitted at once.
+ * Errors: MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE. */
+int moco_server_create(moco_ctx *ctx, size_t device_budget_bytes, int max_slots,
+                       moco_server **out);
+
+/* Register a source and prepare its template (host memory, m x n of dtype,
+ * copied during the call).  Source ids are any int, unique per server.
+ * Errors: MOCO_EINVAL (bad geometry, duplicate id), MOCO_ENOMEM (the slots for
+ * this frame size do not fit the device budget), MOCO_EDEVICE. */
+int moco_server_add_source(moco_server *srv, int source, const void *h_template,
+                           moco_dtype dtype, int m, int n, int w, int downsample);
+
+/* Submit one frame (host memory of the source's size and dtype, copied during
+ * the call).  Returns MOCO_OK when admitted, MOCO_EBUSY when no slot is free
+ * (back-pressure: poll, then retry), MOCO_EINVAL for an unknown source. */
+int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64_t tag);
+
+/* Wait up to timeout_us (0: do not wait, < 0: wait without limit) for finished
+ * requests and copy up to `max` results into `results` (host), oldest first.
+ * Returns the number copied (>= 0) or a negative status. */
+int moco_server_poll(moco_server *srv, moco_result *results, int max, int timeout_us);
+
+/* Requests admitted and not yet published (queued or on the GPU). */
+int moco_server_pending(moco_server *srv);
+
+/* Stop the server: requests not yet on the GPU are cancelled, batches on the
+ * GPU finish, then everything is freed.  Results not polled are dropped.
+ * Returns the number of cancelled requests.  Safe on NULL (returns 0). */
+int moco_server_destroy(moco_server *srv);
+
 /* Stage timing (tracing).  Stages of the pipeline, in launch order. */
 typedef enum {
     MOCO_STAGE_COARSE = 0,   /* 2x2 box mean / conversion of the frames */

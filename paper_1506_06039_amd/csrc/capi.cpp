@@ -4,7 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -663,6 +669,405 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
         HIP_TRY(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
     }
     return MOCO_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching of single frames from many sources.
+// ===========================================================================
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvSource {
+    moco_tmpl *tmpl = nullptr;
+    moco::Geom g{};
+    moco_form form = MOCO_FORM_AUTO;
+    size_t fbytes = 0;
+    size_t pf = 0;
+};
+
+struct SrvRequest {
+    uint64_t tag;
+    int source;
+    int slot;
+    Clock::time_point t0;
+};
+
+// Device and pinned buffers of one batch in flight.
+struct SrvLane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char *d_frames = nullptr, *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int32_t *d_shifts = nullptr, *d_coarse = nullptr;
+    double *d_fmin = nullptr, *d_frefine = nullptr, *d_gaps = nullptr;
+    int32_t *h_shifts = nullptr, *h_coarse = nullptr;
+    double *h_fmin = nullptr, *h_frefine = nullptr, *h_gaps = nullptr;
+    std::vector<SrvRequest> reqs;
+    bool active = false;
+    int status = MOCO_OK;
+};
+
+}  // namespace
+
+struct moco_server {
+    moco_ctx *ctx = nullptr;  // the server's own context
+    size_t budget = 0;
+    int max_slots = 0;
+    std::map<int, SrvSource> sources;
+    size_t slot_bytes = 0;  // largest frame of any source
+    size_t pf_max = 0;      // largest per-frame scratch of any source
+    size_t tmpl_bytes = 0;  // device bytes held by prepared templates (estimate)
+    char *h_slots = nullptr;  // pinned staging, max_slots x slot_bytes
+    std::vector<int> free_slots;
+    SrvLane lane[2];
+    hipStream_t setup = nullptr;
+    std::deque<SrvRequest> pending;
+    std::deque<moco_result> completed;
+    int inflight = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    std::thread worker;
+};
+
+namespace {
+
+void lane_free(SrvLane &L)
+{
+    if (L.d_frames) (void)hipFree(L.d_frames);
+    if (L.d_scratch) (void)hipFree(L.d_scratch);
+    if (L.d_shifts) (void)hipFree(L.d_shifts);
+    if (L.h_shifts) (void)hipHostFree(L.h_shifts);
+    L.d_frames = L.d_scratch = nullptr;
+    L.d_shifts = nullptr;
+    L.h_shifts = nullptr;
+}
+
+// (Re)size the slot staging and both lanes for max_slots frames of slot_bytes
+// with pf_max scratch each.  Called with no batch in flight.
+int server_size_buffers(moco_server *srv, size_t slot_bytes, size_t pf_max)
+{
+    const size_t ns = (size_t)srv->max_slots;
+    const size_t res_i32 = ns * 4 * sizeof(int32_t);            // shifts + coarse
+    const size_t res_f64 = ns * (1 + 9 + 2) * sizeof(double);   // fmin, frefine, gaps
+    const size_t per_lane = ns * slot_bytes + ns * pf_max + res_i32 + res_f64 + 4096;
+    if (2 * per_lane + srv->tmpl_bytes > srv->budget)
+        return fail(MOCO_ENOMEM, "server needs %zu device bytes for %d slots, budget is %zu",
+                    2 * per_lane + srv->tmpl_bytes, srv->max_slots, srv->budget);
+    if (srv->h_slots) (void)hipHostFree(srv->h_slots);
+    srv->h_slots = nullptr;
+    hipError_t e = hipHostMalloc((void **)&srv->h_slots, ns * slot_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(MOCO_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+    for (auto &L : srv->lane) {
+        lane_free(L);
+        if ((e = hipMalloc(&L.d_frames, ns * slot_bytes)) != hipSuccess ||
+            (e = hipMalloc(&L.d_scratch, ns * pf_max)) != hipSuccess ||
+            (e = hipMalloc(&L.d_shifts, res_i32 + res_f64)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&L.h_shifts, res_i32 + res_f64, hipHostMallocDefault)) !=
+                hipSuccess)
+            return fail(MOCO_ENOMEM, "server buffers: %s", hipGetErrorString(e));
+        L.scratch_bytes = ns * pf_max;
+        L.d_coarse = L.d_shifts + 2 * ns;
+        L.d_fmin = (double *)(L.d_coarse + 2 * ns);
+        L.d_frefine = L.d_fmin + ns;
+        L.d_gaps = L.d_frefine + 9 * ns;
+        L.h_coarse = L.h_shifts + 2 * ns;
+        L.h_fmin = (double *)(L.h_coarse + 2 * ns);
+        L.h_frefine = L.h_fmin + ns;
+        L.h_gaps = L.h_frefine + 9 * ns;
+    }
+    srv->slot_bytes = slot_bytes;
+    srv->pf_max = pf_max;
+    return MOCO_OK;
+}
+
+// Enqueue one batch on its lane: frames host -> device, the search per source
+// group, results device -> host, completion event.
+int server_enqueue(moco_server *srv, SrvLane &L)
+{
+    std::stable_sort(L.reqs.begin(), L.reqs.end(),
+                     [](const SrvRequest &x, const SrvRequest &y) { return x.source < y.source; });
+    const size_t nb = L.reqs.size();
+    std::vector<size_t> off(nb);
+    size_t o = 0;
+    for (size_t k = 0; k < nb; ++k) {
+        const SrvSource &sc = srv->sources.at(L.reqs[k].source);
+        off[k] = o;
+        HIP_TRY(hipMemcpyAsync(L.d_frames + o, srv->h_slots + (size_t)L.reqs[k].slot * srv->slot_bytes,
+                               sc.fbytes, hipMemcpyHostToDevice, L.stream));
+        o += sc.fbytes;
+    }
+    for (size_t a = 0; a < nb;) {
+        size_t b = a;
+        while (b < nb && L.reqs[b].source == L.reqs[a].source) ++b;
+        const SrvSource &sc = srv->sources.at(L.reqs[a].source);
+        moco_outputs out{};
+        out.shifts = L.d_shifts + 2 * a;
+        out.coarse = L.d_coarse + 2 * a;
+        out.fmin = L.d_fmin + a;
+        out.frefine = L.d_frefine + 9 * a;
+        out.gaps = L.d_gaps + 2 * a;
+        int rc = run_stack(srv->ctx, L.d_frames + off[a], sc.tmpl->t, (int)(b - a), sc.g, sc.form,
+                           &out, L.stream, L.d_scratch, L.scratch_bytes);
+        if (rc) return rc;
+        a = b;
+    }
+    const size_t ns = (size_t)srv->max_slots;
+    const size_t res = ns * 4 * sizeof(int32_t) + ns * 12 * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(L.h_shifts, L.d_shifts, res, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipEventRecord(L.done, L.stream));
+    return MOCO_OK;
+}
+
+// Publish the results of a finished lane (called with srv->mu held).
+void server_publish(moco_server *srv, SrvLane &L)
+{
+    const auto now = Clock::now();
+    for (size_t k = 0; k < L.reqs.size(); ++k) {
+        const SrvRequest &q = L.reqs[k];
+        moco_result r{};
+        r.tag = q.tag;
+        r.source = q.source;
+        r.status = L.status;
+        if (L.status == MOCO_OK) {
+            r.shift[0] = L.h_shifts[2 * k];
+            r.shift[1] = L.h_shifts[2 * k + 1];
+            r.coarse[0] = L.h_coarse[2 * k];
+            r.coarse[1] = L.h_coarse[2 * k + 1];
+            r.fmin = L.h_fmin[k];
+            for (int u = 0; u < 9; ++u) r.frefine[u] = L.h_frefine[9 * k + u];
+            r.gaps[0] = L.h_gaps[2 * k];
+            r.gaps[1] = L.h_gaps[2 * k + 1];
+        }
+        r.latency_us = std::chrono::duration<double, std::micro>(now - q.t0).count();
+        srv->completed.push_back(r);
+        srv->free_slots.push_back(q.slot);
+    }
+    srv->inflight -= (int)L.reqs.size();
+    L.reqs.clear();
+    L.active = false;
+}
+
+void server_loop(moco_server *srv)
+{
+    (void)hipSetDevice(srv->ctx->device);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    for (;;) {
+        const bool any_active = srv->lane[0].active || srv->lane[1].active;
+        if (!any_active) {
+            srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
+            if (srv->stop && srv->pending.empty()) break;
+        }
+        // launch the waiting requests into a free lane
+        int fl = !srv->lane[0].active ? 0 : (!srv->lane[1].active ? 1 : -1);
+        if (fl >= 0 && !srv->pending.empty() && !srv->stop) {
+            SrvLane &L = srv->lane[fl];
+            while (!srv->pending.empty() && (int)L.reqs.size() < srv->max_slots) {
+                L.reqs.push_back(srv->pending.front());
+                srv->pending.pop_front();
+            }
+            L.active = true;
+            lk.unlock();
+            int rc = server_enqueue(srv, L);
+            lk.lock();
+            L.status = rc;
+            if (rc != MOCO_OK) {
+                // the batch never reached the GPU in full: wait for what did, then fail it
+                lk.unlock();
+                (void)hipStreamSynchronize(L.stream);
+                lk.lock();
+                server_publish(srv, L);
+                srv->cv_done.notify_all();
+            }
+            continue;
+        }
+        // finish lanes whose batch has completed, oldest first
+        bool progressed = false;
+        for (auto &L : srv->lane) {
+            if (!L.active) continue;
+            lk.unlock();
+            hipError_t q = hipEventQuery(L.done);
+            lk.lock();
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) L.status = MOCO_EDEVICE;
+            server_publish(srv, L);
+            progressed = true;
+        }
+        if (progressed) {
+            srv->cv_done.notify_all();
+            continue;
+        }
+        if (srv->stop && srv->pending.empty() && !srv->lane[0].active && !srv->lane[1].active)
+            break;
+        // a batch is on the GPU: wait briefly for new requests or its completion
+        srv->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int moco_server_create(moco_ctx *ctx, size_t device_budget_bytes, int max_slots,
+                       moco_server **out)
+{
+    if (!ctx || !out || max_slots < 1)
+        return fail(MOCO_EINVAL, "moco_server_create: null ctx/out or max_slots < 1");
+    *out = nullptr;
+    moco_server *srv = new (std::nothrow) moco_server;
+    if (!srv) return fail(MOCO_ENOMEM, "out of host memory");
+    srv->budget = device_budget_bytes ? device_budget_bytes : (size_t)1 << 30;
+    srv->max_slots = max_slots;
+    int rc = moco_create(ctx->device, srv->budget, &srv->ctx);
+    if (rc) {
+        delete srv;
+        return rc;
+    }
+    DeviceGuard dg(ctx->device);
+    hipError_t e = hipStreamCreateWithFlags(&srv->setup, hipStreamNonBlocking);
+    for (auto &L : srv->lane) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        moco_server_destroy(srv);
+        return fail(MOCO_EDEVICE, "server streams: %s", hipGetErrorString(e));
+    }
+    srv->worker = std::thread(server_loop, srv);
+    *out = srv;
+    return MOCO_OK;
+}
+
+int moco_server_add_source(moco_server *srv, int source, const void *h_template,
+                           moco_dtype dtype, int m, int n, int w, int downsample)
+{
+    if (!srv || !h_template) return fail(MOCO_EINVAL, "moco_server_add_source: null argument");
+    moco::Geom g;
+    int rc = validate(m, n, w, downsample, dtype, &g);
+    if (rc) return rc;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->sources.count(source)) return fail(MOCO_EINVAL, "source %d already exists", source);
+    DeviceGuard dg(srv->ctx->device);
+    const size_t fbytes = (size_t)m * n * dtype_size(dtype);
+    void *d_t = nullptr;
+    hipError_t e = hipMalloc(&d_t, fbytes);
+    if (e != hipSuccess) return fail(MOCO_ENOMEM, "template upload: %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d_t, h_template, fbytes, hipMemcpyHostToDevice, srv->setup);
+    if (e == hipSuccess) e = hipStreamSynchronize(srv->setup);
+    moco_tmpl *tp = nullptr;
+    rc = e == hipSuccess ? moco_template_create(srv->ctx, d_t, dtype, m, n, w, downsample,
+                                                srv->setup, &tp)
+                         : fail(MOCO_EDEVICE, "template upload: %s", hipGetErrorString(e));
+    (void)hipFree(d_t);
+    if (rc) return rc;
+    SrvSource sc;
+    sc.tmpl = tp;
+    sc.g = g;
+    moco_form resolved = MOCO_FORM_AUTO;
+    (void)moco_template_form(tp, MOCO_FORM_AUTO, &resolved);
+    sc.form = resolved;
+    sc.fbytes = fbytes;
+    sc.pf = per_frame_scratch(g, resolved, tp->t);
+    const size_t tb = fbytes + (size_t)g.mg * g.ng * 8 + (size_t)g.W * g.W * 16 +
+                      (tp->t.int8_ok ? moco::int8_template_bytes(g) : 0);
+    // larger frames or scratch than the buffers hold: resize once nothing is in flight
+    if (fbytes > srv->slot_bytes || sc.pf > srv->pf_max) {
+        srv->cv_done.wait(lk, [&] { return srv->pending.empty() && srv->inflight == 0; });
+        srv->tmpl_bytes += tb;
+        rc = server_size_buffers(srv, std::max(fbytes, srv->slot_bytes),
+                                 std::max(sc.pf, srv->pf_max));
+        if (rc) {
+            srv->tmpl_bytes -= tb;
+            moco_template_destroy(tp);
+            return rc;
+        }
+        srv->free_slots.clear();
+        for (int k = srv->max_slots - 1; k >= 0; --k) srv->free_slots.push_back(k);
+    } else {
+        srv->tmpl_bytes += tb;
+    }
+    srv->sources[source] = sc;
+    return MOCO_OK;
+}
+
+int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64_t tag)
+{
+    if (!srv || !h_frame) return fail(MOCO_EINVAL, "moco_server_submit: null argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->sources.find(source);
+    if (it == srv->sources.end()) return fail(MOCO_EINVAL, "unknown source %d", source);
+    if (srv->stop) return fail(MOCO_ECANCELED, "server is shutting down");
+    if (srv->free_slots.empty()) return MOCO_EBUSY;
+    const int slot = srv->free_slots.back();
+    srv->free_slots.pop_back();
+    SrvRequest q{tag, source, slot, Clock::now()};
+    const size_t fbytes = it->second.fbytes;
+    lk.unlock();
+    std::memcpy(srv->h_slots + (size_t)slot * srv->slot_bytes, h_frame, fbytes);
+    lk.lock();
+    srv->pending.push_back(q);
+    srv->inflight += 1;
+    srv->cv_work.notify_one();
+    return MOCO_OK;
+}
+
+int moco_server_poll(moco_server *srv, moco_result *results, int max, int timeout_us)
+{
+    if (!srv || (max > 0 && !results) || max < 0)
+        return fail(MOCO_EINVAL, "moco_server_poll: bad arguments");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto ready = [&] { return !srv->completed.empty(); };
+    if (timeout_us < 0)
+        srv->cv_done.wait(lk, [&] { return ready() || srv->inflight == 0; });
+    else if (timeout_us > 0)
+        srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+    int k = 0;
+    while (k < max && !srv->completed.empty()) {
+        results[k++] = srv->completed.front();
+        srv->completed.pop_front();
+    }
+    return k;
+}
+
+int moco_server_pending(moco_server *srv)
+{
+    if (!srv) return 0;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    return srv->inflight;
+}
+
+int moco_server_destroy(moco_server *srv)
+{
+    if (!srv) return 0;
+    int cancelled = 0;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        cancelled = (int)srv->pending.size();
+        for (auto &q : srv->pending) srv->free_slots.push_back(q.slot);
+        srv->inflight -= cancelled;
+        srv->pending.clear();
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    {
+        DeviceGuard dg(srv->ctx ? srv->ctx->device : 0);
+        for (auto &L : srv->lane) {
+            if (L.stream) (void)hipStreamSynchronize(L.stream);
+            lane_free(L);
+            if (L.done) (void)hipEventDestroy(L.done);
+            if (L.stream) (void)hipStreamDestroy(L.stream);
+        }
+        for (auto &kv : srv->sources) moco_template_destroy(kv.second.tmpl);
+        if (srv->h_slots) (void)hipHostFree(srv->h_slots);
+        if (srv->setup) (void)hipStreamDestroy(srv->setup);
+    }
+    if (srv->ctx) moco_destroy(srv->ctx);
+    delete srv;
+    return cancelled;
 }
 
 }  // extern "C"

@@ -67,6 +67,25 @@ class _Stack(ctypes.Structure):
 
 _lib.moco_align_batch.argtypes = [_vp, ctypes.POINTER(_Stack), _i, _i, _i, _vp]
 _lib.moco_align_batch.restype = _i
+class ServerResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("source", ctypes.c_int), ("status", ctypes.c_int),
+                ("shift", ctypes.c_int32 * 2), ("coarse", ctypes.c_int32 * 2),
+                ("fmin", ctypes.c_double), ("frefine", ctypes.c_double * 9),
+                ("gaps", ctypes.c_double * 2), ("latency_us", ctypes.c_double)]
+
+
+_lib.moco_server_create.argtypes = [_vp, ctypes.c_size_t, _i, ctypes.POINTER(_vp)]
+_lib.moco_server_create.restype = _i
+_lib.moco_server_add_source.argtypes = [_vp, _i, _vp, _i, _i, _i, _i, _i]
+_lib.moco_server_add_source.restype = _i
+_lib.moco_server_submit.argtypes = [_vp, _i, _vp, ctypes.c_uint64]
+_lib.moco_server_submit.restype = _i
+_lib.moco_server_poll.argtypes = [_vp, ctypes.POINTER(ServerResult), _i, _i]
+_lib.moco_server_poll.restype = _i
+_lib.moco_server_pending.argtypes = [_vp]
+_lib.moco_server_pending.restype = _i
+_lib.moco_server_destroy.argtypes = [_vp]
+_lib.moco_server_destroy.restype = _i
 _lib.moco_template_form.argtypes = [_vp, _i, ctypes.POINTER(_i)]
 _lib.moco_template_form.restype = _i
 _lib.moco_last_error.argtypes = []
@@ -266,3 +285,57 @@ def int8_products(tmpl: Template) -> int:
     base-256 digits of the frame times two of the template (frames that need a
     third digit add two more products)."""
     return 4
+
+
+class Server:
+    """moco_server_*: single host frames from many sources, continuous batching."""
+
+    def __init__(self, ctx: Context, device_budget: int = 0, max_slots: int = 64):
+        h = _vp()
+        _check(_lib.moco_server_create(ctx.handle, device_budget, max_slots, ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def add_source(self, source: int, template, w: int, downsample: bool):
+        """template: host numpy array (uint16 or float32), m x n."""
+        import numpy as np
+        t = np.ascontiguousarray(template)
+        code = MOCO_U16 if t.dtype == np.uint16 else MOCO_F32 if t.dtype == np.float32 else None
+        if code is None:
+            raise TypeError("template must be uint16 or float32")
+        m, n = t.shape
+        _check(_lib.moco_server_add_source(self.handle, source, t.ctypes.data, code, m, n, w,
+                                           int(bool(downsample))))
+
+    def submit(self, source: int, frame, tag: int) -> bool:
+        """True when admitted, False on back-pressure (no free slot)."""
+        import numpy as np
+        f = np.ascontiguousarray(frame)
+        rc = _lib.moco_server_submit(self.handle, source, f.ctypes.data, tag)
+        if rc == MOCO_EBUSY:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_results: int = 256, timeout_us: int = 0):
+        buf = (ServerResult * max_results)()
+        k = _lib.moco_server_poll(self.handle, buf, max_results, timeout_us)
+        if k < 0:
+            _check(k)
+        return [buf[i] for i in range(k)]
+
+    def pending(self) -> int:
+        return _lib.moco_server_pending(self.handle)
+
+    def close(self) -> int:
+        if getattr(self, "handle", None):
+            n = _lib.moco_server_destroy(self.handle)
+            self.handle = None
+            return n
+        return 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

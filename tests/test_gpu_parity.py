@@ -297,3 +297,89 @@ def test_batch_validation_is_all_or_nothing(gpu_lib):
     assert ei.value.code == gpu_lib.MOCO_EINVAL and "stack 1" in str(ei.value)
     torch.cuda.synchronize()
     assert int(marker.shifts.min()) == -99   # nothing was enqueued
+
+
+def _serve_all(srv, frames_by_req, max_poll=64):
+    """Submit (source, frame, tag) requests in order, polling on back-pressure;
+    returns {tag: result}."""
+    out = {}
+    pending_max = 0
+    for src, fr, tag in frames_by_req:
+        while not srv.submit(src, fr, tag):
+            for r in srv.poll(max_poll, timeout_us=2000):
+                out[r.tag] = r
+        pending_max = max(pending_max, srv.pending())
+    while len(out) < len(frames_by_req):
+        got = srv.poll(max_poll, timeout_us=200000)
+        assert got or srv.pending() > 0, "server lost requests"
+        for r in got:
+            out[r.tag] = r
+    return out, pending_max
+
+
+def test_server_results_equal_alone_and_in_the_mix(gpu_lib):
+    # three sources of different shape and dtype, interleaved requests, few slots:
+    # every result must equal moco_align on that frame alone
+    ctx = gpu_lib.Context(0)
+    srcs = {
+        1: (synth.poisson512_u16(T=12, seed=1), 32, True),
+        2: (synth.PoissonScene(256, 256, 12, seed=2), 16, False),
+        3: (synth.blobs128_f32(seed=3), 10, False),
+    }
+    srv = gpu_lib.Server(ctx, max_slots=5)
+    frames = {}
+    for sid, (sc, w, ds) in srcs.items():
+        srv.add_source(sid, sc.template, w, ds)
+        frames[sid] = sc.frames(0, 8)
+    reqs = []
+    for k in range(8):
+        for sid in (1, 2, 3):
+            reqs.append((sid, frames[sid][k], sid * 1000 + k))
+    _say("case server 3 sources x 8 frames, 5 slots")
+    out, pending_max = _serve_all(srv, reqs)
+    assert pending_max <= 5
+    assert srv.close() == 0
+    for sid, (sc, w, ds) in srcs.items():
+        alone = _run(gpu_lib, frames[sid], sc.template, w, ds)
+        for k in range(8):
+            r = out[sid * 1000 + k]
+            assert r.status == 0 and r.source == sid
+            assert list(r.shift) == alone["shifts"][k].tolist(), (sid, k)
+            assert list(r.coarse) == alone["coarse"][k].tolist()
+            assert r.fmin == alone["fmin"][k] or (np.isnan(r.fmin) and np.isnan(alone["fmin"][k]))
+            assert np.array_equal(np.array(list(r.frefine)), alone["frefine"][k], equal_nan=True)
+            assert r.latency_us > 0
+    # and the oracle agrees on the first frames of the downsampled uint16 source
+    sc, w, ds = srcs[1]
+    orc = oracle.align(frames[1][:3], sc.template, w, ds)
+    for k in range(3):
+        r = out[1000 + k]
+        assert list(r.shift) == orc.shifts[k].tolist()
+        assert r.fmin == orc.fmin[k]
+
+
+def test_server_rejects_bad_use_and_cancels_on_destroy(gpu_lib):
+    ctx = gpu_lib.Context(0)
+    srv = gpu_lib.Server(ctx, max_slots=3)
+    sc = synth.PoissonScene(128, 128, 8, seed=9)
+    srv.add_source(7, sc.template, 8, False)
+    with pytest.raises(gpu_lib.MocoError):          # duplicate source id
+        srv.add_source(7, sc.template, 8, False)
+    with pytest.raises(gpu_lib.MocoError):          # unknown source
+        srv.submit(8, sc.frame(1), 1)
+    admitted = sum(srv.submit(7, sc.frame(k), k) for k in range(6))
+    assert 1 <= admitted <= 6
+    assert srv.pending() <= 3
+    n_cancel = srv.close()
+    assert 0 <= n_cancel <= admitted
+
+
+def test_server_memory_admission(gpu_lib):
+    # a budget too small for the slots of a 512x512 source is refused
+    ctx = gpu_lib.Context(0)
+    srv = gpu_lib.Server(ctx, device_budget=4 << 20, max_slots=64)
+    sc = synth.poisson512_u16(T=2)
+    with pytest.raises(gpu_lib.MocoError) as ei:
+        srv.add_source(1, sc.template, 32, True)
+    assert ei.value.code == gpu_lib.MOCO_ENOMEM
+    srv.close()
