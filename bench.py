@@ -67,6 +67,56 @@ def load_traffic(kernel: str, source: str, frames_per_launch: float):
     return per_frame * frames_per_launch
 
 
+def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz: float = 30.0):
+    """Single-frame serving of the same workload: nsrc sources, each with its own
+    resident template (the first frame of its slice of the stack).  Closed loop:
+    a source sends its next frame at the later of its next rate_hz tick and the
+    completion of its previous frame.  Saturation: every source resubmits as soon
+    as its previous frame completes (up to 8 in flight per source)."""
+    per = frames_np.shape[0] // nsrc
+    srv = moco.Server(ctx, device_budget=8 << 30, max_slots=8 * nsrc)
+    for k in range(nsrc):
+        srv.add_source(k, frames_np[k * per], W_WIN, DS)
+
+    def run(closed_loop: bool):
+        lat, done, tag = [], 0, 0
+        nxt = [0.0] * nsrc
+        inflight = [0] * nsrc
+        cursor = [1] * nsrc
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            if now > seconds:
+                break
+            for k in range(nsrc):
+                limit = 1 if closed_loop else 8
+                if inflight[k] < limit and (not closed_loop or now >= nxt[k]):
+                    fr = frames_np[k * per + cursor[k]]
+                    if srv.submit(k, fr, tag):
+                        tag += 1
+                        inflight[k] += 1
+                        cursor[k] = cursor[k] % (per - 1) + 1
+                        nxt[k] = max(nxt[k] + 1.0 / rate_hz, now)
+            for r in srv.poll(256, timeout_us=200):
+                inflight[r.source] -= 1
+                lat.append(r.latency_us)
+                done += 1
+        while srv.pending():
+            for r in srv.poll(256, timeout_us=10000):
+                lat.append(r.latency_us)
+                done += 1
+        wall = time.perf_counter() - t0
+        lat = np.array(lat) if lat else np.zeros(1)
+        return {"frames": done, "frames_per_s": round(done / wall, 1),
+                "p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1)}
+
+    out = {"sources": nsrc, "rate_hz": rate_hz, "frame": "512x512 uint16",
+           "closed_loop": run(True), "saturation": run(False)}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +128,8 @@ def main():
                     help="frames for the oracle baseline (0: 4 per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of each serving measurement (0: skip serving)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), the "
                          "reference for HBM byte counters, and exit")
@@ -192,6 +244,9 @@ def main():
         lat.append(time.perf_counter() - t)
     lat_us = np.array(lat) * 1e6
 
+    serving = measure_serving(moco, ctx, frames_np, args.serve_seconds) \
+        if args.serve_seconds > 0 else None
+
     # rerun the stack once more for the parity sample (the timed outputs were overwritten by
     # the latency loop's first rows)
     moco.moco_align(ctx, frames, tp, form=args.form, out=out)
@@ -218,6 +273,7 @@ def main():
                    "downsample": DS, "form": form_ran, "template": "frame 0"},
         "roofline": roof,
         "stages": stages,
+        "serving": serving,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
                         "p99": round(float(np.percentile(lat_us, 99)), 1),
                         "frames": 1, "iters": args.latency_iters} if lat_us.size else None),
