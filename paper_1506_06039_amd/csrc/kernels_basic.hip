@@ -609,6 +609,310 @@ __global__ __launch_bounds__(kBlock) void k_refine_u16(const uint16_t *__restric
     }
 }
 
+// uint16 x2 step, rolling form, for an even row length and 4-byte aligned
+// buffers.  One wave owns 64 column groups of four template columns and a band
+// of template rows; each lane walks down the band and keeps the three frame
+// rows it needs (i+2s*-1, i+2s*, i+2s*+1, columns j0+2t*-1 .. j0+2t*+4) in
+// registers, so every frame row is loaded once per lane, one row ahead of use.
+// Frame rows are read as four dwords starting at column j0+2t*-2, which is even
+// because t* contributes 2t*: the pairs of adjacent columns that the three
+// column shifts need are those dwords or byte-aligned joins of two of them.
+//
+// Narrow mode (pixel bound M <= 32767 for frame and template): differences of
+// two pixels come from one packed 16-bit subtract (|d| <= 32767 fits) and their
+// squares from one 2-way 16-bit dot product into a 32-bit sum; the sums are
+// read as unsigned and flushed into 64 bits every `flush` rows, flush*4*M^2 <
+// 2^32, so no 32-bit sum wraps.  Wide mode: each square in 32 bits (d^2 <
+// 2^32), added into 64-bit sums.  Terms outside the overlap domain (a frame
+// column or row outside the frame, a template column past n) are masked to
+// zero; a frame row outside the frame is skipped as a whole.  Partial sums go
+// to [frame][band*ncw + cw][9] as exact FP64 integers.
+constexpr int kRollMinRows = 8;
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
+
+// Operands of one frame row: x[2v+p] holds the frame columns that template
+// columns j0+2p, j0+2p+1 meet under column shift 2t*+v-1, i.e. columns
+// j0+2t*+v-1+2p and one more, with masked terms zeroed.
+struct RollRow {
+    uint32_t x[6];
+};
+
+template <bool MASK>
+__device__ __forceinline__ void roll_join(const uint32_t p[4], RollRow &r,
+                                          const uint32_t (&mk)[3][2])
+{
+    // p[k] holds columns (c, c+1) with c = j0+2t*-2+2k; X[k] holds columns
+    // j0+2t*-1+k and j0+2t*+k
+    uint32_t X[5];
+    X[0] = __builtin_amdgcn_alignbyte(p[1], p[0], 2);
+    X[1] = p[1];
+    X[2] = __builtin_amdgcn_alignbyte(p[2], p[1], 2);
+    X[3] = p[2];
+    X[4] = __builtin_amdgcn_alignbyte(p[3], p[2], 2);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) r.x[2 * v + pr] = MASK ? X[v + 2 * pr] & mk[v][pr] : X[v + 2 * pr];
+}
+
+__device__ __forceinline__ uint32_t sub_u16x2(uint32_t f, uint32_t b)
+{
+    short2v d = __builtin_bit_cast(short2v, f) - __builtin_bit_cast(short2v, b);
+    return __builtin_bit_cast(uint32_t, d);
+}
+
+__device__ __forceinline__ int sqr_acc(uint32_t d, int acc)
+{
+    short2v v = __builtin_bit_cast(short2v, d);
+    return __builtin_amdgcn_sdot2(v, v, acc, false);
+}
+
+// MODE 0: narrow, no flush inside the band; 1: narrow with flushes; 2: wide
+template <bool MASK, int MODE>
+__device__ __forceinline__ void roll_rows(const uint16_t *__restrict__ fb,
+                                          const uint16_t *__restrict__ tmpl, int m, int n, int i0,
+                                          int i1, int S0, int j0, int c0, int flush, bool wide_ok,
+                                          const uint32_t (&mk)[3][2], unsigned long long (&acc)[9])
+{
+    int acc32[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc32[q] = 0;
+    auto load_frame = [&](int r, uint32_t (&p)[4]) {
+        if (r >= 0 && r < m) {
+            const char *row = (const char *)(fb + (size_t)r * n);
+            if (!MASK) {
+                const u32x4a q = *(const u32x4a *)(row + 2u * (unsigned)(c0 - 1));
+                p[0] = q.x;
+                p[1] = q.y;
+                p[2] = q.z;
+                p[3] = q.w;
+            } else if (r > 0 && r < m - 1 && wide_ok) {
+                // may run into the rows before and after: in the frame, masked
+                const u32x4a q = *(const u32x4a *)((const char *)fb +
+                                                   2u * (unsigned)(r * n + c0 - 1));
+                p[0] = q.x;
+                p[1] = q.y;
+                p[2] = q.z;
+                p[3] = q.w;
+            } else {
+                // a dword outside the row (both its columns: n is even) is read
+                // at column 0 instead and masked
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = c0 - 1 + 2 * k;
+                    const int o = (c >= 0 && c + 1 < n) ? c : 0;
+                    p[k] = *(const uint32_t *)(row + 2u * (unsigned)o);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) p[k] = 0;
+        }
+    };
+    auto load_tmpl = [&](int i, uint32_t (&t)[2]) {
+        const char *row = (const char *)(tmpl + (size_t)i * n);
+        if (!MASK || (i < m - 1 && n >= 6)) {
+            // masked lanes (j0 <= n+2) may run into the next row
+            const u32x2a q = *(const u32x2a *)(row + 2u * (unsigned)j0);
+            t[0] = q.x;
+            t[1] = q.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int o = (j0 + 2 * k + 1 < n) ? j0 + 2 * k : 0;
+                t[k] = *(const uint32_t *)(row + 2u * (unsigned)o);
+            }
+        }
+    };
+    uint32_t P[4], TB[2];
+    RollRow R0, R1, R2;
+    load_frame(i0 + S0 - 1, P);
+    roll_join<MASK>(P, R0, mk);
+    load_frame(i0 + S0, P);
+    roll_join<MASK>(P, R1, mk);
+    load_frame(i0 + S0 + 1, P);
+    load_tmpl(i0, TB);
+    int since = 0;
+    // a masked term has both its frame and its template value zeroed
+    auto one = [&](int u, const RollRow &R, const uint32_t (&Bm)[6]) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            if (MODE != 2) {
+                const uint32_t d0 = sub_u16x2(R.x[2 * v], Bm[2 * v]);
+                const uint32_t d1 = sub_u16x2(R.x[2 * v + 1], Bm[2 * v + 1]);
+                acc32[3 * u + v] = sqr_acc(d1, sqr_acc(d0, acc32[3 * u + v]));
+            } else {
+#pragma unroll
+                for (int pr = 0; pr < 2; ++pr) {
+                    const uint32_t fx = R.x[2 * v + pr], bx = Bm[2 * v + pr];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int d = (int)((fx >> (16 * h)) & 0xffffu) -
+                                      (int)((bx >> (16 * h)) & 0xffffu);
+                        acc[3 * u + v] += (unsigned)d * (unsigned)d;
+                    }
+                }
+            }
+        }
+    };
+    auto step = [&](int i, const RollRow &ra, const RollRow &rb, RollRow &rc) {
+        roll_join<MASK>(P, rc, mk);  // frame row i+S0+1
+        uint32_t Bm[6];
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int pr = 0; pr < 2; ++pr) Bm[2 * v + pr] = MASK ? TB[pr] & mk[v][pr] : TB[pr];
+        if (i + 1 < i1) {
+            load_frame(i + S0 + 2, P);
+            load_tmpl(i + 1, TB);
+        }
+        if ((unsigned)(i + S0 - 1) < (unsigned)m) one(0, ra, Bm);
+        if ((unsigned)(i + S0) < (unsigned)m) one(1, rb, Bm);
+        if ((unsigned)(i + S0 + 1) < (unsigned)m) one(2, rc, Bm);
+        if (MODE == 1 && ++since == flush) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                acc[q] += (unsigned)acc32[q];
+                acc32[q] = 0;
+            }
+            since = 0;
+        }
+    };
+    for (int i = i0; i < i1; i += 3) {
+        step(i, R0, R1, R2);
+        if (i + 1 < i1) step(i + 1, R1, R2, R0);
+        if (i + 2 < i1) step(i + 2, R2, R0, R1);
+    }
+    if (MODE != 2) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[q] += (unsigned)acc32[q];
+    }
+}
+
+// Per-frame mode: narrow and a single flush at the end of a band of `rows`
+// rows (the fast kernel), else narrow with flushes or wide (the slow kernel).
+__device__ __forceinline__ int roll_flush(const int32_t *pmax, int tmax, int frame)
+{
+    if (!pmax || tmax < 0) return -1;  // wide
+    const long long M = max((long long)pmax[frame], (long long)tmax);
+    if (M > 32767) return -1;
+    return M > 0 ? (int)min(0xffffffffLL / (4 * M * M), (long long)(1 << 30)) : (1 << 30);
+}
+
+// One wave: frame, band of template rows, 64 column groups (`cw`).
+template <bool SLOW>
+__device__ __forceinline__ void roll_unit(const uint16_t *__restrict__ frames,
+                                          const uint16_t *__restrict__ tmpl, int m, int n, int br,
+                                          int ncw, int frame, int unit, int flush,
+                                          const int32_t *__restrict__ coarse_st,
+                                          double *__restrict__ partial, int units)
+{
+    const int lane = threadIdx.x % 64;
+    const int band = unit / ncw, cw = unit % ncw;
+    const int i0 = band * br, i1 = min(m, i0 + br);
+    const bool fast = flush >= i1 - i0;
+    if (fast == SLOW) return;
+    const int S0 = 2 * coarse_st[2 * frame], T0 = 2 * coarse_st[2 * frame + 1];
+    // column groups: with more than one wave per band, wave 0 takes the 32
+    // groups at either end of the row, where the masked terms are, and the
+    // others the middle, so that those read without masks; a lane past the
+    // groups gets group ncg (columns n.. : every term masked)
+    const int ncg = (n + 3) / 4;
+    int g;
+    if (ncw == 1)
+        g = lane;
+    else if (cw == 0)
+        g = lane < 32 ? lane : ncg - 64 + lane;
+    else
+        g = 32 + (cw - 1) * 64 + lane < ncg - 32 ? 32 + (cw - 1) * 64 + lane : ncg;
+    if (g > ncg) g = ncg;
+    const int j0 = 4 * g;
+    const int c0 = j0 + T0 - 1;  // odd: the dword at column c0-1 is aligned
+    uint32_t mk[3][2];
+    bool clean = true;
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+            uint32_t b = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 2 * pr + h, c = c0 + q + v;
+                if (j0 + q < n && c >= 0 && c < n) b |= 0xffffu << (16 * h);
+            }
+            mk[v][pr] = b;
+            clean = clean && b == 0xffffffffu;
+        }
+    const uint16_t *fb = frames + (size_t)frame * m * n;
+    // rows 1..m-2 may be read as one 16-byte span from column j0+2t*-2
+    // (j0 <= n+2) when that stays inside the frame: |2t*| <= n-8
+    const bool wide_ok = abs(T0) + 8 <= n;
+    unsigned long long acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0;
+    if (!SLOW) {
+        if (__all(clean))
+            roll_rows<false, 0>(fb, tmpl, m, n, i0, i1, S0, j0, c0, flush, wide_ok, mk, acc);
+        else
+            roll_rows<true, 0>(fb, tmpl, m, n, i0, i1, S0, j0, c0, flush, wide_ok, mk, acc);
+    } else if (flush > 0) {
+        roll_rows<true, 1>(fb, tmpl, m, n, i0, i1, S0, j0, c0, flush, wide_ok, mk, acc);
+    } else {
+        roll_rows<true, 2>(fb, tmpl, m, n, i0, i1, S0, j0, c0, flush, wide_ok, mk, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        unsigned long long v = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+            lo = __shfl_xor(lo, off);
+            hi = __shfl_xor(hi, off);
+            v += ((unsigned long long)hi << 32) | lo;
+        }
+        acc[q] = v;
+    }
+    if (lane == 0) {
+        double *dst = partial + ((size_t)frame * units + unit) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dst[q] = (double)acc[q];
+    }
+}
+
+// Fast kernel: one wave per (frame, unit); waves of frames in the slow mode
+// return at once.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_refine_roll(
+    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl, int m, int n, int br,
+    int nbr, int ncw, int C, const int32_t *__restrict__ coarse_st,
+    const int32_t *__restrict__ pmax, int tmax, double *__restrict__ partial)
+{
+    const int units = nbr * ncw;
+    const long long wid =
+        (long long)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    if (wid >= (long long)C * units) return;
+    const int frame = (int)(wid / units), unit = (int)(wid % units);
+    roll_unit<false>(frames, tmpl, m, n, br, ncw, frame, unit, roll_flush(pmax, tmax, frame),
+                     coarse_st, partial, units);
+}
+
+// Slow kernel: one block per frame, its waves take the units the fast kernel
+// left (none for most workloads).
+__global__ __launch_bounds__(kBlock) void k_refine_roll_slow(
+    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl, int m, int n, int br,
+    int nbr, int ncw, const int32_t *__restrict__ coarse_st, const int32_t *__restrict__ pmax,
+    int tmax, double *__restrict__ partial)
+{
+    const int units = nbr * ncw, frame = blockIdx.x;
+    const int flush = roll_flush(pmax, tmax, frame);
+    if (flush >= br) return;  // every band of this frame was done by the fast kernel
+    for (int unit = __builtin_amdgcn_readfirstlane(threadIdx.x / 64); unit < units;
+         unit += kBlock / 64)
+        roll_unit<true>(frames, tmpl, m, n, br, ncw, frame, unit, flush, coarse_st, partial, units);
+}
+
 __global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restrict__ partial,
                                                           int C, int nband, int m, int n,
                                                           const int32_t *__restrict__ coarse_st,
@@ -616,13 +920,28 @@ __global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restri
                                                           double *__restrict__ frefine,
                                                           double *__restrict__ gaps)
 {
-    const int frame = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per frame: lanes take every 64th partial, then a fixed tree
+    const int lane = threadIdx.x % 64;
+    const int frame = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
     if (frame >= C) return;
+    double e9[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) e9[q] = 0.0;
+    for (int b = lane; b < nband; b += 64) {
+        const double *src = partial + ((size_t)frame * nband + b) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e9[q] += src[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e9[q] += __shfl_xor(e9[q], off);
+    if (lane != 0) return;
     const int cs = coarse_st[2 * frame], ct = coarse_st[2 * frame + 1];
     Cand c{INFINITY, INT32_MIN, 0, INFINITY};
+#pragma unroll
     for (int q = 0; q < 9; ++q) {
-        double e = 0.0;
-        for (int b = 0; b < nband; ++b) e += partial[((size_t)frame * nband + b) * 9 + q];
+        const double e = e9[q];
         int u = q / 3 - 1, v = q % 3 - 1;
         int s = 2 * cs + u, t = 2 * ct + v;
         double area = (double)(m - abs(s)) * (double)(n - abs(t));
@@ -633,6 +952,14 @@ __global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restri
     shifts[2 * frame] = c.s;
     shifts[2 * frame + 1] = c.t;
     if (gaps) gaps[2 * frame + 1] = c.second - c.f;
+}
+
+void launch_finish(const double *partial, int C, int nunits, const Geom &g,
+                   const int32_t *coarse_st, int32_t *shifts, double *frefine, double *gaps,
+                   hipStream_t st)
+{
+    k_refine_finish<<<(C + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
+        partial, C, nunits, g.m, g.n, coarse_st, shifts, frefine, gaps);
 }
 
 int grid_for(size_t total)
@@ -715,6 +1042,27 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
     clear_stale_error();
     if (C == 0) return hipSuccess;
     const size_t esz = g.dtype == MOCO_U16 ? 2 : 4;
+    if (refine_rolling(g, frames, traw)) {
+        const int br = roll_band_rows(g, C);
+        const int nbr = (g.m + br - 1) / br, ncw = ((g.n + 3) / 4 + 63) / 64;
+        const int units = nbr * ncw;
+        const long long waves = (long long)C * units;
+        const long long blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+        if (blocks > INT32_MAX) return hipErrorInvalidValue;
+        k_refine_roll<<<(unsigned)blocks, kBlock, 0, st>>>((const uint16_t *)frames,
+                                                          (const uint16_t *)traw, g.m, g.n, br,
+                                                          nbr, ncw, C, coarse_st, pmax, tmax,
+                                                          partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_refine_roll_slow<<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
+                                                 g.m, g.n, br, nbr, ncw, coarse_st, pmax, tmax,
+                                                 partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        launch_finish(partial, C, units, g, coarse_st, shifts, frefine, gaps, st);
+        return hipGetLastError();
+    }
     int br = refine_band_rows(g);
     if (g.dtype == MOCO_U16 && refine_u16_banded(g)) {
         const int nband = (g.m + kRefBand - 1) / kRefBand;
@@ -724,9 +1072,7 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                                                g.m, g.n, coarse_st, pmax, tmax, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, nband, g.m, g.n,
-                                                                      coarse_st, shifts, frefine,
-                                                                      gaps);
+        launch_finish(partial, C, nband, g, coarse_st, shifts, frefine, gaps, st);
         return hipGetLastError();
     }
     if (br > 0) {
@@ -743,9 +1089,7 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                                                             coarse_st, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_refine_finish<<<(C + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, C, nband, g.m, g.n,
-                                                                      coarse_st, shifts, frefine,
-                                                                      gaps);
+        launch_finish(partial, C, nband, g, coarse_st, shifts, frefine, gaps, st);
         return hipGetLastError();
     }
     if (g.dtype == MOCO_U16)
@@ -773,13 +1117,40 @@ bool refine_u16_banded(const Geom &g)
     return (size_t)(kRefBand + 2) * g.n * sizeof(uint16_t) + 32 <= 48 * 1024;
 }
 
-size_t refine_partial_bytes(const Geom &g)
+bool refine_rolling(const Geom &g, const void *frames, const void *traw)
+{
+    return g.dtype == MOCO_U16 && g.n % 2 == 0 && ((uintptr_t)frames & 3) == 0 &&
+           ((uintptr_t)traw & 3) == 0;
+}
+
+int roll_band_rows(const Geom &g, int C)
+{
+    // long bands for big stacks (fewer partial sums), short ones for a few
+    // frames so that the launch still spreads over the chip
+    return (long long)C * g.m >= 16384 ? 4 * kRollMinRows : kRollMinRows;
+}
+
+static size_t refine_partial_bytes_fixed(const Geom &g)
 {
     if (g.dtype == MOCO_U16 && refine_u16_banded(g))
         return (size_t)((g.m + kRefBand - 1) / kRefBand) * 9 * sizeof(double);
     int br = refine_band_rows(g);
     if (br <= 0) return 0;
     return (size_t)((g.m + br - 1) / br) * 9 * sizeof(double);
+}
+
+size_t refine_partial_bytes(const Geom &g)
+{
+    // the larger of the rolling layout (shortest bands) and the fixed-band one,
+    // which unaligned buffers fall back to
+    size_t b = refine_partial_bytes_fixed(g);
+    if (g.dtype == MOCO_U16 && g.n % 2 == 0) {
+        const size_t nbr = (size_t)(g.m + kRollMinRows - 1) / kRollMinRows;
+        const size_t ncw = (size_t)((g.n + 3) / 4 + 63) / 64;
+        const size_t r = nbr * ncw * 9 * sizeof(double);
+        if (r > b) b = r;
+    }
+    return b;
 }
 
 }  // namespace moco

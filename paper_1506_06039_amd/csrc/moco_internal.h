@@ -71,6 +71,9 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
 int refine_band_rows(const Geom &g);
 bool refine_u16_banded(const Geom &g);
 size_t refine_partial_bytes(const Geom &g);   // per frame
+// uint16, even n and 4-byte aligned frame/template buffers: the rolling kernel
+bool refine_rolling(const Geom &g, const void *frames, const void *traw);
+int roll_band_rows(const Geom &g, int C);
 
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);

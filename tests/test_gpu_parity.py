@@ -76,6 +76,8 @@ RAGGED = [
     (300, 17, 8, True, "f32", 3),     # tall, odd n, n' = 8 = w
     (130, 262, 40, False, "u16", 2),  # several LDS row tiles, ragged tail
     (2, 2, 1, True, "f32", 3),        # smallest downsampled image
+    (48, 1100, 8, True, "u16", 3),    # wide rows: interior waves of the refine need no masks
+    (40, 1030, 6, True, "u16", 3),    # n % 4 == 2: a template column group half past the edge
 ]
 
 
