@@ -122,10 +122,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="auto", choices=["auto", "fp64", "int8"])
+    ap.add_argument("--form", default="auto", choices=["auto", "fft", "fp64", "int8"])
     ap.add_argument("--frames", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="frames for the oracle baseline (0: 4 per host thread)")
+                    help="frames for the oracle baseline (0: batches of 4 per host thread "
+                         "until --cpu-seconds have passed)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--compare-forms", default="fft,fp64",
+                    help="other correlation forms to time on the same stack (comma list, "
+                         "empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--serve-seconds", type=float, default=2.0,
@@ -229,6 +234,30 @@ def main():
     roof["kernel"] = kname
     roof = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()}
 
+    # the same stack through the other correlation forms (the plain FFT form of the
+    # paper, the direct FP64 sums), same outputs, same protocol
+    forms = {form_ran: {"frames_per_s": round(fps, 2), "ms_per_step": round(ms_per_step, 4)}}
+    for fm in [f for f in args.compare_forms.split(",") if f]:
+        if fm == form_ran:
+            continue
+        try:
+            moco.resolved_form(ctx, tp, fm)
+        except moco.MocoError:
+            forms[fm] = None
+            continue
+        steps = args.steps if fm != "fp64" else max(1, min(args.steps, 3))
+        moco.moco_align(ctx, frames, tp, form=fm, out=out)
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(steps):
+            moco.moco_align(ctx, frames, tp, form=fm, out=out)
+        torch.cuda.synchronize(dev)
+        dt = time.perf_counter() - t
+        forms[fm] = {"frames_per_s": round(T * steps / dt, 2),
+                     "ms_per_step": round(1000.0 * dt / steps, 4), "steps": steps}
+        print("[bench] form %s: %.3f ms/step" % (fm, 1000.0 * dt / steps), file=sys.stderr,
+              flush=True)
+
     # single-frame latency (submit -> result on host)
     lat = []
     one = moco.Result(shifts=out.shifts[:1], fmin=out.fmin[:1], frefine=out.frefine[:1],
@@ -273,6 +302,7 @@ def main():
                    "downsample": DS, "form": form_ran, "template": "frame 0"},
         "roofline": roof,
         "stages": stages,
+        "forms": forms,
         "serving": serving,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
                         "p99": round(float(np.percentile(lat_us, 99)), 1),
@@ -282,10 +312,20 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         nthr = oracle.threads()
-        ns = args.cpu_sample or max(8, 4 * nthr)
-        ns = min(ns, T)
         t = time.perf_counter()
-        orc = oracle.align(frames_np[:ns], tmpl_np, W_WIN, DS)
+        if args.cpu_sample:
+            ns = min(args.cpu_sample, T)
+            orc = oracle.align(frames_np[:ns], tmpl_np, W_WIN, DS)
+        else:
+            # batches of 4 frames per host thread until the time budget is spent
+            parts, ns = [], 0
+            while ns < T and (time.perf_counter() - t) < args.cpu_seconds:
+                nb = min(4 * nthr, T - ns)
+                parts.append(oracle.align(frames_np[ns:ns + nb], tmpl_np, W_WIN, DS))
+                ns += nb
+            orc = oracle.AlignResult(*[np.concatenate([getattr(p, f) for p in parts])
+                                       for f in ("coarse", "shifts", "fmin", "gap_c", "frefine",
+                                                 "gap_r", "kappa")], None)
         dt = time.perf_counter() - t
         result["cpu_baseline"] = {
             "value": round(ns / dt, 3), "unit": "frames/s", "cores": nthr, "kind": "oracle",

@@ -62,7 +62,11 @@ typedef enum {
  * energy split of sec. 2) is computed.  Every form computes the same f. */
 typedef enum {
     MOCO_FORM_AUTO = 0,       /* library choice: MOCO_FORM_INT8_MFMA for uint16 when it
-                                 applies, else MOCO_FORM_FP64_EXACT */
+                                 applies, else MOCO_FORM_FFT when it applies, else
+                                 MOCO_FORM_FP64_EXACT */
+    MOCO_FORM_FFT = 1,        /* h from FP64 complex transforms of the zero-padded grids
+                                 (sec. 2, the FFT construction of h), transform lengths
+                                 5-smooth and at most 2048; f to about 1e-12 relative */
     MOCO_FORM_FP64_EXACT = 3, /* direct FP64 sums on the vector ALUs; bit-exact f for uint16 */
     MOCO_FORM_INT8_MFMA = 4   /* uint16 only: exact integer correlation on int8 matrix
                                  cores (balanced base-256 limbs); bit-exact f */
@@ -151,7 +155,9 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
  * MOCO_FORM_AUTO resolves to MOCO_FORM_INT8_MFMA when that form applies to the
  * template (uint16 data, searched grid of fewer than 131072 pixels and at most
  * 2048 columns, w <= 512, template grid values within two balanced base-256
- * digits, i.e. |value| <= 32639), else to MOCO_FORM_FP64_EXACT.
+ * digits, i.e. |value| <= 32639), else to MOCO_FORM_FFT when the transform
+ * lengths (5-smooth, at least m'+w-1 by n'+w-1) are at most 2048, else to
+ * MOCO_FORM_FP64_EXACT.
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
 

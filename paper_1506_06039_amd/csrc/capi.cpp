@@ -116,18 +116,19 @@ int ensure_scratch(moco_ctx *ctx, size_t bytes, hipStream_t st)
 
 // Per-frame scratch of the FP64 exact form.
 struct ExactLayout {
-    size_t coarse, sat, h, cst, part, total_per_frame;
+    size_t coarse, atab, h, cst, pm, part, total_per_frame;
 };
 
 ExactLayout exact_layout(const moco::Geom &g)
 {
     ExactLayout L;
     L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
-    L.sat = align_up((size_t)(g.mg + 1) * (g.ng + 1) * sizeof(double), 256);
+    L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 2 * sizeof(int32_t);
+    L.pm = sizeof(int32_t);
     L.part = align_up(moco::refine_partial_bytes(g), 8);
-    L.total_per_frame = L.coarse + L.sat + L.h + L.cst + L.part;
+    L.total_per_frame = L.coarse + L.atab + L.h + L.cst + L.pm + L.part;
     return L;
 }
 
@@ -192,6 +193,12 @@ void free_tmpl(moco::Tmpl &t)
     if (t.btab) (void)hipFree(t.btab);
     if (t.i8.tp) (void)hipFree(t.i8.tp);
     if (t.i8.atab) (void)hipFree(t.i8.atab);
+    if (t.fft.twp) (void)hipFree(t.fft.twp);
+    if (t.fft.twq) (void)hipFree(t.fft.twq);
+    if (t.fft.spec) (void)hipFree(t.fft.spec);
+    t.fft.twp = nullptr;
+    t.fft.twq = nullptr;
+    t.fft.spec = nullptr;
     t.raw = nullptr;
     t.coarse = nullptr;
     t.btab = nullptr;
@@ -266,6 +273,55 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
     return rc;
 }
 
+// Twiddle table w_n^k = exp(-2 pi i k/n), k < n, rounded from long double.
+int upload_twiddles(int n, double2 **dst)
+{
+    std::vector<double2> h((size_t)n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < n; ++k) {
+        const long double a = two_pi * (long double)k / (long double)n;
+        h[(size_t)k] = double2{(double)cosl(a), (double)-sinl(a)};
+    }
+    hipError_t e = hipMalloc(dst, (size_t)n * sizeof(double2));
+    if (e == hipSuccess) e = hipMemcpy(*dst, h.data(), (size_t)n * sizeof(double2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MOCO_ENOMEM, "FFT twiddle table: %s", hipGetErrorString(e));
+    return MOCO_OK;
+}
+
+// Prepare the template side of the FFT form: plans, twiddles and the 2-D
+// transform of the zero-padded b'.  Leaves t.fft_ok false when the transform
+// lengths exceed the supported maximum.
+int prepare_fft_template(moco::Tmpl &t, hipStream_t st)
+{
+    const moco::Geom &g = t.g;
+    t.fft_ok = false;
+    if (!moco::fft_applicable(g)) return MOCO_OK;
+    const moco::FftGeom fg = moco::fft_geom(g);
+    moco::FftTmpl &f = t.fft;
+    if (!moco::fft_plan(fg.P, &f.pp) || !moco::fft_plan(fg.Q, &f.pq))
+        return fail(MOCO_EINVAL, "no FFT plan for %dx%d", fg.P, fg.Q);
+    f.qh = fg.qh;
+    int rc = upload_twiddles(fg.P, &f.twp);
+    if (!rc) rc = upload_twiddles(fg.Q, &f.twq);
+    if (rc) return rc;
+    double2 *s1 = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&f.spec, (size_t)fg.qh * fg.P * sizeof(double2))) != hipSuccess ||
+        (e = hipMalloc(&s1, moco::fft_s1_bytes(g))) != hipSuccess) {
+        if (s1) (void)hipFree(s1);
+        return fail(MOCO_ENOMEM, "FFT template allocation: %s", hipGetErrorString(e));
+    }
+    if ((e = moco::launch_fft_rows(t.coarse, 1, g, f, s1, st)) != hipSuccess ||
+        (e = moco::launch_fft_spec(s1, g, f, f.spec, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        (void)hipFree(s1);
+        return fail(MOCO_EDEVICE, "FFT template preparation: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(s1);
+    t.fft_ok = true;
+    return MOCO_OK;
+}
+
 // The int8 pipeline over one stack, in chunks that fit `sbytes` of scratch at
 // `sbase`; every launch goes to stream st.
 int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
@@ -331,11 +387,18 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
     char *base = sbase;
     const moco_dtype dtype = g.dtype;
-    double *coarse = (double *)base;
-    double *sat = (double *)(base + L.coarse * C);
-    double *h = (double *)(base + (L.coarse + L.sat) * C);
-    int32_t *cst = (int32_t *)(base + (L.coarse + L.sat + L.h) * C);
-    double *part = (double *)(base + (L.coarse + L.sat + L.h + L.cst) * C);
+    size_t off = 0;
+    double *coarse = (double *)(base + off);
+    off += L.coarse * C;
+    double *atab = (double *)(base + off);
+    off += L.atab * C;
+    double *h = (double *)(base + off);
+    off += L.h * C;
+    int32_t *cst = (int32_t *)(base + off);
+    off += L.cst * C;
+    int32_t *pm = (int32_t *)(base + off);
+    off += L.pm * C;
+    double *part = (double *)(base + align_up(off, 8));
     const size_t fbytes = (size_t)g.m * g.n * dtype_size(dtype);
     const int W = g.W;
     for (int f0 = 0; f0 < T; f0 += C) {
@@ -347,7 +410,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
-            HIP_TRY(moco::launch_sat_sq(coarse, c, g, sat, st));
+            HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
@@ -355,7 +418,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
-            HIP_TRY(moco::launch_combine(sat, tt.btab, h, c, g,
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g,
                                      out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
                                      out->fmin ? out->fmin + f0 : nullptr,
                                      out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
@@ -370,7 +433,94 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
                                         out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
                                         out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
-                                        st));
+                                        st, pm, tt.pbound));
+        }
+    }
+    return MOCO_OK;
+}
+
+// Per-frame scratch of the FFT form.
+struct FftLayout {
+    size_t coarse, atab, s1, s2, h, cst, pm, part, total_per_frame;
+};
+
+FftLayout fft_layout(const moco::Geom &g)
+{
+    FftLayout L;
+    L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
+    L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
+    L.s1 = align_up(moco::fft_s1_bytes(g), 256);
+    L.s2 = align_up(moco::fft_s2_bytes(g), 256);
+    L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
+    L.cst = 2 * sizeof(int32_t);
+    L.pm = sizeof(int32_t);
+    L.part = align_up(moco::refine_partial_bytes(g), 8);
+    L.total_per_frame = L.coarse + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.part;
+    return L;
+}
+
+// The FFT pipeline over one stack: the exact form's grid, energies, combine
+// and refine around the transform-based correlation.
+int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
+            const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
+            size_t sbytes)
+{
+    FftLayout L = fft_layout(g);
+    int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
+    C = std::min(C, 4096);
+    if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
+    char *base = sbase;
+    const moco_dtype dtype = g.dtype;
+    size_t off = 0;
+    double *coarse = (double *)(base + off);
+    off += L.coarse * C;
+    double *atab = (double *)(base + off);
+    off += L.atab * C;
+    double2 *s1 = (double2 *)(base + off);
+    off += L.s1 * C;
+    double2 *s2 = (double2 *)(base + off);
+    off += L.s2 * C;
+    double *h = (double *)(base + off);
+    off += L.h * C;
+    int32_t *cst = (int32_t *)(base + off);
+    off += L.cst * C;
+    int32_t *pm = (int32_t *)(base + off);
+    off += L.pm * C;
+    double *part = (double *)(base + align_up(off, 8));
+    const size_t fbytes = (size_t)g.m * g.n * dtype_size(dtype);
+    const int W = g.W;
+    for (int f0 = 0; f0 < T; f0 += C) {
+        int c = std::min(C, T - f0);
+        const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
+        int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
+            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+            HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, s1, st));
+            HIP_TRY(moco::launch_fft_corr(s1, c, g, tt.fft, s2, h, st));
+        }
+        {
+            StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g,
+                                     out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
+                                     out->fmin ? out->fmin + f0 : nullptr, coarse_st,
+                                     out->shifts + 2 * (size_t)f0,
+                                     out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
+                                     out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
+        }
+        if (g.ds) {
+            StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
+            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, coarse_st, out->shifts + 2 * (size_t)f0,
+                                        out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
+                                        out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
+                                        st, pm, tt.pbound));
         }
     }
     return MOCO_OK;
@@ -378,8 +528,9 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &tt)
 {
-    return form == MOCO_FORM_INT8_MFMA ? int8_layout(g, tt.i8.npad).total_per_frame
-                                       : exact_layout(g).total_per_frame;
+    if (form == MOCO_FORM_INT8_MFMA) return int8_layout(g, tt.i8.npad).total_per_frame;
+    if (form == MOCO_FORM_FFT) return fft_layout(g).total_per_frame;
+    return exact_layout(g).total_per_frame;
 }
 
 int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
@@ -387,7 +538,17 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
               char *sbase, size_t sbytes)
 {
     if (form == MOCO_FORM_INT8_MFMA) return run_int8(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
+    if (form == MOCO_FORM_FFT) return run_fft(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
     return run_exact(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
+}
+
+// The form AUTO runs: exact integers on matrix cores where they apply, else
+// the transforms, else direct FP64 sums.
+moco_form auto_form(const moco::Tmpl &t)
+{
+    if (t.int8_ok) return MOCO_FORM_INT8_MFMA;
+    if (t.fft_ok) return MOCO_FORM_FFT;
+    return MOCO_FORM_FP64_EXACT;
 }
 
 // Validation shared by moco_align and moco_align_batch; resolves AUTO.
@@ -408,7 +569,8 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "template prepared for (m=%d n=%d w=%d ds=%d dtype=%d), call has "
                     "(m=%d n=%d w=%d ds=%d dtype=%d)",
                     tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
-    if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA)
+    if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA &&
+        form != MOCO_FORM_FFT)
         return fail(MOCO_EINVAL, "unknown form %d", (int)form);
     if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
         return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
@@ -419,7 +581,10 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "the int8 matrix-core form does not apply to this template (needs uint16, "
                     "grid area below 131072, grid width at most 2048 and template values "
                     "within two base-256 digits)");
-    if (form == MOCO_FORM_AUTO) form = tt.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
+    if (form == MOCO_FORM_FFT && !tt.fft_ok)
+        return fail(MOCO_EINVAL, "the FFT form does not apply to this template (transform "
+                                 "lengths above %d)", moco::kFftMaxLen);
+    if (form == MOCO_FORM_AUTO) form = auto_form(tt);
     *resolved = form;
     return MOCO_OK;
 }
@@ -469,13 +634,17 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
     const moco::Tmpl &t = tmpl->t;
     switch (requested) {
     case MOCO_FORM_AUTO:
-        *resolved = t.int8_ok ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FP64_EXACT;
+        *resolved = auto_form(t);
         return MOCO_OK;
     case MOCO_FORM_FP64_EXACT:
         *resolved = requested;
         return MOCO_OK;
     case MOCO_FORM_INT8_MFMA:
         if (!t.int8_ok) return fail(MOCO_EINVAL, "the int8 matrix-core form does not apply");
+        *resolved = requested;
+        return MOCO_OK;
+    case MOCO_FORM_FFT:
+        if (!t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
         *resolved = requested;
         return MOCO_OK;
     default:
@@ -529,34 +698,38 @@ int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype
     moco::Tmpl &t = tp->t;
     t.g = g;
     size_t raw_bytes = (size_t)m * n * dtype_size(dtype);
-    double *sat = nullptr;
+    int32_t *pb = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&](int code) {
-        if (sat) (void)hipStreamSynchronize(st), (void)hipFree(sat);
+        if (pb) (void)hipStreamSynchronize(st), (void)hipFree(pb);
         free_tmpl(t);
         delete tp;
         return code;
     };
+    t.pbound = -1;
+    int32_t pbv = INT32_MAX;
     if ((e = hipMalloc(&t.raw, raw_bytes)) != hipSuccess ||
         (e = hipMalloc(&t.coarse, (size_t)g.mg * g.ng * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&t.btab, (size_t)g.W * g.W * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&sat, (size_t)(g.mg + 1) * (g.ng + 1) * sizeof(double))) != hipSuccess)
+        (e = hipMalloc(&pb, sizeof(int32_t))) != hipSuccess)
         return cleanup(fail(MOCO_ENOMEM, "template allocation failed: %s", hipGetErrorString(e)));
+    // the template's energies over D at (s,t) are its frame-side energies at (-s,-t)
     if ((e = hipMemcpyAsync(t.raw, d_template, raw_bytes, hipMemcpyDeviceToDevice, st)) !=
             hipSuccess ||
         (e = moco::launch_coarse(t.raw, dtype, 1, g, t.coarse, st)) != hipSuccess ||
-        (e = moco::launch_sat_sq(t.coarse, 1, g, sat, st)) != hipSuccess ||
-        (e = moco::launch_btab(sat, g, t.btab, st)) != hipSuccess)
+        (e = moco::launch_energy(t.coarse, 1, g, true, t.btab, pb, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&pbv, pb, sizeof pbv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
         return cleanup(fail(MOCO_EDEVICE, "template preparation failed: %s", hipGetErrorString(e)));
-    // the table of template energies is all that is kept of its SAT
-    if ((e = hipStreamSynchronize(st)) != hipSuccess)
-        return cleanup(fail(MOCO_EDEVICE, "template preparation failed: %s", hipGetErrorString(e)));
-    (void)hipFree(sat);
-    sat = nullptr;
+    (void)hipFree(pb);
+    pb = nullptr;
+    t.pbound = pbv == INT32_MAX ? -1 : pbv;
     if (dtype == MOCO_U16) {
         int rc8 = prepare_int8_template(t, st);
         if (rc8) return cleanup(rc8);
     }
+    int rcf = prepare_fft_template(t, st);
+    if (rcf) return cleanup(rcf);
     *out = tp;
     return MOCO_OK;
 }
@@ -972,7 +1145,8 @@ int moco_server_add_source(moco_server *srv, int source, const void *h_template,
     sc.fbytes = fbytes;
     sc.pf = per_frame_scratch(g, resolved, tp->t);
     const size_t tb = fbytes + (size_t)g.mg * g.ng * 8 + (size_t)g.W * g.W * 16 +
-                      (tp->t.int8_ok ? moco::int8_template_bytes(g) : 0);
+                      (tp->t.int8_ok ? moco::int8_template_bytes(g) : 0) +
+                      (tp->t.fft_ok ? (size_t)tp->t.fft.qh * tp->t.fft.pp.n * sizeof(double2) : 0);
     // larger frames or scratch than the buffers hold: resize once nothing is in flight
     if (fbytes > srv->slot_bytes || sc.pf > srv->pf_max) {
         srv->cv_done.wait(lk, [&] { return srv->pending.empty() && srv->inflight == 0; });

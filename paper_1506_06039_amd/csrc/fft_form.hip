@@ -1,0 +1,431 @@
+// FFT form of the correlation (sec. 2: h from the transforms of the
+// zero-padded frame and template, FP64 complex arithmetic).
+//
+// With P >= m'+w-1 and Q >= n'+w-1, c = IFFT(FFT(a') * conj(FFT(b'))) on the
+// P x Q grid has c[s mod P][t mod Q] = h(s,t) for |s|,|t| <= w-1: the padding
+// keeps every wrapped index in the zero border.  (The paper pads to m+w by n+w
+// and flips b; the conjugate form needs one row and column less.)
+//
+// Three passes per frame, each a batch of one-dimensional transforms held in
+// LDS (mixed-radix Stockham: radices 8, 4, 2, 3, 5, self-sorting, one LDS
+// read and one LDS write of every element per radix pass):
+//   rows    two real grid rows packed as one complex row, length Q; the two
+//           half spectra (Q/2+1 bins) are split off and written bin-major,
+//           S1[k][i];
+//   columns for each bin k, the column S1[k][0..m'), zero-padded to P,
+//           forward; times conj of the template's spectrum; inverse; only the
+//           2w-1 outputs at s mod P are kept, S2[s][k];
+//   rows    two rows of S2, each extended to its Hermitian length-Q spectrum,
+//           packed as one complex row, inverse; the 2w-1 outputs at t mod Q
+//           of the real and imaginary parts are the two rows of h, times
+//           1/(PQ).
+// The template's spectrum is the first two passes without the product and
+// inverse, once per template.
+#include <hip/hip_runtime.h>
+
+#include "moco_internal.h"
+
+namespace moco {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr size_t kLdsBudget = 48 * 1024;  // LDS bytes a block's two buffers may use
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+// a * conj(b)
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b)
+{
+    return {fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y)};
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 rot(double2 a)
+{
+    return INV ? double2{-a.y, a.x} : double2{a.y, -a.x};
+}
+
+// Small DFTs in registers: y_k = sum_q v_q e^{-+2 pi i qk/R} (minus: forward).
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+    __device__ static void run(double2 (&v)[2])
+    {
+        double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+    __device__ static void run(double2 (&v)[4])
+    {
+        double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        double2 t2 = cadd(v[1], v[3]), t3 = rot<INV>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+    __device__ static void run(double2 (&v)[8])
+    {
+        constexpr double h = 0.70710678118654752440;  // sqrt(1/2)
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, INV>::run(e);
+        Dft<4, INV>::run(o);
+        // o_k times e^{-+2 pi i k/8}
+        const double2 o1 = INV ? double2{h * (o[1].x - o[1].y), h * (o[1].x + o[1].y)}
+                               : double2{h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+        const double2 o2 = rot<INV>(o[2]);
+        const double2 o3 = INV ? double2{-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y)}
+                               : double2{h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+    __device__ static void run(double2 (&v)[3])
+    {
+        constexpr double r3 = 0.86602540378443864676;  // sqrt(3)/2
+        const double2 t1 = cadd(v[1], v[2]);
+        const double2 t2 = {v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y};
+        const double2 d = rot<INV>(cscale(csub(v[1], v[2]), r3));
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, d);
+        v[2] = csub(t2, d);
+    }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+    __device__ static void run(double2 (&v)[5])
+    {
+        constexpr double c1 = 0.30901699437494742410;   // cos(2 pi/5) = (sqrt 5 - 1)/4
+        constexpr double c2 = -0.80901699437494742410;  // cos(4 pi/5) = -(sqrt 5 + 1)/4
+        constexpr double s1 = 0.95105651629515357212;   // sin(2 pi/5)
+        constexpr double s2 = 0.58778525229247312917;   // sin(4 pi/5)
+        const double2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+        const double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+        const double2 p1 = {v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y};
+        const double2 p2 = {v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y};
+        // -+i (s1 d1 + s2 d2) and -+i (s2 d1 - s1 d2)
+        const double2 q1 = rot<INV>(double2{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
+        const double2 q2 = rot<INV>(double2{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
+        v[0] = cadd(v[0], cadd(b1, b2));
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    }
+};
+
+__device__ __forceinline__ int divq(int x, unsigned long long mag)
+{
+    // floor(x / d) for mag = ceil(2^32 / d), exact while x * d < 2^32
+    return (int)(((unsigned long long)(unsigned)x * mag) >> 32);
+}
+
+// One Stockham pass of radix R over `rows` rows of length N: butterfly j
+// (0 <= j < N/R) reads in[j + r N/R], r < R, twiddles them by w_N^{r (j mod
+// Ns) N/(Ns R)}, transforms and writes out[(j div Ns) Ns R + (j mod Ns) + r Ns].
+template <int R, bool INV>
+__device__ __forceinline__ void fft_pass(const double2 *in, double2 *out, int rows, int N, int Ns,
+                                         unsigned long long mag_nr, unsigned long long mag_ns,
+                                         const double2 *__restrict__ tw)
+{
+    const int NR = N / R;
+    const int stw = N / (Ns * R);
+    const int total = rows * NR;
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        const int row = divq(idx, mag_nr), j = idx - row * NR;
+        const int jq = divq(j, mag_ns), jm = j - jq * Ns;
+        const double2 *src = in + row * N + j;
+        double2 v[R];
+        v[0] = src[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const double2 x = src[r * NR];
+            double2 t = tw[r * jm * stw];
+            if (INV) t.y = -t.y;
+            v[r] = cmul(x, t);
+        }
+        Dft<R, INV>::run(v);
+        double2 *dst = out + row * N + jq * Ns * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r * Ns] = v[r];
+    }
+}
+
+// Transform `rows` rows held in a; b is the other buffer.  Returns the buffer
+// that holds the result.  Ends with a barrier.
+template <bool INV>
+__device__ double2 *fft_lds(double2 *a, double2 *b, int rows, const FftPlan &pl,
+                            const double2 *__restrict__ tw)
+{
+    for (int p = 0; p < pl.npass; ++p) {
+        switch (pl.radix[p]) {
+        case 8: fft_pass<8, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
+        case 4: fft_pass<4, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
+        case 2: fft_pass<2, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
+        case 3: fft_pass<3, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
+        default: fft_pass<5, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
+        }
+        __syncthreads();
+        double2 *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Pass 1: rows.  Block (group of rp row pairs, frame).  grid: mg x ng FP64 per
+// frame.  s1: [frame][qh][mg] complex.
+__global__ __launch_bounds__(kBlock) void k_fft_rows(const double *__restrict__ grid, int mg,
+                                                     int ng, int rp, FftPlan pq,
+                                                     const double2 *__restrict__ twq,
+                                                     double2 *__restrict__ s1)
+{
+    extern __shared__ double2 lds[];
+    const int Q = pq.n, qh = Q / 2 + 1;
+    const int npairs = (mg + 1) / 2;
+    const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
+    const double *a = grid + (size_t)blockIdx.y * mg * ng;
+    double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
+    for (int pr = 0; pr < np; ++pr) {
+        const int r = 2 * (pair0 + pr);
+        const double *x = a + (size_t)r * ng;
+        const double *y = r + 1 < mg ? x + ng : nullptr;
+        for (int j = threadIdx.x; j < Q; j += kBlock)
+            bufa[pr * Q + j] = j < ng ? double2{x[j], y ? y[j] : 0.0} : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    const double2 *z = fft_lds<false>(bufa, bufb, np, pq, twq);
+    // Z = X + iY with X, Y the spectra of the real rows r, r+1:
+    // X_k = (Z_k + conj Z_{-k})/2, Y_k = (Z_k - conj Z_{-k})/(2i)
+    double2 *out = s1 + (size_t)blockIdx.y * qh * mg;
+    for (int idx = threadIdx.x; idx < np * qh; idx += kBlock) {
+        const int k = idx / np, pr = idx - k * np;
+        const double2 zk = z[pr * Q + k], zc = z[pr * Q + (k == 0 ? 0 : Q - k)];
+        const int r = 2 * (pair0 + pr);
+        out[(size_t)k * mg + r] = double2{0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y)};
+        if (r + 1 < mg) out[(size_t)k * mg + r + 1] = double2{0.5 * (zk.y + zc.y), 0.5 * (zc.x - zk.x)};
+    }
+}
+
+// Pass 2: columns.  Block (group of kb bins, frame).  SPEC: write the full
+// column transforms to spec[k][p] (the template).  Otherwise multiply by
+// conj(spec), inverse, keep s = -(w-1) .. w-1 into s2[frame][s+w-1][k].
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_fft_cols(const double2 *__restrict__ s1, int mg,
+                                                     int qh, int kb, int w, FftPlan pp,
+                                                     const double2 *__restrict__ twp,
+                                                     double2 *__restrict__ spec,
+                                                     double2 *__restrict__ s2)
+{
+    extern __shared__ double2 lds[];
+    const int P = pp.n;
+    const int k0 = blockIdx.x * kb, nk = min(kb, qh - k0);
+    const double2 *col = s1 + (size_t)blockIdx.y * qh * mg + (size_t)k0 * mg;
+    double2 *bufa = lds, *bufb = lds + (size_t)kb * P;
+    for (int kk = 0; kk < nk; ++kk)
+        for (int p = threadIdx.x; p < P; p += kBlock)
+            bufa[kk * P + p] = p < mg ? col[(size_t)kk * mg + p] : double2{0.0, 0.0};
+    __syncthreads();
+    double2 *v = fft_lds<false>(bufa, bufb, nk, pp, twp);
+    if (SPEC) {
+        for (int kk = 0; kk < nk; ++kk)
+            for (int p = threadIdx.x; p < P; p += kBlock)
+                spec[(size_t)(k0 + kk) * P + p] = v[kk * P + p];
+        return;
+    }
+    for (int kk = 0; kk < nk; ++kk)
+        for (int p = threadIdx.x; p < P; p += kBlock)
+            v[kk * P + p] = cmulc(v[kk * P + p], spec[(size_t)(k0 + kk) * P + p]);
+    __syncthreads();
+    double2 *u = fft_lds<true>(v, v == bufa ? bufb : bufa, nk, pp, twp);
+    const int W = 2 * w - 1;
+    double2 *out = s2 + (size_t)blockIdx.y * W * qh;
+    for (int idx = threadIdx.x; idx < W * nk; idx += kBlock) {
+        const int si = idx / nk, kk = idx - si * nk;
+        const int s = si - (w - 1);
+        out[(size_t)si * qh + k0 + kk] = u[kk * P + (s < 0 ? s + P : s)];
+    }
+}
+
+// Pass 3: rows back.  Block (group of rp pairs of shift rows, frame).  Rows
+// si, si+1 of s2 are half spectra of real rows; Z = X + iY over the full
+// length Q, inverse; h[si][t] = Re z_t / PQ, h[si+1][t] = Im z_t / PQ.
+__global__ __launch_bounds__(kBlock) void k_fft_rows_back(const double2 *__restrict__ s2, int qh,
+                                                          int w, int rp, double scale,
+                                                          FftPlan pq,
+                                                          const double2 *__restrict__ twq,
+                                                          double *__restrict__ h)
+{
+    extern __shared__ double2 lds[];
+    const int Q = pq.n, W = 2 * w - 1;
+    const int npairs = (W + 1) / 2;
+    const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
+    const double2 *src = s2 + (size_t)blockIdx.y * W * qh;
+    double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
+    for (int pr = 0; pr < np; ++pr) {
+        const int si = 2 * (pair0 + pr);
+        const double2 *x = src + (size_t)si * qh;
+        const double2 *y = si + 1 < W ? x + qh : nullptr;
+        for (int k = threadIdx.x; k < Q; k += kBlock) {
+            // X_k for k >= qh is conj X_{Q-k}
+            const bool lo = k < qh;
+            const int kk = lo ? k : Q - k;
+            double2 X = x[kk], Y = y ? y[kk] : double2{0.0, 0.0};
+            if (!lo) {
+                X.y = -X.y;
+                Y.y = -Y.y;
+            }
+            bufa[pr * Q + k] = double2{X.x - Y.y, X.y + Y.x};
+        }
+    }
+    __syncthreads();
+    const double2 *z = fft_lds<true>(bufa, bufb, np, pq, twq);
+    double *out = h + (size_t)blockIdx.y * W * W;
+    for (int idx = threadIdx.x; idx < np * W; idx += kBlock) {
+        const int pr = idx / W, ti = idx - pr * W;
+        const int t = ti - (w - 1);
+        const double2 v = z[pr * Q + (t < 0 ? t + Q : t)];
+        const int si = 2 * (pair0 + pr);
+        out[(size_t)si * W + ti] = v.x * scale;
+        if (si + 1 < W) out[(size_t)(si + 1) * W + ti] = v.y * scale;
+    }
+}
+
+int rows_per_block(int n)
+{
+    int r = (int)(kLdsBudget / (2 * (size_t)n * sizeof(double2)));
+    return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
+
+}  // namespace
+
+// ---- host side ------------------------------------------------------------
+
+static bool smooth235(int x)
+{
+    for (int p : {2, 3, 5})
+        while (x % p == 0) x /= p;
+    return x == 1;
+}
+
+static int next_smooth(int x)
+{
+    if (x < 2) x = 2;
+    while (!smooth235(x)) ++x;
+    return x;
+}
+
+bool fft_plan(int n, FftPlan *pl)
+{
+    if (n < 2 || n > kFftMaxLen || !smooth235(n)) return false;
+    FftPlan p{};
+    p.n = n;
+    int rem = n, ns = 1;
+    auto add = [&](int r) {
+        p.radix[p.npass] = r;
+        p.ns[p.npass] = ns;
+        const unsigned long long nr = (unsigned long long)(n / r);
+        p.mag_nr[p.npass] = ((1ULL << 32) + nr - 1) / nr;
+        p.mag_ns[p.npass] = ((1ULL << 32) + ns - 1) / ns;
+        ++p.npass;
+        ns *= r;
+        rem /= r;
+    };
+    while (rem % 8 == 0) add(8);
+    while (rem % 4 == 0) add(4);
+    while (rem % 2 == 0) add(2);
+    while (rem % 3 == 0) add(3);
+    while (rem % 5 == 0) add(5);
+    *pl = p;
+    return true;
+}
+
+FftGeom fft_geom(const Geom &g)
+{
+    FftGeom f{};
+    f.P = next_smooth(g.mg + g.w - 1);
+    f.Q = next_smooth(g.ng + g.w - 1);
+    f.qh = f.Q / 2 + 1;
+    return f;
+}
+
+bool fft_applicable(const Geom &g)
+{
+    const FftGeom f = fft_geom(g);
+    return f.P <= kFftMaxLen && f.Q <= kFftMaxLen;
+}
+
+size_t fft_s1_bytes(const Geom &g) { return (size_t)fft_geom(g).qh * g.mg * sizeof(double2); }
+
+size_t fft_s2_bytes(const Geom &g) { return (size_t)g.W * fft_geom(g).qh * sizeof(double2); }
+
+hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
+                           double2 *s1, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const int rp = rows_per_block(ft.pq.n);
+    const int npairs = (g.mg + 1) / 2;
+    const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
+    k_fft_rows<<<dim3((npairs + rp - 1) / rp, C), kBlock, lds, st>>>(grid, g.mg, g.ng, rp, ft.pq,
+                                                                    ft.twq, s1);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
+                           hipStream_t st)
+{
+    clear_stale_error();
+    const int kb = rows_per_block(ft.pp.n);
+    const size_t lds = 2 * (size_t)kb * ft.pp.n * sizeof(double2);
+    k_fft_cols<true><<<dim3((ft.qh + kb - 1) / kb, 1), kBlock, lds, st>>>(
+        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, spec, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
+                           double2 *s2, double *h, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const int kb = rows_per_block(ft.pp.n);
+    const size_t ldsc = 2 * (size_t)kb * ft.pp.n * sizeof(double2);
+    k_fft_cols<false><<<dim3((ft.qh + kb - 1) / kb, C), kBlock, ldsc, st>>>(
+        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, ft.spec, s2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rp = rows_per_block(ft.pq.n);
+    const int npairs = (g.W + 1) / 2;
+    const size_t ldsr = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
+    const double scale = 1.0 / ((double)ft.pp.n * (double)ft.pq.n);
+    k_fft_rows_back<<<dim3((npairs + rp - 1) / rp, C), kBlock, ldsr, st>>>(
+        s2, ft.qh, g.w, rp, scale, ft.pq, ft.twq, h);
+    return hipGetLastError();
+}
+
+}  // namespace moco

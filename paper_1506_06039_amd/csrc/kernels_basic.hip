@@ -121,53 +121,135 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const T *__restrict__ fr, int
     }
 }
 
-// Summed-area table of squares: P is (mg+1) x (ng+1), P[0][*] = P[*][0] = 0,
-// P[i+1][j+1] = sum of x^2 over rows <= i, cols <= j.  One block per frame.
-__global__ __launch_bounds__(kBlock) void k_sat_sq(const double *__restrict__ coarse, int mg,
-                                                   int ng, double *__restrict__ sat)
+// Exclusive prefix sums out[k] = v[0] + ... + v[k-1], k = 0..n (n <= 2*kBlock),
+// in a fixed order: pairs per thread, a shuffle scan per wave, wave carries.
+// Every thread of the block must call it; it starts and ends with a barrier.
+__device__ void block_excl_scan(const double *v, double *out, int n, double *wsum)
 {
-    const double *a = coarse + (size_t)blockIdx.x * mg * ng;
-    double *P = sat + (size_t)blockIdx.x * (mg + 1) * (ng + 1);
-    const int ld = ng + 1;
-    for (int j = threadIdx.x; j <= ng; j += blockDim.x) P[j] = 0.0;
-    for (int i = threadIdx.x; i < mg; i += blockDim.x) {
-        P[(size_t)(i + 1) * ld] = 0.0;
-        double acc = 0.0;
-        const double *row = a + (size_t)i * ng;
-        for (int j = 0; j < ng; ++j) {
-            acc += row[j] * row[j];
-            P[(size_t)(i + 1) * ld + j + 1] = acc;
-        }
-    }
     __syncthreads();
-    for (int j = threadIdx.x; j < ng; j += blockDim.x) {
-        double acc = 0.0;
+    const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+    const double x0 = 2 * t < n ? v[2 * t] : 0.0, x1 = 2 * t + 1 < n ? v[2 * t + 1] : 0.0;
+    const double l = x0 + x1;
+    double inc = l;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    double carry = 0.0;
+    for (int k = 0; k < wave; ++k) carry += wsum[k];
+    const double ex = carry + (inc - l);
+    if (2 * t <= n) out[2 * t] = ex;
+    if (2 * t + 1 <= n) out[2 * t + 1] = ex + x0;
+    __syncthreads();
+}
+
+// Frame overlap energies A(s,t) = sum of a'^2 over rows [max(0,s), mg-1+min(0,s)]
+// and columns [max(0,t), ng-1+min(0,t)] (the frame side of D at (s,t)), for
+// |s|,|t| <= w-1, written [s+w-1][t+w-1].  One block per frame, one pass of
+// coalesced column sums over the grid, then only its border: with E = w-1,
+//   A = total - (rows cut at the top or bottom) - (columns cut at the left or
+//       right) + (the corner block cut twice),
+// from the row sums of the E border rows at either end, the column sums of
+// the E border columns at either side, and for each corner the 2-D prefix
+// sums of its E x E block (a running column sum per row, scanned along the
+// row).  All sums run in a fixed order.  flip: write A(s,t) at [-s+w-1][-t+w-1]
+// instead (the template's energies over D at (s,t) are its A at (-s,-t)).
+// pmax (may be null): per frame,
+// ceil(pscale * largest grid value), the pixel bound the x2 step uses, or
+// INT32_MAX when pscale is 0.
+__global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ grid, int mg,
+                                                   int ng, int w, bool flip,
+                                                   double *__restrict__ atab,
+                                                   int32_t *__restrict__ pmax, double pscale)
+{
+    extern __shared__ double elds[];
+    const int E = w - 1, W = 2 * w - 1;
+    double *colL = elds, *colR = colL + (E + 1), *rowT = colR + (E + 1), *rowB = rowT + (E + 1);
+    double *CL = rowB + (E + 1), *CR = CL + (E + 1), *RT = CR + (E + 1), *RB = RT + (E + 1);
+    double *cp = RB + (E + 1), *ks = cp + (E + 1), *red = ks + (E + 2);
+    __shared__ double wsum[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const double *a = grid + (size_t)blockIdx.x * mg * ng;
+    double *A = atab + (size_t)blockIdx.x * W * W;
+
+    // column sums (every column: the total; border columns kept) and the maximum
+    double tot = 0.0, mx = 0.0;
+    for (int j = tid; j < ng; j += kBlock) {
+        double cs = 0.0, cm = 0.0;
         for (int i = 0; i < mg; ++i) {
-            size_t k = (size_t)(i + 1) * ld + j + 1;
-            acc += P[k];
-            P[k] = acc;
+            const double x = a[(size_t)i * ng + j];
+            cs = fma(x, x, cs);
+            cm = fmax(cm, x);
+        }
+        tot += cs;
+        mx = fmax(mx, cm);
+        if (j < E) colL[j] = cs;
+        if (j >= ng - E) colR[ng - 1 - j] = cs;
+    }
+    // border row sums, one wave per row
+    for (int rr = wave; rr < 2 * E; rr += kBlock / 64) {
+        const int i = rr < E ? rr : mg - 1 - (rr - E);
+        double rs = 0.0;
+        for (int j = lane; j < ng; j += 64) {
+            const double x = a[(size_t)i * ng + j];
+            rs = fma(x, x, rs);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off);
+        if (lane == 0) {
+            if (rr < E)
+                rowT[rr] = rs;
+            else
+                rowB[rr - E] = rs;
         }
     }
-}
+    red[tid] = tot;
+    red[kBlock + tid] = mx;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            red[tid] += red[tid + off];
+            red[kBlock + tid] = fmax(red[kBlock + tid], red[kBlock + tid + off]);
+        }
+        __syncthreads();
+    }
+    tot = red[0];
+    if (pmax && tid == 0) {
+        const double b = ceil(pscale * red[kBlock]);
+        pmax[blockIdx.x] = (pscale > 0.0 && b < 2147483647.0) ? (int32_t)b : INT32_MAX;
+    }
+    block_excl_scan(rowT, RT, E, wsum);
+    block_excl_scan(rowB, RB, E, wsum);
+    block_excl_scan(colL, CL, E, wsum);
+    block_excl_scan(colR, CR, E, wsum);
 
-__device__ inline double rect(const double *P, int ld, int r0, int r1, int c0, int c1)
-{
-    // inclusive rows r0..r1, cols c0..c1 (empty if r1 < r0 or c1 < c0)
-    if (r1 < r0 || c1 < c0) return 0.0;
-    return P[(size_t)(r1 + 1) * ld + c1 + 1] - P[(size_t)r0 * ld + c1 + 1] -
-           P[(size_t)(r1 + 1) * ld + c0] + P[(size_t)r0 * ld + c0];
-}
-
-// Template energies B(s,t): sum of b^2 over rows max(0,-s)..mg-1-max(0,s),
-// cols max(0,-t)..ng-1-max(0,t).
-__global__ __launch_bounds__(kBlock) void k_btab(const double *__restrict__ satb, int mg, int ng,
-                                                 int w, double *__restrict__ btab)
-{
-    const int W = 2 * w - 1;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < W * W; k += gridDim.x * blockDim.x) {
-        int s = k / W - (w - 1), t = k % W - (w - 1);
-        btab[k] = rect(satb, ng + 1, max(0, -s), mg - 1 - max(0, s), max(0, -t),
-                       ng - 1 - max(0, t));
+    // the four corners: bit 1 = rows cut at the bottom (s < 0), bit 0 = columns
+    // cut at the right (t < 0)
+    for (int c = 0; c < 4; ++c) {
+        const bool bottom = c & 2, right = c & 1;
+        for (int j = tid; j < E; j += kBlock) cp[j] = 0.0;
+        for (int s = 0; s <= E; ++s) {
+            if (s > 0) {
+                const int row = bottom ? mg - s : s - 1;
+                for (int j = tid; j < E; j += kBlock) {
+                    const double x = a[(size_t)row * ng + (right ? ng - 1 - j : j)];
+                    cp[j] = fma(x, x, cp[j]);
+                }
+            }
+            block_excl_scan(cp, ks, E, wsum);  // ks[t]: the s x t corner block
+            if (bottom && s == 0) continue;   // s = 0 belongs to the top corners
+            const double rcut = bottom ? RB[s] : RT[s];
+            const int si = (bottom ? -s : s) + E;
+            for (int t = tid + (right ? 1 : 0); t <= E; t += kBlock) {
+                const int ti = (right ? -t : t) + E;
+                const size_t k = (size_t)si * W + ti;
+                A[flip ? (size_t)W * W - 1 - k : k] = ((tot - rcut) - (right ? CR[t] : CL[t])) + ks[t];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -250,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_corr_fp64(const double *__restrict__
 
 // ---------------------------------------------------------------------------
 // Combine, normalise, argmin.  One block per frame.
-__global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ sat,
+__global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ atab,
                                                     const double *__restrict__ btab,
                                                     const double *__restrict__ hbuf, int mg,
                                                     int ng, int w, int ds,
@@ -263,12 +345,12 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ s
 {
     const int W = 2 * w - 1;
     const int frame = blockIdx.x;
-    const double *P = sat + (size_t)frame * (mg + 1) * (ng + 1);
+    const double *At = atab + (size_t)frame * W * W;
     const double *h = hbuf + (size_t)frame * W * W;
     Cand c{INFINITY, INT32_MIN, 0, INFINITY};
     for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
         int s = k / W - (w - 1), t = k % W - (w - 1);
-        double A = rect(P, ng + 1, max(0, s), mg - 1 + min(0, s), max(0, t), ng - 1 + min(0, t));
+        double A = At[k];
         double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
         double f = (A + btab[k] - 2.0 * h[k]) / area;
         if (fsurf) fsurf[(size_t)frame * W * W + k] = f;
@@ -986,21 +1068,6 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
     return hipGetLastError();
 }
 
-hipError_t launch_sat_sq(const double *coarse, int C, const Geom &g, double *sat, hipStream_t st)
-{
-    clear_stale_error();
-    if (C == 0) return hipSuccess;
-    k_sat_sq<<<C, kBlock, 0, st>>>(coarse, g.mg, g.ng, sat);
-    return hipGetLastError();
-}
-
-hipError_t launch_btab(const double *sat_b, const Geom &g, double *btab, hipStream_t st)
-{
-    clear_stale_error();
-    k_btab<<<grid_for((size_t)g.W * g.W), kBlock, 0, st>>>(sat_b, g.mg, g.ng, g.w, btab);
-    return hipGetLastError();
-}
-
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st)
 {
@@ -1023,13 +1090,33 @@ hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, 
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const double *sat, const double *btab, const double *h, int C,
+hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
+                         int32_t *pmax, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    // pixel bound from the grid: a box mean times four bounds its four pixels
+    // (non-negative uint16) when the grid covers every pixel
+    double pscale = 0.0;
+    if (g.dtype == MOCO_U16) {
+        if (!g.ds)
+            pscale = 1.0;
+        else if (g.m % 2 == 0 && g.n % 2 == 0)
+            pscale = 4.0;
+    }
+    const int E = g.w - 1;
+    const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
+    k_energy<<<C, kBlock, lds, st>>>(coarse, g.mg, g.ng, g.w, flip, atab, pmax, pscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
-    k_combine<<<C, kBlock, 0, st>>>(sat, btab, h, g.mg, g.ng, g.w, g.ds, fsurf, fmin, coarse_st,
+    k_combine<<<C, kBlock, 0, st>>>(atab, btab, h, g.mg, g.ng, g.w, g.ds, fsurf, fmin, coarse_st,
                                     shifts, gaps, frefine);
     return hipGetLastError();
 }

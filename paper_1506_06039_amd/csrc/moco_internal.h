@@ -32,14 +32,45 @@ struct Int8Tmpl {
     int npad = 0, padl = 0, trow = 0;
 };
 
+// One-dimensional transform plan: length n = product of the radices, applied
+// in order; ns[p] is the product of the radices before pass p.  mag_* are
+// ceil(2^32 / d) for d = n / radix[p] and d = ns[p] (division by multiply).
+constexpr int kFftMaxLen = 2048;
+constexpr int kFftMaxPass = 16;
+struct FftPlan {
+    int n = 0, npass = 0;
+    int radix[kFftMaxPass];
+    int ns[kFftMaxPass];
+    unsigned long long mag_nr[kFftMaxPass];
+    unsigned long long mag_ns[kFftMaxPass];
+};
+
+// Transform sizes of the FFT form: P >= mg+w-1, Q >= ng+w-1, both 5-smooth;
+// qh = Q/2+1 half-spectrum bins.
+struct FftGeom {
+    int P, Q, qh;
+};
+
+// Template side of the FFT form (device memory owned by the template).
+struct FftTmpl {
+    FftPlan pp, pq;                 // column (length P) and row (length Q) plans
+    int qh = 0;
+    double2 *twp = nullptr;         // w_P^k = exp(-2 pi i k/P), k < P
+    double2 *twq = nullptr;         // w_Q^k, k < Q
+    double2 *spec = nullptr;        // [qh][P] 2-D transform of the zero-padded b'
+};
+
 // Resident, prepared template.  All pointers are device memory owned by it.
 struct Tmpl {
     Geom g;
     void *raw;        // m x n pixels of g.dtype (full resolution, for the x2 refine)
     double *coarse;   // mg x ng FP64 (box mean when ds)
     double *btab;     // W x W: sum of b'^2 over D_{s,t}, [s+w-1][t+w-1]
+    int32_t pbound;   // bound of the template's pixel values (uint16), -1: none
     bool int8_ok;     // the int8 form applies (uint16, template digits fit two planes)
     Int8Tmpl i8;
+    bool fft_ok;      // the FFT form applies (transform lengths within kFftMaxLen)
+    FftTmpl fft;
 };
 
 // Per-frame intermediate results of the coarse search (device).
@@ -57,11 +88,13 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 // All return hipSuccess or the launch error; they only enqueue.
 hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g, double *coarse,
                          hipStream_t st);
-hipError_t launch_sat_sq(const double *coarse, int C, const Geom &g, double *sat, hipStream_t st);
-hipError_t launch_btab(const double *sat_b, const Geom &g, double *btab, hipStream_t st);
+// atab[frame][W][W]: the frame's energies over D at (s,t) ([-s][-t] when flip);
+// pmax[frame] (may be null): a pixel bound for the x2 step (uint16), else INT32_MAX
+hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
+                         int32_t *pmax, hipStream_t st);
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st);
-hipError_t launch_combine(const double *sat, const double *btab, const double *h, int C,
+hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st);
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
@@ -92,5 +125,18 @@ hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, co
                               int C, const Geom &g, double *fsurf, double *fmin,
                               int32_t *coarse_st, int32_t *shifts, double *gaps, double *frefine,
                               hipStream_t st);
+
+// ---- FFT form (fft_form.hip) --------------------------------------------
+bool fft_plan(int n, FftPlan *pl);
+FftGeom fft_geom(const Geom &g);
+bool fft_applicable(const Geom &g);
+size_t fft_s1_bytes(const Geom &g);   // per frame: [qh][mg] complex
+size_t fft_s2_bytes(const Geom &g);   // per frame: [W][qh] complex
+hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
+                           double2 *s1, hipStream_t st);
+hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
+                           hipStream_t st);
+hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
+                           double2 *s2, double *h, hipStream_t st);
 
 }  // namespace moco
