@@ -260,6 +260,9 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
             (e = hipMalloc(&t.i8.atab, (size_t)g.W * g.W * sizeof(long long))) != hipSuccess) {
             rc = fail(MOCO_ENOMEM, "int8 template allocation: %s", hipGetErrorString(e));
         } else if ((e = moco::launch_tpad(limbs, g, t.i8, st)) != hipSuccess ||
+                   (e = hipMemsetAsync(t.i8.tp + moco::int8_template_bytes(g) -
+                                           moco::kInt8ZeroTail,
+                                       0, moco::kInt8ZeroTail, st)) != hipSuccess ||
                    (e = hipMemcpyAsync(t.i8.atab, atab, (size_t)g.W * g.W * sizeof(long long),
                                        hipMemcpyDeviceToDevice, st)) != hipSuccess ||
                    (e = hipStreamSynchronize(st)) != hipSuccess) {

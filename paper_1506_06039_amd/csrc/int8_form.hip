@@ -32,7 +32,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kBlock = 256;
 constexpr int kWaves = 4;
 constexpr int kStrip = 128;          // frame columns per strip
-constexpr int kRowStride = kStrip + 16;  // LDS bytes per ring row (bank offset)
+constexpr int kSlotStride = 2 * kStrip + 16;  // LDS bytes per ring slot: two digit rows + bank offset
 constexpr int kPhases = 8;           // byte-phase copies of each template row
 constexpr int kMaxTrow = 1024;       // template row bytes held per phase and digit
 
@@ -307,6 +307,20 @@ __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, 
     }
 }
 
+// s_waitcnt vmcnt(N) lgkmcnt(0), then s_barrier.  As compiler builtins (not
+// inline asm) the wait is visible to the compiler's own counter tracking, so it
+// adds no waits of its own for transfers this one already covers; the empty
+// asm statements keep memory accesses from moving across.
+template <int N>
+__device__ __forceinline__ void wait_barrier()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // k_corr_int8: block = 4 waves = 4 frames (one per wave), one (s-group,
 // t-group) of NS x NT tiles of 32 shifts.  NPA digit planes of the frame
@@ -317,23 +331,26 @@ __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, 
 // operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
 // (template row i as a Toeplitz operand) from the shared template buffer, four
 // K-chunks of 32 columns, 16 MFMAs per chunk, operands of chunk k+1 loaded
-// before the MFMAs of chunk k.  Template row i+1 streams global -> LDS (no
-// registers) into the other of two statically distinct buffers while row i is
-// in use; the row loop is unrolled by two so that every LDS read provably
-// targets a buffer other than the one being filled.
-template <int NS, int NT, int NPA, int PA0>
+// before the MFMAs of chunk k.  Template row i+2 and frame row i+s_lo+RING+1
+// stream global -> LDS (no registers) while row i is in use, two rows ahead:
+// the template rows rotate through three statically distinct buffers (the row
+// loop is unrolled by three, so every LDS read provably targets a buffer other
+// than the ones being filled), and the wait at the end of a row lets that
+// row's own transfers (a fixed NDMA + NPA per wave) stay in flight.
+template <int NS, int NT, int NPA, int PA0, int NDMA>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
-    const int8_t *__restrict__ tp, int C, int mg, int npad, int trow, int padl, int w,
-    int tgroups, long long *__restrict__ hout)
+    const int8_t *__restrict__ tp, const int8_t *__restrict__ zsrc, int C, int mg, int npad,
+    int trow, int padl, int w, int tgroups, long long *__restrict__ hout)
 {
     constexpr int RING = 32 * NS;     // frame rows an iteration reads
     constexpr int RS = RING + 2;      // ring slots: two rows arrive ahead of use
     constexpr int NACC = NPA * 2;
     constexpr int KC = kStrip / 32;   // MFMA K-chunks per strip (npad is a multiple of kStrip)
-    __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * NPA * RS * kRowStride];
+    __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * RS * kSlotStride];
     __shared__ __attribute__((aligned(16))) int8_t s_tA[2 * kPhases * kMaxTrow];
     __shared__ __attribute__((aligned(16))) int8_t s_tB[2 * kPhases * kMaxTrow];
+    __shared__ __attribute__((aligned(16))) int8_t s_tC[2 * kPhases * kMaxTrow];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int rho = lane % 32, h = lane / 32;
@@ -359,7 +376,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         if (!any) return;
     }
     const int8_t *fl = limbs + (size_t)(live ? frame : 0) * 3 * plane + (size_t)PA0 * plane;
-    int8_t *my_ring = s_ring + (size_t)wave * NPA * RS * kRowStride;
+    int8_t *my_ring = s_ring + (size_t)wave * RS * kSlotStride;
 
     v16i acc[NS][NT][NACC];
 #pragma unroll
@@ -369,48 +386,63 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
 #pragma unroll
             for (int c = 0; c < NACC; ++c) acc[a][b][c] = v16i{0};
 
-    // Frame row r (columns ks..ks+127 of every digit plane) into ring slot
-    // (r - s_lo) mod RS: global -> LDS by eight lanes per plane when the row
-    // exists, zeros written directly otherwise.  Each wave fills its own ring.
+    // Frame row r (columns ks..ks+127 of the digit planes) into ring slot
+    // (r - s_lo) mod RS: one global -> LDS transfer of four bytes per lane, lanes
+    // 0-31 the first plane and 32-63 the second (with one plane, a copy of it
+    // into the slot's unused half).  A row outside the frame (or of a frame past
+    // the stack) comes from the zero block.  Every lane takes part, so each call
+    // is exactly one transfer.  Each wave fills its own ring.
+    //
+    // The compiler cannot tell ring slots apart, so it would wait for every ring
+    // transfer before the next ring read; the slot address goes through an empty
+    // asm so that it does not.  The reads of a row are ordered after its
+    // transfer by the explicit waits: the rows step i reads were all requested
+    // by step i-2 or earlier, and step i-1 ends with every transfer but its own
+    // retired.
     auto ring_fill = [&](int r, int ks) {
         const int slot = (r - s_lo) % RS;
-        if (live && r >= 0 && r < mg) {
-#pragma unroll
-            for (int p = 0; p < NPA; ++p)
-                if (lane < kStrip / 16)
-                    __builtin_amdgcn_global_load_lds(
-                        (const void *)(fl + (size_t)p * plane + (size_t)r * npad + ks + lane * 16),
-                        (__attribute__((address_space(3))) void *)(my_ring +
-                                                                   ((size_t)p * RS + slot) * kRowStride),
-                        16, 0, 0);
-        } else {
-            const int p = lane / 32, off = 4 * (lane % 32);
-            if (p < NPA && off < kStrip)
-                *(int *)(my_ring + ((size_t)p * RS + slot) * kRowStride + off) = 0;
-        }
+        const bool have = live && r >= 0 && r < mg;
+        const int p = NPA == 2 ? lane / 32 : 0;
+        unsigned la = (unsigned)(uintptr_t)(__attribute__((address_space(3))) void *)(
+            my_ring + (size_t)slot * kSlotStride);
+        asm volatile("" : "+v"(la));
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(have ? fl + (size_t)p * plane + (size_t)r * npad + ks + (lane % 32) * 4
+                                : zsrc + (lane % 32) * 4),
+            (__attribute__((address_space(3))) void *)(uintptr_t)la, 4, 0, 0);
     };
+    // template row ti into dst, global -> LDS: wave v moves bytes [v Qw, (v+1) Qw)
+    // of the row (Qw = rowbytes/4) in exactly NDMA transfers of 1 KB with every
+    // lane active.  The last transfer runs up to 1 KB past the quarter: into the
+    // next quarter with the very bytes that wave writes there, or for the last
+    // quarter past the row (inside the buffer: 3 Qw + NDMA KB <= 16 KB; and
+    // inside the template allocation, whose last row is followed by a 1 KB
+    // zero tail), where nothing reads.
     const int rowbytes = 2 * kPhases * trow;      // one template row: both digits, all phases
-    // template row ti into dst, global -> LDS, 1 KB per wave instruction
+    const int qw = rowbytes / kWaves;
     auto dma_row = [&](int ti, int8_t *dst) {
-        const int8_t *src = tp + (size_t)ti * rowbytes;
-        for (int c = wave; c * 1024 < rowbytes; c += kWaves) {
-            if (c * 1024 + lane * 16 < rowbytes)
-                __builtin_amdgcn_global_load_lds(
-                    (const void *)(src + c * 1024 + lane * 16),
-                    (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
-        }
+        const int8_t *src = tp + (size_t)ti * rowbytes + wave * qw;
+#pragma unroll
+        for (int c = 0; c < NDMA; ++c)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(src + c * 1024 + lane * 16),
+                (__attribute__((address_space(3))) void *)(dst + wave * qw + c * 1024), 16, 0, 0);
     };
 
     for (int ks = 0; ks < npad; ks += kStrip) {
-        // rows for i = i_lo and the two that follow: i_lo + s_lo + q, q < RING + 1
+        // rows for i = i_lo and the two that follow: i_lo + s_lo + q, q < RING + 1;
+        // template rows i_lo and i_lo + 1
         for (int q = 0; q <= RING; ++q) ring_fill(i_lo + s_lo + q, ks);
         dma_row(i_lo, s_tA);
-        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        dma_row(i_lo + 1 < i_hi ? i_lo + 1 : i_lo, s_tB);
+        wait_barrier<0>();
 
-        // one template row: MFMAs with row i from tcur while template row i+1 and
-        // frame row i + s_lo + RING + 1 stream in
-        auto step = [&](int i, const int8_t *tcur, int8_t *tnext) {
-            if (i + 1 < i_hi) dma_row(i + 1, tnext);
+        // one template row: MFMAs with row i from tcur while template row i+2
+        // and frame row i + s_lo + RING + 1 (both used two rows later) stream in
+        auto step = [&](int i, const int8_t *tcur, int8_t *tnext2) {
+            // past the last row a transfer still goes out (a valid row into a
+            // buffer no later row reads), keeping the count per row fixed
+            dma_row(i + 2 < i_hi ? i + 2 : i_lo, tnext2);
             ring_fill(i + s_lo + RING + 1, ks);
 
             // operand addresses of K-chunk 0; chunk kc adds kc*32 bytes.  The byte
@@ -420,8 +452,8 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
             for (int st = 0; st < NS; ++st)
 #pragma unroll
                 for (int p = 0; p < NPA; ++p)
-                    abase[st][p] = my_ring +
-                                   ((size_t)p * RS + (i + 32 * st + rho) % RS) * kRowStride + 16 * h;
+                    abase[st][p] = my_ring + (size_t)((i + 32 * st + rho) % RS) * kSlotStride +
+                                   p * kStrip + 16 * h;
             const int8_t *bbase[NT][2];
 #pragma unroll
             for (int tt = 0; tt < NT; ++tt) {
@@ -481,15 +513,22 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                         for (int q = 0; q < 2; ++q) bv[tt][q] = bn[tt][q];
                 }
             }
-            // Both row transfers must have landed, and this wave's LDS reads of tcur
-            // must be done, before the barrier.  The asm also keeps the compiler from
-            // moving memory accesses across the barrier.
-            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            // The transfers of the previous row (row i+1's template row and ring
+            // row) must have landed, and this wave's LDS reads of tcur must be
+            // done, before the barrier; this row's NDMA + 1 transfers may stay in
+            // flight (the load counter retires in order).
+            wait_barrier<NDMA + 1>();
         };
-        for (int i = i_lo; i < i_hi; i += 2) {
-            step(i, s_tA, s_tB);
-            if (i + 1 < i_hi) step(i + 1, s_tB, s_tA);
+        int i = i_lo;
+        for (; i + 2 < i_hi; i += 3) {
+            step(i, s_tA, s_tC);
+            step(i + 1, s_tB, s_tA);
+            step(i + 2, s_tC, s_tB);
         }
+        if (i < i_hi) step(i, s_tA, s_tC);
+        if (i + 1 < i_hi) step(i + 1, s_tB, s_tA);
+        // nothing may still be landing when the next strip refills the buffers
+        wait_barrier<0>();
     }
 
     if (!live) return;
@@ -609,16 +648,31 @@ __global__ __launch_bounds__(kBlock) void k_combine_i64(const long long *__restr
     if (!ds && frefine && tid < 9) frefine[(size_t)frame * 9 + tid] = NAN;
 }
 
-template <int NS, int NT, int NPA, int PA0>
-hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
-                               int C, const Geom &g, long long *h, hipStream_t st)
+template <int NS, int NT, int NPA, int PA0, int NDMA>
+hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
+                            const Geom &g, long long *h, hipStream_t st)
 {
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
     dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups);
-    k_corr_int8<NS, NT, NPA, PA0><<<grid, kBlock, 0, st>>>(
-        limbs, nlimb, tt.tp, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, h);
+    const int8_t *zsrc = tt.tp + (size_t)g.mg * 2 * kPhases * tt.trow;  // zero tail
+    k_corr_int8<NS, NT, NPA, PA0, NDMA><<<grid, kBlock, 0, st>>>(
+        limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, h);
     return hipGetLastError();
+}
+
+template <int NS, int NT, int NPA, int PA0>
+hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
+                               int C, const Geom &g, long long *h, hipStream_t st)
+{
+    // transfers per wave for a quarter of a template row (4 * trow bytes)
+    switch ((4 * tt.trow + 1023) / 1024) {
+    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1>(limbs, nlimb, tt, C, g, h, st);
+    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2>(limbs, nlimb, tt, C, g, h, st);
+    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3>(limbs, nlimb, tt, C, g, h, st);
+    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4>(limbs, nlimb, tt, C, g, h, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int grid_for(size_t total)
@@ -660,7 +714,9 @@ bool int8_applicable(const Geom &g)
 
 size_t int8_template_bytes(const Geom &g)
 {
-    return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow;
+    // the Toeplitz rows, then kInt8ZeroTail zero bytes (the source of frame
+    // rows outside the frame)
+    return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow + kInt8ZeroTail;
 }
 
 template <bool DS>

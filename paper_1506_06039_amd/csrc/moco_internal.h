@@ -111,7 +111,8 @@ int roll_band_rows(const Geom &g, int C);
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);
 bool int8_applicable(const Geom &g);
-size_t int8_template_bytes(const Geom &g);
+size_t int8_template_bytes(const Geom &g);   // Toeplitz rows + kInt8ZeroTail zero bytes
+constexpr size_t kInt8ZeroTail = 1024;
 // nlimb[frame]: digit planes (2 or 3); vmax[frame]: an upper bound of the frame's
 // pixel values (its largest grid value), or INT32_MAX when the grid does not
 // cover every pixel (odd sides when downsampling)
