@@ -48,7 +48,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build()
     lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -71,6 +71,8 @@ def _load():
     lib.oracle_align.restype = c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = c_int
+    lib.oracle_apply.argtypes = [dp, ip, c_int, c_int, c_int, dp, dp]
+    lib.oracle_apply.restype = None
     _lib = lib
     return lib
 
@@ -199,3 +201,17 @@ def align(frames, template, w: int, downsample: bool, want_surface: bool = False
         if want_surface:
             surf[k0:k1] = sf
     return AlignResult(coarse, shifts, fmin, gap_c, frefine, gap_r, kappa, surf)
+
+
+def apply(frames, shifts, want_frames: bool = True):
+    """The corrected stack and its mean image: frame k moved by its (S,T),
+    black (0) outside the overlap with the template, and the FP64 mean of the
+    corrected frames (summed in frame order).  Returns (corrected or None, mean)."""
+    fr = _f64(frames)
+    T, m, n = fr.shape
+    sh = np.ascontiguousarray(np.asarray(shifts), dtype=np.int32).reshape(T, 2)
+    out = np.empty((T, m, n), np.float64) if want_frames else None
+    mean = np.empty((m, n), np.float64)
+    _load().oracle_apply(_dp(fr), _ip(sh), T, m, n, _dp(out) if out is not None else None,
+                         _dp(mean))
+    return out, mean

@@ -280,6 +280,33 @@ int oracle_align(const double *frames, const double *tmpl, int T, int m, int n, 
     return failed ? -1 : 0;
 }
 
+/* The corrected stack and its mean image (sec. 2: every frame moved by its
+ * translation is the motion-corrected video; sec. 3: the mean of the
+ * corrected video, where each frame is black outside the overlap with the
+ * template).  For frame k with shift (S,T): out[k][i][j] = a_k[i+S][j+T] when
+ * 0 <= i+S < m and 0 <= j+T < n, else 0.  mean[i][j] = (sum over k in order of
+ * out[k][i][j]) / T_frames.  out and mean may each be NULL. */
+void oracle_apply(const double *frames, const int32_t *shifts, int T, int m, int n, double *out,
+                  double *mean)
+{
+    const size_t plane = (size_t)m * n;
+    if (mean)
+        for (size_t p = 0; p < plane; ++p) mean[p] = 0.0;
+    for (int k = 0; k < T; ++k) {
+        const double *a = frames + (size_t)k * plane;
+        const int S = shifts[2 * k], Tt = shifts[2 * k + 1];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) {
+                const long long r = (long long)i + S, c = (long long)j + Tt;
+                const double v = (r >= 0 && r < m && c >= 0 && c < n) ? a[r * n + c] : 0.0;
+                if (out) out[(size_t)k * plane + (size_t)i * n + j] = v;
+                if (mean) mean[(size_t)i * n + j] += v;
+            }
+    }
+    if (mean && T > 0)
+        for (size_t p = 0; p < plane; ++p) mean[p] /= (double)T;
+}
+
 /* Number of OpenMP threads a parallel region would use. */
 int oracle_threads(void)
 {

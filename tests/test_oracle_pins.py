@@ -303,3 +303,64 @@ def test_validation_rules():
     assert not oracle.validate(1, 8, 8, 0, 0)       # w < 1
     assert not oracle.validate(1, 8, 8, 2, 2)       # ds not in {0,1}
     assert not oracle.validate(-1, 8, 8, 2, 0)
+
+
+# --- the corrected stack and its mean image (sec. 2, the motion-corrected
+# video; sec. 3, fig. 1 and fig. 2) ------------------------------------------
+
+def test_correction_of_a_rolled_frame_is_the_template_except_where_black():
+    # fig. 1's caption: a corrected frame matches the template except where it
+    # is black.  A noise-free frame roll(b,(S,T)) moved back by (S,T) is b on
+    # the overlap set D_{S,T} (taken literally, 1-based) and 0 on the rest.
+    rng = np.random.default_rng(11)
+    m, n = 9, 13
+    b = _ints(rng, m, n, 1, 200).astype(np.float64)
+    for S, T in [(0, 0), (3, -5), (-4, 2), (8, 12), (-8, -12)]:
+        a = np.roll(b, (S, T), axis=(0, 1))
+        out, mean = oracle.apply(a[None], [[S, T]])
+        D = overlap_set(m, n, S, T)          # 1-based (i', j') with (i'+S, j'+T) inside
+        want = np.zeros((m, n))
+        for (ip, jp) in D:
+            want[ip - 1, jp - 1] = b[ip - 1, jp - 1]
+        assert np.array_equal(out[0], want), (S, T)
+        assert np.array_equal(mean, want)
+
+
+def test_correction_composes_and_beyond_the_frame_is_black():
+    # moving by s1 then s2 equals moving by s1+s2, except where the second move
+    # reads outside the frame; a shift of a whole side or more leaves nothing
+    rng = np.random.default_rng(12)
+    m, n = 11, 7
+    a = _ints(rng, m, n, 1, 99).astype(np.float64)
+    for s1, s2 in [((2, 1), (3, -2)), ((-4, 3), (1, 1)), ((5, -6), (-7, 2))]:
+        c1, _ = oracle.apply(a[None], [s1])
+        c2, _ = oracle.apply(c1, [s2])
+        c12, _ = oracle.apply(a[None], [(s1[0] + s2[0], s1[1] + s2[1])])
+        i = np.arange(m)[:, None] + s2[0]
+        j = np.arange(n)[None, :] + s2[1]
+        inside = (i >= 0) & (i < m) & (j >= 0) & (j < n)
+        assert np.array_equal(c2[0], np.where(inside, c12[0], 0.0)), (s1, s2)
+    for S, T in [(m, 0), (0, -n), (-m - 3, 2 * n)]:
+        c, mean = oracle.apply(a[None], [(S, T)])
+        assert not c.any() and not mean.any()
+
+
+def test_mean_image_of_the_corrected_stack():
+    # fig. 2: the mean of the corrected video.  Integer data keep every sum
+    # exact, so the mean equals the exact rational mean; zero shifts give the
+    # plain mean of the frames.
+    rng = np.random.default_rng(13)
+    T, m, n = 7, 6, 5
+    fr = rng.integers(0, 1000, size=(T, m, n)).astype(np.float64)
+    sh = np.zeros((T, 2), np.int32)
+    _, mean = oracle.apply(fr, sh)
+    from fractions import Fraction
+    for i in range(m):
+        for j in range(n):
+            exact = Fraction(int(fr[:, i, j].sum()), T)
+            assert mean[i, j] == float(exact)
+    sh = rng.integers(-3, 4, size=(T, 2)).astype(np.int32)
+    out, mean = oracle.apply(fr, sh)
+    for i in range(m):
+        for j in range(n):
+            assert mean[i, j] == float(Fraction(int(out[:, i, j].sum()), T))
