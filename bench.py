@@ -30,7 +30,7 @@ WORKLOAD = "poisson512_u16_ds_w32"
 M = N = 512
 W_WIN = 32
 DS = True
-STAGES = ["coarse", "energy", "prep", "corr", "combine", "refine"]
+STAGES = ["coarse", "energy", "prep", "corr", "combine", "refine", "apply"]
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
@@ -128,6 +128,8 @@ def main():
                     help="frames for the oracle baseline (0: batches of 4 per host thread "
                          "until --cpu-seconds have passed)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--apply-steps", type=int, default=5,
+                    help="timed moco_apply runs (corrected stack + mean) on the same stack")
     ap.add_argument("--compare-forms", default="fft,fp64",
                     help="other correlation forms to time on the same stack (comma list, "
                          "empty: none)")
@@ -258,6 +260,26 @@ def main():
         print("[bench] form %s: %.3f ms/step" % (fm, 1000.0 * dt / steps), file=sys.stderr,
               flush=True)
 
+    # the correction itself: corrected stack + mean image from the shifts just
+    # found (HBM-bound: every frame read once and written once)
+    apply_res = None
+    if args.apply_steps > 0:
+        corrected = torch.empty_like(frames)
+        mean_img = torch.empty((M, N), dtype=torch.float64, device=dev)
+        moco.moco_apply(ctx, frames, out.shifts, out=corrected, mean_out=mean_img)
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(args.apply_steps):
+            moco.moco_apply(ctx, frames, out.shifts, out=corrected, mean_out=mean_img)
+        torch.cuda.synchronize(dev)
+        dt = (time.perf_counter() - t) / args.apply_steps
+        nbytes = 2.0 * T * M * N * frames.element_size()
+        apply_res = {"ms": round(1000.0 * dt, 4), "frames_per_s": round(T / dt, 1),
+                     "GB_per_s": round(nbytes / dt / 1e9, 1),
+                     "frac_hbm": round(nbytes / dt / 1e9 / PEAK_HBM_GBS, 4),
+                     "bytes": "one read and one write of every frame"}
+        del corrected
+
     # single-frame latency (submit -> result on host)
     lat = []
     one = moco.Result(shifts=out.shifts[:1], fmin=out.fmin[:1], frefine=out.frefine[:1],
@@ -303,6 +325,7 @@ def main():
         "roofline": roof,
         "stages": stages,
         "forms": forms,
+        "apply": apply_res,
         "serving": serving,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
                         "p99": round(float(np.percentile(lat_us, 99)), 1),

@@ -151,6 +151,25 @@ typedef struct {
 int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
                      int lanes, void *hip_stream);
 
+/* Apply the correction (sec. 2: each frame moved by the translation found for
+ * it is the motion-corrected video; sec. 3, fig. 1 and 2: corrected frames are
+ * black outside their overlap with the template, and the mean of the
+ * corrected video is the check of a correction).
+ *
+ * d_frames: T x m x n row-major (device, `dtype`), d_shifts: T x 2 int32 (S,T)
+ * per frame (device; any values, typically moco_outputs.shifts).  d_out
+ * (device, nullable): T x m x n of `dtype`, out[k][i][j] = frame_k[i+S][j+T]
+ * when 0 <= i+S < m and 0 <= j+T < n, else 0; it must not overlap d_frames.
+ * d_mean (device, nullable): m x n FP64, the mean over the T corrected frames
+ * (sums in frame order within chunks, chunks in order; for uint16 data every
+ * sum is exact and the mean is the correctly rounded quotient).  At least one
+ * of d_out, d_mean.  The mean's partial sums (up to 32 x m x n FP64) use the
+ * context's scratch.  Enqueued on hip_stream; T = 0 is a no-op.
+ * Errors: MOCO_EINVAL, MOCO_ENOMEM (one m x n FP64 plane exceeds the budget),
+ * MOCO_EDEVICE. */
+int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int T, int m, int n,
+               moco_dtype dtype, void *d_out, double *d_mean, void *hip_stream);
+
 /* The correlation form a call with `requested` runs for this template:
  * MOCO_FORM_AUTO resolves to MOCO_FORM_INT8_MFMA when that form applies to the
  * template (uint16 data, searched grid of fewer than 131072 pixels and at most
@@ -220,12 +239,13 @@ int moco_server_destroy(moco_server *srv);
 /* Stage timing (tracing).  Stages of the pipeline, in launch order. */
 typedef enum {
     MOCO_STAGE_COARSE = 0,   /* 2x2 box mean / conversion of the frames */
-    MOCO_STAGE_ENERGY = 1,   /* summed-area tables of squared grid values */
+    MOCO_STAGE_ENERGY = 1,   /* overlap energies of the frames */
     MOCO_STAGE_PREP = 2,     /* int8 form: limb split of the frames */
     MOCO_STAGE_CORR = 3,     /* cross-correlation h */
     MOCO_STAGE_COMBINE = 4,  /* f = (A+B-2h)/Area, argmin, gap */
     MOCO_STAGE_REFINE = 5,   /* nine full-resolution evaluations */
-    MOCO_STAGE_COUNT = 6
+    MOCO_STAGE_APPLY = 6,    /* moco_apply: corrected frames and mean image */
+    MOCO_STAGE_COUNT = 7
 } moco_stage;
 
 /* Turn stage timing on (1) or off (0) for a context.  While on, every stage

@@ -631,6 +631,42 @@ void moco_destroy(moco_ctx *ctx)
     delete ctx;
 }
 
+int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int T, int m, int n,
+               moco_dtype dtype, void *d_out, double *d_mean, void *hip_stream)
+{
+    if (!ctx) return fail(MOCO_EINVAL, "moco_apply: null ctx");
+    if (dtype != MOCO_U16 && dtype != MOCO_F32) return fail(MOCO_EINVAL, "unknown dtype %d", (int)dtype);
+    if (m < 1 || n < 1) return fail(MOCO_EINVAL, "image size %dx%d must be positive", m, n);
+    if ((long long)m * n > (1LL << 30)) return fail(MOCO_EINVAL, "image %dx%d too large", m, n);
+    if (T < 0) return fail(MOCO_EINVAL, "T=%d must be >= 0", T);
+    if (T == 0) return MOCO_OK;
+    if (!d_frames || !d_shifts) return fail(MOCO_EINVAL, "null frames or shifts");
+    if (!d_out && !d_mean) return fail(MOCO_EINVAL, "neither corrected frames nor a mean asked for");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    int kchunk = T;
+    double *partial = nullptr;
+    if (d_mean) {
+        kchunk = moco::apply_chunk_frames(T, m, n, ctx->budget);
+        if (kchunk == 0)
+            return fail(MOCO_ENOMEM, "the mean's partial sums (%zu bytes) exceed the budget %zu",
+                        (size_t)m * n * sizeof(double), ctx->budget);
+        const size_t need = (size_t)((T + kchunk - 1) / kchunk) * m * n * sizeof(double);
+        int rc = ensure_scratch(ctx, need, st);
+        if (rc) return rc;
+        partial = (double *)ctx->scratch;
+    } else if (T > 16) {
+        kchunk = (T + 31) / 32;
+    }
+    {
+        StageTimer tm(ctx, MOCO_STAGE_APPLY, st);
+        HIP_TRY(moco::launch_apply(d_frames, dtype, d_shifts, T, m, n, kchunk, d_out, partial,
+                                   d_mean, st));
+    }
+    return MOCO_OK;
+}
+
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved)
 {
     if (!tmpl || !resolved) return fail(MOCO_EINVAL, "moco_template_form: null argument");

@@ -140,4 +140,14 @@ hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, 
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s2, double *h, hipStream_t st);
 
+// ---- the corrected stack and its mean image (apply.hip) ---------------
+// frames per chunk of the mean's partial sums (0: one chunk of [m][n] FP64
+// partial sums exceeds `budget`)
+int apply_chunk_frames(int T, int m, int n, size_t budget);
+// out (nullable): corrected frames, same dtype; mean (nullable): [m][n] FP64,
+// needs partial: ceil(T/kchunk) x m x n FP64
+hipError_t launch_apply(const void *frames, moco_dtype dt, const int32_t *shifts, int T, int m,
+                        int n, int kchunk, void *out, double *partial, double *mean,
+                        hipStream_t st);
+
 }  // namespace moco

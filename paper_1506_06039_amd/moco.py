@@ -92,6 +92,8 @@ _lib.moco_last_error.argtypes = []
 _lib.moco_last_error.restype = ctypes.c_char_p
 _lib.moco_version.argtypes = []
 _lib.moco_version.restype = ctypes.c_char_p
+_lib.moco_apply.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]
+_lib.moco_apply.restype = _i
 
 
 def _check(rc: int):
@@ -208,6 +210,28 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
     return out
 
 
+def moco_apply(ctx: Context, frames: torch.Tensor, shifts: torch.Tensor, frames_out: bool = True,
+               mean: bool = True, out: torch.Tensor | None = None,
+               mean_out: torch.Tensor | None = None):
+    """The corrected stack (T, m, n), same dtype, black outside each frame's
+    overlap with the template, and its FP64 mean image (m, n); enqueued on the
+    current stream.  Returns (corrected or None, mean or None)."""
+    if not frames.is_cuda or frames.dim() != 3 or not frames.is_contiguous():
+        raise ValueError("frames must be a contiguous 3-D device tensor")
+    T, m, n = frames.shape
+    if shifts.dtype != torch.int32 or tuple(shifts.shape) != (T, 2) or not shifts.is_contiguous():
+        raise ValueError("shifts must be a contiguous (T, 2) int32 tensor")
+    dev = frames.device
+    if frames_out and out is None:
+        out = torch.empty_like(frames)
+    if mean and mean_out is None:
+        mean_out = torch.empty((m, n), dtype=torch.float64, device=dev)
+    _check(_lib.moco_apply(ctx.handle, frames.data_ptr(), shifts.data_ptr(), T, m, n,
+                           _dtype_code(frames), out.data_ptr() if frames_out else None,
+                           mean_out.data_ptr() if mean else None, _stream_handle(dev)))
+    return (out if frames_out else None), (mean_out if mean else None)
+
+
 def _new_result(T: int, W: int, dev, surface: bool) -> Result:
     return Result(
         shifts=torch.empty((T, 2), dtype=torch.int32, device=dev),
@@ -257,7 +281,7 @@ def align(frames: torch.Tensor, template: torch.Tensor, w: int, downsample: bool
     return r
 
 
-STAGE_COUNT = 6
+STAGE_COUNT = 7
 
 
 def profile_enable(ctx: Context, on: bool = True):

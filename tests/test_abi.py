@@ -74,3 +74,11 @@ def test_binding_fails_loudly_without_library(tmp_path):
     r = subprocess.run(["python", "-c", code], capture_output=True, env=env)
     assert r.returncode != 0
     assert b"libmoco.so is not built" in r.stderr
+
+
+def test_apply_rejects_bad_arguments_without_gpu(lib):
+    lib.moco_apply.restype = ctypes.c_int
+    lib.moco_apply.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int] * 4 + [ctypes.c_void_p] * 3
+    assert lib.moco_apply(None, None, None, 1, 8, 8, 1, None, None, None) == -1   # null ctx
+    lib.moco_last_error.restype = ctypes.c_char_p
+    assert b"null" in lib.moco_last_error()
