@@ -67,6 +67,48 @@ def load_traffic(kernel: str, source: str, frames_per_launch: float):
     return per_frame * frames_per_launch
 
 
+# The paper's timing table (sec. 3): stack shapes and moco's seconds on its
+# (unnamed) hardware, with its rules: downsample once iff a side exceeds 256,
+# window min(m', n')/3 on the searched grid.
+PAPER_SHAPES = [(512, 512, 1500, 66.0), (512, 512, 2000, 90.0), (512, 512, 6984, 288.0),
+                (416, 460, 1000, 35.0), (256, 256, 2028, 84.0)]
+
+
+def measure_paper_shapes(moco, ctx, steps: int):
+    """Synthetic Poisson stacks of the paper's shapes, aligned by AUTO (warm-up
+    run, then `steps` timed runs); the paper's seconds beside them are context,
+    not a target (other hardware, real videos)."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    rows = []
+    for k, (m, n, T, paper_s) in enumerate(PAPER_SHAPES):
+        ds = m > 256 or n > 256
+        mg, ng = (m // 2, n // 2) if ds else (m, n)
+        w = min(mg, ng) // 3
+        sc = synth.PoissonScene(m, n, T, seed=100 + k)
+        fr_np = sc.frames(0, T, workers=synth.default_workers())
+        frames = torch.from_numpy(fr_np).to(dev)
+        tp = moco.Template(ctx, torch.from_numpy(fr_np[0].copy()).to(dev), w, ds)
+        res = moco.moco_align(ctx, frames, tp)
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(steps):
+            moco.moco_align(ctx, frames, tp, out=res)
+        torch.cuda.synchronize(dev)
+        dt = (time.perf_counter() - t) / steps
+        rows.append({"shape": "%dx%dx%d" % (m, n, T), "w": w, "downsample": ds,
+                     "form": moco.resolved_form(ctx, tp, "auto"),
+                     "seconds": round(dt, 5), "frames_per_s": round(T / dt, 1),
+                     "paper_seconds": paper_s, "paper_frames_per_s": round(T / paper_s, 2)})
+        print("[bench] paper shape %s w=%d: %.2f ms" % (rows[-1]["shape"], w, 1000 * dt),
+              file=sys.stderr, flush=True)
+        tp.close()
+        del frames, res, fr_np
+        torch.cuda.empty_cache()
+    return rows
+
+
 def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz: float = 30.0):
     """Single-frame serving of the same workload: nsrc sources, each with its own
     resident template (the first frame of its slice of the stack).  Closed loop:
@@ -128,6 +170,8 @@ def main():
                     help="frames for the oracle baseline (0: batches of 4 per host thread "
                          "until --cpu-seconds have passed)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--paper-steps", type=int, default=2,
+                    help="timed runs per shape of the paper's timing table (0: skip)")
     ap.add_argument("--apply-steps", type=int, default=5,
                     help="timed moco_apply runs (corrected stack + mean) on the same stack")
     ap.add_argument("--compare-forms", default="fft,fp64",
@@ -297,6 +341,8 @@ def main():
 
     serving = measure_serving(moco, ctx, frames_np, args.serve_seconds) \
         if args.serve_seconds > 0 else None
+    paper_shapes = measure_paper_shapes(moco, ctx, args.paper_steps) \
+        if args.paper_steps > 0 else None
 
     # rerun the stack once more for the parity sample (the timed outputs were overwritten by
     # the latency loop's first rows)
@@ -327,6 +373,7 @@ def main():
         "forms": forms,
         "apply": apply_res,
         "serving": serving,
+        "paper_shapes": paper_shapes,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
                         "p99": round(float(np.percentile(lat_us, 99)), 1),
                         "frames": 1, "iters": args.latency_iters} if lat_us.size else None),

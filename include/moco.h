@@ -61,8 +61,10 @@ typedef enum {
 /* How the correlation sum of a[i+s][j+t]*b[i][j] (the third term of the
  * energy split of sec. 2) is computed.  Every form computes the same f. */
 typedef enum {
-    MOCO_FORM_AUTO = 0,       /* library choice: MOCO_FORM_INT8_MFMA for uint16 when it
-                                 applies, else MOCO_FORM_FFT when it applies, else
+    MOCO_FORM_AUTO = 0,       /* library choice: of MOCO_FORM_INT8_MFMA (uint16) and
+                                 MOCO_FORM_FFT the one a per-frame time model of the
+                                 template's geometry ranks faster among those that apply
+                                 (int8 for small windows, the FFT for wide ones), else
                                  MOCO_FORM_FP64_EXACT */
     MOCO_FORM_FFT = 1,        /* h from FP64 complex transforms of the zero-padded grids
                                  (sec. 2, the FFT construction of h), transform lengths
@@ -170,13 +172,15 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
 int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int T, int m, int n,
                moco_dtype dtype, void *d_out, double *d_mean, void *hip_stream);
 
-/* The correlation form a call with `requested` runs for this template:
- * MOCO_FORM_AUTO resolves to MOCO_FORM_INT8_MFMA when that form applies to the
- * template (uint16 data, searched grid of fewer than 131072 pixels and at most
- * 2048 columns, w <= 512, template grid values within two balanced base-256
- * digits, i.e. |value| <= 32639), else to MOCO_FORM_FFT when the transform
- * lengths (5-smooth, at least m'+w-1 by n'+w-1) are at most 2048, else to
- * MOCO_FORM_FP64_EXACT.
+/* The correlation form a call with `requested` runs for this template.
+ * MOCO_FORM_INT8_MFMA applies to uint16 templates with a searched grid of fewer
+ * than 131072 pixels and at most 2048 columns, w <= 512, and grid values within
+ * two balanced base-256 digits (|value| <= 32639); MOCO_FORM_FFT applies when
+ * the transform lengths (5-smooth, at least m'+w-1 by n'+w-1) are at most 2048.
+ * MOCO_FORM_AUTO resolves to whichever of the two applies, the one a per-frame
+ * time model ranks faster when both do (the int8 form's work grows with the
+ * (2w-1)^2 shifts, the FFT's with P Q log(P Q): at a 256x256 grid the int8
+ * form for w <= 32, the FFT above), else to MOCO_FORM_FP64_EXACT.
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
 

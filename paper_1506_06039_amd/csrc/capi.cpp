@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -545,10 +546,36 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     return run_exact(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
 }
 
-// The form AUTO runs: exact integers on matrix cores where they apply, else
-// the transforms, else direct FP64 sums.
+// Per-frame time models of the two fast forms (seconds), from their kernels'
+// rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
+// issues 64x64-shift tiles of four digit products at about 2.7e15 ops/s,
+// beside 0.35 us of prep, combine and refine per 512x512 frame; the FFT form's
+// three transform passes took 1.26 us at 288x288 and scale with P Q log2(P Q),
+// beside 0.55 us of grid, energies, combine and refine per 512x512 frame (those
+// parts scale with the frame's pixels).
+double int8_model_s(const moco::Tmpl &t)
+{
+    const moco::Geom &g = t.g;
+    const double groups = std::ceil(g.W / 64.0);
+    const double macs = groups * groups * 64.0 * 64.0 * g.mg * (double)t.i8.npad;
+    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + macs * 4.0 * 2.0 / 2.7e15;
+}
+
+double fft_model_s(const moco::Tmpl &t)
+{
+    const moco::Geom &g = t.g;
+    const double pq = (double)t.fft.pp.n * t.fft.pq.n;
+    const double ref = 288.0 * 288.0 * std::log2(288.0 * 288.0);
+    return 0.55e-6 * ((double)g.m * g.n / 262144.0) + 1.26e-6 * pq * std::log2(pq) / ref;
+}
+
+// The form AUTO runs: the faster of the exact int8 form and the FFT form by
+// the models above when both apply, else whichever applies, else direct FP64
+// sums.
 moco_form auto_form(const moco::Tmpl &t)
 {
+    if (t.int8_ok && t.fft_ok)
+        return int8_model_s(t) <= fft_model_s(t) ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FFT;
     if (t.int8_ok) return MOCO_FORM_INT8_MFMA;
     if (t.fft_ok) return MOCO_FORM_FFT;
     return MOCO_FORM_FP64_EXACT;

@@ -145,3 +145,24 @@ def test_fft_form_resolution(gpu_lib):
     assert gpu_lib.resolved_form(ctx, tp, "auto") == "int8"
     tp.close()
     ctx.close()
+
+
+def test_wide_window_paper_shape_auto_picks_fft(gpu_lib):
+    # the paper's 416x460 stack with its window min(m',n')/3 = 69 on the 208x230
+    # grid: the FFT form is the faster one there; the int8 form (3x3 groups of
+    # 64x64 shift tiles) stays exact
+    sc = synth.PoissonScene(416, 460, 3, seed=7)
+    fr = sc.frames(0, 3)
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(sc.template), 69, True)
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft"
+    tp.close()
+    ctx.close()
+    _say("case paper shape 416x460 w=69 ds=1")
+    orc = oracle.align(fr, sc.template, 69, True, want_surface=True)
+    res = _run(gpu_lib, fr, sc.template, 69, True, form="auto", surface=True)
+    check(res, orc, True, exact=False, label="416x460 auto")
+    check_surface(res["fsurf"], orc.surf, label="416x460 auto surface")
+    ex = _run(gpu_lib, fr, sc.template, 69, True, form="int8", surface=True)
+    check(ex, orc, True, exact=True, label="416x460 int8")
+    check_surface(ex["fsurf"], orc.surf, exact=True, label="416x460 int8 surface")
