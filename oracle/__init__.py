@@ -159,7 +159,7 @@ def align(frames, template, w: int, downsample: bool, want_surface: bool = False
     """
     frames = np.asarray(frames)
     T, m, n = frames.shape
-    ds = 1 if downsample else 0
+    ds = int(downsample)   # levels of 2x2 downsampling (True = 1)
     if not validate(T, m, n, w, ds):
         raise ValueError("invalid search: T=%d m=%d n=%d w=%d ds=%d" % (T, m, n, w, ds))
     tm = _f64(template)

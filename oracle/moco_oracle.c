@@ -17,7 +17,8 @@
  *     inside the m x n image                                          (sec. 2, overlap set)
  *   - the search over every (s,t) with max(|s|,|t|) < w, the argmin,
  *     then the x2 upsampling step that evaluates f at (2s+u, 2t+v),
- *     u,v in {-1,0,1}, on the finer grid and keeps the minimum        (sec. 2, last paragraph)
+ *     u,v in {-1,0,1}, on the finer grid and keeps the minimum, once per
+ *     level of downsampling                                           (sec. 2, last paragraph)
  *   - "downsampled": a 2x2 box mean (the paper names no filter; this is
  *     the reading used throughout), odd trailing row/column dropped.
  *
@@ -141,23 +142,66 @@ typedef struct {
     double kappa;               /* (A+B)/(Area*fmin) at the coarse argmin */
 } oracle_result;
 
-/* Align one frame a against template b (both m x n, FP64).  surf may be NULL.
- * Follows the search of section 2: (optional) downsample both, score every
- * shift of the window, take the argmin, then (if downsampled) one x2 step with
- * nine evaluations at full resolution. */
-static void align_one(const double *a, const double *b, int m, int n, int w, int ds,
-                      double *scratch_a, double *scratch_b, double *surf, oracle_result *r)
+/* Best and second-best of the nine f at (2s+u, 2t+v), u,v in {-1,0,1}, on one
+ * level's images (m x n); f9 (may be NULL) receives the nine values. */
+static void nine(const double *a, const double *b, int m, int n, int s0, int t0, double *f9,
+                 int *bs, int *bt, double *best, double *second)
 {
-    const double *ga = a, *gb = b;
-    int mg = m, ng = n;
-    if (ds) {
-        oracle_downsample(a, m, n, scratch_a);
-        oracle_downsample(b, m, n, scratch_b);
-        ga = scratch_a;
-        gb = scratch_b;
-        mg = m / 2;
-        ng = n / 2;
+    double rb = NAN, rsec = INFINITY;
+    int rs = 0, rt = 0, rhave = 0;
+    for (int u = -1; u <= 1; ++u)
+        for (int v = -1; v <= 1; ++v) {
+            int s = 2 * s0 + u, t = 2 * t0 + v;
+            double f = oracle_f(a, b, m, n, s, t);
+            if (f9) f9[(u + 1) * 3 + (v + 1)] = f;
+            if (!rhave || precedes(f, s, t, rb, rs, rt)) {
+                if (rhave) {
+                    double g = isnan(rb) ? INFINITY : rb;
+                    if (g < rsec) rsec = g;
+                }
+                rb = f;
+                rs = s;
+                rt = t;
+                rhave = 1;
+            } else {
+                double g = isnan(f) ? INFINITY : f;
+                if (g < rsec) rsec = g;
+            }
+        }
+    *bs = rs;
+    *bt = rt;
+    *best = rb;
+    *second = rsec;
+}
+
+/* Align one frame a against template b (both m x n, FP64).  surf may be NULL.
+ * Follows the search of section 2: downsample both `levels` times (0: not at
+ * all), score every shift of the window on the coarsest images, take the
+ * argmin, then at each finer level multiply it by two and keep the best of
+ * the nine evaluations around it, down to full resolution.  pa, pb: room for
+ * the downsampled images of every level (m*n/2 each suffices). */
+static void align_one(const double *a, const double *b, int m, int n, int w, int levels,
+                      double *pa, double *pb, double *surf, oracle_result *r)
+{
+    /* the image pyramid: level 0 is the frame itself */
+    const double *la[8], *lb[8];
+    int lm[8], ln[8];
+    la[0] = a;
+    lb[0] = b;
+    lm[0] = m;
+    ln[0] = n;
+    size_t off = 0;
+    for (int l = 1; l <= levels; ++l) {
+        oracle_downsample(la[l - 1], lm[l - 1], ln[l - 1], pa + off);
+        oracle_downsample(lb[l - 1], lm[l - 1], ln[l - 1], pb + off);
+        la[l] = pa + off;
+        lb[l] = pb + off;
+        lm[l] = lm[l - 1] / 2;
+        ln[l] = ln[l - 1] / 2;
+        off += (size_t)lm[l] * ln[l];
     }
+    const double *ga = la[levels], *gb = lb[levels];
+    const int mg = lm[levels], ng = ln[levels];
     int W = 2 * w - 1;
     double best = NAN, second = INFINITY;
     int bs = 0, bt = 0, have = 0;
@@ -188,36 +232,19 @@ static void align_one(const double *a, const double *b, int m, int n, int w, int
         oracle_terms(ga, gb, mg, ng, bs, bt, q);
         r->kappa = (q[0] + q[1]) / (q[3] * best);
     }
-    if (!ds) {
+    if (levels == 0) {
         r->shift_s = bs;
         r->shift_t = bt;
         for (int k = 0; k < 9; ++k) r->frefine[k] = NAN;
         r->gap_r = INFINITY;
         return;
     }
+    int s = bs, t = bt;
     double rb = NAN, rsec = INFINITY;
-    int rs = 0, rt = 0, rhave = 0;
-    for (int u = -1; u <= 1; ++u)
-        for (int v = -1; v <= 1; ++v) {
-            int s = 2 * bs + u, t = 2 * bt + v;
-            double f = oracle_f(a, b, m, n, s, t);
-            r->frefine[(u + 1) * 3 + (v + 1)] = f;
-            if (!rhave || precedes(f, s, t, rb, rs, rt)) {
-                if (rhave) {
-                    double g = isnan(rb) ? INFINITY : rb;
-                    if (g < rsec) rsec = g;
-                }
-                rb = f;
-                rs = s;
-                rt = t;
-                rhave = 1;
-            } else {
-                double g = isnan(f) ? INFINITY : f;
-                if (g < rsec) rsec = g;
-            }
-        }
-    r->shift_s = rs;
-    r->shift_t = rt;
+    for (int l = levels - 1; l >= 0; --l)
+        nine(la[l], lb[l], lm[l], ln[l], s, t, l == 0 ? r->frefine : NULL, &s, &t, &rb, &rsec);
+    r->shift_s = s;
+    r->shift_t = t;
     r->gap_r = rsec - rb;
 }
 
@@ -226,8 +253,8 @@ static void align_one(const double *a, const double *b, int m, int n, int w, int
 int oracle_validate(int T, int m, int n, int w, int ds)
 {
     if (T < 0 || m < 1 || n < 1 || w < 1) return -1;
-    if (ds != 0 && ds != 1) return -1;
-    int mg = ds ? m / 2 : m, ng = ds ? n / 2 : n;
+    if (ds < 0 || ds > 4) return -1;
+    int mg = m >> ds, ng = n >> ds;
     if (mg < 1 || ng < 1) return -1;
     if (w > mg || w > ng) return -1;
     return 0;
@@ -243,7 +270,7 @@ int oracle_align(const double *frames, const double *tmpl, int T, int m, int n, 
     if (oracle_validate(T, m, n, w, ds) != 0) return -1;
     int W = 2 * w - 1;
     size_t mn = (size_t)m * n;
-    size_t cn = (size_t)(m / 2 > 0 ? m / 2 : 1) * (size_t)(n / 2 > 0 ? n / 2 : 1);
+    size_t cn = mn / 2 + 1;   /* every downsampled level: m n (1/4 + 1/16 + ...) < m n / 3 */
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else

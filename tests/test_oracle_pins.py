@@ -301,7 +301,8 @@ def test_validation_rules():
     assert oracle.validate(0, 8, 8, 4, 1)           # T = 0 is valid
     assert not oracle.validate(1, 1, 8, 1, 1)       # m' = 0
     assert not oracle.validate(1, 8, 8, 0, 0)       # w < 1
-    assert not oracle.validate(1, 8, 8, 2, 2)       # ds not in {0,1}
+    assert oracle.validate(1, 8, 8, 2, 2)           # two levels: 2x2 grid, w = 2
+    assert not oracle.validate(1, 8, 8, 2, -1)      # levels >= 0
     assert not oracle.validate(-1, 8, 8, 2, 0)
 
 
@@ -364,3 +365,53 @@ def test_mean_image_of_the_corrected_stack():
     for i in range(m):
         for j in range(n):
             assert mean[i, j] == float(Fraction(int(out[:, i, j].sum()), T))
+
+
+# --- more than one level of downsampling (sec. 2, last paragraph: the argmin
+# is multiplied by two "multiple times", nine evaluations each time) --------
+
+def _smooth_scene(rng, m, n, k=12):
+    i = np.arange(m)[:, None]
+    j = np.arange(n)[None, :]
+    img = np.zeros((m, n))
+    for _ in range(k):
+        ci, cj = rng.uniform(0, m), rng.uniform(0, n)
+        sg = rng.uniform(3, 6)
+        img += rng.uniform(50, 200) * np.exp(-((i - ci) ** 2 + (j - cj) ** 2) / (2 * sg * sg))
+    return np.rint(img + 20)
+
+
+def test_multilevel_coarse_surface_is_the_search_on_twice_downsampled_images():
+    rng = np.random.default_rng(21)
+    m, n = 64, 48
+    b = _smooth_scene(rng, m, n)
+    fr = np.stack([np.roll(b, (5, -7), axis=(0, 1)), np.roll(b, (-9, 3), axis=(0, 1))])
+    box = lambda x: x[..., : x.shape[-2] // 2 * 2, : x.shape[-1] // 2 * 2].reshape(
+        x.shape[:-2] + (x.shape[-2] // 2, 2, x.shape[-1] // 2, 2)).mean(axis=(-3, -1))
+    r2 = oracle.align(fr, b, 5, 2, want_surface=True)
+    r0 = oracle.align(box(box(fr)), box(box(b)), 5, 0, want_surface=True)
+    assert np.array_equal(r2.surf, r0.surf)
+    assert np.array_equal(r2.coarse, r0.coarse)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_multilevel_recovers_planted_shifts_of_every_parity(levels):
+    rng = np.random.default_rng(22 + levels)
+    m = n = 128
+    b = _smooth_scene(rng, m, n, k=20)
+    shifts = [(0, 0), (5, -7), (-6, 9), (11, 3), (-13, -2), (8, 10)]
+    fr = np.stack([np.roll(b, s, axis=(0, 1)) for s in shifts])
+    w = (m >> levels) // 3
+    r = oracle.align(fr, b, w, levels)
+    assert [tuple(x) for x in r.shifts] == shifts
+    # the coarse argmin is the planted shift divided by 2^levels, to within a
+    # step of each level's refinement
+    for (S, T), (cs, ct) in zip(shifts, r.coarse):
+        assert abs(cs * (1 << levels) - S) < (1 << levels) and abs(ct * (1 << levels) - T) < (1 << levels)
+
+
+def test_multilevel_validation():
+    assert oracle.validate(1, 64, 64, 8, 3)          # 8x8 coarse grid, w = 8
+    assert not oracle.validate(1, 64, 64, 9, 3)      # w > m'
+    assert not oracle.validate(1, 64, 64, 1, 5)      # at most 4 levels
+    assert not oracle.validate(1, 15, 64, 1, 4)      # m >> 4 = 0
