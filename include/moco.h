@@ -11,9 +11,11 @@
  * where D_{s,t} is the set of pixels (i,j) such that both (i,j) and
  * (i+s,j+t) lie inside the m x n image (sec. 2, objective and overlap set).
  * Every shift with max(|s|,|t|) < w is scored (sec. 2, first paragraph), on
- * the 2x2-box-downsampled frame when `downsample` is set; the argmin is then
- * multiplied by two and f_{2s+u,2t+v}, u,v in {-1,0,1}, is evaluated at full
- * resolution and the minimum kept (sec. 2, last paragraph).
+ * the frame box-downsampled by 2x2 `downsample` times (0: the frame itself;
+ * 1: once, the paper's setting for frames larger than 256x256); the argmin is
+ * then multiplied by two and f_{2s+u,2t+v}, u,v in {-1,0,1}, evaluated on the
+ * next finer level with the minimum kept, once per level down to full
+ * resolution (sec. 2, last paragraph).
  *
  * Indices are 0-based.  Row shift s runs along m, column shift t along n.
  * A frame made as np.roll(template, (S,T), axis=(0,1)) returns (S,T); the
@@ -121,11 +123,14 @@ void moco_template_destroy(moco_tmpl *tmpl);
 
 /* Align one stack: T frames of m x n pixels (d_frames, T*m*n elements of
  * `dtype`) against a template prepared with the same (dtype, m, n, w,
- * downsample).  T == 0 is a no-op.  Validation (MOCO_EINVAL): m,n >= 1 (>= 2
- * when downsampling); downsample in {0,1}; 1 <= w <= min(m',n') where
- * m' = m/2, n' = n/2 when downsampling (floor), else m, n; T >= 0; known dtype
- * and form; non-null frames, template and out->shifts; template parameters
- * equal to the call's.  MOCO_FORM_INT8_MFMA on float32 data is MOCO_EINVAL. */
+ * downsample).  T == 0 is a no-op.  Validation (MOCO_EINVAL): downsample (the
+ * number of 2x2 levels) in 0..4; m' = m >> downsample, n' = n >> downsample
+ * (each level drops an odd trailing row/column) at least 1; 1 <= w <=
+ * min(m',n'); T >= 0; known dtype and form; non-null frames, template and
+ * out->shifts; template parameters equal to the call's.  MOCO_FORM_INT8_MFMA on
+ * float32 data, or with more than one level, is MOCO_EINVAL.  The nine refine
+ * values and the refine gap are those of the full-resolution step; the levels
+ * in between keep only their argmin. */
 int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m, int n,
                int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
                void *hip_stream);
@@ -262,6 +267,12 @@ int moco_profile_enable(moco_ctx *ctx, int enable);
  * the record.  Arrays are host memory of MOCO_STAGE_COUNT elements, filled
  * (not accumulated).  Errors: MOCO_EINVAL, MOCO_EDEVICE. */
 int moco_profile_read(moco_ctx *ctx, double *ms, int64_t *launches);
+
+/* The paper's default parameters for an m x n stack (sec. 3): downsample once
+ * when the frame is larger than 256x256 (a side above 256), else not at all,
+ * and the window w = min(m',n')/3 (floor, at least 1) on the searched grid.
+ * Host only.  Errors: MOCO_EINVAL (m or n < 1, null outputs). */
+int moco_default_params(int m, int n, int *w, int *downsample);
 
 /* Human-readable message of the calling thread's last failure ("" if none). */
 const char *moco_last_error(void);

@@ -70,11 +70,13 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int validate(int m, int n, int w, int ds, moco_dtype dt, moco::Geom *g)
 {
     if (dt != MOCO_U16 && dt != MOCO_F32) return fail(MOCO_EINVAL, "unknown dtype %d", (int)dt);
-    if (ds != 0 && ds != 1) return fail(MOCO_EINVAL, "downsample must be 0 or 1, got %d", ds);
+    if (ds < 0 || ds > moco::kMaxLevels)
+        return fail(MOCO_EINVAL, "downsample (levels) must be 0..%d, got %d", moco::kMaxLevels, ds);
     if (m < 1 || n < 1) return fail(MOCO_EINVAL, "image size %dx%d must be positive", m, n);
-    if (ds && (m < 2 || n < 2))
-        return fail(MOCO_EINVAL, "downsampling needs m,n >= 2 (got %dx%d)", m, n);
-    int mg = ds ? m / 2 : m, ng = ds ? n / 2 : n;
+    if ((m >> ds) < 1 || (n >> ds) < 1)
+        return fail(MOCO_EINVAL, "%d levels of downsampling need m,n >= %d (got %dx%d)", ds,
+                    1 << ds, m, n);
+    int mg = m >> ds, ng = n >> ds;
     if (w < 1 || w > mg || w > ng)
         return fail(MOCO_EINVAL, "window w=%d must satisfy 1 <= w <= min(%d,%d)", w, mg, ng);
     if ((long long)m * n > (1LL << 30)) return fail(MOCO_EINVAL, "image %dx%d too large", m, n);
@@ -115,21 +117,96 @@ int ensure_scratch(moco_ctx *ctx, size_t bytes, hipStream_t st)
     return MOCO_OK;
 }
 
+// Geometry of pyramid level l (0 = the frames) of a search.
+moco::Geom level_geom(const moco::Geom &g, int l)
+{
+    moco::Geom q = g;
+    q.ds = l;
+    q.mg = g.m >> l;
+    q.ng = g.n >> l;
+    return q;
+}
+
+// FP64 elements of levels 1 .. ds-1 of one frame's pyramid (the levels the
+// intermediate x2 steps read).
+size_t inter_elems(const moco::Geom &g)
+{
+    size_t e = 0;
+    for (int l = 1; l < g.ds; ++l) e += (size_t)(g.m >> l) * (g.n >> l);
+    return e;
+}
+
+// The searched grid of C frames into `grid` (level ds; the frames in FP64
+// when ds = 0) and, when ds >= 2, levels 1 .. ds-1 into `inter` (level by
+// level, each C x m_l x n_l).
+hipError_t build_levels(const void *frames, moco_dtype dt, int C, const moco::Geom &g,
+                        double *inter, double *grid, hipStream_t st)
+{
+    if (g.ds <= 1) return moco::launch_coarse(frames, dt, C, g, grid, st);
+    hipError_t e = moco::launch_coarse(frames, dt, C, level_geom(g, 1), inter, st);
+    double *prev = inter;
+    size_t off = (size_t)C * (g.m >> 1) * (g.n >> 1);
+    for (int l = 2; l <= g.ds && e == hipSuccess; ++l) {
+        double *out = l == g.ds ? grid : inter + off;
+        e = moco::launch_half(prev, C, g.m >> (l - 1), g.n >> (l - 1), out, st);
+        prev = out;
+        off += (size_t)C * (g.m >> l) * (g.n >> l);
+    }
+    return e;
+}
+
+// Level l (1 <= l < ds) of the chunk's pyramid, and of the template's.
+double *inter_level(double *inter, int C, const moco::Geom &g, int l)
+{
+    size_t off = 0;
+    for (int k = 1; k < l; ++k) off += (size_t)C * (g.m >> k) * (g.n >> k);
+    return inter + off;
+}
+
+// The x2 steps above full resolution: from the searched grid's argmin `cst`
+// down to level 1; returns the level-1 result (cst itself when ds <= 1).
+// shA, shB: C x 2 int32 each; partial: the level refine's partial sums.
+hipError_t refine_levels(const moco::Tmpl &tt, int C, const moco::Geom &g, double *inter,
+                         const int32_t *cst, int32_t *shA, int32_t *shB, double *partial,
+                         hipStream_t st, const int32_t **level1)
+{
+    const int32_t *cur = cst;
+    for (int l = g.ds - 1; l >= 1; --l) {
+        int32_t *out = (g.ds - 1 - l) % 2 == 0 ? shA : shB;
+        hipError_t e = moco::launch_refine_level(inter_level(inter, C, g, l),
+                                                 inter_level(tt.pyr, 1, g, l), C, g.m >> l,
+                                                 g.n >> l, cur, out, partial, st);
+        if (e != hipSuccess) return e;
+        cur = out;
+    }
+    *level1 = cur;
+    return hipSuccess;
+}
+
+// Partial sums of every refine step of a search, per frame.
+size_t refine_steps_partial_bytes(const moco::Geom &g)
+{
+    size_t b = moco::refine_partial_bytes(g);
+    for (int l = 1; l < g.ds; ++l) b = std::max(b, moco::refine_level_partial_bytes(g.m >> l, g.n >> l));
+    return b;
+}
+
 // Per-frame scratch of the FP64 exact form.
 struct ExactLayout {
-    size_t coarse, atab, h, cst, pm, part, total_per_frame;
+    size_t coarse, inter, atab, h, cst, pm, part, total_per_frame;
 };
 
 ExactLayout exact_layout(const moco::Geom &g)
 {
     ExactLayout L;
     L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
+    L.inter = align_up(inter_elems(g) * sizeof(double), 256);
     L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
-    L.cst = 2 * sizeof(int32_t);
+    L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
-    L.part = align_up(moco::refine_partial_bytes(g), 8);
-    L.total_per_frame = L.coarse + L.atab + L.h + L.cst + L.pm + L.part;
+    L.part = align_up(refine_steps_partial_bytes(g), 8);
+    L.total_per_frame = L.coarse + L.inter + L.atab + L.h + L.cst + L.pm + L.part;
     return L;
 }
 
@@ -197,6 +274,8 @@ void free_tmpl(moco::Tmpl &t)
     if (t.fft.twp) (void)hipFree(t.fft.twp);
     if (t.fft.twq) (void)hipFree(t.fft.twq);
     if (t.fft.spec) (void)hipFree(t.fft.spec);
+    if (t.pyr) (void)hipFree(t.pyr);
+    t.pyr = nullptr;
     t.fft.twp = nullptr;
     t.fft.twq = nullptr;
     t.fft.spec = nullptr;
@@ -394,11 +473,14 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     size_t off = 0;
     double *coarse = (double *)(base + off);
     off += L.coarse * C;
+    double *inter = (double *)(base + off);
+    off += L.inter * C;
     double *atab = (double *)(base + off);
     off += L.atab * C;
     double *h = (double *)(base + off);
     off += L.h * C;
     int32_t *cst = (int32_t *)(base + off);
+    int32_t *shA = cst + 2 * (size_t)C, *shB = cst + 4 * (size_t)C;
     off += L.cst * C;
     int32_t *pm = (int32_t *)(base + off);
     off += L.pm * C;
@@ -408,9 +490,10 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
+        int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         {
             StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
-            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+            HIP_TRY(build_levels(fr, dtype, c, g, inter, coarse, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
@@ -424,17 +507,16 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
             HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g,
                                      out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
-                                     out->fmin ? out->fmin + f0 : nullptr,
-                                     out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
+                                     out->fmin ? out->fmin + f0 : nullptr, coarse_st,
                                      out->shifts + 2 * (size_t)f0,
                                      out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
                                      out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
         }
         if (g.ds) {
             StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
-            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g,
-                                        out->coarse ? out->coarse + 2 * (size_t)f0 : cst,
-                                        out->shifts + 2 * (size_t)f0,
+            const int32_t *lvl1 = nullptr;
+            HIP_TRY(refine_levels(tt, c, g, inter, coarse_st, shA, shB, part, st, &lvl1));
+            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, lvl1, out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
                                         out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
                                         st, pm, tt.pbound));
@@ -445,21 +527,23 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame scratch of the FFT form.
 struct FftLayout {
-    size_t coarse, atab, s1, s2, h, cst, pm, part, total_per_frame;
+    size_t coarse, inter, atab, s1, s2, h, cst, pm, part, total_per_frame;
 };
 
 FftLayout fft_layout(const moco::Geom &g)
 {
     FftLayout L;
     L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
+    L.inter = align_up(inter_elems(g) * sizeof(double), 256);
     L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.s1 = align_up(moco::fft_s1_bytes(g), 256);
     L.s2 = align_up(moco::fft_s2_bytes(g), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
-    L.cst = 2 * sizeof(int32_t);
+    L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
-    L.part = align_up(moco::refine_partial_bytes(g), 8);
-    L.total_per_frame = L.coarse + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.part;
+    L.part = align_up(refine_steps_partial_bytes(g), 8);
+    L.total_per_frame =
+        L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.part;
     return L;
 }
 
@@ -478,6 +562,8 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     size_t off = 0;
     double *coarse = (double *)(base + off);
     off += L.coarse * C;
+    double *inter = (double *)(base + off);
+    off += L.inter * C;
     double *atab = (double *)(base + off);
     off += L.atab * C;
     double2 *s1 = (double2 *)(base + off);
@@ -487,6 +573,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     double *h = (double *)(base + off);
     off += L.h * C;
     int32_t *cst = (int32_t *)(base + off);
+    int32_t *shA = cst + 2 * (size_t)C, *shB = cst + 4 * (size_t)C;
     off += L.cst * C;
     int32_t *pm = (int32_t *)(base + off);
     off += L.pm * C;
@@ -499,7 +586,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         {
             StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
-            HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st));
+            HIP_TRY(build_levels(fr, dtype, c, g, inter, coarse, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
@@ -521,7 +608,9 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         }
         if (g.ds) {
             StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
-            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, coarse_st, out->shifts + 2 * (size_t)f0,
+            const int32_t *lvl1 = nullptr;
+            HIP_TRY(refine_levels(tt, c, g, inter, coarse_st, shA, shB, part, st, &lvl1));
+            HIP_TRY(moco::launch_refine(fr, tt.raw, c, g, lvl1, out->shifts + 2 * (size_t)f0,
                                         out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr,
                                         out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr, part,
                                         st, pm, tt.pbound));
@@ -626,6 +715,18 @@ extern "C" {
 const char *moco_last_error(void) { return g_err.c_str(); }
 
 const char *moco_version(void) { return "moco-mi355x 0.1"; }
+
+int moco_default_params(int m, int n, int *w, int *downsample)
+{
+    if (!w || !downsample) return fail(MOCO_EINVAL, "moco_default_params: null output");
+    if (m < 1 || n < 1) return fail(MOCO_EINVAL, "image size %dx%d must be positive", m, n);
+    const int ds = (m > 256 || n > 256) ? 1 : 0;
+    const int mg = m >> ds, ng = n >> ds;
+    const int ww = std::min(mg, ng) / 3;
+    *w = ww < 1 ? 1 : ww;
+    *downsample = ds;
+    return MOCO_OK;
+}
 
 int moco_create(int device, size_t scratch_budget_bytes, moco_ctx **out)
 {
@@ -774,15 +875,18 @@ int moco_template_create(moco_ctx *ctx, const void *d_template, moco_dtype dtype
     };
     t.pbound = -1;
     int32_t pbv = INT32_MAX;
+    t.pyr = nullptr;
     if ((e = hipMalloc(&t.raw, raw_bytes)) != hipSuccess ||
         (e = hipMalloc(&t.coarse, (size_t)g.mg * g.ng * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&t.btab, (size_t)g.W * g.W * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&pb, sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc(&pb, sizeof(int32_t))) != hipSuccess ||
+        (inter_elems(g) &&
+         (e = hipMalloc(&t.pyr, inter_elems(g) * sizeof(double))) != hipSuccess))
         return cleanup(fail(MOCO_ENOMEM, "template allocation failed: %s", hipGetErrorString(e)));
     // the template's energies over D at (s,t) are its frame-side energies at (-s,-t)
     if ((e = hipMemcpyAsync(t.raw, d_template, raw_bytes, hipMemcpyDeviceToDevice, st)) !=
             hipSuccess ||
-        (e = moco::launch_coarse(t.raw, dtype, 1, g, t.coarse, st)) != hipSuccess ||
+        (e = build_levels(t.raw, dtype, 1, g, t.pyr, t.coarse, st)) != hipSuccess ||
         (e = moco::launch_energy(t.coarse, 1, g, true, t.btab, pb, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&pbv, pb, sizeof pbv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)

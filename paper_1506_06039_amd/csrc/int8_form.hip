@@ -705,9 +705,11 @@ Int8Geom int8_geom(const Geom &g)
 bool int8_applicable(const Geom &g)
 {
     // exact int32 accumulation needs fewer than 2^17 terms per shift; the
-    // prep kernel holds at most 2048 grid columns; the correlation kernel holds
-    // template rows of at most kMaxTrow bytes
-    if (g.dtype != MOCO_U16 || (long long)g.mg * g.ng >= 131072 || g.ng > 2048 || g.w > 512)
+    // prep kernel holds at most 2048 grid columns and forms grid values from
+    // one 2x2 level at most; the correlation kernel holds template rows of at
+    // most kMaxTrow bytes
+    if (g.dtype != MOCO_U16 || g.ds > 1 || (long long)g.mg * g.ng >= 131072 || g.ng > 2048 ||
+        g.w > 512)
         return false;
     return int8_geom(g).trow <= kMaxTrow;
 }

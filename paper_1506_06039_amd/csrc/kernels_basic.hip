@@ -160,6 +160,24 @@ __global__ __launch_bounds__(kBlock) void k_coarse_ds4(const T *__restrict__ fr,
     }
 }
 
+// One more level of the image pyramid: the 2x2 box mean of an FP64 level,
+// odd trailing row/column dropped, summed in the same order as the first level.
+__global__ __launch_bounds__(kBlock) void k_half(const double *__restrict__ in, int C, int m,
+                                                 int n, double *__restrict__ out)
+{
+    const int mh = m / 2, nh = n / 2;
+    const size_t plane = (size_t)mh * nh;
+    const size_t total = (size_t)C * plane;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = idx / plane;
+        const int r = (int)(idx - f * plane);
+        const int i = r / nh, j = r - i * nh;
+        const double *p = in + f * (size_t)m * n + (size_t)(2 * i) * n + 2 * j;
+        out[idx] = (((p[0] + p[1]) + p[n]) + p[n + 1]) / 4.0;
+    }
+}
+
 // Exclusive prefix sums out[k] = v[0] + ... + v[k-1], k = 0..n (n <= 2*kBlock),
 // in a fixed order: pairs per thread, a shuffle scan per wave, wave carries.
 // Every thread of the block must call it; it starts and ends with a barrier.
@@ -433,6 +451,15 @@ struct RefAcc<float> {
     __device__ static type term(float x, float y)
     {
         double d = (double)x - (double)y;
+        return d * d;
+    }
+};
+template <>
+struct RefAcc<double> {
+    using type = double;
+    __device__ static type term(double x, double y)
+    {
+        double d = x - y;
         return d * d;
     }
 };
@@ -1149,10 +1176,8 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
     // (non-negative uint16) when the grid covers every pixel
     double pscale = 0.0;
     if (g.dtype == MOCO_U16) {
-        if (!g.ds)
-            pscale = 1.0;
-        else if (g.m % 2 == 0 && g.n % 2 == 0)
-            pscale = 4.0;
+        const int b = 1 << g.ds;   // a level-L grid value is the mean of a b x b block
+        if (g.m % b == 0 && g.n % b == 0) pscale = (double)b * b;
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
@@ -1235,6 +1260,54 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
     else
         k_refine<float><<<C, kBlock, 0, st>>>((const float *)frames, (const float *)traw, g.m,
                                               g.n, coarse_st, shifts, frefine, gaps);
+    return hipGetLastError();
+}
+
+hipError_t launch_half(const double *in, int C, int m, int n, double *out, hipStream_t st)
+{
+    clear_stale_error();
+    const size_t total = (size_t)C * (m / 2) * (n / 2);
+    if (total == 0) return hipSuccess;
+    k_half<<<grid_for(total), kBlock, 0, st>>>(in, C, m, n, out);
+    return hipGetLastError();
+}
+
+// Rows per block of the FP64 level refine (0: rows too wide to stage).
+static int level_band_rows(int n)
+{
+    const size_t row = (size_t)n * sizeof(double);
+    if (3 * row > 40 * 1024) return 0;
+    const int br = (int)(40 * 1024 / row) - 2;
+    return br > 16 ? 16 : br;
+}
+
+size_t refine_level_partial_bytes(int m, int n)
+{
+    const int br = level_band_rows(n);
+    return br > 0 ? (size_t)((m + br - 1) / br) * 9 * sizeof(double) : 0;
+}
+
+hipError_t launch_refine_level(const double *frames, const double *tmpl, int C, int m, int n,
+                               const int32_t *in_st, int32_t *out_st, double *partial,
+                               hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const int br = level_band_rows(n);
+    if (br <= 0) {
+        k_refine<double><<<C, kBlock, 0, st>>>(frames, tmpl, m, n, in_st, out_st, nullptr,
+                                               nullptr);
+        return hipGetLastError();
+    }
+    const int nband = (m + br - 1) / br;
+    k_refine_band<double><<<dim3(nband, C), kBlock, (size_t)(br + 2) * n * sizeof(double), st>>>(
+        frames, tmpl, m, n, br, in_st, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    Geom gl{};
+    gl.m = m;
+    gl.n = n;
+    launch_finish(partial, C, nband, gl, in_st, out_st, nullptr, nullptr, st);
     return hipGetLastError();
 }
 

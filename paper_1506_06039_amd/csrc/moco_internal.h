@@ -10,12 +10,14 @@
 
 namespace moco {
 
-// Geometry of one search: full-resolution m x n, searched grid mg x ng,
+// Geometry of one search: full-resolution m x n, `ds` levels of 2x2
+// downsampling (0: none), searched grid mg x ng = (m >> ds) x (n >> ds),
 // window w (W = 2w-1 shifts per axis).
 struct Geom {
     int m, n, mg, ng, w, W, ds;
     moco_dtype dtype;
 };
+constexpr int kMaxLevels = 4;
 
 // Geometry of the int8 form: grid columns padded to a multiple of 32, and the
 // template rows laid out with `padl` leading zero bytes in rows of `trow`.
@@ -67,6 +69,8 @@ struct Tmpl {
     double *coarse;   // mg x ng FP64 (box mean when ds)
     double *btab;     // W x W: sum of b'^2 over D_{s,t}, [s+w-1][t+w-1]
     int32_t pbound;   // bound of the template's pixel values (uint16), -1: none
+    double *pyr;      // levels 1 .. ds-1 of the template's image pyramid, FP64, one after
+                      // another (nullptr when ds <= 1); level ds is `coarse`
     bool int8_ok;     // the int8 form applies (uint16, template digits fit two planes)
     Int8Tmpl i8;
     bool fft_ok;      // the FFT form applies (transform lengths within kFftMaxLen)
@@ -101,6 +105,14 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, double *partial, hipStream_t st,
                          const int32_t *pmax = nullptr, int tmax = -1);
+// one more pyramid level: in C x m x n FP64 -> out C x (m/2) x (n/2)
+hipError_t launch_half(const double *in, int C, int m, int n, double *out, hipStream_t st);
+// the +-1 step at an intermediate pyramid level (FP64 images of that level):
+// in_st (s,t) of the level below -> out_st the best of (2s+u, 2t+v)
+hipError_t launch_refine_level(const double *frames, const double *tmpl, int C, int m, int n,
+                               const int32_t *in_st, int32_t *out_st, double *partial,
+                               hipStream_t st);
+size_t refine_level_partial_bytes(int m, int n);   // per frame
 int refine_band_rows(const Geom &g);
 bool refine_u16_banded(const Geom &g);
 size_t refine_partial_bytes(const Geom &g);   // per frame

@@ -94,6 +94,8 @@ _lib.moco_version.argtypes = []
 _lib.moco_version.restype = ctypes.c_char_p
 _lib.moco_apply.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]
 _lib.moco_apply.restype = _i
+_lib.moco_default_params.argtypes = [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
+_lib.moco_default_params.restype = _i
 
 
 def _check(rc: int):
@@ -146,18 +148,18 @@ class Context:
 class Template:
     """moco_template_create / moco_template_destroy."""
 
-    def __init__(self, ctx: Context, template: torch.Tensor, w: int, downsample: bool):
+    def __init__(self, ctx: Context, template: torch.Tensor, w: int, downsample: int):
         if not template.is_cuda or template.dim() != 2:
             raise ValueError("template must be a 2-D device tensor")
         template = template.contiguous()
         m, n = template.shape
         h = _vp()
         _check(_lib.moco_template_create(ctx.handle, template.data_ptr(), _dtype_code(template),
-                                         m, n, w, int(bool(downsample)),
+                                         m, n, w, int(downsample),
                                          _stream_handle(template.device), ctypes.byref(h)))
         self.handle = h
         self.ctx = ctx
-        self.m, self.n, self.w, self.downsample = m, n, w, bool(downsample)
+        self.m, self.n, self.w, self.downsample = m, n, w, int(downsample)
         self.dtype = template.dtype
 
     def close(self):
@@ -230,6 +232,13 @@ def moco_apply(ctx: Context, frames: torch.Tensor, shifts: torch.Tensor, frames_
                            _dtype_code(frames), out.data_ptr() if frames_out else None,
                            mean_out.data_ptr() if mean else None, _stream_handle(dev)))
     return (out if frames_out else None), (mean_out if mean else None)
+
+
+def default_params(m: int, n: int):
+    """The paper's defaults for an m x n stack: (w, downsample levels)."""
+    w, ds = _i(), _i()
+    _check(_lib.moco_default_params(m, n, ctypes.byref(w), ctypes.byref(ds)))
+    return w.value, ds.value
 
 
 def _new_result(T: int, W: int, dev, surface: bool) -> Result:
@@ -329,7 +338,7 @@ class Server:
             raise TypeError("template must be uint16 or float32")
         m, n = t.shape
         _check(_lib.moco_server_add_source(self.handle, source, t.ctypes.data, code, m, n, w,
-                                           int(bool(downsample))))
+                                           int(downsample)))
 
     def submit(self, source: int, frame, tag: int) -> bool:
         """True when admitted, False on back-pressure (no free slot)."""

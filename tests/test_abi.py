@@ -82,3 +82,17 @@ def test_apply_rejects_bad_arguments_without_gpu(lib):
     assert lib.moco_apply(None, None, None, 1, 8, 8, 1, None, None, None) == -1   # null ctx
     lib.moco_last_error.restype = ctypes.c_char_p
     assert b"null" in lib.moco_last_error()
+
+
+def test_default_params_follow_the_paper_without_gpu(lib):
+    # sec. 3: downsample once iff the frame is larger than 256x256; window
+    # min(m', n')/3 on the searched grid
+    lib.moco_default_params.restype = ctypes.c_int
+    lib.moco_default_params.argtypes = [ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    w, ds = ctypes.c_int(), ctypes.c_int()
+    for (m, n), want in [((512, 512), (85, 1)), ((256, 256), (85, 0)), ((416, 460), (69, 1)),
+                         ((800, 300), (50, 1)), ((10, 4), (1, 0)), ((1, 1), (1, 0))]:
+        assert lib.moco_default_params(m, n, ctypes.byref(w), ctypes.byref(ds)) == 0
+        assert (w.value, ds.value) == want, (m, n)
+    assert lib.moco_default_params(0, 5, ctypes.byref(w), ctypes.byref(ds)) == -1
