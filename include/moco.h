@@ -64,13 +64,25 @@ typedef enum {
  * energy split of sec. 2) is computed.  Every form computes the same f. */
 typedef enum {
     MOCO_FORM_AUTO = 0,       /* library choice: of MOCO_FORM_INT8_MFMA (uint16) and
-                                 MOCO_FORM_FFT the one a per-frame time model of the
-                                 template's geometry ranks faster among those that apply
-                                 (int8 for small windows, the FFT for wide ones), else
-                                 MOCO_FORM_FP64_EXACT */
+                                 MOCO_FORM_FFT_CERTIFIED the one a per-frame time model of
+                                 the template's geometry ranks faster among those that
+                                 apply (int8 for small windows, the FFT for wide ones),
+                                 else MOCO_FORM_FP64_EXACT */
     MOCO_FORM_FFT = 1,        /* h from FP64 complex transforms of the zero-padded grids
                                  (sec. 2, the FFT construction of h), transform lengths
                                  5-smooth and at most 2048; f to about 1e-12 relative */
+    MOCO_FORM_FFT_CERTIFIED = 2, /* MOCO_FORM_FFT with a certified argmin: per frame, if
+                                 the gap between the best and second-best f of the searched
+                                 grid does not exceed twice the transforms' error bound
+                                 (moco_template_fft_bound), the frame's correlation is
+                                 recomputed by MOCO_FORM_FP64_EXACT's direct sums and the
+                                 frame combined again; otherwise the computed argmin is the
+                                 exact argmin of the grid.  Recomputed frames equal
+                                 MOCO_FORM_FP64_EXACT's results bit for bit; on uint16 data
+                                 that is the exact argmin with bit-exact f, so the searched
+                                 grid's shift is the exact one on every frame (on float32
+                                 data, the FP64 form's own rounding decides ties closer
+                                 than it) */
     MOCO_FORM_FP64_EXACT = 3, /* direct FP64 sums on the vector ALUs; bit-exact f for uint16 */
     MOCO_FORM_INT8_MFMA = 4   /* uint16 only: exact integer correlation on int8 matrix
                                  cores (balanced base-256 limbs); bit-exact f */
@@ -88,6 +100,9 @@ typedef struct moco_tmpl moco_tmpl;
  *   coarse  T x 2 int32   argmin (s*,t*) on the searched grid
  *   gaps    T x 2 double  (second-best minus best f on the searched grid,
  *                          second-best minus best of the nine; +inf when n/a)
+ *   recomputed T int32    1 where MOCO_FORM_FFT_CERTIFIED recomputed the frame's
+ *                          correlation by direct sums (its argmin was not
+ *                          certified), else 0 (every other form writes 0)
  * f is in squared intensity units of the searched grid (box-mean units when
  * downsampled). */
 typedef struct {
@@ -97,6 +112,7 @@ typedef struct {
     double *frefine;
     int32_t *coarse;
     double *gaps;
+    int32_t *recomputed;
 } moco_outputs;
 
 /* Create a context on HIP device `device`.  `scratch_budget_bytes` caps the
@@ -180,14 +196,26 @@ int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int
 /* The correlation form a call with `requested` runs for this template.
  * MOCO_FORM_INT8_MFMA applies to uint16 templates with a searched grid of fewer
  * than 131072 pixels and at most 2048 columns, w <= 512, and grid values within
- * two balanced base-256 digits (|value| <= 32639); MOCO_FORM_FFT applies when
- * the transform lengths (5-smooth, at least m'+w-1 by n'+w-1) are at most 2048.
- * MOCO_FORM_AUTO resolves to whichever of the two applies, the one a per-frame
+ * two balanced base-256 digits (|value| <= 32639); MOCO_FORM_FFT and
+ * MOCO_FORM_FFT_CERTIFIED apply when the transform lengths (5-smooth, at least
+ * m'+w-1 by n'+w-1) are at most 2048.  MOCO_FORM_AUTO resolves to whichever of
+ * MOCO_FORM_INT8_MFMA and MOCO_FORM_FFT_CERTIFIED applies, the one a per-frame
  * time model ranks faster when both do (the int8 form's work grows with the
  * (2w-1)^2 shifts, the FFT's with P Q log(P Q): at a 256x256 grid the int8
  * form for w <= 32, the FFT above), else to MOCO_FORM_FP64_EXACT.
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
+
+/* Error bound of the FFT forms for this template (sec. 2, the FFT construction
+ * of h, evaluated in FP64): for every shift of the window the computed
+ * correlation h^ satisfies |h^ - h| <= kf * sqrt(m' n' Sa Sb), and each
+ * computed overlap energy is within ke * Sa (frame) or ke * Sb (template),
+ * where Sa, Sb are the sums of squares of the searched grids of the frame and
+ * the template.  These are the coefficients MOCO_FORM_FFT_CERTIFIED's
+ * certificate uses: a first-order bound in the unit roundoff for each
+ * transform pass, doubled.  Host only.
+ * Errors: MOCO_EINVAL (null argument, or the FFT form does not apply). */
+int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke);
 
 /* ---- Serving: single frames from many sources, continuous batching ----
  *

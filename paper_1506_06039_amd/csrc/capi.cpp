@@ -527,7 +527,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame scratch of the FFT form.
 struct FftLayout {
-    size_t coarse, inter, atab, s1, s2, h, cst, pm, part, total_per_frame;
+    size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, part, total_per_frame;
 };
 
 FftLayout fft_layout(const moco::Geom &g)
@@ -541,17 +541,21 @@ FftLayout fft_layout(const moco::Geom &g)
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
+    L.flag = sizeof(int32_t);
     L.part = align_up(refine_steps_partial_bytes(g), 8);
     L.total_per_frame =
-        L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.part;
+        L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.flag + L.part;
     return L;
 }
 
 // The FFT pipeline over one stack: the exact form's grid, energies, combine
-// and refine around the transform-based correlation.
+// and refine around the transform-based correlation.  With `certify`, frames
+// whose argmin the error bound of the transforms does not certify get their
+// correlation recomputed by direct FP64 sums and are combined again before the
+// x2 steps.
 int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
-            size_t sbytes)
+            size_t sbytes, bool certify)
 {
     FftLayout L = fft_layout(g);
     int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
@@ -577,13 +581,22 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     off += L.cst * C;
     int32_t *pm = (int32_t *)(base + off);
     off += L.pm * C;
+    int32_t *flag = (int32_t *)(base + off);
+    off += L.flag * C;
     double *part = (double *)(base + align_up(off, 8));
     const size_t fbytes = (size_t)g.m * g.n * dtype_size(dtype);
     const int W = g.W;
+    double kf = 0.0, ke = 0.0;
+    if (certify) moco::fft_error_coefs(g, tt.fft, &kf, &ke);
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
         int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
+        int32_t *recheck = out->recomputed ? out->recomputed + f0 : flag;
+        double *fsurf = out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr;
+        double *fmin = out->fmin ? out->fmin + f0 : nullptr;
+        double *gaps = out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr;
+        double *frefine = out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr;
         {
             StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
             HIP_TRY(build_levels(fr, dtype, c, g, inter, coarse, st));
@@ -599,12 +612,19 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
-            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g,
-                                     out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr,
-                                     out->fmin ? out->fmin + f0 : nullptr, coarse_st,
-                                     out->shifts + 2 * (size_t)f0,
-                                     out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr,
-                                     out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr, st));
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
+                                         out->shifts + 2 * (size_t)f0, gaps, frefine, st,
+                                         nullptr, certify ? recheck : nullptr, kf, ke));
+        }
+        if (certify) {
+            // the frames left uncertified: direct sums, combined again
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            HIP_TRY(moco::launch_corr_fp64(coarse, tt.coarse, c, g, h, st, recheck));
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
+                                         out->shifts + 2 * (size_t)f0, gaps, frefine, st,
+                                         recheck));
+        } else if (out->recomputed) {
+            HIP_TRY(moco::launch_fill_i32(out->recomputed + f0, c, 0, st));
         }
         if (g.ds) {
             StageTimer tm(ctx, MOCO_STAGE_REFINE, st);
@@ -622,7 +642,8 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &tt)
 {
     if (form == MOCO_FORM_INT8_MFMA) return int8_layout(g, tt.i8.npad).total_per_frame;
-    if (form == MOCO_FORM_FFT) return fft_layout(g).total_per_frame;
+    if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED)
+        return fft_layout(g).total_per_frame;
     return exact_layout(g).total_per_frame;
 }
 
@@ -630,8 +651,15 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
               const moco::Geom &g, moco_form form, const moco_outputs *out, hipStream_t st,
               char *sbase, size_t sbytes)
 {
+    if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED)
+        return run_fft(ctx, d_frames, tt, T, g, out, st, sbase, sbytes,
+                       form == MOCO_FORM_FFT_CERTIFIED);
+    // the exact forms recompute nothing
+    if (out->recomputed && T > 0) {
+        hipError_t e = moco::launch_fill_i32(out->recomputed, T, 0, st);
+        if (e != hipSuccess) return fail(MOCO_EDEVICE, "fill: %s", hipGetErrorString(e));
+    }
     if (form == MOCO_FORM_INT8_MFMA) return run_int8(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
-    if (form == MOCO_FORM_FFT) return run_fft(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
     return run_exact(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
 }
 
@@ -660,13 +688,13 @@ double fft_model_s(const moco::Tmpl &t)
 
 // The form AUTO runs: the faster of the exact int8 form and the FFT form by
 // the models above when both apply, else whichever applies, else direct FP64
-// sums.
+// sums.  The FFT form runs with its argmin certificate.
 moco_form auto_form(const moco::Tmpl &t)
 {
     if (t.int8_ok && t.fft_ok)
-        return int8_model_s(t) <= fft_model_s(t) ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FFT;
+        return int8_model_s(t) <= fft_model_s(t) ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FFT_CERTIFIED;
     if (t.int8_ok) return MOCO_FORM_INT8_MFMA;
-    if (t.fft_ok) return MOCO_FORM_FFT;
+    if (t.fft_ok) return MOCO_FORM_FFT_CERTIFIED;
     return MOCO_FORM_FP64_EXACT;
 }
 
@@ -689,7 +717,7 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "(m=%d n=%d w=%d ds=%d dtype=%d)",
                     tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
     if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA &&
-        form != MOCO_FORM_FFT)
+        form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED)
         return fail(MOCO_EINVAL, "unknown form %d", (int)form);
     if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
         return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
@@ -700,7 +728,7 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "the int8 matrix-core form does not apply to this template (needs uint16, "
                     "grid area below 131072, grid width at most 2048 and template values "
                     "within two base-256 digits)");
-    if (form == MOCO_FORM_FFT && !tt.fft_ok)
+    if ((form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED) && !tt.fft_ok)
         return fail(MOCO_EINVAL, "the FFT form does not apply to this template (transform "
                                  "lengths above %d)", moco::kFftMaxLen);
     if (form == MOCO_FORM_AUTO) form = auto_form(tt);
@@ -811,12 +839,21 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
         *resolved = requested;
         return MOCO_OK;
     case MOCO_FORM_FFT:
+    case MOCO_FORM_FFT_CERTIFIED:
         if (!t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
         *resolved = requested;
         return MOCO_OK;
     default:
         return fail(MOCO_EINVAL, "unknown form %d", (int)requested);
     }
+}
+
+int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke)
+{
+    if (!tmpl || !kf || !ke) return fail(MOCO_EINVAL, "moco_template_fft_bound: null argument");
+    if (!tmpl->t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
+    moco::fft_error_coefs(tmpl->t.g, tmpl->t.fft, kf, ke);
+    return MOCO_OK;
 }
 
 int moco_profile_enable(moco_ctx *ctx, int enable)

@@ -365,6 +365,39 @@ bool fft_plan(int n, FftPlan *pl)
     return true;
 }
 
+// Error coefficients of the FFT form for the argmin certificate (first order
+// in the unit roundoff u = 2^-53, then doubled).  Each radix-r pass over the
+// whole array is a scaled unitary map computed with a relative 2-norm error of
+// at most eta_r = (5 + c_r) u: twiddles rounded from long double (2u), their
+// complex product (3u), and the small DFT's own roundings, c_r = 1, 2, 6, 10,
+// 18 for r = 2, 4, 8, 3, 5 (the add levels of radices 2, 4, 8 plus the
+// sqrt(1/2) products of radix 8; for radices 3 and 5 a componentwise bound of
+// each output by its inputs' magnitudes, times sqrt(r) to a 2-norm).  A 2-D
+// transform sums the passes of both lengths plus 2u for packing two real rows,
+// eps.  With x, y the zero-padded grids (m'n' nonzeros each), the computed
+// correlation satisfies |h^ - h| <= (2 eps + eps' + 2.9u + 2u) max(|x|_2 |y|_1,
+// |x|_1 |y|_2) to first order (frame and template transforms, the complex
+// product, the inverse, the 1/(PQ) scale), and |y|_1 <= sqrt(m'n') |y|_2;
+// kf = 2 (3 eps + 5u).  The energy sums of the grids are computed with at most
+// m'+n'+2w+16 roundings along any path, four of them combined by three
+// additions: ke = (4 (m'+n'+2w+16) + 6) u.
+void fft_error_coefs(const Geom &g, const FftTmpl &ft, double *kf, double *ke)
+{
+    const double u = 0x1p-53;
+    auto plan_eps = [&](const FftPlan &pl) {
+        double e = 0.0;
+        for (int p = 0; p < pl.npass; ++p) {
+            const int r = pl.radix[p];
+            const double c = r == 2 ? 1.0 : r == 4 ? 2.0 : r == 8 ? 6.0 : r == 3 ? 10.0 : 18.0;
+            e += (5.0 + c) * u;
+        }
+        return e;
+    };
+    const double eps = plan_eps(ft.pp) + plan_eps(ft.pq) + 2.0 * u;
+    *kf = 2.0 * (3.0 * eps + 5.0 * u);
+    *ke = (4.0 * (g.mg + g.ng + 2.0 * g.w + 16.0) + 6.0) * u;
+}
+
 FftGeom fft_geom(const Geom &g)
 {
     FftGeom f{};

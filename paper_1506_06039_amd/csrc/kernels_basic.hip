@@ -322,8 +322,10 @@ __global__ __launch_bounds__(kBlock) void k_corr_fp64(const double *__restrict__
                                                       const double *__restrict__ tc, int mg,
                                                       int ng, int w, int lanes_per_s,
                                                       int s_per_blk, int rowlen,
-                                                      double *__restrict__ hout)
+                                                      double *__restrict__ hout,
+                                                      const int32_t *__restrict__ only)
 {
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds[];
     double *ring = lds;                                   // s_per_blk x rowlen
     double *trow = lds + (size_t)s_per_blk * rowlen;      // ng
@@ -390,6 +392,33 @@ __global__ __launch_bounds__(kBlock) void k_corr_fp64(const double *__restrict__
 
 // ---------------------------------------------------------------------------
 // Combine, normalise, argmin.  One block per frame.
+// Certificate of an argmin computed from an inexact correlation.  With
+// |h^ - h| <= kf sqrt(m'n' Sa Sb) for every shift (Sa, Sb: the grids' sums of
+// squares, the energies at shift (0,0)) and energy sums within ke (Sa or Sb),
+// every computed f is within Delta/Area + u|f^| of the exact f, where
+// Delta = 1.01 (ke (Sa+Sb) + 2u sqrt(Sa Sb) + 2 kf sqrt(m'n' Sa Sb)) also
+// covers the rounding of A + B - 2h and of the division.  If the computed gap
+// between the best and the second-best f exceeds twice the largest such bound
+// (smallest overlap area (m'-w+1)(n'-w+1)), no other shift can reach the
+// computed argmin's exact f, so it is the exact argmin of eq. (f) and its
+// ties do not arise.  A lone shift (w = 1) is certified; a non-finite best f
+// is not.
+__device__ bool certified(const double *At, const double *btab, int mg, int ng, int w, double f1,
+                          double f2, double kf, double ke)
+{
+    const double u = 0x1p-53;
+    if (!(f1 == f1) || isinf(f1)) return false;
+    if (isinf(f2)) return true;
+    const int W = 2 * w - 1, c0 = (w - 1) * W + (w - 1);
+    const double sa = fmax(At[c0], 0.0), sb = fmax(btab[c0], 0.0);
+    const double sab = sqrt(sa) * sqrt(sb);
+    const double delta =
+        1.01 * (ke * (sa + sb) + 2.0 * u * sab + 2.0 * kf * sqrt((double)mg * (double)ng) * sab);
+    const double amin = (double)(mg - (w - 1)) * (double)(ng - (w - 1));
+    const double margin = (f2 - f1) - 1.01 * u * (fabs(f1) + fabs(f2));
+    return margin > 2.0 * delta / amin;
+}
+
 __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ atab,
                                                     const double *__restrict__ btab,
                                                     const double *__restrict__ hbuf, int mg,
@@ -399,10 +428,14 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ a
                                                     int32_t *__restrict__ coarse_st,
                                                     int32_t *__restrict__ shifts,
                                                     double *__restrict__ gaps,
-                                                    double *__restrict__ frefine)
+                                                    double *__restrict__ frefine,
+                                                    const int32_t *__restrict__ only,
+                                                    int32_t *__restrict__ recheck, double kf,
+                                                    double ke)
 {
     const int W = 2 * w - 1;
     const int frame = blockIdx.x;
+    if (only && !only[frame]) return;
     const double *At = atab + (size_t)frame * W * W;
     const double *h = hbuf + (size_t)frame * W * W;
     Cand c{INFINITY, INT32_MIN, 0, INFINITY};
@@ -425,8 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ a
             shifts[2 * frame + 1] = r.t;
             if (gaps) gaps[2 * frame + 1] = INFINITY;
         }
+        if (recheck) recheck[frame] = certified(At, btab, mg, ng, w, r.f, r.second, kf, ke) ? 0 : 1;
     }
     if (!ds && frefine && threadIdx.x < 9) frefine[(size_t)frame * 9 + threadIdx.x] = NAN;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int count, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1146,7 +1186,7 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
 }
 
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
-                            double *h, hipStream_t st)
+                            double *h, hipStream_t st, const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1163,7 +1203,7 @@ hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, 
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     dim3 grid((g.W + s_per_blk - 1) / s_per_blk, C);
     k_corr_fp64<<<grid, kBlock, lds, st>>>(coarse, tcoarse, g.mg, g.ng, g.w, lanes_per_s, s_per_blk,
-                                          rowlen, h);
+                                          rowlen, h, only);
     return hipGetLastError();
 }
 
@@ -1187,12 +1227,21 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
 
 hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
-                          int32_t *shifts, double *gaps, double *frefine, hipStream_t st)
+                          int32_t *shifts, double *gaps, double *frefine, hipStream_t st,
+                          const int32_t *only, int32_t *recheck, double kf, double ke)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     k_combine<<<C, kBlock, 0, st>>>(atab, btab, h, g.mg, g.ng, g.w, g.ds, fsurf, fmin, coarse_st,
-                                    shifts, gaps, frefine);
+                                    shifts, gaps, frefine, only, recheck, kf, ke);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int count, int32_t v, hipStream_t st)
+{
+    clear_stale_error();
+    if (count <= 0) return hipSuccess;
+    k_fill_i32<<<(count + kBlock - 1) / kBlock, kBlock, 0, st>>>(p, count, v);
     return hipGetLastError();
 }
 

@@ -96,11 +96,19 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
 // pmax[frame] (may be null): a pixel bound for the x2 step (uint16), else INT32_MAX
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
                          int32_t *pmax, hipStream_t st);
+// only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
-                            double *h, hipStream_t st);
+                            double *h, hipStream_t st, const int32_t *only = nullptr);
+// only (may be null): frames whose only[f] is 0 are skipped.  recheck (may be
+// null): recheck[f] = 0 when the argmin is certified against a correlation
+// error of at most kf sqrt(m'n' Sa Sb) and energy errors of at most ke (Sa or
+// Sb), else 1.
 hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
-                          int32_t *shifts, double *gaps, double *frefine, hipStream_t st);
+                          int32_t *shifts, double *gaps, double *frefine, hipStream_t st,
+                          const int32_t *only = nullptr, int32_t *recheck = nullptr,
+                          double kf = 0.0, double ke = 0.0);
+hipError_t launch_fill_i32(int32_t *p, int count, int32_t v, hipStream_t st);
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, double *partial, hipStream_t st,
@@ -143,6 +151,9 @@ hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, co
 bool fft_plan(int n, FftPlan *pl);
 FftGeom fft_geom(const Geom &g);
 bool fft_applicable(const Geom &g);
+// coefficients of the certificate: |h^ - h| <= kf sqrt(m'n' Sa Sb), energy
+// errors <= ke Sa (Sa, Sb: the grids' sums of squares)
+void fft_error_coefs(const Geom &g, const FftTmpl &ft, double *kf, double *ke);
 size_t fft_s1_bytes(const Geom &g);   // per frame: [qh][mg] complex
 size_t fft_s2_bytes(const Geom &g);   // per frame: [W][qh] complex
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,

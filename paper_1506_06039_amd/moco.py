@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libmoco.so")
 
 MOCO_OK, MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE, MOCO_EBUSY, MOCO_ECANCELED = 0, -1, -2, -3, -4, -5
 MOCO_U16, MOCO_F32 = 1, 2
-FORMS = {"auto": 0, "fft": 1, "fp64": 3, "int8": 4}
+FORMS = {"auto": 0, "fft": 1, "fft_cert": 2, "fp64": 3, "int8": 4}
 
 
 class MocoError(RuntimeError):
@@ -37,7 +37,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 class _Outputs(ctypes.Structure):
     _fields_ = [("shifts", ctypes.c_void_p), ("fmin", ctypes.c_void_p),
                 ("fsurf", ctypes.c_void_p), ("frefine", ctypes.c_void_p),
-                ("coarse", ctypes.c_void_p), ("gaps", ctypes.c_void_p)]
+                ("coarse", ctypes.c_void_p), ("gaps", ctypes.c_void_p),
+                ("recomputed", ctypes.c_void_p)]
 
 
 _vp = ctypes.c_void_p
@@ -88,6 +89,9 @@ _lib.moco_server_destroy.argtypes = [_vp]
 _lib.moco_server_destroy.restype = _i
 _lib.moco_template_form.argtypes = [_vp, _i, ctypes.POINTER(_i)]
 _lib.moco_template_form.restype = _i
+_lib.moco_template_fft_bound.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+_lib.moco_template_fft_bound.restype = _i
 _lib.moco_last_error.argtypes = []
 _lib.moco_last_error.restype = ctypes.c_char_p
 _lib.moco_version.argtypes = []
@@ -183,6 +187,7 @@ class Result:
     coarse: torch.Tensor            # (T, 2) int32
     gaps: torch.Tensor              # (T, 2) float64
     fsurf: torch.Tensor | None      # (T, W, W) float64
+    recomputed: torch.Tensor | None = None  # (T,) int32
 
 
 def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "auto",
@@ -202,10 +207,9 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
             frefine=torch.empty((T, 9), dtype=torch.float64, device=dev),
             coarse=torch.empty((T, 2), dtype=torch.int32, device=dev),
             gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
-            fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None)
-    o = _Outputs(out.shifts.data_ptr(), out.fmin.data_ptr(),
-                 out.fsurf.data_ptr() if out.fsurf is not None else None,
-                 out.frefine.data_ptr(), out.coarse.data_ptr(), out.gaps.data_ptr())
+            fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None,
+            recomputed=torch.empty(T, dtype=torch.int32, device=dev))
+    o = _outputs(out)
     _check(_lib.moco_align(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), FORMS[form],
                            ctypes.byref(o), _stream_handle(dev)))
@@ -248,7 +252,15 @@ def _new_result(T: int, W: int, dev, surface: bool) -> Result:
         frefine=torch.empty((T, 9), dtype=torch.float64, device=dev),
         coarse=torch.empty((T, 2), dtype=torch.int32, device=dev),
         gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
-        fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None)
+        fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None,
+        recomputed=torch.empty(T, dtype=torch.int32, device=dev))
+
+
+def _outputs(r: Result) -> "_Outputs":
+    return _Outputs(r.shifts.data_ptr(), r.fmin.data_ptr(),
+                    r.fsurf.data_ptr() if r.fsurf is not None else None,
+                    r.frefine.data_ptr(), r.coarse.data_ptr(), r.gaps.data_ptr(),
+                    r.recomputed.data_ptr() if r.recomputed is not None else None)
 
 
 def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
@@ -268,9 +280,7 @@ def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
         res = it[2] if len(it) > 2 and it[2] is not None else \
             _new_result(T, 2 * tmpl.w - 1, dev, surface)
         results.append(res)
-        o = _Outputs(res.shifts.data_ptr(), res.fmin.data_ptr(),
-                     res.fsurf.data_ptr() if res.fsurf is not None else None,
-                     res.frefine.data_ptr(), res.coarse.data_ptr(), res.gaps.data_ptr())
+        o = _outputs(res)
         stacks[k] = _Stack(frames.data_ptr(), tmpl.handle.value, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), o)
     stream = _stream_handle(dev if dev is not None else ctx.device)
@@ -311,6 +321,14 @@ def resolved_form(ctx: Context, tmpl: Template, form: str) -> str:
     r = _i()
     _check(_lib.moco_template_form(tmpl.handle, FORMS[form], ctypes.byref(r)))
     return {v: k for k, v in FORMS.items()}[r.value]
+
+
+def fft_bound(tmpl: Template):
+    """moco_template_fft_bound: (kf, ke) with |h^ - h| <= kf sqrt(m'n' Sa Sb)
+    and energy errors <= ke Sa (Sa, Sb: the grids' sums of squares)."""
+    kf, ke = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.moco_template_fft_bound(tmpl.handle, ctypes.byref(kf), ctypes.byref(ke)))
+    return kf.value, ke.value
 
 
 def int8_products(tmpl: Template) -> int:

@@ -232,3 +232,33 @@ def mixed_stacks(nstacks: int = 64, seed: int = 0, max_len: int = 3000, min_len:
         sc = PoissonScene(m, n, T, seed=seed, stack=k + 1, max_shift=max(lim, 0))
         out.append(dict(scene=sc, T=T, m=m, n=n, w=w, downsample=ds))
     return out
+
+
+FAMILY_TIES = 4
+
+
+def row_periodic(m: int, n: int, T: int, dtype: str = "u16", max_shift: int = 4,
+                 noisy_every: int = 0, seed: int = 0):
+    """A template whose rows repeat with period two (two random rows, uint16 counts
+    around 200 or float32 around 1) and frames that are exact rolls of it by
+    planted shifts (|S|, |T| <= max_shift).  Every ``noisy_every``-th frame
+    (0: none) also gets Poisson (uint16) or Gaussian (float32, sigma 0.1) noise.
+    Many shifts then score exactly alike on the noise-free frames: the
+    degenerate case of the search's ties.  Returns (template, frames, shifts)."""
+    rng = _rng(seed, FAMILY_TIES, 0, SCENE_ID)
+    if dtype == "u16":
+        rows = rng.integers(100, 300, size=(2, n)).astype(np.float64)
+    else:
+        rows = rng.uniform(0.5, 1.5, size=(2, n))
+    base = rows[np.arange(m) % 2]
+    shifts = rng.integers(-max_shift, max_shift + 1, size=(T, 2)).astype(np.int32)
+    frames = np.empty((T, m, n), np.uint16 if dtype == "u16" else np.float32)
+    for k in range(T):
+        a = np.roll(base, (int(shifts[k, 0]), int(shifts[k, 1])), axis=(0, 1))
+        if noisy_every and k % noisy_every == noisy_every - 1:
+            fr = _rng(seed, FAMILY_TIES, 0, k)
+            a = fr.poisson(a).astype(np.float64) if dtype == "u16" else \
+                a + fr.normal(0.0, 0.1, size=a.shape)
+        frames[k] = a
+    tmpl = base.astype(np.uint16 if dtype == "u16" else np.float32)
+    return tmpl, frames, shifts

@@ -96,3 +96,29 @@ def test_default_params_follow_the_paper_without_gpu(lib):
         assert lib.moco_default_params(m, n, ctypes.byref(w), ctypes.byref(ds)) == 0
         assert (w.value, ds.value) == want, (m, n)
     assert lib.moco_default_params(0, 5, ctypes.byref(w), ctypes.byref(ds)) == -1
+
+
+def test_fft_bound_null_arguments_rejected_without_gpu(lib):
+    lib.moco_template_fft_bound.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.moco_template_fft_bound.restype = ctypes.c_int
+    assert lib.moco_template_fft_bound(None, None, None) == -1
+
+
+def test_binding_structs_match_the_header(lib, tmp_path):
+    """The ctypes records of the binding have the header's sizes and field offsets."""
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "moco.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(moco_outputs),\n'
+        "         offsetof(moco_outputs, recomputed), sizeof(moco_stack),\n"
+        "         offsetof(moco_stack, out), sizeof(moco_result), offsetof(moco_result, latency_us));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    from paper_1506_06039_amd import moco
+    want = [ctypes.sizeof(moco._Outputs), moco._Outputs.recomputed.offset,
+            ctypes.sizeof(moco._Stack), moco._Stack.out.offset,
+            ctypes.sizeof(moco.ServerResult), moco.ServerResult.latency_us.offset]
+    assert got == want

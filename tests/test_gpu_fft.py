@@ -155,7 +155,7 @@ def test_wide_window_paper_shape_auto_picks_fft(gpu_lib):
     fr = sc.frames(0, 3)
     ctx = gpu_lib.Context(0)
     tp = gpu_lib.Template(ctx, _to_dev(sc.template), 69, True)
-    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft"
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft_cert"
     tp.close()
     ctx.close()
     _say("case paper shape 416x460 w=69 ds=1")

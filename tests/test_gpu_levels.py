@@ -57,7 +57,7 @@ def test_auto_with_two_levels_is_not_int8(gpu_lib):
     sc = synth.poisson512_u16(T=4)
     ctx = gpu_lib.Context(0)
     tp = gpu_lib.Template(ctx, _dev(sc.template), 16, 2)
-    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft"
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft_cert"
     with pytest.raises(gpu_lib.MocoError) as ei:
         gpu_lib.moco_align(ctx, _dev(sc.frames(0, 2)), tp, form="int8")
     assert ei.value.code == gpu_lib.MOCO_EINVAL

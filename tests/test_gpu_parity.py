@@ -202,7 +202,7 @@ def test_int8_bright_template_falls_back(gpu_lib):
     r = gpu_lib.moco_align(ctx, _to_dev(fr), tp, form="auto")
     torch.cuda.synchronize()
     assert r.shifts.cpu().numpy().tolist() == [[1, -2]]
-    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft"
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft_cert"
 
 
 def test_auto_picks_int8_for_uint16(gpu_lib):
@@ -211,7 +211,7 @@ def test_auto_picks_int8_for_uint16(gpu_lib):
     tp = gpu_lib.Template(ctx, _to_dev(sc.template), 32, True)
     assert gpu_lib.resolved_form(ctx, tp, "auto") == "int8"
     tf = gpu_lib.Template(ctx, _to_dev(sc.template.astype(np.float32)), 32, True)
-    assert gpu_lib.resolved_form(ctx, tf, "auto") == "fft"
+    assert gpu_lib.resolved_form(ctx, tf, "auto") == "fft_cert"
 
 
 def test_int8_equals_fp64_on_a_stack(gpu_lib):
@@ -284,7 +284,7 @@ def test_batch_of_uneven_stacks_matches_single_calls_and_oracle(gpu_lib):
         got = {k: getattr(r, k).cpu().numpy() for k in ("shifts", "fmin", "frefine", "coarse", "gaps")}
         orc = oracle.align(fr[:2], tm, sp["w"], sp["downsample"])
         got2 = {k: v[:2] for k, v in got.items()}
-        exact = gpu_lib.resolved_form(ctx, tp, "auto") != "fft"
+        exact = gpu_lib.resolved_form(ctx, tp, "auto") not in ("fft", "fft_cert")
         check(got2, orc, sp["downsample"], exact=exact,
               label="batch %dx%d w%d" % (sp["m"], sp["n"], sp["w"]))
 
