@@ -344,13 +344,15 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     int trow, int padl, int w, int tgroups, long long *__restrict__ hout)
 {
     constexpr int RING = 32 * NS;     // frame rows an iteration reads
-    constexpr int RS = RING + 2;      // ring slots: two rows arrive ahead of use
+    constexpr int RS = RING + 3;      // ring slots: a pair of rows reads RING + 1, the next
+                                      // pair's two arrive meanwhile
     constexpr int NACC = NPA * 2;
     constexpr int KC = kStrip / 32;   // MFMA K-chunks per strip (npad is a multiple of kStrip)
     __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * RS * kSlotStride];
     __shared__ __attribute__((aligned(16))) int8_t s_tA[2 * kPhases * kMaxTrow];
     __shared__ __attribute__((aligned(16))) int8_t s_tB[2 * kPhases * kMaxTrow];
     __shared__ __attribute__((aligned(16))) int8_t s_tC[2 * kPhases * kMaxTrow];
+    __shared__ __attribute__((aligned(16))) int8_t s_tD[2 * kPhases * kMaxTrow];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int rho = lane % 32, h = lane / 32;
@@ -430,21 +432,15 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     };
 
     for (int ks = 0; ks < npad; ks += kStrip) {
-        // rows for i = i_lo and the two that follow: i_lo + s_lo + q, q < RING + 1;
-        // template rows i_lo and i_lo + 1
+        // frame rows for the first pair (template rows i_lo and i_lo + 1):
+        // i_lo + s_lo + q, q < RING + 1; template rows i_lo and i_lo + 1
         for (int q = 0; q <= RING; ++q) ring_fill(i_lo + s_lo + q, ks);
         dma_row(i_lo, s_tA);
-        dma_row(i_lo + 1 < i_hi ? i_lo + 1 : i_lo, s_tB);
+        if (i_lo + 1 < i_hi) dma_row(i_lo + 1, s_tB);
         wait_barrier<0>();
 
-        // one template row: MFMAs with row i from tcur while template row i+2
-        // and frame row i + s_lo + RING + 1 (both used two rows later) stream in
-        auto step = [&](int i, const int8_t *tcur, int8_t *tnext2) {
-            // past the last row a transfer still goes out (a valid row into a
-            // buffer no later row reads), keeping the count per row fixed
-            dma_row(i + 2 < i_hi ? i + 2 : i_lo, tnext2);
-            ring_fill(i + s_lo + RING + 1, ks);
-
+        // MFMAs of template row i (from tcur) against frame rows i + s
+        auto rowmma = [&](int i, const int8_t *tcur) {
             // operand addresses of K-chunk 0; chunk kc adds kc*32 bytes.  The byte
             // phase of a template read does not depend on kc (32 is a multiple of 8).
             const int8_t *abase[NS][NPA];
@@ -502,6 +498,17 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                             for (int q = 0; q < 2; ++q)
                                 acc[st][tt][p * 2 + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                     av[st][p], bv[tt][q], acc[st][tt][p * 2 + q], 0, 0, 0);
+                // issue order: one MFMA, one LDS read of the next chunk, ..., then
+                // the remaining MFMAs (with one wave per SIMD, a burst of reads
+                // would hold back the MFMA issue, and reads sunk next to their
+                // uses would stall on their latency)
+#pragma unroll
+                for (int g = 0; g < NS * NPA + NT * 2; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, NS * NT * NPA * 2, 0);
+                __builtin_amdgcn_sched_barrier(0);
                 if (kc + 1 < KC) {
 #pragma unroll
                     for (int st = 0; st < NS; ++st)
@@ -513,22 +520,25 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                         for (int q = 0; q < 2; ++q) bv[tt][q] = bn[tt][q];
                 }
             }
-            // The transfers of the previous row (row i+1's template row and ring
-            // row) must have landed, and this wave's LDS reads of tcur must be
-            // done, before the barrier; this row's NDMA + 1 transfers may stay in
-            // flight (the load counter retires in order).
-            wait_barrier<NDMA + 1>();
         };
-        int i = i_lo;
-        for (; i + 2 < i_hi; i += 3) {
-            step(i, s_tA, s_tC);
-            step(i + 1, s_tB, s_tA);
-            step(i + 2, s_tC, s_tB);
+        // A pair of template rows i, i+1 (from t0, t1) while the next pair's
+        // template rows (into n0, n1, the buffers of the previous pair) and frame
+        // rows i + s_lo + RING + 1, + 2 stream in.  One barrier per pair: every
+        // transfer of this pair has landed and every wave is done with t0, t1
+        // before the next pair reads n0, n1 and refills t0, t1.
+        auto pair = [&](int i, const int8_t *t0, const int8_t *t1, int8_t *n0, int8_t *n1) {
+            if (i + 2 < i_hi) dma_row(i + 2, n0);
+            if (i + 3 < i_hi) dma_row(i + 3, n1);
+            ring_fill(i + s_lo + RING + 1, ks);
+            ring_fill(i + s_lo + RING + 2, ks);
+            rowmma(i, t0);
+            if (i + 1 < i_hi) rowmma(i + 1, t1);
+            wait_barrier<0>();
+        };
+        for (int i = i_lo; i < i_hi; i += 4) {
+            pair(i, s_tA, s_tB, s_tC, s_tD);
+            if (i + 2 < i_hi) pair(i + 2, s_tC, s_tD, s_tA, s_tB);
         }
-        if (i < i_hi) step(i, s_tA, s_tC);
-        if (i + 1 < i_hi) step(i + 1, s_tB, s_tA);
-        // nothing may still be landing when the next strip refills the buffers
-        wait_barrier<0>();
     }
 
     if (!live) return;
