@@ -129,7 +129,7 @@ def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz
         srv.add_source(k, frames_np[k * per], W_WIN, DS)
 
     def run(closed_loop: bool):
-        lat, done, tag = [], 0, 0
+        lat, done, tag, refused = [], 0, 0, 0
         nxt = [0.0] * nsrc
         inflight = [0] * nsrc
         cursor = [1] * nsrc
@@ -147,6 +147,8 @@ def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz
                         inflight[k] += 1
                         cursor[k] = cursor[k] % (per - 1) + 1
                         nxt[k] = max(nxt[k] + 1.0 / rate_hz, now)
+                    else:
+                        refused += 1
             for r in srv.poll(256, timeout_us=200):
                 inflight[r.source] -= 1
                 lat.append(r.latency_us)
@@ -157,14 +159,124 @@ def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz
                 done += 1
         wall = time.perf_counter() - t0
         lat = np.array(lat) if lat else np.zeros(1)
-        return {"frames": done, "frames_per_s": round(done / wall, 1),
+        return {"frames": done, "frames_per_s": round(done / wall, 1), "seconds": round(wall, 2),
+                "admitted": tag, "refused_busy": refused,
                 "p50_us": round(float(np.percentile(lat, 50)), 1),
-                "p99_us": round(float(np.percentile(lat, 99)), 1)}
+                "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "p99_9_us": round(float(np.percentile(lat, 99.9)), 1)}
 
     out = {"sources": nsrc, "rate_hz": rate_hz, "frame": "512x512 uint16",
            "closed_loop": run(True), "saturation": run(False)}
     srv.close()
     return out
+
+
+def measure_batch(moco, ctx, steps: int, unique: int = 8):
+    """The mixed batch: 64 stacks of uneven length, frame size and window
+    (128x128, 256x256, 512x512, 512x796; 50-3000 frames; w from {8, 16, 32, 48};
+    downsampled iff a side exceeds 256), each stack's first `unique` synthetic
+    frames repeated to its length, template = its frame 0.  One moco_align_batch
+    call under AUTO against a loop of moco_align calls, one per stack, on the
+    same stream with the same outputs."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    items, total, nbytes = [], 0, 0
+    t0 = time.time()
+    for sp in synth.mixed_stacks(64):
+        sc, T = sp["scene"], sp["T"]
+        u = min(unique, T)
+        uniq = torch.from_numpy(sc.frames(0, u)).to(dev)
+        fr = torch.empty((T, sp["m"], sp["n"]), dtype=uniq.dtype, device=dev)
+        for k in range(0, T, u):
+            fr[k:k + u] = uniq[:min(u, T - k)]
+        tp = moco.Template(ctx, torch.from_numpy(sc.template).to(dev), sp["w"], sp["downsample"])
+        items.append((fr, tp, moco._new_result(T, 2 * sp["w"] - 1, dev, False)))
+        total += T
+        nbytes += fr.numel() * fr.element_size()
+        del uniq
+    print("[bench] batch of %d stacks, %d frames (%.1f GB) ready in %.1fs"
+          % (len(items), total, nbytes / 1e9, time.time() - t0), file=sys.stderr, flush=True)
+    forms = {}
+    for it in items:
+        f = moco.resolved_form(ctx, it[1], "auto")
+        forms[f] = forms.get(f, 0) + 1
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t) / steps
+
+    dt_batch = timed(lambda: moco.moco_align_batch(ctx, items, form="auto"))
+    dt_loop = timed(lambda: [moco.moco_align(ctx, fr, tp, out=res) for fr, tp, res in items])
+    for it in items:
+        it[1].close()
+    del items
+    torch.cuda.empty_cache()
+    return {"stacks": 64, "frames": total, "bytes": nbytes, "unique_frames_per_stack": unique,
+            "forms": forms, "steps": steps,
+            "batched": {"seconds": round(dt_batch, 5), "frames_per_s": round(total / dt_batch, 1)},
+            "per_stack_loop": {"seconds": round(dt_loop, 5),
+                               "frames_per_s": round(total / dt_loop, 1)}}
+
+
+def measure_h2d(moco, ctx, tp, frames, out, steps: int, chunk: int = 250):
+    """End to end from pinned host memory (the stack copied to the device, then
+    aligned): the copy and the search one after the other, and chunked with the
+    copy of chunk k+1 on a second stream (default priority) while chunk k is
+    aligned."""
+    import torch
+    dev = frames.device
+    T = frames.shape[0]
+    host = torch.empty(frames.shape, dtype=frames.dtype, pin_memory=True)
+    host.copy_(frames.cpu())
+    dst = torch.empty_like(frames)
+    copy_stream = torch.cuda.Stream(device=dev)
+    compute = torch.cuda.current_stream(dev)
+    nb = host.numel() * host.element_size()
+
+    def sequential():
+        dst.copy_(host, non_blocking=True)
+        moco.moco_align(ctx, dst, tp, out=out)
+
+    def pipelined():
+        evs = []
+        for a in range(0, T, chunk):
+            b = min(T, a + chunk)
+            with torch.cuda.stream(copy_stream):
+                dst[a:b].copy_(host[a:b], non_blocking=True)
+                e = torch.cuda.Event()
+                e.record(copy_stream)
+            evs.append((a, b, e))
+        for a, b, e in evs:
+            compute.wait_event(e)
+            part = moco.Result(shifts=out.shifts[a:b], fmin=out.fmin[a:b],
+                               frefine=out.frefine[a:b], coarse=out.coarse[a:b],
+                               gaps=out.gaps[a:b], fsurf=None)
+            moco.moco_align(ctx, dst[a:b], tp, out=part)
+
+    def copy_only():
+        dst.copy_(host, non_blocking=True)
+
+    res = {}
+    for name, fn in (("copy_only", copy_only), ("sequential", sequential),
+                     ("pipelined", pipelined)):
+        fn()
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize(dev)
+        dt = (time.perf_counter() - t) / steps
+        res[name] = {"ms": round(1000 * dt, 3), "frames_per_s": round(T / dt, 1)}
+    res["copy_only"]["GB_per_s"] = round(nb / (res["copy_only"]["ms"] / 1000) / 1e9, 1)
+    res["chunk_frames"] = chunk
+    del host, dst
+    return res
 
 
 def main():
@@ -187,7 +299,11 @@ def main():
                          "empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed runs of the 64-stack mixed batch, batched and per stack (0: skip)")
+    ap.add_argument("--h2d-steps", type=int, default=3,
+                    help="timed end-to-end runs from pinned host memory (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of each serving measurement (0: skip serving)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), the "
@@ -242,13 +358,17 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize(dev)
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t_start = time.perf_counter()
     ev0.record()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        step_ev[k].record()
         moco.moco_align(ctx, frames, tp, form=args.form, out=out)
+    step_ev[args.steps].record()
     ev1.record()
     torch.cuda.synchronize(dev)
     t_end = time.perf_counter()
+    step_ms = [step_ev[k].elapsed_time(step_ev[k + 1]) for k in range(args.steps)]
     moco.profile_enable(ctx, False)
     stage_ms, stage_launches = moco.profile_read(ctx)
     wall_s = t_end - t_start
@@ -361,6 +481,8 @@ def main():
         if args.serve_seconds > 0 else None
     paper_shapes = measure_paper_shapes(moco, ctx, args.paper_steps) \
         if args.paper_steps > 0 else None
+    h2d = measure_h2d(moco, ctx, tp, frames, out, args.h2d_steps) if args.h2d_steps > 0 else None
+    batch = measure_batch(moco, ctx, args.batch_steps) if args.batch_steps > 0 else None
 
     # rerun the stack once more for the parity sample (the timed outputs were overwritten by
     # the latency loop's first rows)
@@ -379,6 +501,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "gpu_ms_per_step": round(gpu_ms / args.steps, 4),
+        "gpu_ms_per_step_median": round(float(np.median(step_ms)), 4),
+        "gpu_ms_per_step_min": round(float(np.min(step_ms)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -392,8 +516,11 @@ def main():
         "apply": apply_res,
         "serving": serving,
         "paper_shapes": paper_shapes,
+        "h2d": h2d,
+        "batch": batch,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
                         "p99": round(float(np.percentile(lat_us, 99)), 1),
+                        "p99_9": round(float(np.percentile(lat_us, 99.9)), 1),
                         "frames": 1, "iters": args.latency_iters} if lat_us.size else None),
     }
 
