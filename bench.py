@@ -47,13 +47,18 @@ def useful_macs(mg: int, ng: int, w: int) -> int:
 
 def kernel_source_sha(fname: str) -> str:
     """Hash of a kernel file's device code: the text up to the end of its
-    anonymous namespace (the kernels and the launch-variant choice), so that a
-    change to the host-side checks after it keeps the counters valid."""
+    anonymous namespace (the kernels and the launch-variant choice), without
+    comments and blank space, so that a change to the host-side checks after it,
+    or to comments, keeps the counters valid."""
+    import re
     p = os.path.join(ROOT, "paper_1506_06039_amd", "csrc", fname)
     text = open(p, "rb").read()
     cut = text.find(b"\n}  // namespace\n")
     if cut >= 0:
         text = text[:cut]
+    text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+    text = re.sub(rb"//[^\n]*", b"", text)
+    text = re.sub(rb"\s+", b" ", text)
     return hashlib.sha256(text).hexdigest()[:16]
 
 

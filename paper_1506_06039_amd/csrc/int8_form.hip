@@ -330,13 +330,14 @@ __device__ __forceinline__ void wait_barrier()
 // Per template row i and strip of 128 frame columns: each wave reads its A
 // operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
 // (template row i as a Toeplitz operand) from the shared template buffer, four
-// K-chunks of 32 columns, 16 MFMAs per chunk, operands of chunk k+1 loaded
-// before the MFMAs of chunk k.  Template row i+2 and frame row i+s_lo+RING+1
-// stream global -> LDS (no registers) while row i is in use, two rows ahead:
-// the template rows rotate through three statically distinct buffers (the row
-// loop is unrolled by three, so every LDS read provably targets a buffer other
-// than the ones being filled), and the wait at the end of a row lets that
-// row's own transfers (a fixed NDMA + NPA per wave) stay in flight.
+// K-chunks of 32 columns, 16 MFMAs per chunk, the LDS reads of chunk k+1
+// interleaved with the MFMAs of chunk k.  Template rows are taken in pairs:
+// while rows i, i+1 are in use, template rows i+2, i+3 and frame rows
+// i+s_lo+RING+1, +2 stream global -> LDS (no registers) into the other two of
+// four statically distinct template buffers (the pair loop is unrolled by two,
+// so every LDS read provably targets a buffer other than the ones being
+// filled) and two free ring slots; one wait for every transfer and one
+// barrier per pair.
 template <int NS, int NT, int NPA, int PA0, int NDMA>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
@@ -398,8 +399,8 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     // The compiler cannot tell ring slots apart, so it would wait for every ring
     // transfer before the next ring read; the slot address goes through an empty
     // asm so that it does not.  The reads of a row are ordered after its
-    // transfer by the explicit waits: the rows step i reads were all requested
-    // by step i-2 or earlier, and step i-1 ends with every transfer but its own
+    // transfer by the explicit waits: the rows a pair reads were requested by
+    // the previous pair (or before the first), which ended with every transfer
     // retired.
     auto ring_fill = [&](int r, int ks) {
         const int slot = (r - s_lo) % RS;
