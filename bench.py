@@ -176,6 +176,54 @@ def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz
     return out
 
 
+def measure_peaks(dev, iters: int = 20000, reps: int = 3):
+    """What the device sustains, beside the published peaks: int8 MFMA ops/s of
+    a register-only loop of 32x32x32 MFMAs (one wave per SIMD, as the
+    correlation kernel runs), and the HBM bytes/s of a plain 1 GiB device copy
+    (read + write), both timed with HIP events on the stream they run on."""
+    import ctypes
+    import torch
+    res = {}
+    path = os.path.join(ROOT, "paper_1506_06039_amd", "libmoco_probe.so")
+    stream = torch.cuda.current_stream(dev)
+    if os.path.exists(path):
+        lib = ctypes.CDLL(path)
+        lib.probe_mfma_i8.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p]
+        lib.probe_mfma_i8.restype = ctypes.c_int
+        lib.probe_mfma_i8_ops.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.probe_mfma_i8_ops.restype = ctypes.c_double
+        blocks = torch.cuda.get_device_properties(dev).multi_processor_count
+        out = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+        if lib.probe_mfma_i8(blocks, 100, out.data_ptr(), stream.cuda_stream) == 0:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                lib.probe_mfma_i8(blocks, iters, out.data_ptr(), stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            sec = e0.elapsed_time(e1) / 1000.0 / reps
+            tops = lib.probe_mfma_i8_ops(blocks, iters) / sec / 1e12
+            res["int8_mfma_tops"] = round(tops, 1)
+            res["int8_frac_of_published"] = round(tops / PEAK_INT8_TOPS, 4)
+            res["mfma_probe"] = "%d blocks x 4 waves, %d x 16 MFMAs per wave" % (blocks, iters)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize(dev)
+    sec = e0.elapsed_time(e1) / 1000.0 / reps
+    gbs = 2.0 * src.numel() / sec / 1e9
+    res["hbm_copy_GBps"] = round(gbs, 1)
+    res["hbm_frac_of_published"] = round(gbs / PEAK_HBM_GBS, 4)
+    del src, dst
+    return res
+
+
 def measure_batch(moco, ctx, steps: int, unique: int = 8):
     """The mixed batch: 64 stacks of uneven length, frame size and window
     (128x128, 256x256, 512x512, 512x796; 50-3000 frames; w from {8, 16, 32, 48};
@@ -304,6 +352,8 @@ def main():
                          "empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the sustained MFMA and copy measurements")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed runs of the 64-stack mixed batch, batched and per stack (0: skip)")
     ap.add_argument("--h2d-steps", type=int, default=3,
@@ -410,6 +460,9 @@ def main():
         dtype = "f64"
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = load_traffic(kname, ksrc, frames_per_launch)
+    peaks = measure_peaks(dev) if not args.no_peaks else None
+    if peaks and form_ran == "int8" and "int8_mfma_tops" in peaks:
+        roof["frac_of_measured_peak"] = roof["achieved"] / peaks["int8_mfma_tops"]
     roof["kernel"] = kname
     roof = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()}
 
@@ -516,6 +569,7 @@ def main():
         "config": {"workload": WORKLOAD, "frames": T, "m": M, "n": N, "w": W_WIN,
                    "downsample": DS, "form": form_ran, "template": "frame 0"},
         "roofline": roof,
+        "peaks_measured": peaks,
         "stages": stages,
         "forms": forms,
         "apply": apply_res,

@@ -24,6 +24,22 @@ FLAGS = [
 ]
 
 
+PROBE_SOURCE = "probe.hip"
+PROBE_LIB = os.path.join(PKG, "libmoco_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """libmoco_probe.so: the matrix-core rate probe the benchmark reports beside
+    the published peak (not part of libmoco.so)."""
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", os.path.join(CSRC, PROBE_SOURCE), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
@@ -42,6 +58,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 

@@ -1,0 +1,56 @@
+// Sustained int8 matrix-core rate of the device, for the roofline beside the
+// published peak: every wave issues back-to-back v_mfma_i32_32x32x32_i8 on
+// register operands into 16 independent accumulators, with no memory traffic
+// in the loop.  Measurement infrastructure only (libmoco_probe.so, loaded by
+// the benchmark); the search never calls it.
+#include <hip/hip_runtime.h>
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kBlock = 256;
+constexpr int kAcc = 16;
+
+__global__ __launch_bounds__(kBlock, 1) void k_mfma_i8_probe(int iters, int *__restrict__ out)
+{
+    v16i acc[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) acc[k] = v16i{0};
+    const v4i a = {(int)threadIdx.x, 0x01020304, 0x05060708, 0x090a0b0c};
+    const v4i b = {(int)blockIdx.x, 0x0d0e0f10, 0x11121314, 0x15161718};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k)
+            acc[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[k], 0, 0, 0);
+    }
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s += acc[k][r];
+    out[(size_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Launch `blocks` blocks of four waves, each running `iters` iterations of 16
+// MFMAs (32x32x32 int8, 65536 operations each), on `stream`; d_out holds
+// blocks * 256 ints.  Returns the launch status.
+int probe_mfma_i8(int blocks, int iters, int *d_out, void *stream)
+{
+    if (blocks < 1 || iters < 1 || !d_out) return (int)hipErrorInvalidValue;
+    k_mfma_i8_probe<<<blocks, kBlock, 0, (hipStream_t)stream>>>(iters, d_out);
+    return (int)hipGetLastError();
+}
+
+// Operations one launch performs.
+double probe_mfma_i8_ops(int blocks, int iters)
+{
+    return (double)blocks * (kBlock / 64) * iters * kAcc * 32.0 * 32.0 * 32.0 * 2.0;
+}
+
+}  // extern "C"
