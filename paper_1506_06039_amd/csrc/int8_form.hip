@@ -99,7 +99,7 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 }
 
 template <bool DS, int kMaxCol4>
-__global__ __launch_bounds__(kBlock) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
                                                      int8_t *__restrict__ limbs,
                                                      int32_t *__restrict__ nlimb,
