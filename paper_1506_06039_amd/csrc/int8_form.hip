@@ -342,7 +342,7 @@ template <int NS, int NT, int NPA, int PA0, int NDMA>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
     const int8_t *__restrict__ tp, const int8_t *__restrict__ zsrc, int C, int mg, int npad,
-    int trow, int padl, int w, int tgroups, long long *__restrict__ hout)
+    int trow, int padl, int w, int tgroups, int nslice, long long *__restrict__ hout)
 {
     constexpr int RING = 32 * NS;     // frame rows an iteration reads
     constexpr int RS = RING + 3;      // ring slots: a pair of rows reads RING + 1, the next
@@ -363,7 +363,13 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int s_lo = -(w - 1) + 32 * NS * sg;
     const int t_lo = -(w - 1) + 32 * NT * tg;
     const int s_hi = min(s_lo + RING - 1, w - 1);
-    const int i_lo = max(0, -s_hi), i_hi = min(mg, mg - s_lo);
+    // template rows of this block: slice blockIdx.z of the rows the shift group
+    // overlaps (nslice > 1 splits a few frames' work over many blocks, which then
+    // add their exact partial sums into the zeroed table)
+    const int r_lo = max(0, -s_hi), r_hi = min(mg, mg - s_lo);
+    const int slen = (r_hi - r_lo + nslice - 1) / nslice;
+    const int i_lo = r_lo + (int)blockIdx.z * slen, i_hi = min(r_hi, i_lo + slen);
+    if (i_lo >= i_hi) return;
     const size_t plane = (size_t)mg * npad;
 
     // does this wave's frame take part in this pass?
@@ -560,7 +566,9 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                     for (int q = 0; q < 2; ++q)
                         v += (long long)acc[st][tt][p * 2 + q][r] * (1LL << (8 * (PA0 + p + q)));
                 size_t k = (size_t)(s + w - 1) * W + (t + w - 1);
-                if (PA0 == 0)
+                if (nslice > 1)
+                    atomicAdd((unsigned long long *)&H[k], (unsigned long long)v);
+                else if (PA0 == 0)
                     H[k] = v;
                 else
                     H[k] += v;
@@ -661,29 +669,53 @@ __global__ __launch_bounds__(kBlock) void k_combine_i64(const long long *__restr
 
 template <int NS, int NT, int NPA, int PA0, int NDMA>
 hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                            const Geom &g, long long *h, hipStream_t st)
+                            const Geom &g, int nslice, long long *h, hipStream_t st)
 {
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
-    dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups);
+    dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups, nslice);
     const int8_t *zsrc = tt.tp + (size_t)g.mg * 2 * kPhases * tt.trow;  // zero tail
     k_corr_int8<NS, NT, NPA, PA0, NDMA><<<grid, kBlock, 0, st>>>(
-        limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, h);
+        limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, nslice, h);
     return hipGetLastError();
 }
 
 template <int NS, int NT, int NPA, int PA0>
 hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
-                               int C, const Geom &g, long long *h, hipStream_t st)
+                               int C, const Geom &g, int nslice, long long *h, hipStream_t st)
 {
     // transfers per wave for a quarter of a template row (4 * trow bytes)
     switch ((4 * tt.trow + 1023) / 1024) {
-    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1>(limbs, nlimb, tt, C, g, h, st);
-    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2>(limbs, nlimb, tt, C, g, h, st);
-    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3>(limbs, nlimb, tt, C, g, h, st);
-    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4>(limbs, nlimb, tt, C, g, h, st);
+    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4>(limbs, nlimb, tt, C, g, nslice, h, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Row slices per block group: with fewer blocks than compute units (a few
+// frames), enough slices to cover the device twice over, each slice at least 8
+// template rows (a slice first fills its ring with 32 NS + 1 frame rows).
+int corr_slices(int C, const Geom &g, int NS, int NT)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    const long long groups = (long long)((g.W + 32 * NS - 1) / (32 * NS)) *
+                             ((g.W + 32 * NT - 1) / (32 * NT));
+    const long long blocks = (long long)(C + kWaves - 1) / kWaves * groups;
+    if (blocks >= cus) return 1;
+    const long long want = (2LL * cus + blocks - 1) / blocks;
+    const int most = max(1, g.mg / 8);
+    return (int)(want < most ? want : most);
 }
 
 int grid_for(size_t total)
@@ -782,13 +814,21 @@ hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int
     clear_stale_error();
     if (C == 0) return hipSuccess;
     hipError_t e;
-    if (g.W <= 32) {
-        if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, h, st)) != hipSuccess)
-            return e;
-        return launch_corr_variant<1, 1, 1, 2>(limbs, nlimb, tt, C, g, h, st);
+    const bool small = g.W <= 32;
+    const int nslice = small ? corr_slices(C, g, 1, 1) : corr_slices(C, g, 2, 2);
+    if (nslice > 1) {
+        // the slices add into a zeroed table
+        if ((e = launch_fill_i32((int32_t *)h, 2 * C * g.W * g.W, 0, st)) != hipSuccess) return e;
     }
-    if ((e = launch_corr_variant<2, 2, 2, 0>(limbs, nlimb, tt, C, g, h, st)) != hipSuccess) return e;
-    return launch_corr_variant<2, 2, 1, 2>(limbs, nlimb, tt, C, g, h, st);
+    if (small) {
+        if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st)) !=
+            hipSuccess)
+            return e;
+        return launch_corr_variant<1, 1, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
+    }
+    if ((e = launch_corr_variant<2, 2, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st)) != hipSuccess)
+        return e;
+    return launch_corr_variant<2, 2, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
 }
 
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
