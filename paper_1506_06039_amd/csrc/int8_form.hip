@@ -98,8 +98,8 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
     for (int q = 0; q < 4; ++q) X[q] = (j0 + q < ng) ? grid_value<DS>(a, n, i, j0 + q) : 0;
 }
 
-template <bool DS, int kMaxCol4>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
+template <bool DS, int kMaxCol4, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
                                                      int8_t *__restrict__ limbs,
                                                      int32_t *__restrict__ nlimb,
@@ -107,12 +107,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                      long long *__restrict__ atab,
                                                      long long *__restrict__ edge)
 {
-    // dynamic LDS: colE[npad] | rowbuf[kWaves][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
+    // dynamic LDS: colE[npad] | rowbuf[NW][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
     extern __shared__ long long lds_prep[];
     const int we1 = w > 1 ? w - 1 : 1;
     long long *colE = lds_prep;
     long long *rowbuf_base = colE + npad;   // X^2 of the first / last w-1 columns of an edge row
-    long long *rT = rowbuf_base + (size_t)kWaves * 2 * we1;
+    long long *rT = rowbuf_base + (size_t)NW * 2 * we1;
     long long *rB = rT + w;
     long long *cL = rB + w;
     long long *cR = cL + w;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     long long my_etot = 0;
     int my_need3 = 0;
 
-    for (int i = wave; i < mg; i += kWaves) {
+    for (int i = wave; i < mg; i += NW) {
         const bool top = i < we, bot = i >= mg - we;
         long long rpart = 0;
 #pragma unroll
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     // third digit plane, only for frames that need it
     if (need3) {
         int8_t *L2 = L0 + 2 * plane;
-        for (int i = wave; i < mg; i += kWaves)
+        for (int i = wave; i < mg; i += NW)
             for (int j0 = 4 * lane; j0 < npad; j0 += 256) {
                 int d2p = 0;
                 for (int q = 0; q < 4; ++q) {
@@ -764,6 +764,25 @@ size_t int8_template_bytes(const Geom &g)
     return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow + kInt8ZeroTail;
 }
 
+template <bool DS, int NW>
+void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int nc, size_t lds,
+                    int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
+                    long long *edge, hipStream_t st)
+{
+    if (nc <= 1)
+        k_prep_u16<DS, 1, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
+                                                       limbs, nlimb, vmax, atab, edge);
+    else if (nc <= 2)
+        k_prep_u16<DS, 2, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
+                                                       limbs, nlimb, vmax, atab, edge);
+    else if (nc <= 4)
+        k_prep_u16<DS, 4, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
+                                                       limbs, nlimb, vmax, atab, edge);
+    else
+        k_prep_u16<DS, 8, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
+                                                       limbs, nlimb, vmax, atab, edge);
+}
+
 template <bool DS>
 void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
                  int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, hipStream_t st)
@@ -771,20 +790,17 @@ void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t 
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
     const int we1 = g.w > 1 ? g.w - 1 : 1;
-    const size_t lds = ((size_t)npad + (size_t)kWaves * 2 * we1 + 4 * (size_t)g.w + 2) *
-                       sizeof(long long);
-    if (nc <= 1)
-        k_prep_u16<DS, 1><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                                  nlimb, vmax, atab, edge);
-    else if (nc <= 2)
-        k_prep_u16<DS, 2><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                                  nlimb, vmax, atab, edge);
-    else if (nc <= 4)
-        k_prep_u16<DS, 4><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                                  nlimb, vmax, atab, edge);
+    auto lds_for = [&](int nw) {
+        return ((size_t)npad + (size_t)nw * 2 * we1 + 4 * (size_t)g.w + 2) * sizeof(long long);
+    };
+    // a few frames: sixteen waves per frame (one block of four waves streams a
+    // frame at a fraction of the device's bandwidth)
+    if (C <= 128 && lds_for(16) <= 64 * 1024)
+        prep_launch_nw<DS, 16>(frames, C, g, npad, nc, lds_for(16), limbs, nlimb, vmax, atab,
+                               edge, st);
     else
-        k_prep_u16<DS, 8><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad, limbs,
-                                                  nlimb, vmax, atab, edge);
+        prep_launch_nw<DS, kWaves>(frames, C, g, npad, nc, lds_for(kWaves), limbs, nlimb, vmax,
+                                   atab, edge, st);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
