@@ -596,7 +596,8 @@ __device__ inline bool precedes_i(double f1, int s1, int t1, double f2, int s2, 
     return t1 < t2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_combine_i64(const long long *__restrict__ atab,
+template <int TB>
+__global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict__ atab,
                                                         const long long *__restrict__ btab_t,
                                                         const long long *__restrict__ hbuf,
                                                         int mg, int ng, int w, int ds,
@@ -629,8 +630,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_i64(const long long *__restr
             c.second = fmin(c.second, f);
         }
     }
-    __shared__ double sf[kBlock], ss2[kBlock];
-    __shared__ int si_[kBlock], sj_[kBlock];
+    __shared__ double sf[TB], ss2[TB];
+    __shared__ int si_[TB], sj_[TB];
     int tid = threadIdx.x;
     sf[tid] = c.f; ss2[tid] = c.second; si_[tid] = c.s; sj_[tid] = c.t;
     __syncthreads();
@@ -695,7 +696,7 @@ hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const 
 }
 
 // Row slices per block group: with fewer blocks than compute units (a few
-// frames), enough slices to cover the device twice over, each slice at least 8
+// frames), enough slices to cover the device twice over, each slice at least 4
 // template rows (a slice first fills its ring with 32 NS + 1 frame rows).
 int corr_slices(int C, const Geom &g, int NS, int NT)
 {
@@ -714,7 +715,7 @@ int corr_slices(int C, const Geom &g, int NS, int NT)
     const long long blocks = (long long)(C + kWaves - 1) / kWaves * groups;
     if (blocks >= cus) return 1;
     const long long want = (2LL * cus + blocks - 1) / blocks;
-    const int most = max(1, g.mg / 8);
+    const int most = max(1, g.mg / 4);
     return (int)(want < most ? want : most);
 }
 
@@ -855,7 +856,12 @@ hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, co
     clear_stale_error();
     if (C == 0) return hipSuccess;
     const double scale = g.ds ? 0.0625 : 1.0;
-    k_combine_i64<<<C, kBlock, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale, fsurf, fmin,
+    // a few frames: four times the threads per frame
+    if (C <= 128)
+        k_combine_i64<1024><<<C, 1024, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale,
+                                                 fsurf, fmin, coarse_st, shifts, gaps, frefine);
+    else
+        k_combine_i64<kBlock><<<C, kBlock, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale, fsurf, fmin,
                                         coarse_st, shifts, gaps, frefine);
     return hipGetLastError();
 }
