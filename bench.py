@@ -266,6 +266,19 @@ def measure_batch(moco, ctx, steps: int, unique: int = 8):
 
     dt_batch = timed(lambda: moco.moco_align_batch(ctx, items, form="auto"))
     dt_loop = timed(lambda: [moco.moco_align(ctx, fr, tp, out=res) for fr, tp, res in items])
+    # the same batch after timing the forms of every stack's key (moco_tune) at
+    # that stack's length (stacks that share a key: the last one's measurement)
+    moco.tune_clear()
+    t_tune = time.perf_counter()
+    for it in items:
+        moco.tune(ctx, it[1], frames=min(it[0].shape[0], 2048))
+    t_tune = time.perf_counter() - t_tune
+    tuned_forms = {}
+    for it in items:
+        f = moco.resolved_form(ctx, it[1], "auto")
+        tuned_forms[f] = tuned_forms.get(f, 0) + 1
+    dt_tuned = timed(lambda: moco.moco_align_batch(ctx, items, form="auto"))
+    moco.tune_clear()
     for it in items:
         it[1].close()
     del items
@@ -273,6 +286,9 @@ def measure_batch(moco, ctx, steps: int, unique: int = 8):
     return {"stacks": 64, "frames": total, "bytes": nbytes, "unique_frames_per_stack": unique,
             "forms": forms, "steps": steps,
             "batched": {"seconds": round(dt_batch, 5), "frames_per_s": round(total / dt_batch, 1)},
+            "batched_tuned": {"seconds": round(dt_tuned, 5),
+                              "frames_per_s": round(total / dt_tuned, 1), "forms": tuned_forms,
+                              "tuning_seconds": round(t_tune, 2)},
             "per_stack_loop": {"seconds": round(dt_loop, 5),
                                "frames_per_s": round(total / dt_loop, 1)}}
 
@@ -461,6 +477,13 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = load_traffic(kname, ksrc, frames_per_launch)
     peaks = measure_peaks(dev) if not args.no_peaks else None
+    # what the timing-based form choice picks for this key (AUTO above used the
+    # time model; the table is cleared again)
+    moco.tune_clear()
+    tuned_form, tuned_times = moco.tune(ctx, tp, frames=T)
+    moco.tune_clear()
+    tuned = {"form": tuned_form,
+             "us_per_frame": {k: round(v * 1e6, 4) for k, v in tuned_times.items()}}
     if peaks and form_ran == "int8" and "int8_mfma_tops" in peaks:
         roof["frac_of_measured_peak"] = roof["achieved"] / peaks["int8_mfma_tops"]
     roof["kernel"] = kname
@@ -570,6 +593,7 @@ def main():
                    "downsample": DS, "form": form_ran, "template": "frame 0"},
         "roofline": roof,
         "peaks_measured": peaks,
+        "tuned": tuned,
         "stages": stages,
         "forms": forms,
         "apply": apply_res,

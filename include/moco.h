@@ -206,6 +206,38 @@ int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
 
+/* ---- Form choice by measurement ------------------------------------------
+ *
+ * MOCO_FORM_AUTO resolves through a per-process table of forms keyed by
+ * (m, n, w, downsample, dtype): a form recorded for a template's key is used
+ * when it applies to the template; otherwise the time model described at
+ * moco_template_form decides.  The table starts empty, so AUTO is the model's
+ * choice until a form is tuned or set. */
+
+/* Time the forms that apply to `tmpl` (of MOCO_FORM_INT8_MFMA and
+ * MOCO_FORM_FFT_CERTIFIED; MOCO_FORM_FP64_EXACT when neither does) on
+ * `frames` copies of the template, one warm-up and three timed calls each with
+ * HIP events on hip_stream, and record the fastest for the template's key.
+ * The forms rank differently with the stack length (a few frames take the
+ * int8 form's row-sliced launch), so `frames` should be the length of the
+ * stacks the key will serve; 0 means 1024, the many-frame regime.  *chosen receives it; seconds_per_frame (nullable, 5
+ * doubles indexed by moco_form) receives each timed form's seconds per frame
+ * (-1 for forms not timed).  Synchronises hip_stream; allocates the frames
+ * outside the context's budget for the duration of the call.
+ * Errors: MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE. */
+int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream,
+              moco_form *chosen, double *seconds_per_frame);
+
+/* Record `form` (a concrete form, not AUTO) for the key, e.g. from a saved
+ * table of earlier measurements.  Host only.  Errors: MOCO_EINVAL. */
+int moco_tune_set(int m, int n, int w, int downsample, moco_dtype dtype, moco_form form);
+
+/* The form recorded for the key.  Errors: MOCO_EINVAL (none recorded). */
+int moco_tune_get(int m, int n, int w, int downsample, moco_dtype dtype, moco_form *form);
+
+/* Forget every recorded form. */
+void moco_tune_clear(void);
+
 /* Error bound of the FFT forms for this template (sec. 2, the FFT construction
  * of h, evaluated in FP64): for every shift of the window the computed
  * correlation h^ satisfies |h^ - h| <= kf * sqrt(m' n' Sa Sb), and each

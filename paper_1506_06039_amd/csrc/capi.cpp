@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "moco_internal.h"
@@ -686,11 +687,42 @@ double fft_model_s(const moco::Tmpl &t)
     return 0.55e-6 * ((double)g.m * g.n / 262144.0) + 1.26e-6 * pq * std::log2(pq) / ref;
 }
 
-// The form AUTO runs: the faster of the exact int8 form and the FFT form by
-// the models above when both apply, else whichever applies, else direct FP64
-// sums.  The FFT form runs with its argmin certificate.
+// Forms chosen by measurement (moco_tune) or set by the caller, per search
+// key; AUTO follows them where the form applies to the template.
+struct TuneKey {
+    int m, n, w, ds, dtype;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(m, n, w, ds, dtype) < std::tie(o.m, o.n, o.w, o.ds, o.dtype);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, moco_form> g_tune;
+
+TuneKey tune_key(const moco::Geom &g) { return TuneKey{g.m, g.n, g.w, g.ds, (int)g.dtype}; }
+
+bool form_applies(const moco::Tmpl &t, moco_form f)
+{
+    switch (f) {
+    case MOCO_FORM_FP64_EXACT: return true;
+    case MOCO_FORM_INT8_MFMA: return t.int8_ok;
+    case MOCO_FORM_FFT:
+    case MOCO_FORM_FFT_CERTIFIED: return t.fft_ok;
+    default: return false;
+    }
+}
+
+// The form AUTO runs: a form recorded for the template's key (moco_tune,
+// moco_tune_set) when it applies; else the faster of the exact int8 form and
+// the FFT form by the models above when both apply, else whichever applies,
+// else direct FP64 sums.  The FFT form runs with its argmin certificate.
 moco_form auto_form(const moco::Tmpl &t)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(t.g));
+        if (it != g_tune.end() && form_applies(t, it->second)) return it->second;
+    }
     if (t.int8_ok && t.fft_ok)
         return int8_model_s(t) <= fft_model_s(t) ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FFT_CERTIFIED;
     if (t.int8_ok) return MOCO_FORM_INT8_MFMA;
@@ -854,6 +886,104 @@ int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke)
     if (!tmpl->t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
     moco::fft_error_coefs(tmpl->t.g, tmpl->t.fft, kf, ke);
     return MOCO_OK;
+}
+
+int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream,
+              moco_form *chosen, double *seconds_per_frame)
+{
+    if (!ctx || !tmpl || !chosen) return fail(MOCO_EINVAL, "moco_tune: null argument");
+    if (tmpl->device != ctx->device)
+        return fail(MOCO_EINVAL, "template lives on device %d, context on device %d",
+                    tmpl->device, ctx->device);
+    const moco::Tmpl &t = tmpl->t;
+    const moco::Geom &g = t.g;
+    const int T = frames > 0 ? frames : 1024;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (seconds_per_frame)
+        for (int k = 0; k < 5; ++k) seconds_per_frame[k] = -1.0;
+    std::vector<moco_form> cand;
+    if (t.int8_ok) cand.push_back(MOCO_FORM_INT8_MFMA);
+    if (t.fft_ok) cand.push_back(MOCO_FORM_FFT_CERTIFIED);
+    if (cand.empty()) cand.push_back(MOCO_FORM_FP64_EXACT);
+    DeviceGuard dg(ctx->device);
+    // T copies of the template (its own frame: a realistic image, the shift at
+    // zero) and a shift output
+    const size_t fbytes = (size_t)g.m * g.n * dtype_size(g.dtype);
+    char *d_frames = nullptr;
+    int32_t *d_shifts = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&d_frames, fbytes * T);
+    if (e == hipSuccess) e = hipMalloc(&d_shifts, sizeof(int32_t) * 2 * T);
+    for (int k = 0; k < T && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(d_frames + fbytes * k, t.raw, fbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = e == hipSuccess ? MOCO_OK : fail(MOCO_ENOMEM, "moco_tune: %s", hipGetErrorString(e));
+    moco_form best = cand[0];
+    double best_s = INFINITY;
+    moco_outputs out{};
+    out.shifts = d_shifts;
+    for (size_t c = 0; c < cand.size() && rc == MOCO_OK; ++c) {
+        const moco_form f = cand[c];
+        rc = moco_align(ctx, d_frames, tmpl, T, g.m, g.n, g.w, g.ds, g.dtype, f, &out, st);
+        const int reps = 3;
+        if (rc == MOCO_OK && (e = hipEventRecord(e0, st)) != hipSuccess)
+            rc = fail(MOCO_EDEVICE, "moco_tune: %s", hipGetErrorString(e));
+        for (int r = 0; r < reps && rc == MOCO_OK; ++r)
+            rc = moco_align(ctx, d_frames, tmpl, T, g.m, g.n, g.w, g.ds, g.dtype, f, &out, st);
+        float ms = 0.f;
+        if (rc == MOCO_OK && ((e = hipEventRecord(e1, st)) != hipSuccess ||
+                              (e = hipEventSynchronize(e1)) != hipSuccess ||
+                              (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess))
+            rc = fail(MOCO_EDEVICE, "moco_tune: %s", hipGetErrorString(e));
+        if (rc != MOCO_OK) break;
+        const double sec = ms / 1000.0 / reps / T;
+        if (seconds_per_frame) seconds_per_frame[(int)f] = sec;
+        if (sec < best_s) {
+            best_s = sec;
+            best = f;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    if (d_frames) (void)hipFree(d_frames);
+    if (d_shifts) (void)hipFree(d_shifts);
+    if (rc != MOCO_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(g)] = best;
+    }
+    *chosen = best;
+    return MOCO_OK;
+}
+
+int moco_tune_set(int m, int n, int w, int downsample, moco_dtype dtype, moco_form form)
+{
+    if (form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED && form != MOCO_FORM_FP64_EXACT &&
+        form != MOCO_FORM_INT8_MFMA)
+        return fail(MOCO_EINVAL, "moco_tune_set: form %d is not a concrete form", (int)form);
+    if (dtype != MOCO_U16 && dtype != MOCO_F32)
+        return fail(MOCO_EINVAL, "moco_tune_set: unknown dtype %d", (int)dtype);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{m, n, w, downsample, (int)dtype}] = form;
+    return MOCO_OK;
+}
+
+int moco_tune_get(int m, int n, int w, int downsample, moco_dtype dtype, moco_form *form)
+{
+    if (!form) return fail(MOCO_EINVAL, "moco_tune_get: null form");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{m, n, w, downsample, (int)dtype});
+    if (it == g_tune.end()) return fail(MOCO_EINVAL, "moco_tune_get: no form recorded");
+    *form = it->second;
+    return MOCO_OK;
+}
+
+void moco_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
 }
 
 int moco_profile_enable(moco_ctx *ctx, int enable)

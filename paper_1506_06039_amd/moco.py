@@ -92,6 +92,14 @@ _lib.moco_template_form.restype = _i
 _lib.moco_template_fft_bound.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
 _lib.moco_template_fft_bound.restype = _i
+_lib.moco_tune.argtypes = [_vp, _vp, _i, _vp, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]
+_lib.moco_tune.restype = _i
+_lib.moco_tune_set.argtypes = [_i, _i, _i, _i, _i, _i]
+_lib.moco_tune_set.restype = _i
+_lib.moco_tune_get.argtypes = [_i, _i, _i, _i, _i, ctypes.POINTER(_i)]
+_lib.moco_tune_get.restype = _i
+_lib.moco_tune_clear.argtypes = []
+_lib.moco_tune_clear.restype = None
 _lib.moco_last_error.argtypes = []
 _lib.moco_last_error.restype = ctypes.c_char_p
 _lib.moco_version.argtypes = []
@@ -321,6 +329,60 @@ def resolved_form(ctx: Context, tmpl: Template, form: str) -> str:
     r = _i()
     _check(_lib.moco_template_form(tmpl.handle, FORMS[form], ctypes.byref(r)))
     return {v: k for k, v in FORMS.items()}[r.value]
+
+
+_FORM_NAMES = {v: k for k, v in FORMS.items()}
+_DTYPES = {"u16": 1, "f32": 2}
+
+
+def tune(ctx: Context, tmpl: Template, frames: int = 0):
+    """moco_tune: time the forms that apply to this template on `frames` copies
+    of it (0: 1024) and record the fastest for its key; AUTO then picks it.
+    Returns (form, {form: s/frame})."""
+    chosen = _i()
+    sec = (ctypes.c_double * 5)()
+    _check(_lib.moco_tune(ctx.handle, tmpl.handle, frames, _stream_handle(ctx.device),
+                          ctypes.byref(chosen), sec))
+    times = {_FORM_NAMES[k]: sec[k] for k in range(5) if k in _FORM_NAMES and sec[k] >= 0}
+    return _FORM_NAMES[chosen.value], times
+
+
+def tune_set(m: int, n: int, w: int, downsample: int, dtype: str, form: str):
+    """moco_tune_set (dtype "u16" or "f32")."""
+    _check(_lib.moco_tune_set(m, n, w, int(downsample), _DTYPES[dtype], FORMS[form]))
+
+
+def tune_get(m: int, n: int, w: int, downsample: int, dtype: str):
+    """moco_tune_get: the recorded form name, or None."""
+    f = _i()
+    rc = _lib.moco_tune_get(m, n, w, int(downsample), _DTYPES[dtype], ctypes.byref(f))
+    return _FORM_NAMES[f.value] if rc == 0 else None
+
+
+def tune_clear():
+    _lib.moco_tune_clear()
+
+
+def tune_save(path: str, keys):
+    """Write the recorded forms of `keys` ((m, n, w, downsample, dtype) tuples)
+    as a JSON list."""
+    import json
+    rows = []
+    for m, n, w, ds, dt in keys:
+        f = tune_get(m, n, w, ds, dt)
+        if f is not None:
+            rows.append({"m": m, "n": n, "w": w, "downsample": int(ds), "dtype": dt, "form": f})
+    with open(path, "w") as fh:
+        json.dump(rows, fh, indent=1)
+
+
+def tune_load(path: str) -> int:
+    """Record every form of a JSON list written by tune_save; returns how many."""
+    import json
+    rows = json.load(open(path))
+    for r in rows:
+        tune_set(r["m"], r["n"], r["w"], r["downsample"], r["dtype"], r["form"])
+    return len(rows)
 
 
 def fft_bound(tmpl: Template):

@@ -122,3 +122,43 @@ def test_binding_structs_match_the_header(lib, tmp_path):
             ctypes.sizeof(moco._Stack), moco._Stack.out.offset,
             ctypes.sizeof(moco.ServerResult), moco.ServerResult.latency_us.offset]
     assert got == want
+
+
+def test_tune_table_without_gpu(lib):
+    """The per-process table of tuned forms: set, get, reject AUTO, clear."""
+    c_int = ctypes.c_int
+    lib.moco_tune_set.argtypes = [c_int] * 6
+    lib.moco_tune_get.argtypes = [c_int] * 5 + [ctypes.POINTER(c_int)]
+    lib.moco_tune_clear()
+    f = c_int(-7)
+    try:
+        assert lib.moco_tune_get(512, 512, 32, 1, 1, ctypes.byref(f)) == -1
+        assert lib.moco_tune_set(512, 512, 32, 1, 1, 4) == 0
+        assert lib.moco_tune_get(512, 512, 32, 1, 1, ctypes.byref(f)) == 0 and f.value == 4
+        assert lib.moco_tune_get(512, 512, 32, 1, 2, ctypes.byref(f)) == -1   # other dtype
+        assert lib.moco_tune_set(512, 512, 32, 1, 1, 0) == -1   # AUTO is not a concrete form
+        assert lib.moco_tune_set(512, 512, 32, 1, 9, 3) == -1   # unknown dtype
+        assert lib.moco_tune_set(512, 512, 32, 1, 1, 2) == 0    # replaced
+        assert lib.moco_tune_get(512, 512, 32, 1, 1, ctypes.byref(f)) == 0 and f.value == 2
+    finally:
+        lib.moco_tune_clear()
+    assert lib.moco_tune_get(512, 512, 32, 1, 1, ctypes.byref(f)) == -1
+
+
+def test_tune_json_roundtrip_without_gpu(lib, tmp_path):
+    from paper_1506_06039_amd import moco
+    moco.tune_clear()
+    try:
+        moco.tune_set(256, 256, 64, 0, "f32", "fft_cert")
+        moco.tune_set(512, 512, 32, 1, "u16", "int8")
+        path = str(tmp_path / "tune.json")
+        moco.tune_save(path, [(256, 256, 64, 0, "f32"), (512, 512, 32, 1, "u16"),
+                              (128, 128, 10, 0, "f32")])
+        moco.tune_clear()
+        assert moco.tune_get(512, 512, 32, 1, "u16") is None
+        assert moco.tune_load(path) == 2
+        assert moco.tune_get(256, 256, 64, 0, "f32") == "fft_cert"
+        assert moco.tune_get(512, 512, 32, 1, "u16") == "int8"
+        assert moco.tune_get(128, 128, 10, 0, "f32") is None
+    finally:
+        moco.tune_clear()
