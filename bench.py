@@ -557,6 +557,22 @@ def main():
         torch.cuda.synchronize(dev)
         lat.append(time.perf_counter() - t)
     lat_us = np.array(lat) * 1e6
+    # the same single-frame call replayed from a captured graph (one frame buffer
+    # refilled from the stack before each replay)
+    lat_g = []
+    if args.latency_iters:
+        buf = frames[:1].clone()
+        graph = moco.Graph(ctx, buf, tp, form=args.form, out=one)
+        for k in range(args.latency_iters):
+            buf.copy_(frames[k % T: k % T + 1])
+            torch.cuda.synchronize(dev)
+            t = time.perf_counter()
+            graph.launch()
+            host.copy_(one.shifts, non_blocking=True)
+            torch.cuda.synchronize(dev)
+            lat_g.append(time.perf_counter() - t)
+        graph.close()
+    lat_g_us = np.array(lat_g) * 1e6
 
     serving = measure_serving(moco, ctx, frames_np, args.serve_seconds) \
         if args.serve_seconds > 0 else None
@@ -605,6 +621,11 @@ def main():
                         "p99": round(float(np.percentile(lat_us, 99)), 1),
                         "p99_9": round(float(np.percentile(lat_us, 99.9)), 1),
                         "frames": 1, "iters": args.latency_iters} if lat_us.size else None),
+        "latency_graph_us": ({"p50": round(float(np.percentile(lat_g_us, 50)), 1),
+                              "p99": round(float(np.percentile(lat_g_us, 99)), 1),
+                              "p99_9": round(float(np.percentile(lat_g_us, 99.9)), 1),
+                              "frames": 1, "iters": args.latency_iters}
+                             if lat_g_us.size else None),
     }
 
     if not args.no_cpu_baseline:

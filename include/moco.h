@@ -151,6 +151,27 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
                int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
                void *hip_stream);
 
+/* A moco_align call captured as a HIP graph, for callers that repeat the same
+ * call (a frame buffer refilled between calls: a camera, a serving loop):
+ * replaying it aligns whatever d_frames holds when the replay runs into the
+ * same outputs, with one launch instead of one per kernel.  The graph has its
+ * own scratch (the size moco_align would use, allocated here); it refers to
+ * d_frames, the template and the outputs, which must outlive it.  The
+ * arguments and errors are moco_align's (T >= 1); the call is captured on a
+ * stream of its own, with stage timing off, and nothing runs until a launch. */
+typedef struct moco_graph moco_graph;
+int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
+                      int n, int w, int downsample, moco_dtype dtype, moco_form form,
+                      const moco_outputs *out, moco_graph **graph);
+
+/* Replay the captured call on hip_stream (ordered after work enqueued there
+ * before).  Replays on one graph share its scratch: enqueue them on one stream
+ * or synchronise between them.  Errors: MOCO_EINVAL, MOCO_EDEVICE. */
+int moco_graph_launch(moco_graph *graph, void *hip_stream);
+
+/* Release a graph.  Safe on NULL.  Its replays must have completed. */
+void moco_graph_destroy(moco_graph *graph);
+
 /* One stack of a batch: moco_align's arguments as a record. */
 typedef struct {
     const void *d_frames;

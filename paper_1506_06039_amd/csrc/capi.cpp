@@ -43,6 +43,12 @@ struct moco_tmpl {
     moco::Tmpl t{};
 };
 
+struct moco_graph {
+    int device = 0;
+    void *scratch = nullptr;        // its own: the context's scratch may be reallocated
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -1101,6 +1107,84 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     if (rc) return rc;
     return run_stack(ctx, d_frames, tt, T, g, form, out, st, (char *)ctx->scratch, need);
     return MOCO_OK;
+}
+
+int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
+                      int n, int w, int downsample, moco_dtype dtype, moco_form form,
+                      const moco_outputs *out, moco_graph **graph)
+{
+    if (!ctx || !tmpl || !out || !graph)
+        return fail(MOCO_EINVAL, "moco_graph_create: null ctx, template, outputs or graph");
+    *graph = nullptr;
+    moco::Geom g;
+    int rc = check_stack(ctx, d_frames, tmpl, T, m, n, w, downsample, dtype, form, out, &g, &form);
+    if (rc) return rc;
+    if (T < 1) return fail(MOCO_EINVAL, "moco_graph_create: T=%d must be >= 1", T);
+    const moco::Tmpl &tt = tmpl->t;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    const size_t pf = per_frame_scratch(g, form, tt);
+    if (pf > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf,
+                    ctx->budget);
+    const size_t need = pf * std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / pf));
+    moco_graph *gr = new (std::nothrow) moco_graph;
+    if (!gr) return fail(MOCO_ENOMEM, "moco_graph_create: out of host memory");
+    gr->device = ctx->device;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipError_t e = hipMalloc(&gr->scratch, need);
+    if (e != hipSuccess) {
+        delete gr;
+        return fail(MOCO_ENOMEM, "graph scratch of %zu bytes: %s", need, hipGetErrorString(e));
+    }
+    // capture on a private stream (the legacy default stream cannot be
+    // captured); no stage timing inside a graph
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = run_stack(ctx, d_frames, tt, T, g, form, out, cs, (char *)gr->scratch, need);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph_);
+        if (rc == MOCO_OK && e2 != hipSuccess)
+            rc = fail(MOCO_EDEVICE, "graph capture: %s", hipGetErrorString(e2));
+        if (rc == MOCO_OK && (e2 = hipGraphInstantiate(&gr->exec, graph_, nullptr, nullptr, 0)) !=
+                                 hipSuccess)
+            rc = fail(MOCO_EDEVICE, "graph instantiation: %s", hipGetErrorString(e2));
+    } else {
+        rc = fail(MOCO_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    ctx->profiling = prof;
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != MOCO_OK) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        (void)hipFree(gr->scratch);
+        delete gr;
+        return rc;
+    }
+    *graph = gr;
+    return MOCO_OK;
+}
+
+int moco_graph_launch(moco_graph *graph, void *hip_stream)
+{
+    if (!graph || !graph->exec) return fail(MOCO_EINVAL, "moco_graph_launch: null graph");
+    DeviceGuard dg(graph->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", graph->device);
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(MOCO_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+    return MOCO_OK;
+}
+
+void moco_graph_destroy(moco_graph *graph)
+{
+    if (!graph) return;
+    DeviceGuard dg(graph->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->scratch) (void)hipFree(graph->scratch);
+    delete graph;
 }
 
 int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,

@@ -92,6 +92,13 @@ _lib.moco_template_form.restype = _i
 _lib.moco_template_fft_bound.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
 _lib.moco_template_fft_bound.restype = _i
+_lib.moco_graph_create.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
+                                   ctypes.POINTER(_Outputs), ctypes.POINTER(_vp)]
+_lib.moco_graph_create.restype = _i
+_lib.moco_graph_launch.argtypes = [_vp, _vp]
+_lib.moco_graph_launch.restype = _i
+_lib.moco_graph_destroy.argtypes = [_vp]
+_lib.moco_graph_destroy.restype = None
 _lib.moco_tune.argtypes = [_vp, _vp, _i, _vp, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]
 _lib.moco_tune.restype = _i
 _lib.moco_tune_set.argtypes = [_i, _i, _i, _i, _i, _i]
@@ -222,6 +229,43 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
                            int(tmpl.downsample), _dtype_code(frames), FORMS[form],
                            ctypes.byref(o), _stream_handle(dev)))
     return out
+
+
+class Graph:
+    """moco_graph_*: a moco_align call on `frames` captured once; launch()
+    realigns whatever `frames` holds then, into `out` (kept alive here)."""
+
+    def __init__(self, ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "auto",
+                 surface: bool = False, out: Result | None = None):
+        if not frames.is_cuda or frames.dim() != 3 or not frames.is_contiguous():
+            raise ValueError("frames must be a contiguous 3-D device tensor")
+        T, m, n = frames.shape
+        self.frames, self.tmpl, self.ctx = frames, tmpl, ctx
+        self.out = out if out is not None else \
+            _new_result(T, 2 * tmpl.w - 1, frames.device, surface)
+        o = _outputs(self.out)
+        h = _vp()
+        _check(_lib.moco_graph_create(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
+                                      int(tmpl.downsample), _dtype_code(frames), FORMS[form],
+                                      ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self) -> Result:
+        """Enqueue a replay on the current stream; returns the output record."""
+        _check(_lib.moco_graph_launch(self.handle, _stream_handle(self.frames.device)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.frames.device)
+            _lib.moco_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def moco_apply(ctx: Context, frames: torch.Tensor, shifts: torch.Tensor, frames_out: bool = True,
