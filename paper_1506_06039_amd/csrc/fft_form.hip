@@ -356,11 +356,20 @@ bool fft_plan(int n, FftPlan *pl)
         ns *= r;
         rem /= r;
     };
-    while (rem % 8 == 0) add(8);
-    while (rem % 4 == 0) add(4);
-    while (rem % 2 == 0) add(2);
-    while (rem % 3 == 0) add(3);
-    while (rem % 5 == 0) add(5);
+    // the same radices as taking 8s, then 4s, 2s, 3s and 5s, applied smallest
+    // first: a pass writes runs of Ns consecutive elements, so the large radix,
+    // whose early-pass writes would stride across LDS banks, comes last
+    int c8 = 0, c4 = 0, c2 = 0, c3 = 0, c5 = 0, x = n;
+    while (x % 8 == 0) x /= 8, ++c8;
+    while (x % 4 == 0) x /= 4, ++c4;
+    while (x % 2 == 0) x /= 2, ++c2;
+    while (x % 3 == 0) x /= 3, ++c3;
+    while (x % 5 == 0) x /= 5, ++c5;
+    for (int k = 0; k < c2; ++k) add(2);
+    for (int k = 0; k < c3; ++k) add(3);
+    for (int k = 0; k < c4; ++k) add(4);
+    for (int k = 0; k < c5; ++k) add(5);
+    for (int k = 0; k < c8; ++k) add(8);
     *pl = p;
     return true;
 }
