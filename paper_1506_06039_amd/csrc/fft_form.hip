@@ -29,7 +29,7 @@ namespace moco {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr size_t kLdsBudget = 48 * 1024;  // LDS bytes a block's two buffers may use
+constexpr size_t kLdsBudget = 32 * 1024;  // LDS bytes a block's two buffers may use
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
