@@ -674,7 +674,7 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
 // issues 64x64-shift tiles of four digit products at about 2.7e15 ops/s,
 // beside 0.35 us of prep, combine and refine per 512x512 frame; the FFT form's
-// three transform passes took 1.26 us at 288x288 and scale with P Q log2(P Q),
+// three transform passes took 1.13 us at 288x288 and scale with P Q log2(P Q),
 // beside 0.55 us of grid, energies, combine and refine per 512x512 frame (those
 // parts scale with the frame's pixels).
 double int8_model_s(const moco::Tmpl &t)
@@ -690,7 +690,7 @@ double fft_model_s(const moco::Tmpl &t)
     const moco::Geom &g = t.g;
     const double pq = (double)t.fft.pp.n * t.fft.pq.n;
     const double ref = 288.0 * 288.0 * std::log2(288.0 * 288.0);
-    return 0.55e-6 * ((double)g.m * g.n / 262144.0) + 1.26e-6 * pq * std::log2(pq) / ref;
+    return 0.55e-6 * ((double)g.m * g.n / 262144.0) + 1.13e-6 * pq * std::log2(pq) / ref;
 }
 
 // Forms chosen by measurement (moco_tune) or set by the caller, per search
