@@ -1106,7 +1106,6 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     rc = ensure_scratch(ctx, need, st);
     if (rc) return rc;
     return run_stack(ctx, d_frames, tt, T, g, form, out, st, (char *)ctx->scratch, need);
-    return MOCO_OK;
 }
 
 int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
