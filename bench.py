@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="auto", choices=["auto", "fft", "fp64", "int8"])
+    ap.add_argument("--form", default="auto", choices=["auto", "fft", "fft_cert", "fp64", "int8"])
     ap.add_argument("--frames", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="frames for the oracle baseline (0: batches of 4 per host thread "

@@ -200,7 +200,7 @@ size_t refine_steps_partial_bytes(const moco::Geom &g)
 
 // Per-frame scratch of the FP64 exact form.
 struct ExactLayout {
-    size_t coarse, inter, atab, h, cst, pm, part, total_per_frame;
+    size_t coarse, inter, atab, h, cst, pm, edge, part, total_per_frame;
 };
 
 ExactLayout exact_layout(const moco::Geom &g)
@@ -212,8 +212,9 @@ ExactLayout exact_layout(const moco::Geom &g)
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
+    L.edge = moco::prep_grid_applicable(g) ? align_up(moco::prep_grid_edge_bytes(g), 256) : 0;
     L.part = align_up(refine_steps_partial_bytes(g), 8);
-    L.total_per_frame = L.coarse + L.inter + L.atab + L.h + L.cst + L.pm + L.part;
+    L.total_per_frame = L.coarse + L.inter + L.atab + L.h + L.cst + L.pm + L.edge + L.part;
     return L;
 }
 
@@ -270,6 +271,25 @@ private:
     ProfRec rec_{};
     bool on_ = false;
 };
+
+// The searched grid and its overlap energies: uint16 frames with at most one
+// level in one pass over the raw frames, else the FP64 pyramid and k_energy.
+hipError_t grid_and_energies(moco_ctx *ctx, const void *fr, const moco::Geom &g, int c,
+                             double *inter, double *coarse, double *atab, int32_t *pm,
+                             long long *edge, hipStream_t st)
+{
+    if (edge && moco::prep_grid_applicable(g)) {
+        StageTimer tm(ctx, MOCO_STAGE_PREP, st);
+        return moco::launch_prep_grid((const uint16_t *)fr, c, g, coarse, atab, pm, edge, st);
+    }
+    hipError_t e;
+    {
+        StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
+        if ((e = build_levels(fr, g.dtype, c, g, inter, coarse, st)) != hipSuccess) return e;
+    }
+    StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+    return moco::launch_energy(coarse, c, g, false, atab, pm, st);
+}
 
 void free_tmpl(moco::Tmpl &t)
 {
@@ -484,6 +504,8 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     off += L.inter * C;
     double *atab = (double *)(base + off);
     off += L.atab * C;
+    long long *edge = L.edge ? (long long *)(base + off) : nullptr;
+    off += L.edge * C;
     double *h = (double *)(base + off);
     off += L.h * C;
     int32_t *cst = (int32_t *)(base + off);
@@ -498,14 +520,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
         int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
-        {
-            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
-            HIP_TRY(build_levels(fr, dtype, c, g, inter, coarse, st));
-        }
-        {
-            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
-            HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st));
-        }
+        HIP_TRY(grid_and_energies(ctx, fr, g, c, inter, coarse, atab, pm, edge, st));
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
             HIP_TRY(moco::launch_corr_fp64(coarse, tt.coarse, c, g, h, st));
@@ -534,7 +549,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame scratch of the FFT form.
 struct FftLayout {
-    size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, part, total_per_frame;
+    size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, edge, part, total_per_frame;
 };
 
 FftLayout fft_layout(const moco::Geom &g)
@@ -549,9 +564,10 @@ FftLayout fft_layout(const moco::Geom &g)
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
     L.flag = sizeof(int32_t);
+    L.edge = moco::prep_grid_applicable(g) ? align_up(moco::prep_grid_edge_bytes(g), 256) : 0;
     L.part = align_up(refine_steps_partial_bytes(g), 8);
-    L.total_per_frame =
-        L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.flag + L.part;
+    L.total_per_frame = L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.flag +
+                        L.edge + L.part;
     return L;
 }
 
@@ -577,6 +593,8 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     off += L.inter * C;
     double *atab = (double *)(base + off);
     off += L.atab * C;
+    long long *edge = L.edge ? (long long *)(base + off) : nullptr;
+    off += L.edge * C;
     double2 *s1 = (double2 *)(base + off);
     off += L.s1 * C;
     double2 *s2 = (double2 *)(base + off);
@@ -604,14 +622,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         double *fmin = out->fmin ? out->fmin + f0 : nullptr;
         double *gaps = out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr;
         double *frefine = out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr;
-        {
-            StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
-            HIP_TRY(build_levels(fr, dtype, c, g, inter, coarse, st));
-        }
-        {
-            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
-            HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st));
-        }
+        HIP_TRY(grid_and_energies(ctx, fr, g, c, inter, coarse, atab, pm, edge, st));
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
             HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, s1, st));

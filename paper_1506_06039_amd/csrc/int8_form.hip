@@ -98,14 +98,22 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
     for (int q = 0; q < 4; ++q) X[q] = (j0 + q < ng) ? grid_value<DS>(a, n, i, j0 + q) : 0;
 }
 
-template <bool DS, int kMaxCol4, int NW>
+//
+// With GRID, the same pass serves the FP64 forms instead: no digit planes;
+// the grid values are written as FP64 box means (raw values without
+// downsampling) to grid [frame][mg][ng], and the energy table as FP64 in
+// grid units to atab_d (the integer sums divided by 16 when downsampling: an
+// exact scaling, the same values a FP64 pass over the grid gives).
+template <bool DS, int kMaxCol4, int NW, bool GRID>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
                                                      int8_t *__restrict__ limbs,
                                                      int32_t *__restrict__ nlimb,
                                                      int32_t *__restrict__ vmax,
                                                      long long *__restrict__ atab,
-                                                     long long *__restrict__ edge)
+                                                     long long *__restrict__ edge,
+                                                     double *__restrict__ grid,
+                                                     double *__restrict__ atab_d)
 {
     // dynamic LDS: colE[npad] | rowbuf[NW][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
     extern __shared__ long long lds_prep[];
@@ -167,12 +175,18 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                 int j = j0 + q;
                 int X = Xs[q];
                 my_xmax = max(my_xmax, X);
-                int d0 = bdigit(X);
-                int x1 = (X - d0) >> 8;
-                int d1 = bdigit(x1);
-                if (((x1 - d1) >> 8) != 0) my_need3 = 1;
-                d0p |= (d0 & 255) << (8 * q);
-                d1p |= (d1 & 255) << (8 * q);
+                if (GRID) {
+                    if (j < ng)
+                        grid[(size_t)frame * mg * ng + (size_t)i * ng + j] =
+                            DS ? 0.25 * (double)X : (double)X;
+                } else {
+                    int d0 = bdigit(X);
+                    int x1 = (X - d0) >> 8;
+                    int d1 = bdigit(x1);
+                    if (((x1 - d1) >> 8) != 0) my_need3 = 1;
+                    d0p |= (d0 & 255) << (8 * q);
+                    d1p |= (d1 & 255) << (8 * q);
+                }
                 long long x2 = (long long)X * X;
                 rpart += x2;
                 col[c][q] += x2;
@@ -181,8 +195,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                     if (j >= ng - we) rowbuf(wave, 1)[ng - 1 - j] = x2;
                 }
             }
-            *(int *)(L0 + (size_t)i * npad + j0) = d0p;
-            *(int *)(L1 + (size_t)i * npad + j0) = d1p;
+            if (!GRID) {
+                *(int *)(L0 + (size_t)i * npad + j0) = d0p;
+                *(int *)(L1 + (size_t)i * npad + j0) = d1p;
+            }
         }
         long long r = wave_sum_i64(rpart);
         my_etot += r;
@@ -243,25 +259,30 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     }
     __syncthreads();
     const long long Etot = etot;
-    long long *A = atab + (size_t)frame * W * W;
+    auto put = [&](size_t k, long long v) {
+        if (GRID)
+            atab_d[(size_t)frame * W * W + k] = DS ? 0.0625 * (double)v : (double)v;
+        else
+            atab[(size_t)frame * W * W + k] = v;
+    };
     for (int tt = threadIdx.x; tt < W; tt += blockDim.x) {
         const int t = tt - we, at = t < 0 ? -t : t;
         const int lr = t > 0 ? 0 : 1;
         const long long colex = t > 0 ? cL[at] : (t < 0 ? cR[at] : 0);
         const long long base = Etot - colex;
-        A[(size_t)we * W + tt] = base;
+        put((size_t)we * W + tt, base);
         long long ct = 0, cb = 0;
         for (int s = 1; s < w; ++s) {
             if (t != 0) {
                 ct += E[eidx(0, lr, s - 1, at)];
                 cb += E[eidx(1, lr, s - 1, at)];
             }
-            A[(size_t)(we + s) * W + tt] = base - rT[s] + ct;   // shift +s excludes top rows
-            A[(size_t)(we - s) * W + tt] = base - rB[s] + cb;   // shift -s excludes bottom rows
+            put((size_t)(we + s) * W + tt, base - rT[s] + ct);   // shift +s excludes top rows
+            put((size_t)(we - s) * W + tt, base - rB[s] + cb);   // shift -s excludes bottom rows
         }
     }
     // third digit plane, only for frames that need it
-    if (need3) {
+    if (!GRID && need3) {
         int8_t *L2 = L0 + 2 * plane;
         for (int i = wave; i < mg; i += NW)
             for (int j0 = 4 * lane; j0 < npad; j0 += 256) {
@@ -279,7 +300,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
             }
     }
     if (threadIdx.x == 0) {
-        nlimb[frame] = need3 ? 3 : 2;
+        if (!GRID) nlimb[frame] = need3 ? 3 : 2;
         // every pixel is a term of some grid value unless a side is odd when downsampling
         const bool covers = !DS || ((m % 2) == 0 && (n % 2) == 0);
         vmax[frame] = covers ? xmax : INT32_MAX;
@@ -765,43 +786,50 @@ size_t int8_template_bytes(const Geom &g)
     return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow + kInt8ZeroTail;
 }
 
-template <bool DS, int NW>
+template <bool DS, int NW, bool GRID>
 void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int nc, size_t lds,
                     int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
-                    long long *edge, hipStream_t st)
+                    long long *edge, double *grid, double *atab_d, hipStream_t st)
 {
     if (nc <= 1)
-        k_prep_u16<DS, 1, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
-                                                       limbs, nlimb, vmax, atab, edge);
+        k_prep_u16<DS, 1, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
+                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             grid, atab_d);
     else if (nc <= 2)
-        k_prep_u16<DS, 2, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
-                                                       limbs, nlimb, vmax, atab, edge);
+        k_prep_u16<DS, 2, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
+                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             grid, atab_d);
     else if (nc <= 4)
-        k_prep_u16<DS, 4, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
-                                                       limbs, nlimb, vmax, atab, edge);
+        k_prep_u16<DS, 4, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
+                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             grid, atab_d);
     else
-        k_prep_u16<DS, 8, NW><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, npad,
-                                                       limbs, nlimb, vmax, atab, edge);
+        k_prep_u16<DS, 8, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
+                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             grid, atab_d);
 }
 
-template <bool DS>
+size_t prep_lds(const Geom &g, int npad, int nw)
+{
+    const int we1 = g.w > 1 ? g.w - 1 : 1;
+    return ((size_t)npad + (size_t)nw * 2 * we1 + 4 * (size_t)g.w + 2) * sizeof(long long);
+}
+
+template <bool DS, bool GRID>
 void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
-                 int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, hipStream_t st)
+                 int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, double *grid,
+                 double *atab_d, hipStream_t st)
 {
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
-    const int we1 = g.w > 1 ? g.w - 1 : 1;
-    auto lds_for = [&](int nw) {
-        return ((size_t)npad + (size_t)nw * 2 * we1 + 4 * (size_t)g.w + 2) * sizeof(long long);
-    };
     // a few frames: sixteen waves per frame (one block of four waves streams a
     // frame at a fraction of the device's bandwidth)
-    if (C <= 128 && lds_for(16) <= 64 * 1024)
-        prep_launch_nw<DS, 16>(frames, C, g, npad, nc, lds_for(16), limbs, nlimb, vmax, atab,
-                               edge, st);
+    if (C <= 128 && prep_lds(g, npad, 16) <= 64 * 1024)
+        prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, nc, prep_lds(g, npad, 16), limbs, nlimb,
+                                     vmax, atab, edge, grid, atab_d, st);
     else
-        prep_launch_nw<DS, kWaves>(frames, C, g, npad, nc, lds_for(kWaves), limbs, nlimb, vmax,
-                                   atab, edge, st);
+        prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, nc, prep_lds(g, npad, kWaves), limbs,
+                                         nlimb, vmax, atab, edge, grid, atab_d, st);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
@@ -811,9 +839,38 @@ hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npa
     clear_stale_error();
     if (C == 0) return hipSuccess;
     if (g.ds)
-        prep_launch<true>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, st);
+        prep_launch<true, false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, nullptr,
+                                 nullptr, st);
     else
-        prep_launch<false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, st);
+        prep_launch<false, false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, nullptr,
+                                  nullptr, st);
+    return hipGetLastError();
+}
+
+bool prep_grid_applicable(const Geom &g)
+{
+    // the border prefix sums take O(w^2) steps per border row: wide windows
+    // keep the separate grid and energy kernels
+    if (g.dtype != MOCO_U16 || g.ds > 1 || g.ng > 2048 || g.w > 128) return false;
+    const int npad = (g.ng + kStrip - 1) / kStrip * kStrip;
+    return prep_lds(g, npad, kWaves) <= 64 * 1024;
+}
+
+size_t prep_grid_edge_bytes(const Geom &g) { return (size_t)4 * (g.w - 1) * g.w * sizeof(long long); }
+
+hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
+                            double *atab, int32_t *vmax, long long *edge, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (!prep_grid_applicable(g)) return hipErrorInvalidValue;
+    const int npad = (g.ng + kStrip - 1) / kStrip * kStrip;
+    if (g.ds)
+        prep_launch<true, true>(frames, C, g, npad, nullptr, nullptr, vmax, nullptr, edge, grid,
+                                atab, st);
+    else
+        prep_launch<false, true>(frames, C, g, npad, nullptr, nullptr, vmax, nullptr, edge, grid,
+                                 atab, st);
     return hipGetLastError();
 }
 

@@ -140,6 +140,14 @@ hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npa
                            int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge,
                            hipStream_t st);
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
+// The FP64 forms' grid and energies for uint16 frames with at most one 2x2
+// level, in one pass over the raw frames (the prep kernel without digit
+// planes): grid [frame][mg][ng] FP64, atab [frame][W][W] FP64 in grid units,
+// vmax as launch_prep_u16; edge: prep_grid_edge_bytes scratch per frame.
+bool prep_grid_applicable(const Geom &g);
+size_t prep_grid_edge_bytes(const Geom &g);
+hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
+                            double *atab, int32_t *vmax, long long *edge, hipStream_t st);
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st);
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
