@@ -45,17 +45,24 @@ def useful_macs(mg: int, ng: int, w: int) -> int:
     return (W * mg - w * (w - 1)) * (W * ng - w * (w - 1))
 
 
-def kernel_source_sha(fname: str) -> str:
-    """Hash of a kernel file's device code: the text up to the end of its
-    anonymous namespace (the kernels and the launch-variant choice), without
-    comments and blank space, so that a change to the host-side checks after it,
-    or to comments, keeps the counters valid."""
+def kernel_source_sha(fname: str, kernel: str) -> str:
+    """Hash of one kernel's device code in a kernel file: the text before the
+    first section rule (constants and shared helpers) and every section of the
+    anonymous namespace that names the kernel (its definition, its launch
+    shapes), without comments and blank space.  Sections are delimited by
+    comment lines of dashes.  A change to another kernel of the same file, to
+    the host-side checks after the namespace, or to comments keeps the kernel's
+    counters valid."""
     import re
     p = os.path.join(ROOT, "paper_1506_06039_amd", "csrc", fname)
     text = open(p, "rb").read()
     cut = text.find(b"\n}  // namespace\n")
     if cut >= 0:
         text = text[:cut]
+    parts = re.split(rb"\n// -{20,}\n", text)
+    name = kernel.encode()
+    keep = [parts[0]] + [sec for sec in parts[1:] if re.search(rb"\b" + re.escape(name) + rb"\b", sec)]
+    text = b"\n".join(keep)
     text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
     text = re.sub(rb"//[^\n]*", b"", text)
     text = re.sub(rb"\s+", b" ", text)
@@ -72,7 +79,7 @@ def load_traffic(kernel: str, source: str, frames_per_launch: float):
         rec = json.load(open(path)).get(kernel)
     except (ValueError, OSError):
         return None
-    if not rec or rec.get("source_sha256_16") != kernel_source_sha(source):
+    if not rec or rec.get("source_sha256_16") != kernel_source_sha(source, kernel):
         return None
     per_frame = (rec["fetch_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) / \
         rec["frames_per_dispatch"]

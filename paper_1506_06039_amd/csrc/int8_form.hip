@@ -328,6 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Correlation on the matrix cores.
+//
 // s_waitcnt vmcnt(N) lgkmcnt(0), then s_barrier.  As compiler builtins (not
 // inline asm) the wait is visible to the compiler's own counter tracking, so it
 // adds no waits of its own for transfers this one already covers; the empty
@@ -342,7 +345,6 @@ __device__ __forceinline__ void wait_barrier()
     asm volatile("" ::: "memory");
 }
 
-// ---------------------------------------------------------------------------
 // k_corr_int8: block = 4 waves = 4 frames (one per wave), one (s-group,
 // t-group) of NS x NT tiles of 32 shifts.  NPA digit planes of the frame
 // starting at PA0 (main pass: planes 0,1; extra pass: plane 2) times the two
@@ -689,6 +691,9 @@ __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict_
     if (!ds && frefine && tid < 9) frefine[(size_t)frame * 9 + tid] = NAN;
 }
 
+// ---------------------------------------------------------------------------
+// Launch shapes of k_corr_int8: the operand-transfer count per wave, the
+// tile groups and the row slices.
 template <int NS, int NT, int NPA, int PA0, int NDMA>
 hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, int nslice, long long *h, hipStream_t st)
