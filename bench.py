@@ -195,25 +195,29 @@ def measure_peaks(dev, iters: int = 20000, reps: int = 3):
     stream = torch.cuda.current_stream(dev)
     if os.path.exists(path):
         lib = ctypes.CDLL(path)
-        lib.probe_mfma_i8.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+        lib.probe_mfma_i8.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_void_p]
         lib.probe_mfma_i8.restype = ctypes.c_int
         lib.probe_mfma_i8_ops.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.probe_mfma_i8_ops.restype = ctypes.c_double
         blocks = torch.cuda.get_device_properties(dev).multi_processor_count
         out = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
-        if lib.probe_mfma_i8(blocks, 100, out.data_ptr(), stream.cuda_stream) == 0:
+        for rnd, key in ((0, "int8_mfma_tops"), (1, "int8_mfma_tops_random_operands")):
+            if lib.probe_mfma_i8(blocks, 100, rnd, out.data_ptr(), stream.cuda_stream) != 0:
+                break
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
-                lib.probe_mfma_i8(blocks, iters, out.data_ptr(), stream.cuda_stream)
+                lib.probe_mfma_i8(blocks, iters, rnd, out.data_ptr(), stream.cuda_stream)
             e1.record(stream)
             torch.cuda.synchronize(dev)
             sec = e0.elapsed_time(e1) / 1000.0 / reps
             tops = lib.probe_mfma_i8_ops(blocks, iters) / sec / 1e12
-            res["int8_mfma_tops"] = round(tops, 1)
-            res["int8_frac_of_published"] = round(tops / PEAK_INT8_TOPS, 4)
-            res["mfma_probe"] = "%d blocks x 4 waves, %d x 16 MFMAs per wave" % (blocks, iters)
+            res[key] = round(tops, 1)
+            if not rnd:
+                res["int8_frac_of_published"] = round(tops / PEAK_INT8_TOPS, 4)
+        res["mfma_probe"] = ("%d blocks x 4 waves, %d x 16 MFMAs per wave; constant operands, "
+                             "and pseudo-random operands that change every MFMA" % (blocks, iters))
     src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -493,6 +497,9 @@ def main():
              "us_per_frame": {k: round(v * 1e6, 4) for k, v in tuned_times.items()}}
     if peaks and form_ran == "int8" and "int8_mfma_tops" in peaks:
         roof["frac_of_measured_peak"] = roof["achieved"] / peaks["int8_mfma_tops"]
+        if "int8_mfma_tops_random_operands" in peaks:
+            roof["frac_of_measured_peak_random_operands"] = \
+                roof["achieved"] / peaks["int8_mfma_tops_random_operands"]
     roof["kernel"] = kname
     roof = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()}
 
