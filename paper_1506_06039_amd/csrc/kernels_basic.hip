@@ -1073,7 +1073,7 @@ __device__ __forceinline__ void roll_unit(const uint16_t *__restrict__ frames,
 
 // Fast kernel: one wave per (frame, unit); waves of frames in the slow mode
 // return at once.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_refine_roll(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_refine_roll(
     const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl, int m, int n, int br,
     int nbr, int ncw, int C, const int32_t *__restrict__ coarse_st,
     const int32_t *__restrict__ pmax, int tmax, double *__restrict__ partial)
