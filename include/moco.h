@@ -85,7 +85,9 @@ typedef enum {
                                  than it) */
     MOCO_FORM_FP64_EXACT = 3, /* direct FP64 sums on the vector ALUs; bit-exact f for uint16 */
     MOCO_FORM_INT8_MFMA = 4   /* uint16 only: exact integer correlation on int8 matrix
-                                 cores (balanced base-256 limbs); bit-exact f */
+                                 cores (balanced base-128 digits and three products per
+                                 term when the template allows, else base-256 and four:
+                                 moco_template_int8_products); bit-exact f */
 } moco_form;
 
 typedef struct moco_ctx moco_ctx;
@@ -269,6 +271,16 @@ void moco_tune_clear(void);
  * transform pass, doubled.  Host only.
  * Errors: MOCO_EINVAL (null argument, or the FFT form does not apply). */
 int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke);
+
+/* Digit products per correlation term in the int8 form's main pass for this
+ * template (sec. 2, definition of h, evaluated exactly): 3 when two balanced
+ * base-128 digits hold every value of the template's searched grid (at most
+ * 8127) and its Toeplitz rows fit the kernel's buffers -- the products d0 e0,
+ * d1 e1 and (d0 + d1)(e0 + e1) -- else 4 (two base-256 digits each side).
+ * Frames with a grid value beyond two digits take two more products in a
+ * second pass.  Host only.
+ * Errors: MOCO_EINVAL (null argument, or the int8 form does not apply). */
+int moco_template_int8_products(const moco_tmpl *tmpl, int *products);
 
 /* ---- Serving: single frames from many sources, continuous batching ----
  *

@@ -333,8 +333,10 @@ Int8Layout int8_layout(const moco::Geom &g, int npad)
 }
 
 // Prepare the template side of the int8 form: digit planes, Toeplitz rows and
-// the exact energy table.  Leaves t.int8_ok false when the template needs a
-// third digit plane.
+// the exact energy table.  Base-128 digits with a digit-sum plane (three
+// products per term) when two such digits hold every template value and the
+// rows fit the kernel's buffers, else base-256 digits (four products); leaves
+// t.int8_ok false when the template needs a third base-256 digit.
 int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
 {
     const moco::Geom &g = t.g;
@@ -356,19 +358,28 @@ int prepare_int8_template(moco::Tmpl &t, hipStream_t st)
     t.i8.padl = ig.padl;
     t.i8.trow = ig.trow;
     int32_t vmaxv = 0;
-    if ((e = moco::launch_prep_u16((const uint16_t *)t.raw, 1, g, ig.npad, limbs, nl, vm, atab,
-                                   edge, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(&nlimb, nl, sizeof nlimb, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(&vmaxv, vm, sizeof vmaxv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-        rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
-    } else if (nlimb == 2) {
-        if ((e = hipMalloc(&t.i8.tp, moco::int8_template_bytes(g))) != hipSuccess ||
+    for (int dbits = ig.trow <= moco::kInt8SumMaxTrow ? 7 : 8; dbits <= 8; ++dbits) {
+        t.i8.dbits = dbits;
+        t.i8.nq = dbits == 7 ? 3 : 2;
+        if ((e = moco::launch_prep_u16((const uint16_t *)t.raw, 1, g, ig.npad, dbits, limbs, nl,
+                                       vm, atab, edge, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(&nlimb, nl, sizeof nlimb, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(&vmaxv, vm, sizeof vmaxv, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess) {
+            rc = fail(MOCO_EDEVICE, "int8 template preparation: %s", hipGetErrorString(e));
+            break;
+        }
+        if (nlimb == 2) break;
+    }
+    if (rc == MOCO_OK && nlimb == 2) {
+        const size_t tbytes = moco::int8_template_bytes(g, t.i8.nq);
+        if ((e = hipMalloc(&t.i8.tp, tbytes)) != hipSuccess ||
             (e = hipMalloc(&t.i8.atab, (size_t)g.W * g.W * sizeof(long long))) != hipSuccess) {
             rc = fail(MOCO_ENOMEM, "int8 template allocation: %s", hipGetErrorString(e));
         } else if ((e = moco::launch_tpad(limbs, g, t.i8, st)) != hipSuccess ||
-                   (e = hipMemsetAsync(t.i8.tp + moco::int8_template_bytes(g) -
-                                           moco::kInt8ZeroTail,
+                   (e = hipMemsetAsync(t.i8.tp + tbytes - moco::kInt8ZeroTail,
                                        0, moco::kInt8ZeroTail, st)) != hipSuccess ||
                    (e = hipMemcpyAsync(t.i8.atab, atab, (size_t)g.W * g.W * sizeof(long long),
                                        hipMemcpyDeviceToDevice, st)) != hipSuccess ||
@@ -460,7 +471,8 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int32_t *coarse = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         {
             StageTimer tm(ctx, MOCO_STAGE_PREP, st);
-            HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, limbs, nl, vm, atab, edge, st));
+            HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, tt.i8.dbits, limbs, nl, vm, atab, edge,
+                                          st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
@@ -683,7 +695,8 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame time models of the two fast forms (seconds), from their kernels'
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
-// issues 64x64-shift tiles of four digit products at about 2.7e15 ops/s,
+// issues 64x64-shift tiles of three (base-128 digits with their sums) or four
+// (base-256) digit products at about 2.7e15 ops/s,
 // beside 0.35 us of prep, combine and refine per 512x512 frame; the FFT form's
 // three transform passes took 1.13 us at 288x288 and scale with P Q log2(P Q),
 // beside 0.55 us of grid, energies, combine and refine per 512x512 frame (those
@@ -693,7 +706,8 @@ double int8_model_s(const moco::Tmpl &t)
     const moco::Geom &g = t.g;
     const double groups = std::ceil(g.W / 64.0);
     const double macs = groups * groups * 64.0 * 64.0 * g.mg * (double)t.i8.npad;
-    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + macs * 4.0 * 2.0 / 2.7e15;
+    const double products = t.i8.nq == 3 ? 3.0 : 4.0;
+    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + macs * products * 2.0 / 2.7e15;
 }
 
 double fft_model_s(const moco::Tmpl &t)
@@ -902,6 +916,14 @@ int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke)
     if (!tmpl || !kf || !ke) return fail(MOCO_EINVAL, "moco_template_fft_bound: null argument");
     if (!tmpl->t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
     moco::fft_error_coefs(tmpl->t.g, tmpl->t.fft, kf, ke);
+    return MOCO_OK;
+}
+
+int moco_template_int8_products(const moco_tmpl *tmpl, int *products)
+{
+    if (!tmpl || !products) return fail(MOCO_EINVAL, "moco_template_int8_products: null argument");
+    if (!tmpl->t.int8_ok) return fail(MOCO_EINVAL, "the int8 form does not apply");
+    *products = tmpl->t.i8.nq == 3 ? 3 : 4;
     return MOCO_OK;
 }
 
@@ -1576,7 +1598,7 @@ int moco_server_add_source(moco_server *srv, int source, const void *h_template,
     sc.fbytes = fbytes;
     sc.pf = per_frame_scratch(g, resolved, tp->t);
     const size_t tb = fbytes + (size_t)g.mg * g.ng * 8 + (size_t)g.W * g.W * 16 +
-                      (tp->t.int8_ok ? moco::int8_template_bytes(g) : 0) +
+                      (tp->t.int8_ok ? moco::int8_template_bytes(g, tp->t.i8.nq) : 0) +
                       (tp->t.fft_ok ? (size_t)tp->t.fft.qh * tp->t.fft.pp.n * sizeof(double2) : 0);
     // larger frames or scratch than the buffers hold: resize once nothing is in flight
     if (fbytes > srv->slot_bytes || sc.pf > srv->pf_max) {

@@ -32,9 +32,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kBlock = 256;
 constexpr int kWaves = 4;
 constexpr int kStrip = 128;          // frame columns per strip
-constexpr int kSlotStride = 2 * kStrip + 16;  // LDS bytes per ring slot: two digit rows + bank offset
 constexpr int kPhases = 8;           // byte-phase copies of each template row
 constexpr int kMaxTrow = 1024;       // template row bytes held per phase and digit
+constexpr int kMaxTrowSum = kInt8SumMaxTrow;  // the same with a third (digit-sum) template plane
 
 __device__ inline long long wave_sum_i64(long long v)
 {
@@ -49,13 +49,26 @@ __device__ inline long long wave_sum_i64(long long v)
     return v;
 }
 
-// balanced base-256 digit: returns d in [-128,127] with x - d divisible by 256
-__device__ inline int bdigit(int x) { return ((x + 128) & 255) - 128; }
+// balanced digit of base 2^b: returns d in [-2^(b-1), 2^(b-1)) with x - d
+// divisible by 2^b
+__device__ inline int bdigit(int x, int b)
+{
+    const int half = 1 << (b - 1);
+    return ((x + half) & ((1 << b) - 1)) - half;
+}
+
+// byte-wise sum of four packed int8 (mod 256 per byte, no carry between bytes)
+__device__ inline unsigned byte_add(unsigned x, unsigned y)
+{
+    return ((x & 0x7f7f7f7fu) + (y & 0x7f7f7f7fu)) ^ ((x ^ y) & 0x80808080u);
+}
 
 // ---------------------------------------------------------------------------
 // k_prep_u16: one block per frame.
-//   limbs  [frame][3][mg][npad] int8 (plane 2 written only when needed)
-//   nlimb  [frame]               2, or 3 when some |X| > 32639
+//   limbs  [frame][3][mg][npad] int8 balanced digits of base 2^dbits (128 or
+//          256), plane 2 written only when needed
+//   nlimb  [frame]               2, or 3 when some X needs a third digit
+//          (X > 8127 in base 128, X > 32639 in base 256)
 //   atab   [frame][W][W] int64   sum of X^2 over D_{s,t} (frame side)
 //   edge   [frame][2][2][w-1][w] int64 scratch: for the first (top) and last
 //          (bottom) w-1 rows, prefix sums of X^2 over the first q columns (LP)
@@ -107,6 +120,7 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 template <bool DS, int kMaxCol4, int NW, bool GRID>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
+                                                     int dbits,
                                                      int8_t *__restrict__ limbs,
                                                      int32_t *__restrict__ nlimb,
                                                      int32_t *__restrict__ vmax,
@@ -180,10 +194,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                         grid[(size_t)frame * mg * ng + (size_t)i * ng + j] =
                             DS ? 0.25 * (double)X : (double)X;
                 } else {
-                    int d0 = bdigit(X);
-                    int x1 = (X - d0) >> 8;
-                    int d1 = bdigit(x1);
-                    if (((x1 - d1) >> 8) != 0) my_need3 = 1;
+                    int d0 = bdigit(X, dbits);
+                    int x1 = (X - d0) >> dbits;
+                    int d1 = bdigit(x1, dbits);
+                    if (((x1 - d1) >> dbits) != 0) my_need3 = 1;
                     d0p |= (d0 & 255) << (8 * q);
                     d1p |= (d1 & 255) << (8 * q);
                 }
@@ -290,10 +304,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                 for (int q = 0; q < 4; ++q) {
                     int j = j0 + q;
                     int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
-                    int d0 = bdigit(X);
-                    int x1 = (X - d0) >> 8;
-                    int d1 = bdigit(x1);
-                    int d2 = (x1 - d1) >> 8;
+                    int d0 = bdigit(X, dbits);
+                    int x1 = (X - d0) >> dbits;
+                    int d1 = bdigit(x1, dbits);
+                    int d2 = (x1 - d1) >> dbits;
                     d2p |= (d2 & 255) << (8 * q);
                 }
                 *(int *)(L2 + (size_t)i * npad + j0) = d2p;
@@ -310,21 +324,29 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
 // ---------------------------------------------------------------------------
 // Template rows as Toeplitz sources, in eight byte-phase copies so that every
 // operand read is 8-byte aligned: TP[i][q][phi][x] = digit q of
-// Y[i][x + phi - padl] (zero outside 0..ng-1), q = 0,1, phi = 0..7.
+// Y[i][x + phi - padl] (zero outside 0..ng-1), q = 0,1, phi = 0..7; with nq = 3
+// a third plane q = 2 holds the digit sums e0 + e1 (base-128 digits, so the
+// sum stays within int8).
 __global__ __launch_bounds__(kBlock) void k_tpad(const int8_t *__restrict__ tl, int mg, int ng,
-                                                 int npad, int trow, int padl,
+                                                 int npad, int trow, int padl, int nq,
                                                  int8_t *__restrict__ tp)
 {
-    const size_t total = (size_t)mg * 2 * kPhases * trow;
+    const size_t total = (size_t)mg * nq * kPhases * trow;
+    const size_t plane = (size_t)mg * npad;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         int x = (int)(idx % trow);
         size_t r = idx / trow;
         int phi = (int)(r % kPhases);
         r /= kPhases;
-        int q = (int)(r % 2), i = (int)(r / 2);
+        int q = (int)(r % nq), i = (int)(r / nq);
         int j = x + phi - padl;
-        tp[idx] = (j >= 0 && j < ng) ? tl[(size_t)q * mg * npad + (size_t)i * npad + j] : 0;
+        int8_t v = 0;
+        if (j >= 0 && j < ng) {
+            const size_t k = (size_t)i * npad + j;
+            v = q < 2 ? tl[q * plane + k] : (int8_t)(tl[k] + tl[plane + k]);
+        }
+        tp[idx] = v;
     }
 }
 
@@ -350,6 +372,13 @@ __device__ __forceinline__ void wait_barrier()
 // starting at PA0 (main pass: planes 0,1; extra pass: plane 2) times the two
 // template planes.  Every product is a separate exact int32 accumulator.
 //
+// KB (base-128 digits, |d| <= 64): the main pass takes three products instead
+// of four, d0 e0, d1 e1 and (d0 + d1)(e0 + e1), whose operands stay within
+// int8 (Karatsuba); h = H00 + 128 (S - H00 - H11) + 16384 H11.  The template
+// carries its digit sums as a third plane; the frame's are formed in the ring
+// once a row has landed (a byte-wise add of the row's two planes into a third
+// plane of its slot).  The extra pass weights its products by 128^(2+q).
+//
 // Per template row i and strip of 128 frame columns: each wave reads its A
 // operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
 // (template row i as a Toeplitz operand) from the shared template buffer, four
@@ -361,7 +390,7 @@ __device__ __forceinline__ void wait_barrier()
 // so every LDS read provably targets a buffer other than the ones being
 // filled) and two free ring slots; one wait for every transfer and one
 // barrier per pair.
-template <int NS, int NT, int NPA, int PA0, int NDMA>
+template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
     const int8_t *__restrict__ tp, const int8_t *__restrict__ zsrc, int C, int mg, int npad,
@@ -370,13 +399,20 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     constexpr int RING = 32 * NS;     // frame rows an iteration reads
     constexpr int RS = RING + 3;      // ring slots: a pair of rows reads RING + 1, the next
                                       // pair's two arrive meanwhile
-    constexpr int NACC = NPA * 2;
+    constexpr bool SUMP = KB && PA0 == 0;        // three-product main pass
+    constexpr int NA = SUMP ? 3 : NPA;           // frame operands per tile: digits (+ sums)
+    constexpr int NB = SUMP ? 3 : 2;             // template operands per tile
+    constexpr int NACC = SUMP ? 3 : NPA * 2;
+    constexpr int DB = KB ? 7 : 8;               // digit bits
+    constexpr int TQ = KB ? 3 : 2;               // template planes held
+    constexpr int MAXT = KB ? kMaxTrowSum : kMaxTrow;
+    constexpr int SLOT = (SUMP ? 3 : 2) * kStrip + 16;   // LDS bytes per ring slot (+ bank offset)
     constexpr int KC = kStrip / 32;   // MFMA K-chunks per strip (npad is a multiple of kStrip)
-    __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * RS * kSlotStride];
-    __shared__ __attribute__((aligned(16))) int8_t s_tA[2 * kPhases * kMaxTrow];
-    __shared__ __attribute__((aligned(16))) int8_t s_tB[2 * kPhases * kMaxTrow];
-    __shared__ __attribute__((aligned(16))) int8_t s_tC[2 * kPhases * kMaxTrow];
-    __shared__ __attribute__((aligned(16))) int8_t s_tD[2 * kPhases * kMaxTrow];
+    __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * RS * SLOT];
+    __shared__ __attribute__((aligned(16))) int8_t s_tA[TQ * kPhases * MAXT];
+    __shared__ __attribute__((aligned(16))) int8_t s_tB[TQ * kPhases * MAXT];
+    __shared__ __attribute__((aligned(16))) int8_t s_tC[TQ * kPhases * MAXT];
+    __shared__ __attribute__((aligned(16))) int8_t s_tD[TQ * kPhases * MAXT];
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int rho = lane % 32, h = lane / 32;
@@ -408,7 +444,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         if (!any) return;
     }
     const int8_t *fl = limbs + (size_t)(live ? frame : 0) * 3 * plane + (size_t)PA0 * plane;
-    int8_t *my_ring = s_ring + (size_t)wave * RS * kSlotStride;
+    int8_t *my_ring = s_ring + (size_t)wave * RS * SLOT;
 
     v16i acc[NS][NT][NACC];
 #pragma unroll
@@ -436,7 +472,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         const bool have = live && r >= 0 && r < mg;
         const int p = NPA == 2 ? lane / 32 : 0;
         unsigned la = (unsigned)(uintptr_t)(__attribute__((address_space(3))) void *)(
-            my_ring + (size_t)slot * kSlotStride);
+            my_ring + (size_t)slot * SLOT);
         asm volatile("" : "+v"(la));
         __builtin_amdgcn_global_load_lds(
             (const void *)(have ? fl + (size_t)p * plane + (size_t)r * npad + ks + (lane % 32) * 4
@@ -447,10 +483,10 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     // of the row (Qw = rowbytes/4) in exactly NDMA transfers of 1 KB with every
     // lane active.  The last transfer runs up to 1 KB past the quarter: into the
     // next quarter with the very bytes that wave writes there, or for the last
-    // quarter past the row (inside the buffer: 3 Qw + NDMA KB <= 16 KB; and
-    // inside the template allocation, whose last row is followed by a 1 KB
-    // zero tail), where nothing reads.
-    const int rowbytes = 2 * kPhases * trow;      // one template row: both digits, all phases
+    // quarter past the row (inside the buffer: 3 Qw + NDMA KB <= TQ * 8 * MAXT
+    // bytes; and inside the template allocation, whose last row is followed by
+    // a 1 KB zero tail), where nothing reads.
+    const int rowbytes = TQ * kPhases * trow;     // one template row: every plane, all phases
     const int qw = rowbytes / kWaves;
     auto dma_row = [&](int ti, int8_t *dst) {
         const int8_t *src = tp + (size_t)ti * rowbytes + wave * qw;
@@ -460,6 +496,22 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 (const void *)(src + c * 1024 + lane * 16),
                 (__attribute__((address_space(3))) void *)(dst + wave * qw + c * 1024), 16, 0, 0);
     };
+    // SUMP: the digit-sum plane of frame rows r0 .. r0 + nrows - 1, once their
+    // transfers have landed (after a wait): two rows per step, a dword of four
+    // columns per lane.  Each wave writes only its own ring, and its later
+    // reads of these bytes follow in its own LDS order.
+    auto ring_sums = [&](int r0, int nrows) {
+        for (int k = 0; k < nrows; k += 2) {
+            const int kk = k + lane / 32;
+            if (kk < nrows) {
+                int8_t *row = my_ring + (size_t)((r0 + kk - s_lo) % RS) * SLOT;
+                const int c = (lane % 32) * 4;
+                const unsigned x = *(const unsigned *)(row + c);
+                const unsigned y = *(const unsigned *)(row + kStrip + c);
+                *(unsigned *)(row + 2 * kStrip + c) = byte_add(x, y);
+            }
+        }
+    };
 
     for (int ks = 0; ks < npad; ks += kStrip) {
         // frame rows for the first pair (template rows i_lo and i_lo + 1):
@@ -468,19 +520,20 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         dma_row(i_lo, s_tA);
         if (i_lo + 1 < i_hi) dma_row(i_lo + 1, s_tB);
         wait_barrier<0>();
+        if constexpr (SUMP) ring_sums(i_lo + s_lo, RING + 1);
 
         // MFMAs of template row i (from tcur) against frame rows i + s
         auto rowmma = [&](int i, const int8_t *tcur) {
             // operand addresses of K-chunk 0; chunk kc adds kc*32 bytes.  The byte
             // phase of a template read does not depend on kc (32 is a multiple of 8).
-            const int8_t *abase[NS][NPA];
+            const int8_t *abase[NS][NA];
 #pragma unroll
             for (int st = 0; st < NS; ++st)
 #pragma unroll
-                for (int p = 0; p < NPA; ++p)
-                    abase[st][p] = my_ring + (size_t)((i + 32 * st + rho) % RS) * kSlotStride +
+                for (int p = 0; p < NA; ++p)
+                    abase[st][p] = my_ring + (size_t)((i + 32 * st + rho) % RS) * SLOT +
                                    p * kStrip + 16 * h;
-            const int8_t *bbase[NT][2];
+            const int8_t *bbase[NT][NB];
 #pragma unroll
             for (int tt = 0; tt < NT; ++tt) {
                 // template bytes B[i][k - t] for k = ks + kc*32 + 16h + e, t = t_lo + 32 tt + rho,
@@ -488,66 +541,82 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 int x0 = ks + 16 * h - (t_lo + 32 * tt + rho) + padl;
                 int phi = x0 & (kPhases - 1);
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < NB; ++q)
                     bbase[tt][q] = tcur + ((size_t)q * kPhases + phi) * trow + (x0 - phi);
             }
-            auto load_a = [&](int kc, v4i (&av)[NS][NPA]) {
+            auto load_a = [&](int kc, v4i (&av)[NS][NA]) {
 #pragma unroll
                 for (int st = 0; st < NS; ++st)
 #pragma unroll
-                    for (int p = 0; p < NPA; ++p) av[st][p] = *(const v4i *)(abase[st][p] + kc * 32);
+                    for (int p = 0; p < NA; ++p) av[st][p] = *(const v4i *)(abase[st][p] + kc * 32);
             };
-            auto load_b = [&](int kc, v4i (&bv)[NT][2]) {
+            auto load_b = [&](int kc, v4i (&bv)[NT][NB]) {
 #pragma unroll
                 for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < NB; ++q) {
                         const int2 *src = (const int2 *)(bbase[tt][q] + kc * 32);
                         int2 lo = src[0], hi = src[1];
                         bv[tt][q] = v4i{lo.x, lo.y, hi.x, hi.y};
                     }
             };
 
-            v4i av[NS][NPA], bv[NT][2];
+            v4i av[NS][NA], bv[NT][NB];
             load_a(0, av);
             load_b(0, bv);
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                v4i an[NS][NPA], bn[NT][2];
+                v4i an[NS][NA], bn[NT][NB];
                 if (kc + 1 < KC) {
                     load_a(kc + 1, an);
                     load_b(kc + 1, bn);
                 }
+                if constexpr (SUMP) {
 #pragma unroll
-                for (int st = 0; st < NS; ++st)
+                    for (int st = 0; st < NS; ++st)
 #pragma unroll
-                    for (int tt = 0; tt < NT; ++tt)
+                        for (int tt = 0; tt < NT; ++tt) {
+                            acc[st][tt][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                av[st][0], bv[tt][0], acc[st][tt][0], 0, 0, 0);
+                            acc[st][tt][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                av[st][NA - 1], bv[tt][NB - 1], acc[st][tt][1], 0, 0, 0);
+                            acc[st][tt][NACC - 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                av[st][1 % NA], bv[tt][1], acc[st][tt][NACC - 1], 0, 0, 0);
+                        }
+                } else {
 #pragma unroll
-                        for (int p = 0; p < NPA; ++p)
+                    for (int st = 0; st < NS; ++st)
 #pragma unroll
-                            for (int q = 0; q < 2; ++q)
-                                acc[st][tt][p * 2 + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                    av[st][p], bv[tt][q], acc[st][tt][p * 2 + q], 0, 0, 0);
+                        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                            for (int p = 0; p < NPA; ++p)
+#pragma unroll
+                                for (int q = 0; q < 2; ++q)
+                                    acc[st][tt][p * 2 + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                        av[st][p], bv[tt][q], acc[st][tt][p * 2 + q], 0, 0, 0);
+                }
                 // issue order: one MFMA, one LDS read of the next chunk, ..., then
                 // the remaining MFMAs (with one wave per SIMD, a burst of reads
                 // would hold back the MFMA issue, and reads sunk next to their
                 // uses would stall on their latency)
+                constexpr int NRD = NS * NA + NT * NB;
+                constexpr int NMF = NS * NT * NACC;
 #pragma unroll
-                for (int g = 0; g < NS * NPA + NT * 2; ++g) {
+                for (int g = 0; g < (NRD < NMF ? NRD : NMF); ++g) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
                 }
-                __builtin_amdgcn_sched_group_barrier(0x008, NS * NT * NPA * 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
                 __builtin_amdgcn_sched_barrier(0);
                 if (kc + 1 < KC) {
 #pragma unroll
                     for (int st = 0; st < NS; ++st)
 #pragma unroll
-                        for (int p = 0; p < NPA; ++p) av[st][p] = an[st][p];
+                        for (int p = 0; p < NA; ++p) av[st][p] = an[st][p];
 #pragma unroll
                     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) bv[tt][q] = bn[tt][q];
+                        for (int q = 0; q < NB; ++q) bv[tt][q] = bn[tt][q];
                 }
             }
         };
@@ -564,6 +633,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
             rowmma(i, t0);
             if (i + 1 < i_hi) rowmma(i + 1, t1);
             wait_barrier<0>();
+            if constexpr (SUMP) ring_sums(i + s_lo + RING + 1, 2);
         };
         for (int i = i_lo; i < i_hi; i += 4) {
             pair(i, s_tA, s_tB, s_tC, s_tD);
@@ -583,11 +653,18 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 int t = t_lo + 32 * tt + rho;
                 if (s > w - 1 || t > w - 1) continue;
                 long long v = 0;
+                if constexpr (SUMP) {
+                    const long long h00 = acc[st][tt][0][r], sum = acc[st][tt][1][r];
+                    const long long h11 = acc[st][tt][NACC - 1][r];
+                    v = h00 + (sum - h00 - h11) * 128 + h11 * 16384;
+                } else {
 #pragma unroll
-                for (int p = 0; p < NPA; ++p)
+                    for (int p = 0; p < NPA; ++p)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        v += (long long)acc[st][tt][p * 2 + q][r] * (1LL << (8 * (PA0 + p + q)));
+                        for (int q = 0; q < 2; ++q)
+                            v += (long long)acc[st][tt][p * 2 + q][r] *
+                                 (1LL << (DB * (PA0 + p + q)));
+                }
                 size_t k = (size_t)(s + w - 1) * W + (t + w - 1);
                 if (nslice > 1)
                     atomicAdd((unsigned long long *)&H[k], (unsigned long long)v);
@@ -694,31 +771,46 @@ __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict_
 // ---------------------------------------------------------------------------
 // Launch shapes of k_corr_int8: the operand-transfer count per wave, the
 // tile groups and the row slices.
-template <int NS, int NT, int NPA, int PA0, int NDMA>
+template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
 hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, int nslice, long long *h, hipStream_t st)
 {
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
     dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups, nslice);
-    const int8_t *zsrc = tt.tp + (size_t)g.mg * 2 * kPhases * tt.trow;  // zero tail
-    k_corr_int8<NS, NT, NPA, PA0, NDMA><<<grid, kBlock, 0, st>>>(
+    const int8_t *zsrc = tt.tp + (size_t)g.mg * tt.nq * kPhases * tt.trow;  // zero tail
+    k_corr_int8<NS, NT, NPA, PA0, NDMA, KB><<<grid, kBlock, 0, st>>>(
         limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, nslice, h);
     return hipGetLastError();
+}
+
+template <int NS, int NT, int NPA, int PA0, bool KB>
+hipError_t launch_corr_nq(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
+                          const Geom &g, int nslice, long long *h, hipStream_t st)
+{
+    // transfers per wave for a quarter of a template row (nq * 2 * trow bytes);
+    // the buffer bound 3 quarters + NDMA KB <= nq * 8 * max row holds for every
+    // trow up to that maximum
+    switch ((tt.nq * 2 * tt.trow + 1023) / 1024) {
+    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int NS, int NT, int NPA, int PA0>
 hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
                                int C, const Geom &g, int nslice, long long *h, hipStream_t st)
 {
-    // transfers per wave for a quarter of a template row (4 * trow bytes)
-    switch ((4 * tt.trow + 1023) / 1024) {
-    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4>(limbs, nlimb, tt, C, g, nslice, h, st);
-    default: return hipErrorInvalidValue;
+    // base-128 digits with a digit-sum plane (three products), or base-256 (four)
+    if (tt.nq == 3) {
+        if (tt.trow > kMaxTrowSum) return hipErrorInvalidValue;
+        return launch_corr_nq<NS, NT, NPA, PA0, true>(limbs, nlimb, tt, C, g, nslice, h, st);
     }
+    if (tt.trow > kMaxTrow) return hipErrorInvalidValue;
+    return launch_corr_nq<NS, NT, NPA, PA0, false>(limbs, nlimb, tt, C, g, nslice, h, st);
 }
 
 // Row slices per block group: with fewer blocks than compute units (a few
@@ -784,33 +876,33 @@ bool int8_applicable(const Geom &g)
     return int8_geom(g).trow <= kMaxTrow;
 }
 
-size_t int8_template_bytes(const Geom &g)
+size_t int8_template_bytes(const Geom &g, int nq)
 {
     // the Toeplitz rows, then kInt8ZeroTail zero bytes (the source of frame
     // rows outside the frame)
-    return (size_t)g.mg * 2 * kPhases * int8_geom(g).trow + kInt8ZeroTail;
+    return (size_t)g.mg * nq * kPhases * int8_geom(g).trow + kInt8ZeroTail;
 }
 
 template <bool DS, int NW, bool GRID>
-void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int nc, size_t lds,
-                    int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
+void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int nc,
+                    size_t lds, int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
                     long long *edge, double *grid, double *atab_d, hipStream_t st)
 {
     if (nc <= 1)
         k_prep_u16<DS, 1, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
                                                              grid, atab_d);
     else if (nc <= 2)
         k_prep_u16<DS, 2, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
                                                              grid, atab_d);
     else if (nc <= 4)
         k_prep_u16<DS, 4, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
                                                              grid, atab_d);
     else
         k_prep_u16<DS, 8, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, limbs, nlimb, vmax, atab, edge,
+                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
                                                              grid, atab_d);
 }
 
@@ -821,7 +913,7 @@ size_t prep_lds(const Geom &g, int npad, int nw)
 }
 
 template <bool DS, bool GRID>
-void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
+void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int8_t *limbs,
                  int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, double *grid,
                  double *atab_d, hipStream_t st)
 {
@@ -830,25 +922,26 @@ void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int8_t 
     // a few frames: sixteen waves per frame (one block of four waves streams a
     // frame at a fraction of the device's bandwidth)
     if (C <= 128 && prep_lds(g, npad, 16) <= 64 * 1024)
-        prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, nc, prep_lds(g, npad, 16), limbs, nlimb,
+        prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, 16), limbs, nlimb,
                                      vmax, atab, edge, grid, atab_d, st);
     else
-        prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, nc, prep_lds(g, npad, kWaves), limbs,
+        prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, kWaves), limbs,
                                          nlimb, vmax, atab, edge, grid, atab_d, st);
 }
 
-hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad,
+hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
                            int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
                            long long *edge, hipStream_t st)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
+    if (dbits != 7 && dbits != 8) return hipErrorInvalidValue;
     if (g.ds)
-        prep_launch<true, false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, nullptr,
-                                 nullptr, st);
+        prep_launch<true, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
+                                 nullptr, nullptr, st);
     else
-        prep_launch<false, false>(frames, C, g, npad, limbs, nlimb, vmax, atab, edge, nullptr,
-                                  nullptr, st);
+        prep_launch<false, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
+                                  nullptr, nullptr, st);
     return hipGetLastError();
 }
 
@@ -871,19 +964,19 @@ hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double
     if (!prep_grid_applicable(g)) return hipErrorInvalidValue;
     const int npad = (g.ng + kStrip - 1) / kStrip * kStrip;
     if (g.ds)
-        prep_launch<true, true>(frames, C, g, npad, nullptr, nullptr, vmax, nullptr, edge, grid,
-                                atab, st);
+        prep_launch<true, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
+                                grid, atab, st);
     else
-        prep_launch<false, true>(frames, C, g, npad, nullptr, nullptr, vmax, nullptr, edge, grid,
-                                 atab, st);
+        prep_launch<false, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
+                                 grid, atab, st);
     return hipGetLastError();
 }
 
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st)
 {
     clear_stale_error();
-    k_tpad<<<grid_for((size_t)2 * kPhases * g.mg * tt.trow), kBlock, 0, st>>>(tlimbs, g.mg, g.ng, tt.npad,
-                                                                   tt.trow, tt.padl, tt.tp);
+    k_tpad<<<grid_for((size_t)tt.nq * kPhases * g.mg * tt.trow), kBlock, 0, st>>>(
+        tlimbs, g.mg, g.ng, tt.npad, tt.trow, tt.padl, tt.nq, tt.tp);
     return hipGetLastError();
 }
 

@@ -25,13 +25,16 @@ struct Int8Geom {
     int npad, padl, trow;
 };
 
-// Template side of the int8 form (device memory owned by the template).
+// Template side of the int8 form (device memory owned by the template).  Digits
+// of base 2^dbits: 128 with nq = 3 template planes (the two digits and their
+// sum; three digit products per term), or 256 with nq = 2 (four products).
 struct Int8Tmpl {
-    int8_t *tp = nullptr;          // [mg][2][8][trow] digit rows of the template, 8 byte phases
+    int8_t *tp = nullptr;          // [mg][nq][8][trow] digit rows of the template, 8 byte phases
     int32_t vmax = -1;             // bound of the template's pixel values (-1: none)
     long long *atab = nullptr;     // [W][W] sum of Y^2 over the frame-side rows of D at (s,t);
                                    // the template energy at (s,t) is this table at (-s,-t)
     int npad = 0, padl = 0, trow = 0;
+    int dbits = 8, nq = 2;
 };
 
 // One-dimensional transform plan: length n = product of the radices, applied
@@ -131,14 +134,18 @@ int roll_band_rows(const Geom &g, int C);
 // ---- int8 form (int8_form.hip) -----------------------------------------
 Int8Geom int8_geom(const Geom &g);
 bool int8_applicable(const Geom &g);
-size_t int8_template_bytes(const Geom &g);   // Toeplitz rows + kInt8ZeroTail zero bytes
+// the digit-sum form (base 128, three products) also needs template rows of at
+// most this many bytes
+constexpr int kInt8SumMaxTrow = 512;
+size_t int8_template_bytes(const Geom &g, int nq);   // Toeplitz rows + kInt8ZeroTail zero bytes
 constexpr size_t kInt8ZeroTail = 1024;
-// nlimb[frame]: digit planes (2 or 3); vmax[frame]: an upper bound of the frame's
-// pixel values (its largest grid value), or INT32_MAX when the grid does not
-// cover every pixel (odd sides when downsampling)
-hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int8_t *limbs,
-                           int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge,
-                           hipStream_t st);
+// digits of base 2^dbits (7 or 8); nlimb[frame]: digit planes (2 or 3);
+// vmax[frame]: an upper bound of the frame's pixel values (its largest grid
+// value), or INT32_MAX when the grid does not cover every pixel (odd sides when
+// downsampling)
+hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
+                           int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
+                           long long *edge, hipStream_t st);
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
 // The FP64 forms' grid and energies for uint16 frames with at most one 2x2
 // level, in one pass over the raw frames (the prep kernel without digit

@@ -92,6 +92,8 @@ _lib.moco_template_form.restype = _i
 _lib.moco_template_fft_bound.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
 _lib.moco_template_fft_bound.restype = _i
+_lib.moco_template_int8_products.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+_lib.moco_template_int8_products.restype = _i
 _lib.moco_graph_create.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
                                    ctypes.POINTER(_Outputs), ctypes.POINTER(_vp)]
 _lib.moco_graph_create.restype = _i
@@ -438,10 +440,11 @@ def fft_bound(tmpl: Template):
 
 
 def int8_products(tmpl: Template) -> int:
-    """int8 digit products per correlation term in the int8 form: two balanced
-    base-256 digits of the frame times two of the template (frames that need a
-    third digit add two more products)."""
-    return 4
+    """moco_template_int8_products: digit products per correlation term in the
+    int8 form's main pass (3: base-128 digits and their sums; 4: base-256)."""
+    n = ctypes.c_int()
+    _check(_lib.moco_template_int8_products(tmpl.handle, ctypes.byref(n)))
+    return n.value
 
 
 class Server:

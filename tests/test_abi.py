@@ -102,6 +102,9 @@ def test_fft_bound_null_arguments_rejected_without_gpu(lib):
     lib.moco_template_fft_bound.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.moco_template_fft_bound.restype = ctypes.c_int
     assert lib.moco_template_fft_bound(None, None, None) == -1
+    lib.moco_template_int8_products.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.moco_template_int8_products.restype = ctypes.c_int
+    assert lib.moco_template_int8_products(None, None) == -1
 
 
 def test_binding_structs_match_the_header(lib, tmp_path):

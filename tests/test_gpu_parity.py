@@ -189,6 +189,58 @@ def test_int8_third_digit_plane_frames(gpu_lib):
         assert np.array_equal(res8[k], res64[k], equal_nan=True), k
 
 
+def _digit_case(seed, m, tmpl_level, frame_level, patch_level):
+    # smooth random scene at tmpl_level counts, frames rolled copies at
+    # frame_level, odd frames with a patch at patch_level counts per pixel
+    rng = np.random.default_rng(seed)
+    base = rng.uniform(0, 1, size=(m, m))
+    tmpl = rng.poisson(tmpl_level * base + 20).astype(np.uint16)
+    frames = []
+    for k in range(6):
+        lam = np.roll(frame_level * base + 20, (k - 3, 2 * k - 5), (0, 1))
+        f = rng.poisson(lam).astype(np.int64)
+        if k % 2 == 1 and patch_level:
+            f[10:30, 40:70] = patch_level + rng.integers(0, patch_level // 10 + 1, size=(20, 30))
+        frames.append(np.clip(f, 0, 65535).astype(np.uint16))
+    return tmpl, np.stack(frames)
+
+
+# (template level, frame level, patch level, digit products of the main pass):
+# base-128 digits with their sums while the template's grid values stay within
+# 8127; frames beyond that take the extra pass (second digit 1..16 here); a
+# brighter template takes base-256 digits and four products.
+DIGIT_CASES = [
+    (900, 900, 0, 3),
+    (900, 900, 3500, 3),
+    (900, 900, 60000, 3),
+    (3500, 3500, 0, 4),
+    (3500, 3500, 7000, 4),
+    (3500, 3500, 60000, 4),
+]
+
+
+@pytest.mark.parametrize("ds", [True, False])
+@pytest.mark.parametrize("w", [12, 20])
+@pytest.mark.parametrize("case", DIGIT_CASES)
+def test_int8_digit_bases(gpu_lib, case, w, ds):
+    tl, fl, pl, products = case
+    if not ds:
+        # without downsampling the grid values are the pixels, not sums of four:
+        # four times the levels keeps the same digit counts
+        tl, fl, pl = 4 * tl, 4 * fl, min(4 * pl, 60000)
+    tmpl, fr = _digit_case(11 + w, 96, tl, fl, pl)
+    _say("case int8 digits tmpl %d frames %d patch %d w=%d ds=%d" % (tl, fl, pl, w, ds))
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(tmpl), w, ds)
+    assert gpu_lib.int8_products(tp) == products
+    tp.close()
+    res8 = _run(gpu_lib, fr, tmpl, w, ds, "int8", surface=True, ctx=ctx)
+    ctx.close()
+    orc = oracle.align(fr, tmpl, w, ds, want_surface=True)
+    check(res8, orc, ds, exact=True, label="int8 digits")
+    check_surface(res8["fsurf"], orc.surf, exact=True, label="int8 digits surface")
+
+
 def test_int8_bright_template_falls_back(gpu_lib):
     # a template beyond two base-256 digits: the int8 form refuses it, AUTO uses FP64
     rng = np.random.default_rng(5)
