@@ -561,6 +561,25 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                     }
             };
 
+            // t-tile 1 reads its template bytes 32 columns before t-tile 0's
+            // (t is 32 larger), so its operand at chunk kc + 1 is t-tile 0's at
+            // chunk kc: with two t-tiles only t-tile 0 is read after chunk 0
+            constexpr int NTL = NT == 2 ? 1 : NT;   // t-tiles read per later chunk
+            auto load_b_next = [&](int kc, const v4i (&bv)[NT][NB], v4i (&bn)[NT][NB]) {
+#pragma unroll
+                for (int tt = 0; tt < NTL; ++tt)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) {
+                        const int2 *src = (const int2 *)(bbase[tt][q] + kc * 32);
+                        int2 lo = src[0], hi = src[1];
+                        bn[tt][q] = v4i{lo.x, lo.y, hi.x, hi.y};
+                    }
+                if constexpr (NT == 2) {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) bn[1][q] = bv[0][q];
+                }
+            };
+
             v4i av[NS][NA], bv[NT][NB];
             load_a(0, av);
             load_b(0, bv);
@@ -569,7 +588,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 v4i an[NS][NA], bn[NT][NB];
                 if (kc + 1 < KC) {
                     load_a(kc + 1, an);
-                    load_b(kc + 1, bn);
+                    load_b_next(kc + 1, bv, bn);
                 }
                 if constexpr (SUMP) {
 #pragma unroll
@@ -599,7 +618,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 // the remaining MFMAs (with one wave per SIMD, a burst of reads
                 // would hold back the MFMA issue, and reads sunk next to their
                 // uses would stall on their latency)
-                constexpr int NRD = NS * NA + NT * NB;
+                constexpr int NRD = NS * NA + NTL * NB;
                 constexpr int NMF = NS * NT * NACC;
 #pragma unroll
                 for (int g = 0; g < (NRD < NMF ? NRD : NMF); ++g) {
