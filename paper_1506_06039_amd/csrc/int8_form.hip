@@ -279,20 +279,21 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
         else
             atab[(size_t)frame * W * W + k] = v;
     };
-    for (int tt = threadIdx.x; tt < W; tt += blockDim.x) {
+    // one thread per (column shift t, sign of the row shift); the corner sums
+    // run down the rows, their loads unrolled so that several are in flight
+    for (int idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+        const int tt = idx % W, side = idx / W;
         const int t = tt - we, at = t < 0 ? -t : t;
         const int lr = t > 0 ? 0 : 1;
         const long long colex = t > 0 ? cL[at] : (t < 0 ? cR[at] : 0);
         const long long base = Etot - colex;
-        put((size_t)we * W + tt, base);
-        long long ct = 0, cb = 0;
+        if (side == 0) put((size_t)we * W + tt, base);
+        const long long *rx = side ? rB : rT;   // rows excluded at the top (+s) or bottom (-s)
+        long long c = 0;
+#pragma unroll 8
         for (int s = 1; s < w; ++s) {
-            if (t != 0) {
-                ct += E[eidx(0, lr, s - 1, at)];
-                cb += E[eidx(1, lr, s - 1, at)];
-            }
-            put((size_t)(we + s) * W + tt, base - rT[s] + ct);   // shift +s excludes top rows
-            put((size_t)(we - s) * W + tt, base - rB[s] + cb);   // shift -s excludes bottom rows
+            if (t != 0) c += E[eidx(side, lr, s - 1, at)];
+            put((size_t)(side ? we - s : we + s) * W + tt, base - rx[s] + c);
         }
     }
     // third digit plane, only for frames that need it
