@@ -241,6 +241,26 @@ def test_int8_digit_bases(gpu_lib, case, w, ds):
     check_surface(res8["fsurf"], orc.surf, exact=True, label="int8 digits surface")
 
 
+def test_int8_wide_rows_take_base_256(gpu_lib):
+    # a dim template whose Toeplitz rows exceed the digit-sum form's 512 bytes
+    # (800 grid columns): base-256 digits and four products, still exact
+    rng = np.random.default_rng(3)
+    base = rng.uniform(0, 1, size=(64, 800))
+    tmpl = rng.poisson(900 * base + 20).astype(np.uint16)
+    fr = np.stack([rng.poisson(np.roll(900 * base + 20, (k - 2, 3 - k), (0, 1))).astype(np.uint16)
+                   for k in range(5)])
+    _say("case int8 wide rows 64x800 w=8 ds=0")
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(tmpl), 8, False)
+    assert gpu_lib.int8_products(tp) == 4
+    tp.close()
+    res8 = _run(gpu_lib, fr, tmpl, 8, False, "int8", surface=True, ctx=ctx)
+    ctx.close()
+    orc = oracle.align(fr, tmpl, 8, False, want_surface=True)
+    check(res8, orc, False, exact=True, label="int8 wide rows")
+    check_surface(res8["fsurf"], orc.surf, exact=True, label="int8 wide rows surface")
+
+
 def test_int8_bright_template_falls_back(gpu_lib):
     # a template beyond two base-256 digits: the int8 form refuses it, AUTO uses FP64
     rng = np.random.default_rng(5)
