@@ -9,16 +9,19 @@
 //     int64, from row/column energies and corner prefix tables built while the
 //     frame streams in (k_prep_u16);
 //   * the correlation h_{s,t} = sum over D of a[i+s][j+t]*b[i][j] (sec. 2,
-//     definition of h) on int8 MFMA: each value is split into balanced base-256
-//     digits X = d0 + 256*d1 (+ 65536*d2), d in [-128,127], every digit product
-//     is exact in the int32 accumulators, and h = sum 256^(p+q) H_pq in int64
-//     (k_corr_int8).
+//     definition of h) on int8 MFMA: each value is split into balanced digits,
+//     base 128 (X = d0 + 128*d1 (+ 16384*d2), |d| <= 64) when the template's
+//     values allow, with three products per term (d0 e0, d1 e1 and
+//     (d0 + d1)(e0 + e1), Karatsuba), else base 256 (d in [-128,127]) with
+//     four; every digit product is exact in the int32 accumulators and h is
+//     recombined in int64 (k_corr_int8).
 //
 // The correlation is a band contraction: for template row i and frame column
 // k, H[s][t] += A[i+s][k] * B[i][k-t].  M = s (frame rows i+s, read from a
 // per-wave ring of frame rows in LDS), N = t (the template row i laid out as a
-// Toeplitz operand, read from LDS at a per-lane byte offset and re-aligned
-// with v_alignbyte), K = k (32 columns per MFMA).
+// Toeplitz operand, read from LDS at a per-lane byte offset from one of eight
+// byte-phase copies, so that every read is 8-byte aligned), K = k (32 columns
+// per MFMA).
 #include <math.h>
 
 #include "moco_internal.h"
@@ -383,7 +386,8 @@ __device__ __forceinline__ void wait_barrier()
 // Per template row i and strip of 128 frame columns: each wave reads its A
 // operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
 // (template row i as a Toeplitz operand) from the shared template buffer, four
-// K-chunks of 32 columns, 16 MFMAs per chunk, the LDS reads of chunk k+1
+// K-chunks of 32 columns, 12 MFMAs per chunk (16 with four products), the LDS
+// reads of chunk k+1
 // interleaved with the MFMAs of chunk k.  Template rows are taken in pairs:
 // while rows i, i+1 are in use, template rows i+2, i+3 and frame rows
 // i+s_lo+RING+1, +2 stream global -> LDS (no registers) into the other two of
