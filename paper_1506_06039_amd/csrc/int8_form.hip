@@ -387,8 +387,7 @@ __device__ __forceinline__ void wait_barrier()
 // operands (frame rows i+s) from its own ring of 32*NS rows and the B operands
 // (template row i as a Toeplitz operand) from the shared template buffer, four
 // K-chunks of 32 columns, 12 MFMAs per chunk (16 with four products), the LDS
-// reads of chunk k+1
-// interleaved with the MFMAs of chunk k.  Template rows are taken in pairs:
+// reads of chunk k+1 interleaved with the MFMAs of chunk k.  Template rows are taken in pairs:
 // while rows i, i+1 are in use, template rows i+2, i+3 and frame rows
 // i+s_lo+RING+1, +2 stream global -> LDS (no registers) into the other two of
 // four statically distinct template buffers (the pair loop is unrolled by two,
