@@ -198,10 +198,27 @@ __device__ double2 *fft_lds(double2 *a, double2 *b, int rows, const FftPlan &pl,
     return a;
 }
 
-// Pass 1: rows.  Block (group of rp row pairs, frame).  grid: mg x ng FP64 per
-// frame.  s1: [frame][qh][mg] complex.
-__global__ __launch_bounds__(kBlock) void k_fft_rows(const double *__restrict__ grid, int mg,
-                                                     int ng, int rp, FftPlan pq,
+// Grid value (i, j) of a frame: SRC 0 reads the FP64 grid [mg][ng]; SRC 1
+// forms the 2x2 box mean of uint16 pixels [m][n] (a quarter of the integer
+// sum: exact, the value the grid kernels write); SRC 2 takes the uint16 pixel.
+template <int SRC>
+__device__ __forceinline__ double grid_at(const void *src, int n, int ng, int i, int j)
+{
+    if (SRC == 0) return ((const double *)src)[(size_t)i * ng + j];
+    const uint16_t *a = (const uint16_t *)src;
+    if (SRC == 1) {
+        const uint16_t *p = a + (size_t)(2 * i) * n + 2 * j;
+        return 0.25 * (double)((int)p[0] + (int)p[1] + (int)p[n] + (int)p[n + 1]);
+    }
+    return (double)a[(size_t)i * n + j];
+}
+
+// Pass 1: rows.  Block (group of rp row pairs, frame).  src: the frame's grid
+// (SRC 0: mg x ng FP64) or its pixels (SRC 1, 2: m x n uint16).  s1:
+// [frame][qh][mg] complex.
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ src, int m, int n,
+                                                     int mg, int ng, int rp, FftPlan pq,
                                                      const double2 *__restrict__ twq,
                                                      double2 *__restrict__ s1)
 {
@@ -209,14 +226,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const double *__restrict__ 
     const int Q = pq.n, qh = Q / 2 + 1;
     const int npairs = (mg + 1) / 2;
     const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
-    const double *a = grid + (size_t)blockIdx.y * mg * ng;
+    const void *a = SRC == 0
+                        ? (const void *)((const double *)src + (size_t)blockIdx.y * mg * ng)
+                        : (const void *)((const uint16_t *)src + (size_t)blockIdx.y * m * n);
     double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
     for (int pr = 0; pr < np; ++pr) {
         const int r = 2 * (pair0 + pr);
-        const double *x = a + (size_t)r * ng;
-        const double *y = r + 1 < mg ? x + ng : nullptr;
+        const bool two = r + 1 < mg;
         for (int j = threadIdx.x; j < Q; j += kBlock)
-            bufa[pr * Q + j] = j < ng ? double2{x[j], y ? y[j] : 0.0} : double2{0.0, 0.0};
+            bufa[pr * Q + j] = j < ng ? double2{grid_at<SRC>(a, n, ng, r, j),
+                                                two ? grid_at<SRC>(a, n, ng, r + 1, j) : 0.0}
+                                      : double2{0.0, 0.0};
     }
     __syncthreads();
     const double2 *z = fft_lds<false>(bufa, bufb, np, pq, twq);
@@ -434,8 +454,27 @@ hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTm
     const int rp = rows_per_block(ft.pq.n);
     const int npairs = (g.mg + 1) / 2;
     const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
-    k_fft_rows<<<dim3((npairs + rp - 1) / rp, C), kBlock, lds, st>>>(grid, g.mg, g.ng, rp, ft.pq,
-                                                                    ft.twq, s1);
+    k_fft_rows<0><<<dim3((npairs + rp - 1) / rp, C), kBlock, lds, st>>>(
+        grid, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_rows_u16(const uint16_t *frames, int C, const Geom &g, const FftTmpl &ft,
+                               double2 *s1, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.dtype != MOCO_U16 || g.ds > 1) return hipErrorInvalidValue;
+    const int rp = rows_per_block(ft.pq.n);
+    const int npairs = (g.mg + 1) / 2;
+    const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
+    const dim3 grid((npairs + rp - 1) / rp, C);
+    if (g.ds)
+        k_fft_rows<1><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq,
+                                                 s1);
+    else
+        k_fft_rows<2><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq,
+                                                 s1);
     return hipGetLastError();
 }
 

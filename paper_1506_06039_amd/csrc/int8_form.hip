@@ -130,8 +130,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                                                      long long *__restrict__ atab,
                                                      long long *__restrict__ edge,
                                                      double *__restrict__ grid,
-                                                     double *__restrict__ atab_d)
+                                                     double *__restrict__ atab_d,
+                                                     const int32_t *__restrict__ only)
 {
+    // GRID with `only`: frames whose only[f] is 0 are skipped (the whole block)
+    if (GRID && only && !only[blockIdx.x]) return;
     // dynamic LDS: colE[npad] | rowbuf[NW][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
     extern __shared__ long long lds_prep[];
     const int we1 = w > 1 ? w - 1 : 1;
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                 int X = Xs[q];
                 my_xmax = max(my_xmax, X);
                 if (GRID) {
-                    if (j < ng)
+                    if (grid && j < ng)
                         grid[(size_t)frame * mg * ng + (size_t)i * ng + j] =
                             DS ? 0.25 * (double)X : (double)X;
                 } else {
@@ -909,24 +912,25 @@ size_t int8_template_bytes(const Geom &g, int nq)
 template <bool DS, int NW, bool GRID>
 void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int nc,
                     size_t lds, int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
-                    long long *edge, double *grid, double *atab_d, hipStream_t st)
+                    long long *edge, double *grid, double *atab_d, const int32_t *only,
+                    hipStream_t st)
 {
     if (nc <= 1)
         k_prep_u16<DS, 1, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d);
+                                                             grid, atab_d, only);
     else if (nc <= 2)
         k_prep_u16<DS, 2, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d);
+                                                             grid, atab_d, only);
     else if (nc <= 4)
         k_prep_u16<DS, 4, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d);
+                                                             grid, atab_d, only);
     else
         k_prep_u16<DS, 8, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d);
+                                                             grid, atab_d, only);
 }
 
 size_t prep_lds(const Geom &g, int npad, int nw)
@@ -938,7 +942,7 @@ size_t prep_lds(const Geom &g, int npad, int nw)
 template <bool DS, bool GRID>
 void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int8_t *limbs,
                  int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, double *grid,
-                 double *atab_d, hipStream_t st)
+                 double *atab_d, const int32_t *only, hipStream_t st)
 {
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
@@ -946,10 +950,10 @@ void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbi
     // frame at a fraction of the device's bandwidth)
     if (C <= 128 && prep_lds(g, npad, 16) <= 64 * 1024)
         prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, 16), limbs, nlimb,
-                                     vmax, atab, edge, grid, atab_d, st);
+                                     vmax, atab, edge, grid, atab_d, only, st);
     else
         prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, kWaves), limbs,
-                                         nlimb, vmax, atab, edge, grid, atab_d, st);
+                                         nlimb, vmax, atab, edge, grid, atab_d, only, st);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
@@ -961,10 +965,10 @@ hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npa
     if (dbits != 7 && dbits != 8) return hipErrorInvalidValue;
     if (g.ds)
         prep_launch<true, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                 nullptr, nullptr, st);
+                                 nullptr, nullptr, nullptr, st);
     else
         prep_launch<false, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                  nullptr, nullptr, st);
+                                  nullptr, nullptr, nullptr, st);
     return hipGetLastError();
 }
 
@@ -980,7 +984,8 @@ bool prep_grid_applicable(const Geom &g)
 size_t prep_grid_edge_bytes(const Geom &g) { return (size_t)4 * (g.w - 1) * g.w * sizeof(long long); }
 
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
-                            double *atab, int32_t *vmax, long long *edge, hipStream_t st)
+                            double *atab, int32_t *vmax, long long *edge, hipStream_t st,
+                            const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -988,10 +993,10 @@ hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double
     const int npad = (g.ng + kStrip - 1) / kStrip * kStrip;
     if (g.ds)
         prep_launch<true, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
-                                grid, atab, st);
+                                grid, atab, only, st);
     else
         prep_launch<false, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
-                                 grid, atab, st);
+                                 grid, atab, only, st);
     return hipGetLastError();
 }
 

@@ -149,12 +149,15 @@ hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npa
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
 // The FP64 forms' grid and energies for uint16 frames with at most one 2x2
 // level, in one pass over the raw frames (the prep kernel without digit
-// planes): grid [frame][mg][ng] FP64, atab [frame][W][W] FP64 in grid units,
-// vmax as launch_prep_u16; edge: prep_grid_edge_bytes scratch per frame.
+// planes): grid [frame][mg][ng] FP64 (may be null: energies only), atab
+// [frame][W][W] FP64 in grid units, vmax as launch_prep_u16; edge:
+// prep_grid_edge_bytes scratch per frame; only (may be null): frames whose
+// only[f] is 0 are skipped.
 bool prep_grid_applicable(const Geom &g);
 size_t prep_grid_edge_bytes(const Geom &g);
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
-                            double *atab, int32_t *vmax, long long *edge, hipStream_t st);
+                            double *atab, int32_t *vmax, long long *edge, hipStream_t st,
+                            const int32_t *only = nullptr);
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st);
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
@@ -173,6 +176,10 @@ size_t fft_s1_bytes(const Geom &g);   // per frame: [qh][mg] complex
 size_t fft_s2_bytes(const Geom &g);   // per frame: [W][qh] complex
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s1, hipStream_t st);
+// the same from uint16 frames with at most one 2x2 level, forming the grid's
+// FP64 values (box means, or the pixels) as the rows are read
+hipError_t launch_fft_rows_u16(const uint16_t *frames, int C, const Geom &g, const FftTmpl &ft,
+                               double2 *s1, hipStream_t st);
 hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
                            hipStream_t st);
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
