@@ -711,19 +711,19 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame time models of the two fast forms (seconds), from their kernels'
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
-// issues 64x64-shift tiles of three (base-128 digits with their sums) or four
-// (base-256) digit products at about 2.7e15 ops/s,
-// beside 0.35 us of prep, combine and refine per 512x512 frame; the FFT form's
-// three transform passes took 1.13 us at 288x288 and scale with P Q log2(P Q),
-// beside 0.55 us of grid, energies, combine and refine per 512x512 frame (those
+// issues 64x64-shift tiles of three digit products (base-128 digits with their
+// sums) at about 2.4e15 ops/s or four (base 256) at about 2.8e15, beside 0.35
+// us of prep, combine and refine per 512x512 frame; the FFT form's three
+// transform passes took 1.15 us at 288x288 and scale with P Q log2(P Q),
+// beside 0.28 us of energies, combine and refine per 512x512 frame (those
 // parts scale with the frame's pixels).
 double int8_model_s(const moco::Tmpl &t)
 {
     const moco::Geom &g = t.g;
     const double groups = std::ceil(g.W / 64.0);
     const double macs = groups * groups * 64.0 * 64.0 * g.mg * (double)t.i8.npad;
-    const double products = t.i8.nq == 3 ? 3.0 : 4.0;
-    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + macs * products * 2.0 / 2.7e15;
+    const double ops = macs * 2.0 * (t.i8.nq == 3 ? 3.0 : 4.0);
+    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + ops / (t.i8.nq == 3 ? 2.4e15 : 2.8e15);
 }
 
 double fft_model_s(const moco::Tmpl &t)
@@ -731,7 +731,7 @@ double fft_model_s(const moco::Tmpl &t)
     const moco::Geom &g = t.g;
     const double pq = (double)t.fft.pp.n * t.fft.pq.n;
     const double ref = 288.0 * 288.0 * std::log2(288.0 * 288.0);
-    return 0.55e-6 * ((double)g.m * g.n / 262144.0) + 1.13e-6 * pq * std::log2(pq) / ref;
+    return 0.28e-6 * ((double)g.m * g.n / 262144.0) + 1.15e-6 * pq * std::log2(pq) / ref;
 }
 
 // Forms chosen by measurement (moco_tune) or set by the caller, per search
