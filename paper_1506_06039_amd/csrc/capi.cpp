@@ -625,8 +625,10 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     const int W = g.W;
     double kf = 0.0, ke = 0.0;
     if (certify) moco::fft_error_coefs(g, tt.fft, &kf, &ke);
-    // uint16 frames with at most one 2x2 level: no FP64 grid in HBM
-    const bool raw_rows = edge && moco::prep_grid_applicable(g);
+    // at most one 2x2 level: no FP64 grid in HBM (the energies and the row
+    // transforms form its values from the pixels)
+    const bool raw_rows = g.ds <= 1;
+    const bool int_energy = edge && moco::prep_grid_applicable(g);   // uint16
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
@@ -636,18 +638,21 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         double *fmin = out->fmin ? out->fmin + f0 : nullptr;
         double *gaps = out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr;
         double *frefine = out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr;
-        if (raw_rows) {
-            // energies only: the row transforms read the pixels themselves
+        if (raw_rows && int_energy) {
+            // exact integer energies only: the row transforms read the pixels
             StageTimer tm(ctx, MOCO_STAGE_PREP, st);
             HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, nullptr, atab, pm, edge,
                                            st));
+        } else if (raw_rows) {
+            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+            HIP_TRY(moco::launch_energy_px(fr, c, g, atab, pm, st));
         } else {
             HIP_TRY(grid_and_energies(ctx, fr, g, c, inter, coarse, atab, pm, edge, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
             if (raw_rows)
-                HIP_TRY(moco::launch_fft_rows_u16((const uint16_t *)fr, c, g, tt.fft, s1, st));
+                HIP_TRY(moco::launch_fft_rows_px(fr, c, g, tt.fft, s1, st));
             else
                 HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, s1, st));
             HIP_TRY(moco::launch_fft_corr(s1, c, g, tt.fft, s2, h, st));
@@ -662,9 +667,11 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             // the frames left uncertified: direct sums, combined again (their
             // FP64 grid first, when the row transforms read the pixels)
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            if (raw_rows)
+            if (raw_rows && int_energy)
                 HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, coarse, atab, pm, edge,
                                                st, recheck));
+            else if (raw_rows)
+                HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st, recheck));
             HIP_TRY(moco::launch_corr_fp64(coarse, tt.coarse, c, g, h, st, recheck));
             HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
                                          out->shifts + 2 * (size_t)f0, gaps, frefine, st,

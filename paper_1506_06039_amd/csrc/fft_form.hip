@@ -23,6 +23,7 @@
 // inverse, once per template.
 #include <hip/hip_runtime.h>
 
+#include "grid_src.h"
 #include "moco_internal.h"
 
 namespace moco {
@@ -198,23 +199,8 @@ __device__ double2 *fft_lds(double2 *a, double2 *b, int rows, const FftPlan &pl,
     return a;
 }
 
-// Grid value (i, j) of a frame: SRC 0 reads the FP64 grid [mg][ng]; SRC 1
-// forms the 2x2 box mean of uint16 pixels [m][n] (a quarter of the integer
-// sum: exact, the value the grid kernels write); SRC 2 takes the uint16 pixel.
-template <int SRC>
-__device__ __forceinline__ double grid_at(const void *src, int n, int ng, int i, int j)
-{
-    if (SRC == 0) return ((const double *)src)[(size_t)i * ng + j];
-    const uint16_t *a = (const uint16_t *)src;
-    if (SRC == 1) {
-        const uint16_t *p = a + (size_t)(2 * i) * n + 2 * j;
-        return 0.25 * (double)((int)p[0] + (int)p[1] + (int)p[n] + (int)p[n + 1]);
-    }
-    return (double)a[(size_t)i * n + j];
-}
-
-// Pass 1: rows.  Block (group of rp row pairs, frame).  src: the frame's grid
-// (SRC 0: mg x ng FP64) or its pixels (SRC 1, 2: m x n uint16).  s1:
+// Pass 1: rows.  Block (group of rp row pairs, frame).  src: the frames' grid
+// (SRC 0: mg x ng FP64) or their pixels (m x n; see grid_at).  s1:
 // [frame][qh][mg] complex.
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ src, int m, int n,
@@ -226,9 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
     const int Q = pq.n, qh = Q / 2 + 1;
     const int npairs = (mg + 1) / 2;
     const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
-    const void *a = SRC == 0
-                        ? (const void *)((const double *)src + (size_t)blockIdx.y * mg * ng)
-                        : (const void *)((const uint16_t *)src + (size_t)blockIdx.y * m * n);
+    const void *a = grid_frame<SRC>(src, blockIdx.y, m, n, mg, ng);
     double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
     for (int pr = 0; pr < np; ++pr) {
         const int r = 2 * (pair0 + pr);
@@ -459,22 +443,25 @@ hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTm
     return hipGetLastError();
 }
 
-hipError_t launch_fft_rows_u16(const uint16_t *frames, int C, const Geom &g, const FftTmpl &ft,
-                               double2 *s1, hipStream_t st)
+hipError_t launch_fft_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
+                              double2 *s1, hipStream_t st)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
-    if (g.dtype != MOCO_U16 || g.ds > 1) return hipErrorInvalidValue;
+    if (g.ds > 1) return hipErrorInvalidValue;
     const int rp = rows_per_block(ft.pq.n);
     const int npairs = (g.mg + 1) / 2;
     const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
     const dim3 grid((npairs + rp - 1) / rp, C);
-    if (g.ds)
-        k_fft_rows<1><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq,
-                                                 s1);
+    const bool u16 = g.dtype == MOCO_U16;
+    if (u16 && g.ds)
+        k_fft_rows<1><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
+    else if (u16)
+        k_fft_rows<2><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
+    else if (g.ds)
+        k_fft_rows<3><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
     else
-        k_fft_rows<2><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq,
-                                                 s1);
+        k_fft_rows<4><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
     return hipGetLastError();
 }
 

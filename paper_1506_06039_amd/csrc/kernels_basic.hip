@@ -16,6 +16,7 @@
 // of squares stays below 2^48; f then rounds exactly once, at the division.
 #include <math.h>
 
+#include "grid_src.h"
 #include "moco_internal.h"
 
 namespace moco {
@@ -95,16 +96,19 @@ __device__ Cand block_argmin(Cand c)
 }
 
 // ---------------------------------------------------------------------------
+// only (may be null): frames whose only[f] is 0 are skipped
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(const T *__restrict__ fr, int C, int m, int n,
                                                    int mg, int ng, int ds,
-                                                   double *__restrict__ out)
+                                                   double *__restrict__ out,
+                                                   const int32_t *__restrict__ only)
 {
     const size_t plane = (size_t)mg * ng;
     const size_t total = (size_t)C * plane;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         size_t f = idx / plane;
+        if (only && !only[f]) continue;
         int r = (int)(idx - f * plane);
         int i = r / ng, j = r - (r / ng) * ng;
         const T *a = fr + f * (size_t)m * n;
@@ -217,8 +221,11 @@ __device__ void block_excl_scan(const double *v, double *out, int n, double *wsu
 // pmax (may be null): per frame,
 // ceil(pscale * largest grid value), the pixel bound the x2 step uses, or
 // INT32_MAX when pscale is 0.
-__global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ grid, int mg,
-                                                   int ng, int w, bool flip,
+// The grid comes from src as grid_at<SRC> reads it (an FP64 grid, or the
+// frames' pixels).
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src, int m, int n,
+                                                   int mg, int ng, int w, bool flip,
                                                    double *__restrict__ atab,
                                                    int32_t *__restrict__ pmax, double pscale)
 {
@@ -229,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ gr
     double *cp = RB + (E + 1), *ks = cp + (E + 1), *red = ks + (E + 2);
     __shared__ double wsum[kBlock / 64];
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const double *a = grid + (size_t)blockIdx.x * mg * ng;
+    const void *a = grid_frame<SRC>(src, blockIdx.x, m, n, mg, ng);
     double *A = atab + (size_t)blockIdx.x * W * W;
 
     // column sums (every column: the total; border columns kept) and the maximum
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ gr
         double cs = 0.0, cm = 0.0;
 #pragma unroll 8
         for (int i = 0; i < mg; ++i) {
-            const double x = a[(size_t)i * ng + j];
+            const double x = grid_at<SRC>(a, n, ng, i, j);
             cs = fma(x, x, cs);
             cm = fmax(cm, x);
         }
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ gr
         const int i = rr < E ? rr : mg - 1 - (rr - E);
         double rs = 0.0;
         for (int j = lane; j < ng; j += 64) {
-            const double x = a[(size_t)i * ng + j];
+            const double x = grid_at<SRC>(a, n, ng, i, j);
             rs = fma(x, x, rs);
         }
 #pragma unroll
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double *__restrict__ gr
             if (s > 0) {
                 const int row = bottom ? mg - s : s - 1;
                 for (int j = tid; j < E; j += kBlock) {
-                    const double x = a[(size_t)row * ng + (right ? ng - 1 - j : j)];
+                    const double x = grid_at<SRC>(a, n, ng, row, right ? ng - 1 - j : j);
                     cp[j] = fma(x, x, cp[j]);
                 }
             }
@@ -1161,12 +1168,12 @@ int grid_for(size_t total)
 }  // namespace
 
 hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g, double *coarse,
-                         hipStream_t st)
+                         hipStream_t st, const int32_t *only)
 {
     clear_stale_error();
     size_t total = (size_t)C * g.mg * g.ng;
     if (total == 0) return hipSuccess;
-    if (g.ds && g.n % 8 == 0 && ((uintptr_t)frames & 15) == 0 && ((uintptr_t)coarse & 15) == 0) {
+    if (!only && g.ds && g.n % 8 == 0 && ((uintptr_t)frames & 15) == 0 && ((uintptr_t)coarse & 15) == 0) {
         const size_t quads = total / 4;   // ng = n/2 is a multiple of 4
         if (dt == MOCO_U16)
             k_coarse_ds4<uint16_t><<<grid_for(quads), kBlock, 0, st>>>(
@@ -1178,10 +1185,10 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
     }
     if (dt == MOCO_U16)
         k_coarse<uint16_t><<<grid_for(total), kBlock, 0, st>>>(
-            (const uint16_t *)frames, C, g.m, g.n, g.mg, g.ng, g.ds, coarse);
+            (const uint16_t *)frames, C, g.m, g.n, g.mg, g.ng, g.ds, coarse, only);
     else
         k_coarse<float><<<grid_for(total), kBlock, 0, st>>>((const float *)frames, C, g.m, g.n,
-                                                            g.mg, g.ng, g.ds, coarse);
+                                                            g.mg, g.ng, g.ds, coarse, only);
     return hipGetLastError();
 }
 
@@ -1221,7 +1228,37 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
-    k_energy<<<C, kBlock, lds, st>>>(coarse, g.mg, g.ng, g.w, flip, atab, pmax, pscale);
+    k_energy<0><<<C, kBlock, lds, st>>>(coarse, g.m, g.n, g.mg, g.ng, g.w, flip, atab, pmax,
+                                        pscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
+                            int32_t *pmax, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.ds > 1) return hipErrorInvalidValue;
+    double pscale = 0.0;
+    const bool u16 = g.dtype == MOCO_U16;
+    if (u16) {
+        const int b = 1 << g.ds;
+        if (g.m % b == 0 && g.n % b == 0) pscale = (double)b * b;
+    }
+    const int E = g.w - 1;
+    const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
+    if (u16 && g.ds)
+        k_energy<1><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
+                                            pscale);
+    else if (u16)
+        k_energy<2><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
+                                            pscale);
+    else if (g.ds)
+        k_energy<3><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
+                                            pscale);
+    else
+        k_energy<4><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
+                                            pscale);
     return hipGetLastError();
 }
 

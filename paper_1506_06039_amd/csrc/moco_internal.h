@@ -93,12 +93,17 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 
 // ---- launchers (kernels_basic.hip) -------------------------------------
 // All return hipSuccess or the launch error; they only enqueue.
+// only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g, double *coarse,
-                         hipStream_t st);
+                         hipStream_t st, const int32_t *only = nullptr);
 // atab[frame][W][W]: the frame's energies over D at (s,t) ([-s][-t] when flip);
 // pmax[frame] (may be null): a pixel bound for the x2 step (uint16), else INT32_MAX
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
                          int32_t *pmax, hipStream_t st);
+// the same (not flipped) from the frames' pixels, forming the grid values as
+// they are read (at most one 2x2 level): the values launch_coarse would write
+hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
+                            int32_t *pmax, hipStream_t st);
 // only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st, const int32_t *only = nullptr);
@@ -176,10 +181,10 @@ size_t fft_s1_bytes(const Geom &g);   // per frame: [qh][mg] complex
 size_t fft_s2_bytes(const Geom &g);   // per frame: [W][qh] complex
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s1, hipStream_t st);
-// the same from uint16 frames with at most one 2x2 level, forming the grid's
-// FP64 values (box means, or the pixels) as the rows are read
-hipError_t launch_fft_rows_u16(const uint16_t *frames, int C, const Geom &g, const FftTmpl &ft,
-                               double2 *s1, hipStream_t st);
+// the same from the frames' pixels (at most one 2x2 level), forming the
+// grid's FP64 values (box means, or the pixels) as the rows are read
+hipError_t launch_fft_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
+                              double2 *s1, hipStream_t st);
 hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
                            hipStream_t st);
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
