@@ -362,8 +362,8 @@ def measure_h2d(moco, ctx, tp, frames, out, steps: int, chunk: int = 250):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--form", default="auto", choices=["auto", "fft", "fft_cert", "fp64", "int8"])
     ap.add_argument("--frames", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=0,
