@@ -129,6 +129,36 @@ def measure_paper_shapes(moco, ctx, steps: int):
     return rows
 
 
+def measure_float_stack(moco, ctx, steps: int):
+    """The float32 workload: 10000 synthetic 256x256 low-SNR frames, w = 64, no
+    downsampling, template given by the scene, aligned by AUTO (warm-up run,
+    then `steps` timed runs)."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    sc = synth.lowsnr256_f32()
+    T = 10000
+    frames = torch.from_numpy(sc.frames(0, T)).to(dev)
+    tp = moco.Template(ctx, torch.from_numpy(sc.template).to(dev), 64, False)
+    res = moco.moco_align(ctx, frames, tp)
+    torch.cuda.synchronize(dev)
+    t = time.perf_counter()
+    for _ in range(steps):
+        moco.moco_align(ctx, frames, tp, out=res)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t) / steps
+    row = {"workload": "lowsnr256_f32_w64", "frames": T, "m": 256, "n": 256, "w": 64,
+           "downsample": False, "form": moco.resolved_form(ctx, tp, "auto"),
+           "recomputed_frames": int(res.recomputed.sum().item()),
+           "ms_per_stack": round(1000 * dt, 3), "frames_per_s": round(T / dt, 1)}
+    print("[bench] float32 stack 10000 x 256x256 w=64: %.2f ms" % (1000 * dt), file=sys.stderr,
+          flush=True)
+    tp.close()
+    del frames, res
+    torch.cuda.empty_cache()
+    return row
+
+
 def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz: float = 30.0):
     """Single-frame serving of the same workload: nsrc sources, each with its own
     resident template (the first frame of its slice of the stack).  Closed loop:
@@ -381,6 +411,8 @@ def main():
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the sustained MFMA and copy measurements")
+    ap.add_argument("--float-steps", type=int, default=3,
+                    help="timed runs of the 10000 x 256x256 float32 stack, w = 64 (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed runs of the 64-stack mixed batch, batched and per stack (0: skip)")
     ap.add_argument("--h2d-steps", type=int, default=3,
@@ -592,6 +624,8 @@ def main():
         if args.serve_seconds > 0 else None
     paper_shapes = measure_paper_shapes(moco, ctx, args.paper_steps) \
         if args.paper_steps > 0 else None
+    float_stack = measure_float_stack(moco, ctx, args.float_steps) \
+        if args.float_steps > 0 else None
     h2d = measure_h2d(moco, ctx, tp, frames, out, args.h2d_steps) if args.h2d_steps > 0 else None
     batch = measure_batch(moco, ctx, args.batch_steps) if args.batch_steps > 0 else None
 
@@ -629,6 +663,7 @@ def main():
         "apply": apply_res,
         "serving": serving,
         "paper_shapes": paper_shapes,
+        "float_stack": float_stack,
         "h2d": h2d,
         "batch": batch,
         "latency_us": ({"p50": round(float(np.percentile(lat_us, 50)), 1),
