@@ -217,6 +217,33 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
     for (int pr = 0; pr < np; ++pr) {
         const int r = 2 * (pair0 + pr);
         const bool two = r + 1 < mg;
+        if (SRC == 1 && (n & 3) == 0) {
+            // uint16 box means, two grid columns per thread: one 8-byte load per
+            // pixel row (n a multiple of 4 keeps it aligned and ng even)
+            const uint16_t *px = (const uint16_t *)a;
+            for (int j = 2 * threadIdx.x; j < Q; j += 2 * kBlock) {
+                double2 v0{0.0, 0.0}, v1{0.0, 0.0};
+                if (j < ng) {
+                    int s[2][2];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        s[k][0] = s[k][1] = 0;
+                        if (k == 1 && !two) break;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const uint2 q = *(const uint2 *)(px + (size_t)(2 * (r + k) + h) * n + 2 * j);
+                            s[k][0] += (int)(q.x & 0xffffu) + (int)(q.x >> 16);
+                            s[k][1] += (int)(q.y & 0xffffu) + (int)(q.y >> 16);
+                        }
+                    }
+                    v0 = double2{0.25 * (double)s[0][0], 0.25 * (double)s[1][0]};
+                    v1 = double2{0.25 * (double)s[0][1], 0.25 * (double)s[1][1]};
+                }
+                bufa[pr * Q + j] = v0;
+                if (j + 1 < Q) bufa[pr * Q + j + 1] = v1;
+            }
+            continue;
+        }
         for (int j = threadIdx.x; j < Q; j += kBlock)
             bufa[pr * Q + j] = j < ng ? double2{grid_at<SRC>(a, n, ng, r, j),
                                                 two ? grid_at<SRC>(a, n, ng, r + 1, j) : 0.0}
