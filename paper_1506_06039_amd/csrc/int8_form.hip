@@ -86,6 +86,8 @@ __device__ inline int grid_value(const uint16_t *a, int n, int i, int j)
     return (int)a[(size_t)i * n + j];
 }
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 // Four consecutive grid values j0..j0+3 of grid row i (zero beyond ng).  With
 // `vec`, the raw rows are read as 16-byte (box sums) or 8-byte vectors.
 template <bool DS>
@@ -94,8 +96,10 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 {
     if (vec && j0 + 3 < ng) {
         if (DS) {
-            const uint4 r0 = *(const uint4 *)(a + (size_t)(2 * i) * n + 2 * j0);
-            const uint4 r1 = *(const uint4 *)(a + (size_t)(2 * i + 1) * n + 2 * j0);
+            // streamed once: non-temporal loads keep the frames out of the caches
+            const u32x4 r0 = __builtin_nontemporal_load((const u32x4 *)(a + (size_t)(2 * i) * n + 2 * j0));
+            const u32x4 r1 =
+                __builtin_nontemporal_load((const u32x4 *)(a + (size_t)(2 * i + 1) * n + 2 * j0));
             const unsigned u0[4] = {r0.x, r0.y, r0.z, r0.w}, u1[4] = {r1.x, r1.y, r1.z, r1.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q)
