@@ -485,10 +485,12 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         unsigned la = (unsigned)(uintptr_t)(__attribute__((address_space(3))) void *)(
             my_ring + (size_t)slot * SLOT);
         asm volatile("" : "+v"(la));
+        // cache policy 2: non-temporal (the frame rows are read once per strip),
+        // which leaves L2 to the template rows every block reads
         __builtin_amdgcn_global_load_lds(
             (const void *)(have ? fl + (size_t)p * plane + (size_t)r * npad + ks + (lane % 32) * 4
                                 : zsrc + (lane % 32) * 4),
-            (__attribute__((address_space(3))) void *)(uintptr_t)la, 4, 0, 0);
+            (__attribute__((address_space(3))) void *)(uintptr_t)la, 4, 0, 2);
     };
     // template row ti into dst, global -> LDS: wave v moves bytes [v Qw, (v+1) Qw)
     // of the row (Qw = rowbytes/4) in exactly NDMA transfers of 1 KB with every
