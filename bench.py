@@ -86,6 +86,81 @@ def load_traffic(kernel: str, source: str, frames_per_launch: float):
     return per_frame * frames_per_launch
 
 
+SAMPLE_PAPER = 16    # frames per paper-shaped stack checked against the oracle
+SAMPLE_FLOAT = 64    # frames of the float32 stack checked against the oracle
+GAP_REL = 1e-4       # a frame's shift is compared when its oracle gaps exceed this x f
+F_RTOL = 1e-5        # the stated bound on the relative error of f
+
+
+def result_rows(res, idx) -> dict:
+    """The outputs of frames `idx` of a device Result, as numpy arrays."""
+    import torch
+    sel = torch.from_numpy(np.asarray(idx)).to(res.shifts.device)
+    return {k: getattr(res, k)[sel].cpu().numpy()
+            for k in ("shifts", "coarse", "fmin", "frefine", "gaps")}
+
+
+def compare_with_oracle(got: dict, orc, ds: bool) -> dict:
+    """Shift agreement and f error of GPU outputs against the oracle's on the
+    same frames: shifts compared on frames whose oracle gaps (coarse, and the
+    nine when downsampling) exceed GAP_REL x f; f where both picked the same
+    coarse shift; kappa = (A+B)/(Area f) at the oracle's argmin (how much the
+    energy split cancels there)."""
+    clear = orc.gap_c > GAP_REL * np.abs(orc.fmin)
+    clear |= (orc.fmin == 0) & (orc.gap_c > 0)
+    if ds:
+        fr = np.nanmin(orc.frefine, axis=1)
+        clear &= (orc.gap_r > GAP_REL * np.abs(fr)) | ((fr == 0) & (orc.gap_r > 0))
+    same_shift = np.all(got["shifts"] == orc.shifts, axis=1)
+    same_coarse = np.all(got["coarse"] == orc.coarse, axis=1)
+    nz = same_coarse & (orc.fmin != 0)
+    rel = np.abs(got["fmin"][nz] - orc.fmin[nz]) / np.abs(orc.fmin[nz])
+    out = {"frames": int(orc.fmin.size), "clear": int(clear.sum()),
+           "shifts_equal_clear": int((same_shift & clear).sum()),
+           "shifts_equal_all": int(same_shift.sum()),
+           "fmin_rel_err_max": float(rel.max()) if rel.size else 0.0,
+           "fmin_rel_err_median": float(np.median(rel)) if rel.size else 0.0,
+           "f_bit_exact": bool(np.array_equal(got["fmin"][same_coarse], orc.fmin[same_coarse]))}
+    if ds:
+        ro, rg = orc.frefine[same_coarse], got["frefine"][same_coarse]
+        okr = np.isfinite(ro) & (ro != 0)
+        rr = np.abs(rg[okr] - ro[okr]) / np.abs(ro[okr])
+        out["frefine_rel_err_max"] = float(rr.max()) if rr.size else 0.0
+        out["f_bit_exact"] = out["f_bit_exact"] and bool(np.array_equal(rg, ro, equal_nan=True))
+    out["parity_ok"] = bool(out["shifts_equal_clear"] == out["clear"] and
+                            out["fmin_rel_err_max"] <= F_RTOL)
+    return out
+
+
+def kappa_quantiles(orc) -> dict:
+    k = orc.kappa[np.isfinite(orc.kappa)]
+    if not k.size:
+        return {}
+    return {"p50": round(float(np.percentile(k, 50)), 2),
+            "p90": round(float(np.percentile(k, 90)), 2),
+            "max": round(float(k.max()), 2)}
+
+
+def forms_against_oracle(moco, ctx, frames_np, tmpl_np, w, ds, forms, orc) -> dict:
+    """Each applicable form run on the oracle's frames (frames are independent,
+    so these are the results the form gives them inside any stack), compared."""
+    import torch
+    dev = torch.device("cuda", 0)
+    fr = torch.from_numpy(np.ascontiguousarray(frames_np)).to(dev)
+    tp = moco.Template(ctx, torch.from_numpy(np.ascontiguousarray(tmpl_np)).to(dev), w, ds)
+    rows = {}
+    for fm in forms:
+        try:
+            moco.resolved_form(ctx, tp, fm)
+        except moco.MocoError:
+            continue
+        r = moco.moco_align(ctx, fr, tp, form=fm)
+        torch.cuda.synchronize(dev)
+        rows[fm] = compare_with_oracle(result_rows(r, np.arange(fr.shape[0])), orc, ds)
+    tp.close()
+    return rows
+
+
 # The paper's timing table (sec. 3): stack shapes and moco's seconds on its
 # (unnamed) hardware, with its rules: downsample once iff a side exceeds 256,
 # window min(m', n')/3 on the searched grid.
@@ -100,7 +175,7 @@ def measure_paper_shapes(moco, ctx, steps: int):
     import torch
     import synth
     dev = torch.device("cuda", 0)
-    rows = []
+    rows, samples = [], []
     for k, (m, n, T, paper_s) in enumerate(PAPER_SHAPES):
         ds = m > 256 or n > 256
         mg, ng = (m // 2, n // 2) if ds else (m, n)
@@ -116,6 +191,10 @@ def measure_paper_shapes(moco, ctx, steps: int):
             moco.moco_align(ctx, frames, tp, out=res)
         torch.cuda.synchronize(dev)
         dt = (time.perf_counter() - t) / steps
+        idx = np.linspace(1, T - 1, SAMPLE_PAPER).astype(int)
+        samples.append({"key": "%dx%dx%d" % (m, n, T), "frames": fr_np[idx].copy(),
+                        "template": fr_np[0].copy(), "w": w, "ds": ds,
+                        "gpu": result_rows(res, idx)})
         rows.append({"shape": "%dx%dx%d" % (m, n, T), "w": w, "downsample": ds,
                      "form": moco.resolved_form(ctx, tp, "auto"),
                      "recomputed_frames": int(res.recomputed.sum().item()),
@@ -126,7 +205,7 @@ def measure_paper_shapes(moco, ctx, steps: int):
         tp.close()
         del frames, res, fr_np
         torch.cuda.empty_cache()
-    return rows
+    return rows, samples
 
 
 def measure_float_stack(moco, ctx, steps: int):
@@ -151,12 +230,17 @@ def measure_float_stack(moco, ctx, steps: int):
            "downsample": False, "form": moco.resolved_form(ctx, tp, "auto"),
            "recomputed_frames": int(res.recomputed.sum().item()),
            "ms_per_stack": round(1000 * dt, 3), "frames_per_s": round(T / dt, 1)}
+    # frames spread over the stack, kept for the oracle after all GPU timing
+    idx = np.linspace(0, T - 1, SAMPLE_FLOAT).astype(int)
+    sample = {"key": "lowsnr256_f32_w64", "idx": idx, "template": sc.template, "w": 64,
+              "ds": False, "gpu": result_rows(res, idx),
+              "frames": frames[torch.from_numpy(idx).to(dev)].cpu().numpy()}
     print("[bench] float32 stack 10000 x 256x256 w=64: %.2f ms" % (1000 * dt), file=sys.stderr,
           flush=True)
     tp.close()
     del frames, res
     torch.cuda.empty_cache()
-    return row
+    return row, sample
 
 
 def measure_serving(moco, ctx, frames_np, seconds: float, nsrc: int = 8, rate_hz: float = 30.0):
@@ -622,10 +706,10 @@ def main():
 
     serving = measure_serving(moco, ctx, frames_np, args.serve_seconds) \
         if args.serve_seconds > 0 else None
-    paper_shapes = measure_paper_shapes(moco, ctx, args.paper_steps) \
-        if args.paper_steps > 0 else None
-    float_stack = measure_float_stack(moco, ctx, args.float_steps) \
-        if args.float_steps > 0 else None
+    paper_shapes, paper_samples = measure_paper_shapes(moco, ctx, args.paper_steps) \
+        if args.paper_steps > 0 else (None, [])
+    float_stack, float_sample = measure_float_stack(moco, ctx, args.float_steps) \
+        if args.float_steps > 0 else (None, None)
     h2d = measure_h2d(moco, ctx, tp, frames, out, args.h2d_steps) if args.h2d_steps > 0 else None
     batch = measure_batch(moco, ctx, args.batch_steps) if args.batch_steps > 0 else None
 
@@ -703,6 +787,38 @@ def main():
         exact_f = bool(np.array_equal(fmin[:ns], orc.fmin) and
                        np.array_equal(frefine[:ns], orc.frefine))
         result["parity"] = {"frames": ns, "shifts_equal": same_shift, "f_bit_exact": exact_f}
+
+        # after every GPU timing: the oracle on samples of the other workloads,
+        # and each correlation form's f error against it, per config
+        t_chk = time.perf_counter()
+        all_forms = ["int8", "fft", "fft_cert", "fp64"]
+        precision = {}
+        precision["poisson512_u16_ds_w32"] = {
+            "frames": ns, "kappa": kappa_quantiles(orc),
+            "forms": forms_against_oracle(moco, ctx, frames_np[:ns], tmpl_np, W_WIN, DS,
+                                          all_forms, orc)}
+        sc0 = synth.blobs128_f32()
+        fr0 = sc0.frames(0, 100)
+        orc0 = oracle.align(fr0, sc0.template, 10, False)
+        precision["blobs128_f32_w10"] = {
+            "frames": 100, "kappa": kappa_quantiles(orc0),
+            "forms": forms_against_oracle(moco, ctx, fr0, sc0.template, 10, False, all_forms,
+                                          orc0)}
+        if float_sample is not None:
+            fs = float_sample
+            orc2 = oracle.align(fs["frames"], fs["template"], fs["w"], fs["ds"])
+            float_stack["parity"] = compare_with_oracle(fs["gpu"], orc2, fs["ds"])
+            float_stack["parity"]["sample"] = "%d frames spread over the stack" % len(fs["idx"])
+            precision["lowsnr256_f32_w64"] = {
+                "frames": len(fs["idx"]), "kappa": kappa_quantiles(orc2),
+                "forms": forms_against_oracle(moco, ctx, fs["frames"], fs["template"], fs["w"],
+                                              fs["ds"], all_forms, orc2)}
+        for row, smp in zip(paper_shapes or [], paper_samples):
+            orcp = oracle.align(smp["frames"], smp["template"], smp["w"], smp["ds"])
+            row["parity"] = compare_with_oracle(smp["gpu"], orcp, smp["ds"])
+            row["kappa"] = kappa_quantiles(orcp)
+        result["precision"] = precision
+        result["oracle_checks_seconds"] = round(time.perf_counter() - t_chk, 1)
 
     print(json.dumps(result), flush=True)
     tp.close()

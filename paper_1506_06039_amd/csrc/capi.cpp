@@ -313,6 +313,11 @@ void free_tmpl(moco::Tmpl &t)
     t.i8.atab = nullptr;
 }
 
+// Most frames one launch sequence processes (a chunk); larger stacks run in
+// chunks of at most this many frames, so scratch beyond it is never used.
+constexpr int kChunkInt8 = 8192;
+constexpr int kChunkOther = 4096;   // FFT and FP64 forms
+
 // Per-frame scratch of the int8 form.
 struct Int8Layout {
     size_t limbs, nlimb, atab, edge, h, cst, part, total_per_frame;
@@ -452,7 +457,7 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     const int npad = tt.i8.npad;
     Int8Layout L = int8_layout(g, npad);
     int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
-    C = std::min(C, 8192);
+    C = std::min(C, kChunkInt8);
     if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
     char *base = sbase;
     int8_t *limbs = (int8_t *)base;
@@ -505,7 +510,7 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 {
     ExactLayout L = exact_layout(g);
     int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
-    C = std::min(C, 4096);
+    C = std::min(C, kChunkOther);
     if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
     char *base = sbase;
     const moco_dtype dtype = g.dtype;
@@ -691,6 +696,8 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     }
     return MOCO_OK;
 }
+
+int chunk_cap(moco_form form) { return form == MOCO_FORM_INT8_MFMA ? kChunkInt8 : kChunkOther; }
 
 size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &tt)
 {
@@ -1158,7 +1165,9 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     if (pf > ctx->budget)
         return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf,
                     ctx->budget);
-    const size_t need = pf * std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / pf));
+    const size_t frames = std::min<size_t>(std::min<size_t>((size_t)T, (size_t)chunk_cap(form)),
+                                           std::max<size_t>(1, ctx->budget / pf));
+    const size_t need = pf * frames;
     rc = ensure_scratch(ctx, need, st);
     if (rc) return rc;
     return run_stack(ctx, d_frames, tt, T, g, form, out, st, (char *)ctx->scratch, need);
@@ -1182,7 +1191,9 @@ int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
     if (pf > ctx->budget)
         return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf,
                     ctx->budget);
-    const size_t need = pf * std::min<size_t>((size_t)T, std::max<size_t>(1, ctx->budget / pf));
+    const size_t frames = std::min<size_t>(std::min<size_t>((size_t)T, (size_t)chunk_cap(form)),
+                                           std::max<size_t>(1, ctx->budget / pf));
+    const size_t need = pf * frames;
     moco_graph *gr = new (std::nothrow) moco_graph;
     if (!gr) return fail(MOCO_ENOMEM, "moco_graph_create: out of host memory");
     gr->device = ctx->device;
@@ -1253,14 +1264,19 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
     std::vector<moco_form> forms(nstacks);
     std::vector<size_t> pf(nstacks);
     std::vector<double> cost(nstacks);
-    size_t pf_max = 0;
+    size_t pf_max = 0, slice_need = 0;
     for (int k = 0; k < nstacks; ++k) {
         const moco_stack &sk = stacks[k];
         int rc = check_stack(ctx, sk.d_frames, sk.tmpl, sk.T, sk.m, sk.n, sk.w, sk.downsample,
                              sk.dtype, form, &sk.out, &geo[k], &forms[k]);
         if (rc) return fail(rc, "stack %d: %s", k, moco_last_error());
         pf[k] = per_frame_scratch(geo[k], forms[k], sk.tmpl->t);
-        if (sk.T > 0) pf_max = std::max(pf_max, pf[k]);
+        if (sk.T > 0) {
+            pf_max = std::max(pf_max, pf[k]);
+            // a lane slice never needs more than one chunk of its largest stack
+            slice_need = std::max(
+                slice_need, pf[k] * (size_t)std::min(sk.T, chunk_cap(forms[k])));
+        }
         const moco::Geom &g = geo[k];
         cost[k] = (double)sk.T * ((double)g.W * g.W * g.mg * g.ng + (double)g.m * g.n);
     }
@@ -1274,7 +1290,10 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
     int nl = lanes ? std::min(lanes, 8) : 4;
     nl = (int)std::min<size_t>((size_t)nl, ctx->budget / pf_max);
     nl = std::max(1, std::min(nl, nstacks));
-    const size_t slice = ctx->budget / nl / 256 * 256;
+    // lane slices start 256-byte aligned; each must hold one frame of any stack
+    size_t lane_cap = ctx->budget / nl / 256 * 256;
+    while (nl > 1 && lane_cap < pf_max) lane_cap = ctx->budget / --nl / 256 * 256;
+    const size_t slice = std::min(lane_cap, align_up(slice_need, 256));
     int rc = ensure_scratch(ctx, slice * nl, st);
     if (rc) return rc;
     while ((int)ctx->lanes.size() < nl) {
@@ -1337,11 +1356,17 @@ struct SrvSource {
     size_t pf = 0;
 };
 
+// A request carries what the worker needs of its source, copied under the
+// server's lock at submission: the worker never reads the source table.
 struct SrvRequest {
     uint64_t tag;
     int source;
     int slot;
     Clock::time_point t0;
+    const moco::Tmpl *tmpl;
+    moco::Geom g;
+    moco_form form;
+    size_t fbytes;
 };
 
 // Device and pinned buffers of one batch in flight.
@@ -1376,6 +1401,7 @@ struct moco_server {
     std::deque<SrvRequest> pending;
     std::deque<moco_result> completed;
     int inflight = 0;
+    int staging = 0;  // submits holding a slot while they copy into it (lock released)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
@@ -1443,23 +1469,23 @@ int server_enqueue(moco_server *srv, SrvLane &L)
     std::vector<size_t> off(nb);
     size_t o = 0;
     for (size_t k = 0; k < nb; ++k) {
-        const SrvSource &sc = srv->sources.at(L.reqs[k].source);
+        const SrvRequest &q = L.reqs[k];
         off[k] = o;
-        HIP_TRY(hipMemcpyAsync(L.d_frames + o, srv->h_slots + (size_t)L.reqs[k].slot * srv->slot_bytes,
-                               sc.fbytes, hipMemcpyHostToDevice, L.stream));
-        o += sc.fbytes;
+        HIP_TRY(hipMemcpyAsync(L.d_frames + o, srv->h_slots + (size_t)q.slot * srv->slot_bytes,
+                               q.fbytes, hipMemcpyHostToDevice, L.stream));
+        o += q.fbytes;
     }
     for (size_t a = 0; a < nb;) {
         size_t b = a;
         while (b < nb && L.reqs[b].source == L.reqs[a].source) ++b;
-        const SrvSource &sc = srv->sources.at(L.reqs[a].source);
+        const SrvRequest &q = L.reqs[a];
         moco_outputs out{};
         out.shifts = L.d_shifts + 2 * a;
         out.coarse = L.d_coarse + 2 * a;
         out.fmin = L.d_fmin + a;
         out.frefine = L.d_frefine + 9 * a;
         out.gaps = L.d_gaps + 2 * a;
-        int rc = run_stack(srv->ctx, L.d_frames + off[a], sc.tmpl->t, (int)(b - a), sc.g, sc.form,
+        int rc = run_stack(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), q.g, q.form,
                            &out, L.stream, L.d_scratch, L.scratch_bytes);
         if (rc) return rc;
         a = b;
@@ -1625,7 +1651,10 @@ int moco_server_add_source(moco_server *srv, int source, const void *h_template,
                       (tp->t.fft_ok ? (size_t)tp->t.fft.qh * tp->t.fft.pp.n * sizeof(double2) : 0);
     // larger frames or scratch than the buffers hold: resize once nothing is in flight
     if (fbytes > srv->slot_bytes || sc.pf > srv->pf_max) {
-        srv->cv_done.wait(lk, [&] { return srv->pending.empty() && srv->inflight == 0; });
+        // nothing may hold a slot or a lane while the buffers are replaced
+        srv->cv_done.wait(lk, [&] {
+            return srv->pending.empty() && srv->inflight == 0 && srv->staging == 0;
+        });
         srv->tmpl_bytes += tb;
         rc = server_size_buffers(srv, std::max(fbytes, srv->slot_bytes),
                                  std::max(sc.pf, srv->pf_max));
@@ -1653,14 +1682,25 @@ int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64
     if (srv->free_slots.empty()) return MOCO_EBUSY;
     const int slot = srv->free_slots.back();
     srv->free_slots.pop_back();
-    SrvRequest q{tag, source, slot, Clock::now()};
-    const size_t fbytes = it->second.fbytes;
+    const SrvSource &sc = it->second;
+    SrvRequest q{tag, source, slot, Clock::now(), &sc.tmpl->t, sc.g, sc.form, sc.fbytes};
+    // the copy runs unlocked; `staging` keeps the slot buffers from being
+    // replaced (a source that needs larger slots) or freed (destroy) meanwhile
+    srv->staging += 1;
+    char *dst = srv->h_slots + (size_t)slot * srv->slot_bytes;
     lk.unlock();
-    std::memcpy(srv->h_slots + (size_t)slot * srv->slot_bytes, h_frame, fbytes);
+    std::memcpy(dst, h_frame, q.fbytes);
     lk.lock();
+    srv->staging -= 1;
+    if (srv->stop) {
+        srv->free_slots.push_back(slot);
+        srv->cv_done.notify_all();
+        return fail(MOCO_ECANCELED, "server is shutting down");
+    }
     srv->pending.push_back(q);
     srv->inflight += 1;
     srv->cv_work.notify_one();
+    srv->cv_done.notify_all();
     return MOCO_OK;
 }
 
@@ -1694,8 +1734,10 @@ int moco_server_destroy(moco_server *srv)
     if (!srv) return 0;
     int cancelled = 0;
     {
-        std::lock_guard<std::mutex> lk(srv->mu);
+        std::unique_lock<std::mutex> lk(srv->mu);
         srv->stop = true;
+        // submits still copying into their slots finish (and cancel themselves)
+        srv->cv_done.wait(lk, [&] { return srv->staging == 0; });
         cancelled = (int)srv->pending.size();
         for (auto &q : srv->pending) srv->free_slots.push_back(q.slot);
         srv->inflight -= cancelled;

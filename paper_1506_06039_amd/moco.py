@@ -226,7 +226,7 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
             gaps=torch.empty((T, 2), dtype=torch.float64, device=dev),
             fsurf=torch.empty((T, W, W), dtype=torch.float64, device=dev) if surface else None,
             recomputed=torch.empty(T, dtype=torch.int32, device=dev))
-    o = _outputs(out)
+    o = _outputs(out, T, W, dev)
     _check(_lib.moco_align(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), FORMS[form],
                            ctypes.byref(o), _stream_handle(dev)))
@@ -245,7 +245,7 @@ class Graph:
         self.frames, self.tmpl, self.ctx = frames, tmpl, ctx
         self.out = out if out is not None else \
             _new_result(T, 2 * tmpl.w - 1, frames.device, surface)
-        o = _outputs(self.out)
+        o = _outputs(self.out, T, 2 * tmpl.w - 1, frames.device)
         h = _vp()
         _check(_lib.moco_graph_create(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
                                       int(tmpl.downsample), _dtype_code(frames), FORMS[form],
@@ -282,10 +282,19 @@ def moco_apply(ctx: Context, frames: torch.Tensor, shifts: torch.Tensor, frames_
     if shifts.dtype != torch.int32 or tuple(shifts.shape) != (T, 2) or not shifts.is_contiguous():
         raise ValueError("shifts must be a contiguous (T, 2) int32 tensor")
     dev = frames.device
+    if shifts.device != dev:
+        raise ValueError("shifts are on %s, frames on %s" % (shifts.device, dev))
     if frames_out and out is None:
         out = torch.empty_like(frames)
     if mean and mean_out is None:
         mean_out = torch.empty((m, n), dtype=torch.float64, device=dev)
+    if frames_out:
+        _check_tensor("out", out, (T, m, n), frames.dtype, dev)
+        nb = frames.numel() * frames.element_size()
+        if out.data_ptr() < frames.data_ptr() + nb and frames.data_ptr() < out.data_ptr() + nb:
+            raise ValueError("out must not overlap the frames")
+    if mean:
+        _check_tensor("mean_out", mean_out, (m, n), torch.float64, dev)
     _check(_lib.moco_apply(ctx.handle, frames.data_ptr(), shifts.data_ptr(), T, m, n,
                            _dtype_code(frames), out.data_ptr() if frames_out else None,
                            mean_out.data_ptr() if mean else None, _stream_handle(dev)))
@@ -310,7 +319,46 @@ def _new_result(T: int, W: int, dev, surface: bool) -> Result:
         recomputed=torch.empty(T, dtype=torch.int32, device=dev))
 
 
-def _outputs(r: Result) -> "_Outputs":
+_OUT_SPEC = (  # field, trailing shape (after T) as a function of W, dtype, required
+    ("shifts", lambda W: (2,), torch.int32, True),
+    ("fmin", lambda W: (), torch.float64, True),
+    ("frefine", lambda W: (9,), torch.float64, True),
+    ("coarse", lambda W: (2,), torch.int32, True),
+    ("gaps", lambda W: (2,), torch.float64, True),
+    ("fsurf", lambda W: (W, W), torch.float64, False),
+    ("recomputed", lambda W: (), torch.int32, False),
+)
+
+
+def _check_tensor(name: str, t: torch.Tensor, shape, dtype, dev):
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch.Tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if t.dtype != dtype:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if t.device != dev:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, dev))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _validate_result(r: Result, T: int, W: int, dev):
+    """Every output the kernels write must have exactly the shape, dtype and
+    device they assume: a wrong one would be written past its end."""
+    if not isinstance(r, Result):
+        raise ValueError("out must be a Result")
+    for name, shp, dt, required in _OUT_SPEC:
+        t = getattr(r, name)
+        if t is None:
+            if required:
+                raise ValueError("out.%s is required" % name)
+            continue
+        _check_tensor("out." + name, t, (T,) + shp(W), dt, dev)
+
+
+def _outputs(r: Result, T: int, W: int, dev) -> "_Outputs":
+    _validate_result(r, T, W, dev)
     return _Outputs(r.shifts.data_ptr(), r.fmin.data_ptr(),
                     r.fsurf.data_ptr() if r.fsurf is not None else None,
                     r.frefine.data_ptr(), r.coarse.data_ptr(), r.gaps.data_ptr(),
@@ -334,7 +382,7 @@ def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
         res = it[2] if len(it) > 2 and it[2] is not None else \
             _new_result(T, 2 * tmpl.w - 1, dev, surface)
         results.append(res)
-        o = _outputs(res)
+        o = _outputs(res, T, 2 * tmpl.w - 1, dev)
         stacks[k] = _Stack(frames.data_ptr(), tmpl.handle.value, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), o)
     stream = _stream_handle(dev if dev is not None else ctx.device)
@@ -466,11 +514,17 @@ class Server:
         m, n = t.shape
         _check(_lib.moco_server_add_source(self.handle, source, t.ctypes.data, code, m, n, w,
                                            int(downsample)))
+        self._keep[source] = ((m, n), t.dtype)
 
     def submit(self, source: int, frame, tag: int) -> bool:
         """True when admitted, False on back-pressure (no free slot)."""
         import numpy as np
         f = np.ascontiguousarray(frame)
+        spec = self._keep.get(source)
+        if spec is not None and (f.shape != spec[0] or f.dtype != spec[1]):
+            # the library copies the source's frame size from this pointer
+            raise ValueError("source %d takes %s %s frames, got %s %s"
+                             % (source, spec[0], spec[1], f.shape, f.dtype))
         rc = _lib.moco_server_submit(self.handle, source, f.ctypes.data, tag)
         if rc == MOCO_EBUSY:
             return False

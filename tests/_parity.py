@@ -8,6 +8,12 @@ counted and reported, not hidden.
 f values: |f_gpu - f_oracle| <= rtol * max(|f_oracle|, 1e-9*(A+B)/Area); the
 floor only matters for noise-free tests where f_oracle is 0.  rtol is 1e-5
 for every form; the FP64 exact form on uint16 data is held to bit equality.
+
+Gaps (second best minus best f, on the searched grid and among the nine):
+bit-equal where f is held to bit equality; otherwise within the error the f
+rule allows for two values, rtol * (|f_best| + |f_second|) (+ the floor).  The
+nine-point gap is compared only where both sides took the same coarse argmin;
+both sides write +inf where there is no second value.
 """
 import numpy as np
 
@@ -55,9 +61,36 @@ def check(res, orc, ds: bool, exact: bool, rtol: float = F_RTOL, label: str = ""
             assert np.array_equal(rg, ro), "%s: frefine differs" % label
         else:
             assert np.all(np.abs(rg - ro) <= rtol * np.maximum(np.abs(ro), f_floor)), label
+    if "gaps" in res:
+        gg, go = res["gaps"], np.stack([orc.gap_c, orc.gap_r], axis=1)
+        _check_gaps(gg[:, 0], go[:, 0], orc.fmin, exact, rtol, f_floor, label + " gap_c")
+        if ds:
+            fb = np.nanmin(orc.frefine, axis=1)
+            _check_gaps(gg[same, 1], go[same, 1], fb[same], exact, rtol, f_floor,
+                        label + " gap_r")
+        else:
+            assert np.all(np.isinf(gg[:, 1])), "%s: refine gap without downsampling" % label
+        fin = np.isfinite(go[:, 0]) & (go[:, 0] > 0)
+        if fin.any():
+            stats["gap_c_max_abs_err"] = float(np.max(np.abs(gg[fin, 0] - go[fin, 0])))
     if fo.size:
         stats["fmin_max_rel_err"] = float(np.max(np.abs(fg - fo) / np.maximum(np.abs(fo), 1e-300)))
     return stats
+
+
+def _check_gaps(gg, go, fbest, exact, rtol, f_floor, label):
+    inf_o = np.isinf(go)
+    assert np.array_equal(np.isinf(gg), inf_o), "%s: +inf where the oracle has a value" % label
+    fin = ~inf_o
+    if exact:
+        assert np.array_equal(gg[fin], go[fin]), "%s: differs, max |d| %g" % (
+            label, np.max(np.abs(gg[fin] - go[fin])) if fin.any() else 0)
+        return
+    fb = np.abs(fbest[fin])
+    tol = rtol * (np.maximum(fb, f_floor) + np.maximum(fb + np.abs(go[fin]), f_floor))
+    d = np.abs(gg[fin] - go[fin])
+    assert np.all(d <= tol), "%s: max |d| %g beyond %g" % (
+        label, d.max(), tol[np.argmax(d - tol)])
 
 
 def check_surface(sg, so, A_plus_B_over_area=None, exact=False, rtol=F_RTOL, label=""):

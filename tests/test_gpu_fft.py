@@ -102,6 +102,7 @@ FFT_SHAPES = [
     (300, 17, 8, True, "f32", 3),     # grid 150x8: 160 x 15
     (60, 220, 46, False, "f32", 2),   # 108 x 270 (2*3^3*5)
     (40, 1030, 6, True, "u16", 2),    # grid 20x515: 25 x 540
+    (276, 200, 85, False, "f32", 2),  # 360 x 288 (radices 3,3,5,8 and 3,3,4,8)
 ]
 
 
@@ -166,3 +167,35 @@ def test_wide_window_paper_shape_auto_picks_fft(gpu_lib):
     ex = _run(gpu_lib, fr, sc.template, 69, True, form="int8", surface=True)
     check(ex, orc, True, exact=True, label="416x460 int8")
     check_surface(ex["fsurf"], orc.surf, exact=True, label="416x460 int8 surface")
+
+
+# The paper's own setting (sec. 3): downsample once iff a side exceeds 256 and
+# a window of a third of the searched grid's side, here w = 85 on 256x256
+# grids: transform lengths 360 x 360 (the stack shapes of its timing table).
+PAPER_W85 = [(512, 512, 3, 11), (256, 256, 3, 12)]
+
+
+@pytest.mark.parametrize("shape", PAPER_W85, ids=lambda c: "%dx%d" % c[:2])
+def test_paper_default_window_shapes(gpu_lib, shape):
+    m, n, T, seed = shape
+    w, ds = gpu_lib.default_params(m, n)
+    assert w == 85 and ds == (1 if m > 256 else 0)
+    sc = synth.PoissonScene(m, n, T + 1, seed=seed)
+    fr = sc.frames(0, T + 1)
+    tm = fr[0].copy()
+    fr = fr[1:]
+    ctx = gpu_lib.Context(0)
+    tp = gpu_lib.Template(ctx, _to_dev(tm), w, ds)
+    assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft_cert"
+    tp.close()
+    ctx.close()
+    _say("case paper shape %dx%d w=%d ds=%d" % (m, n, w, ds))
+    orc = oracle.align(fr, tm, w, ds, want_surface=True)
+    for form in ("auto", "fft"):
+        res = _run(gpu_lib, fr, tm, w, ds, form=form, surface=True)
+        st = check(res, orc, bool(ds), exact=False, label="paper %dx%d %s" % (m, n, form))
+        err = check_surface(res["fsurf"], orc.surf, label="paper %dx%d %s surface" % (m, n, form))
+        _say(form, st, "surface max rel err %.3g" % err)
+    ex = _run(gpu_lib, fr, tm, w, ds, form="int8", surface=True)
+    check(ex, orc, bool(ds), exact=True, label="paper %dx%d int8" % (m, n))
+    check_surface(ex["fsurf"], orc.surf, exact=True, label="paper %dx%d int8 surface" % (m, n))

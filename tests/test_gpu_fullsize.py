@@ -5,7 +5,7 @@ sampled frames the oracle computes one by one.
 * 2000 frames of 512x512 uint16 (2x downsample, w = 32): the int8 form; sampled
   frames bit-identical to the oracle (shifts, f, the nine refine values, gaps).
 * 10000 frames of 256x256 float32 at low SNR (w = 64): the certified FFT form;
-  shifts of sampled frames equal to the oracle's where the certificate held
+  64 sampled frames: shifts equal to the oracle's where the certificate held
   (and to the FP64 form's where it did not), f within the 1e-5 bar.
 * the 64-stack mixed batch (128x128 .. 512x796, 50-3000 frames, w from
   {8, 16, 32, 48}), each stack's first frames repeated to its length as in the
@@ -75,7 +75,8 @@ def test_full_stack_256_float32_w64_sampled(gpu_lib):
     assert gpu_lib.resolved_form(ctx, tp, "auto") == "fft_cert"
     r = gpu_lib.moco_align(ctx, torch.from_numpy(fr).cuda(), tp)
     torch.cuda.synchronize()
-    idx = np.unique(np.concatenate([np.linspace(0, T - 1, 8).astype(int), [1, 5000]]))
+    idx = np.unique(np.concatenate([np.linspace(0, T - 1, 62).astype(int), [1, 5000]]))
+    assert idx.size >= 64
     got = _host(r, idx)
     orc = oracle.align(fr[idx], sc.template, 64, False)
     st = check(got, orc, False, exact=False, label="full 10000x256^2 f32")

@@ -434,6 +434,52 @@ def test_server_results_equal_alone_and_in_the_mix(gpu_lib):
         assert r.fmin == orc.fmin[k]
 
 
+def test_server_add_source_while_another_thread_submits(gpu_lib):
+    # sources of growing frame size are added while requests of another source
+    # flow (each addition replaces the slot and lane buffers once nothing holds
+    # them); every result equals moco_align on that frame alone
+    import threading
+    ctx = gpu_lib.Context(0)
+    srv = gpu_lib.Server(ctx, max_slots=6)
+    small = synth.PoissonScene(128, 128, 48, seed=21)
+    srv.add_source(1, small.template, 8, False)
+    frames = small.frames(0, 48)
+    results, errors = {}, []
+
+    def submitter():
+        try:
+            out, _ = _serve_all(srv, [(1, frames[k], k) for k in range(48)])
+            results.update(out)
+        except Exception as e:   # surfaced by the main thread
+            errors.append(e)
+
+    _say("case server add_source while submitting")
+    th = threading.Thread(target=submitter)
+    th.start()
+    big = {}
+    for k, side in enumerate((192, 256, 384, 512)):
+        sc = synth.PoissonScene(side, side, 3, seed=40 + k)
+        big[10 + k] = (sc, 16, side > 256)
+        srv.add_source(10 + k, sc.template, 16, side > 256)
+    th.join(timeout=120)
+    assert not th.is_alive(), "submitter did not finish"
+    assert not errors, errors
+    alone = _run(gpu_lib, frames, small.template, 8, False)
+    for k in range(48):
+        r = results[k]
+        assert r.status == 0 and r.source == 1
+        assert list(r.shift) == alone["shifts"][k].tolist(), k
+        assert r.fmin == alone["fmin"][k]
+    # the added sources serve too, equal to their frames alone
+    reqs = [(sid, sc.frame(1), 1000 + sid) for sid, (sc, w, ds) in big.items()]
+    out, _ = _serve_all(srv, reqs)
+    assert srv.close() == 0
+    for sid, (sc, w, ds) in big.items():
+        one = _run(gpu_lib, sc.frame(1)[None], sc.template, w, ds)
+        r = out[1000 + sid]
+        assert list(r.shift) == one["shifts"][0].tolist() and r.fmin == one["fmin"][0]
+
+
 def test_server_rejects_bad_use_and_cancels_on_destroy(gpu_lib):
     ctx = gpu_lib.Context(0)
     srv = gpu_lib.Server(ctx, max_slots=3)

@@ -8,6 +8,7 @@ shifts, statistics of the noise, and a hand-worked fixture.
 """
 import math
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -82,6 +83,147 @@ def test_hand_worked_fixture():
     assert tuple(r.shifts[0]) == rows["argmin"]
     assert r.fmin[0] == 2.0
     assert r.gap_c[0] == rows["gap"]
+
+
+def _read_search_fixture(name):
+    rec = {"coarse": {}, "nine": {}}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            k, *v = line.split()
+            if k in ("m", "n", "w", "ds"):
+                rec[k] = int(v[0])
+            elif k in ("a", "b"):
+                rec[k] = [int(x) for x in v]
+            elif k in ("coarse", "nine"):
+                rec[k][(int(v[0]), int(v[1]))] = Fraction(int(v[2]), int(v[3]))
+            elif k in ("coarse_argmin", "shift"):
+                rec[k] = (int(v[0]), int(v[1]))
+            else:   # gap_c, gap_r, kappa: numerator denominator
+                rec[k] = Fraction(int(v[0]), int(v[1]))
+    return rec
+
+
+def test_hand_worked_search_with_refine_fixture():
+    """Whole search on a 4x4 pair, one 2x2 level, w = 2 (sec. 2: the window on
+    the downsampled images, the argmin doubled and the nine evaluations at full
+    resolution): every coarse value, the coarse gap, kappa at the argmin, the
+    nine values, the final shift and the refine gap, each worked by hand."""
+    rec = _read_search_fixture("hand_4x4_ds1_w2.txt")
+    m, n, w, ds = rec["m"], rec["n"], rec["w"], rec["ds"]
+    a = np.array(rec["a"], np.float64).reshape(m, n)
+    b = np.array(rec["b"], np.float64).reshape(m, n)
+    W = 2 * w - 1
+    assert len(rec["coarse"]) == W * W and len(rec["nine"]) == 9
+    # the hand values agree with the literal 1-based enumeration
+    al, bl = a.astype(int).tolist(), b.astype(int).tolist()
+    for (S, T), v in rec["nine"].items():
+        assert f_exact(al, bl, S, T) == v
+    r = oracle.align(a[None], b, w, bool(ds), want_surface=True)
+    for (s, t), v in rec["coarse"].items():
+        assert r.surf[0, s + w - 1, t + w - 1] == float(v), (s, t)
+    assert tuple(r.coarse[0]) == rec["coarse_argmin"]
+    assert r.fmin[0] == float(rec["coarse"][rec["coarse_argmin"]])
+    # gaps are differences of two rounded f values (second best minus best)
+    best = min(rec["coarse"].values())
+    assert r.gap_c[0] == float(best + rec["gap_c"]) - float(best)
+    assert r.kappa[0] == float(rec["kappa"])
+    cs, ct = rec["coarse_argmin"]
+    for u in (-1, 0, 1):
+        for v in (-1, 0, 1):
+            assert r.frefine[0, (u + 1) * 3 + (v + 1)] == float(rec["nine"][(2 * cs + u, 2 * ct + v)])
+    assert tuple(r.shifts[0]) == rec["shift"]
+    fb = rec["nine"][rec["shift"]]
+    assert r.gap_r[0] == float(fb + rec["gap_r"]) - float(fb)
+    assert abs(r.gap_r[0] - float(rec["gap_r"])) < 1e-15
+
+
+def _tie_key(f, s, t):
+    # the tie order read for the argmin: f, then max(|s|,|t|), |s|+|t|, s, t
+    return (f, max(abs(s), abs(t)), abs(s) + abs(t), s, t)
+
+
+def _box_exact(x):
+    m, n = len(x) // 2, len(x[0]) // 2
+    return [[Fraction(x[2 * i][2 * j] + x[2 * i][2 * j + 1] + x[2 * i + 1][2 * j]
+                      + x[2 * i + 1][2 * j + 1], 4) for j in range(n)] for i in range(m)]
+
+
+def _search_exact(al, bl, w, ds):
+    """The search of sec. 2 in exact rationals on the literal overlap set:
+    (coarse argmin, f1, gap_c, kappa, final shift, gap_r, best of the nine;
+    the last two None without downsampling)."""
+    ga, gb = (_box_exact(al), _box_exact(bl)) if ds else (al, bl)
+    vals = []
+    for s in range(-(w - 1), w):
+        for t in range(-(w - 1), w):
+            vals.append((_tie_key(f_exact(ga, gb, s, t), s, t), s, t))
+    vals.sort()
+    (k1, s1, t1) = vals[0]
+    f1 = k1[0]
+    gap_c = vals[1][0][0] - f1 if len(vals) > 1 else None
+    D = overlap_set(len(ga), len(ga[0]), s1, t1)
+    A = sum(Fraction(ga[i + s1 - 1][j + t1 - 1]) ** 2 for (i, j) in D)
+    B = sum(Fraction(gb[i - 1][j - 1]) ** 2 for (i, j) in D)
+    kappa = (A + B) / (len(D) * f1) if f1 != 0 else None
+    if not ds:
+        return (s1, t1), f1, gap_c, kappa, (s1, t1), None, None
+    nine = sorted((_tie_key(f_exact(al, bl, 2 * s1 + u, 2 * t1 + v), 2 * s1 + u, 2 * t1 + v),
+                   2 * s1 + u, 2 * t1 + v) for u in (-1, 0, 1) for v in (-1, 0, 1))
+    fb = nine[0][0][0]
+    return (s1, t1), f1, gap_c, kappa, (nine[0][1], nine[0][2]), nine[1][0][0] - fb, fb
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_gaps_and_kappa_match_exact_rationals(seed):
+    """gap_c, gap_r (second best minus best, sec. 2 argmin and nine-point step)
+    and kappa = (A+B)/(Area f1) at the argmin (the energy split of sec. 2) on
+    random integer images, against exact rationals with the tie order written
+    out independently."""
+    rng = np.random.default_rng(500 + seed)
+    ds = seed % 2
+    m, n = (int(rng.integers(4, 9)), int(rng.integers(4, 9)))
+    w = int(rng.integers(1, min(m >> ds, n >> ds) + 1))
+    b = _ints(rng, m, n, 0, 40)
+    a = np.roll(b, (int(rng.integers(-2, 3)), int(rng.integers(-2, 3))), axis=(0, 1)) \
+        + _ints(rng, m, n, 0, 9)
+    al, bl = a.tolist(), b.tolist()
+    (cs, ct), f1, gap_c, kappa, shift, gap_r, fb = _search_exact(al, bl, w, ds)
+    r = oracle.align(a[None], b, w, bool(ds))
+    assert tuple(r.coarse[0]) == (cs, ct)
+    assert r.fmin[0] == float(f1)
+    u = 2.0 ** -53
+    if gap_c is None:
+        assert r.gap_c[0] == math.inf
+    else:
+        # a difference of two correctly rounded values
+        assert abs(r.gap_c[0] - float(gap_c)) <= 2 * u * (2 * float(f1) + float(gap_c)) + 1e-300
+    if kappa is None:
+        assert not np.isfinite(r.kappa[0]) or np.isnan(r.kappa[0])
+    else:
+        assert abs(r.kappa[0] - float(kappa)) <= 8 * u * float(kappa)
+    assert tuple(r.shifts[0]) == shift
+    if gap_r is None:
+        assert r.gap_r[0] == math.inf
+    else:
+        assert abs(r.gap_r[0] - float(gap_r)) <= 2 * u * (2 * float(fb) + float(gap_r)) + 1e-300
+
+
+def test_kappa_of_the_search_is_one_over_relative_contrast():
+    """kappa = (A+B)/(Area f) at the argmin: a frame that is the template plus a
+    constant c at the zero shift has f = c^2 and A + B = sum (b+c)^2 + sum b^2,
+    a closed form independent of the oracle's arithmetic."""
+    rng = np.random.default_rng(77)
+    b = _ints(rng, 10, 12, 5, 60)
+    for c in (1, 3, 7):
+        a = b + c
+        r = oracle.align(a[None], b, 1, False)
+        N = b.size
+        AB = int(((b + c) ** 2).sum() + (b ** 2).sum())
+        assert r.fmin[0] == float(c * c)
+        assert r.kappa[0] == pytest.approx(AB / (N * c * c), rel=1e-15)
 
 
 # --- the energy split (sec. 2, Area*f = sum a^2 + sum b^2 - 2 sum ab) -------
