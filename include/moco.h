@@ -153,6 +153,22 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
                int w, int downsample, moco_dtype dtype, moco_form form, const moco_outputs *out,
                void *hip_stream);
 
+/* moco_align for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, validation, results (bit for bit) and kernels as moco_align, but
+ * its scratch is a fixed 64 MiB device array held by the library on each
+ * device (from the first moco_create on that device until the process ends)
+ * instead of the context's budget: it calls no hipMalloc, hipFree or other
+ * allocating routine, and records no stage timing.  Stacks larger than the
+ * array run in chunks that fit it.  Every call on one device shares that
+ * device's array, whatever the context: calls that overlap in time on one
+ * device race (enqueue them on one stream, or synchronise between them).
+ * Errors: those of moco_align; MOCO_ENOMEM when one frame needs more than the
+ * 64 MiB (moco_align serves such frames). */
+int moco_align_noalloc(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
+                       int n, int w, int downsample, moco_dtype dtype, moco_form form,
+                       const moco_outputs *out, void *hip_stream);
+
 /* A moco_align call captured as a HIP graph, for callers that repeat the same
  * call (a frame buffer refilled between calls: a camera, a serving loop):
  * replaying it aligns whatever d_frames holds when the replay runs into the

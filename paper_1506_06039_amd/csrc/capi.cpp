@@ -31,6 +31,7 @@ struct moco_ctx {
     size_t budget = 0;
     void *scratch = nullptr;
     size_t scratch_size = 0;
+    void *fixed_scratch = nullptr;    // this device's copy of the allocation-free scratch
     bool profiling = false;
     std::vector<ProfRec> prof;        // recorded, not yet read
     std::vector<hipEvent_t> ev_pool;  // reusable events
@@ -48,6 +49,14 @@ struct moco_graph {
     void *scratch = nullptr;        // its own: the context's scratch may be reallocated
     hipGraphExec_t exec = nullptr;
 };
+
+// Scratch of moco_align_noalloc: a module-scope device array, so that the
+// entry point needs no allocation.  Each device the library runs on holds its
+// own instance, from the first context created on it until the process ends.
+// In host code `scratch` names a host-side stand-in; its device address on the
+// current device comes from hipGetSymbolAddress (fixed_scratch_address).
+constexpr size_t kFixedScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
 
 namespace {
 
@@ -72,6 +81,29 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (each device holds the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+
+int fixed_scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (device < 0 || device >= kMaxDevices)
+        return fail(MOCO_EINVAL, "device %d beyond the %d the library tracks", device, kMaxDevices);
+    if (!g_fixed_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MOCO_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                        hipGetErrorString(e));
+        g_fixed_ptr[device] = p;
+    }
+    *out = g_fixed_ptr[device];
+    return MOCO_OK;
+}
 
 // Validation shared by template creation and alignment.
 int validate(int m, int n, int w, int ds, moco_dtype dt, moco::Geom *g)
@@ -861,6 +893,16 @@ int moco_create(int device, size_t scratch_budget_bytes, moco_ctx **out)
     if (!ctx) return fail(MOCO_ENOMEM, "out of host memory");
     ctx->device = device;
     ctx->budget = scratch_budget_bytes ? scratch_budget_bytes : (size_t)1 << 30;
+    {
+        // the allocation-free entry point's scratch on this device
+        DeviceGuard dg(device);
+        int rc = dg.ok() ? fixed_scratch_address(device, &ctx->fixed_scratch)
+                         : fail(MOCO_EDEVICE, "cannot select device %d", device);
+        if (rc) {
+            delete ctx;
+            return rc;
+        }
+    }
     *out = ctx;
     return MOCO_OK;
 }
@@ -1171,6 +1213,36 @@ int moco_align(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T
     rc = ensure_scratch(ctx, need, st);
     if (rc) return rc;
     return run_stack(ctx, d_frames, tt, T, g, form, out, st, (char *)ctx->scratch, need);
+}
+
+int moco_align_noalloc(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
+                       int n, int w, int downsample, moco_dtype dtype, moco_form form,
+                       const moco_outputs *out, void *hip_stream)
+{
+    if (!ctx || !tmpl || !out)
+        return fail(MOCO_EINVAL, "moco_align_noalloc: null ctx, template or outputs");
+    moco::Geom g;
+    int rc = check_stack(ctx, d_frames, tmpl, T, m, n, w, downsample, dtype, form, out, &g, &form);
+    if (rc) return rc;
+    if (T == 0) return MOCO_OK;
+    const moco::Tmpl &tt = tmpl->t;
+    const size_t pf = per_frame_scratch(g, form, tt);
+    if (pf > kFixedScratchBytes)
+        return fail(MOCO_ENOMEM,
+                    "moco_align_noalloc: one frame needs %zu bytes of scratch, the fixed "
+                    "scratch holds %zu (use moco_align)", pf, kFixedScratchBytes);
+    if (!ctx->fixed_scratch) return fail(MOCO_EDEVICE, "moco_align_noalloc: no fixed scratch");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    const size_t frames = std::min<size_t>(std::min<size_t>((size_t)T, (size_t)chunk_cap(form)),
+                                           kFixedScratchBytes / pf);
+    // no stage timing here: recording it creates events and grows a host list
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    rc = run_stack(ctx, d_frames, tt, T, g, form, out, (hipStream_t)hip_stream,
+                   (char *)ctx->fixed_scratch, pf * frames);
+    ctx->profiling = prof;
+    return rc;
 }
 
 int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,

@@ -54,6 +54,9 @@ _lib.moco_template_destroy.restype = None
 _lib.moco_align.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
                             ctypes.POINTER(_Outputs), _vp]
 _lib.moco_align.restype = _i
+_lib.moco_align_noalloc.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
+                                    ctypes.POINTER(_Outputs), _vp]
+_lib.moco_align_noalloc.restype = _i
 _lib.moco_profile_enable.argtypes = [_vp, _i]
 _lib.moco_profile_enable.restype = _i
 _lib.moco_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
@@ -230,6 +233,21 @@ def moco_align(ctx: Context, frames: torch.Tensor, tmpl: Template, form: str = "
     _check(_lib.moco_align(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), FORMS[form],
                            ctypes.byref(o), _stream_handle(dev)))
+    return out
+
+
+def moco_align_noalloc(ctx: Context, frames: torch.Tensor, tmpl: Template, out: Result,
+                       form: str = "auto") -> Result:
+    """moco_align through the allocation-free entry point: the library's fixed
+    per-device scratch instead of the context's; the caller brings every
+    output (out), so nothing is allocated here either."""
+    if not frames.is_cuda or frames.dim() != 3 or not frames.is_contiguous():
+        raise ValueError("frames must be a contiguous 3-D device tensor")
+    T, m, n = frames.shape
+    o = _outputs(out, T, 2 * tmpl.w - 1, frames.device)
+    _check(_lib.moco_align_noalloc(ctx.handle, frames.data_ptr(), tmpl.handle, T, m, n, tmpl.w,
+                                   int(tmpl.downsample), _dtype_code(frames), FORMS[form],
+                                   ctypes.byref(o), _stream_handle(frames.device)))
     return out
 
 
