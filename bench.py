@@ -478,7 +478,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--form", default="auto", choices=["auto", "fft", "fft_cert", "fp64", "int8"])
+    ap.add_argument("--form", default="auto",
+                    choices=["auto", "fft", "fft_cert", "fp64", "int8", "fft32"])
     ap.add_argument("--frames", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="frames for the oracle baseline (0: batches of 4 per host thread "
@@ -488,7 +489,7 @@ def main():
                     help="timed runs per shape of the paper's timing table (0: skip)")
     ap.add_argument("--apply-steps", type=int, default=5,
                     help="timed moco_apply runs (corrected stack + mean) on the same stack")
-    ap.add_argument("--compare-forms", default="fft,fft_cert,fp64",
+    ap.add_argument("--compare-forms", default="fft32,fft,fft_cert,fp64",
                     help="other correlation forms to time on the same stack (comma list, "
                          "empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -791,7 +792,7 @@ def main():
         # after every GPU timing: the oracle on samples of the other workloads,
         # and each correlation form's f error against it, per config
         t_chk = time.perf_counter()
-        all_forms = ["int8", "fft", "fft_cert", "fp64"]
+        all_forms = ["int8", "fft32", "fft", "fft_cert", "fp64"]
         precision = {}
         precision["poisson512_u16_ds_w32"] = {
             "frames": ns, "kappa": kappa_quantiles(orc),
@@ -818,6 +819,18 @@ def main():
             row["parity"] = compare_with_oracle(smp["gpu"], orcp, smp["ds"])
             row["kappa"] = kappa_quantiles(orcp)
         result["precision"] = precision
+        # the metric's comparison: the plain single-precision form against the
+        # form the headline ran, same GPU, same stack, with their accuracy
+        c1 = precision["poisson512_u16_ds_w32"]["forms"]
+        if forms.get("fft32") and form_ran in c1 and "fft32" in c1:
+            result["plain_vs_headline"] = {
+                "plain": {"form": "fft32", "frames_per_s": forms["fft32"]["frames_per_s"],
+                          "fmin_rel_err_max": c1["fft32"]["fmin_rel_err_max"],
+                          "parity_ok": c1["fft32"]["parity_ok"]},
+                "headline": {"form": form_ran, "frames_per_s": round(fps, 2),
+                             "fmin_rel_err_max": c1[form_ran]["fmin_rel_err_max"],
+                             "parity_ok": c1[form_ran]["parity_ok"]},
+                "speedup": round(fps / forms["fft32"]["frames_per_s"], 3)}
         result["oracle_checks_seconds"] = round(time.perf_counter() - t_chk, 1)
 
     print(json.dumps(result), flush=True)

@@ -84,10 +84,21 @@ typedef enum {
                                  data, the FP64 form's own rounding decides ties closer
                                  than it) */
     MOCO_FORM_FP64_EXACT = 3, /* direct FP64 sums on the vector ALUs; bit-exact f for uint16 */
-    MOCO_FORM_INT8_MFMA = 4   /* uint16 only: exact integer correlation on int8 matrix
+    MOCO_FORM_INT8_MFMA = 4,  /* uint16 only: exact integer correlation on int8 matrix
                                  cores (balanced base-128 digits and three products per
                                  term when the template allows, else base-256 and four:
                                  moco_template_int8_products); bit-exact f */
+    MOCO_FORM_FFT32 = 5       /* the plain single-precision form: h from FP32 complex
+                                 transforms (sec. 2, the FFT construction of h) of the
+                                 grids less a common offset c (the template grid's mean,
+                                 rounded to an integer for uint16 data), with the overlap
+                                 energies of the centred grids and f = (A + B - 2h)/Area
+                                 in FP64 (the split holds for any common offset); f to
+                                 about 1e-6 relative, not certified: the argmin can
+                                 differ from the exact one where the best and second-best
+                                 f are closer than that.  Never chosen by AUTO; the
+                                 single-precision comparator of the other forms.  Same
+                                 applicability as MOCO_FORM_FFT */
 } moco_form;
 
 typedef struct moco_ctx moco_ctx;

@@ -333,7 +333,13 @@ void free_tmpl(moco::Tmpl &t)
     if (t.fft.twp) (void)hipFree(t.fft.twp);
     if (t.fft.twq) (void)hipFree(t.fft.twq);
     if (t.fft.spec) (void)hipFree(t.fft.spec);
+    if (t.fft.twp32) (void)hipFree(t.fft.twp32);
+    if (t.fft.twq32) (void)hipFree(t.fft.twq32);
+    if (t.fft.spec32) (void)hipFree(t.fft.spec32);
+    if (t.fft.btab32) (void)hipFree(t.fft.btab32);
     if (t.pyr) (void)hipFree(t.pyr);
+    t.fft.twp32 = t.fft.twq32 = t.fft.spec32 = nullptr;
+    t.fft.btab32 = nullptr;
     t.pyr = nullptr;
     t.fft.twp = nullptr;
     t.fft.twq = nullptr;
@@ -446,6 +452,76 @@ int upload_twiddles(int n, double2 **dst)
     return MOCO_OK;
 }
 
+// The same table rounded to FP32 (from the long double values).
+int upload_twiddles32(int n, float2 **dst)
+{
+    std::vector<float2> h((size_t)n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < n; ++k) {
+        const long double a = two_pi * (long double)k / (long double)n;
+        h[(size_t)k] = float2{(float)cosl(a), (float)-sinl(a)};
+    }
+    hipError_t e = hipMalloc(dst, (size_t)n * sizeof(float2));
+    if (e == hipSuccess) e = hipMemcpy(*dst, h.data(), (size_t)n * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MOCO_ENOMEM, "FFT twiddle table: %s", hipGetErrorString(e));
+    return MOCO_OK;
+}
+
+// The single-precision form's template side: the offset c (the mean of the
+// template's grid, rounded to an integer for uint16 data so that centred
+// uint16 grids stay exact in FP32), the energies of b' - c, and the transform
+// of the zero-padded b' - c, computed in FP64 and rounded to FP32.
+int prepare_fft32_template(moco::Tmpl &t, hipStream_t st)
+{
+    const moco::Geom &g = t.g;
+    moco::FftTmpl &f = t.fft;
+    const size_t ne = (size_t)g.mg * g.ng;
+    std::vector<double> grid(ne);
+    hipError_t e = hipMemcpyAsync(grid.data(), t.coarse, ne * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MOCO_EDEVICE, "FFT32 template: %s", hipGetErrorString(e));
+    long double acc = 0.0L;
+    for (double v : grid) acc += v;
+    const double mean = (double)(acc / (long double)ne);
+    f.center = g.dtype == MOCO_U16 ? std::nearbyint(mean) : mean;
+    for (double &v : grid) v -= f.center;
+    int rc = upload_twiddles32(f.pp.n, &f.twp32);
+    if (!rc) rc = upload_twiddles32(f.pq.n, &f.twq32);
+    if (rc) return rc;
+    const size_t nspec = (size_t)f.qh * f.pp.n;
+    double *dgrid = nullptr;
+    double2 *s1 = nullptr, *spec = nullptr;
+    std::vector<double2> hspec(nspec);
+    std::vector<float2> hspec32(nspec);
+    if ((e = hipMalloc(&f.btab32, (size_t)g.W * g.W * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&f.spec32, nspec * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&dgrid, ne * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&s1, moco::fft_s1_bytes(g))) != hipSuccess ||
+        (e = hipMalloc(&spec, nspec * sizeof(double2))) != hipSuccess) {
+        rc = fail(MOCO_ENOMEM, "FFT32 template allocation: %s", hipGetErrorString(e));
+    } else if ((e = moco::launch_energy(t.coarse, 1, g, true, f.btab32, nullptr, st,
+                                        f.center)) != hipSuccess ||
+               (e = hipMemcpyAsync(dgrid, grid.data(), ne * sizeof(double),
+                                   hipMemcpyHostToDevice, st)) != hipSuccess ||
+               (e = moco::launch_fft_rows(dgrid, 1, g, f, s1, st)) != hipSuccess ||
+               (e = moco::launch_fft_spec(s1, g, f, spec, st)) != hipSuccess ||
+               (e = hipMemcpyAsync(hspec.data(), spec, nspec * sizeof(double2),
+                                   hipMemcpyDeviceToHost, st)) != hipSuccess ||
+               (e = hipStreamSynchronize(st)) != hipSuccess) {
+        rc = fail(MOCO_EDEVICE, "FFT32 template preparation: %s", hipGetErrorString(e));
+    } else {
+        for (size_t k = 0; k < nspec; ++k)
+            hspec32[k] = float2{(float)hspec[k].x, (float)hspec[k].y};
+        e = hipMemcpy(f.spec32, hspec32.data(), nspec * sizeof(float2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(MOCO_EDEVICE, "FFT32 template: %s", hipGetErrorString(e));
+    }
+    if (dgrid) (void)hipFree(dgrid);
+    if (s1) (void)hipFree(s1);
+    if (spec) (void)hipFree(spec);
+    return rc;
+}
+
 // Prepare the template side of the FFT form: plans, twiddles and the 2-D
 // transform of the zero-padded b'.  Leaves t.fft_ok false when the transform
 // lengths exceed the supported maximum.
@@ -476,6 +552,8 @@ int prepare_fft_template(moco::Tmpl &t, hipStream_t st)
         return fail(MOCO_EDEVICE, "FFT template preparation: %s", hipGetErrorString(e));
     }
     (void)hipFree(s1);
+    int rc32 = prepare_fft32_template(t, st);
+    if (rc32) return rc32;
     t.fft_ok = true;
     return MOCO_OK;
 }
@@ -601,14 +679,16 @@ struct FftLayout {
     size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, edge, part, total_per_frame;
 };
 
-FftLayout fft_layout(const moco::Geom &g)
+// fp32: the single-precision form's half spectra (FP32 complex)
+FftLayout fft_layout(const moco::Geom &g, bool fp32 = false)
 {
     FftLayout L;
+    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
     L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
     L.inter = align_up(inter_elems(g) * sizeof(double), 256);
     L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
-    L.s1 = align_up(moco::fft_s1_bytes(g), 256);
-    L.s2 = align_up(moco::fft_s2_bytes(g), 256);
+    L.s1 = align_up(moco::fft_s1_bytes(g, esz), 256);
+    L.s2 = align_up(moco::fft_s2_bytes(g, esz), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
@@ -624,14 +704,17 @@ FftLayout fft_layout(const moco::Geom &g)
 // and refine around the transform-based correlation.  With `certify`, frames
 // whose argmin the error bound of the transforms does not certify get their
 // correlation recomputed by direct FP64 sums and are combined again before the
-// x2 steps.
+// x2 steps.  With `fp32` (never certified), the single-precision form: the
+// transforms in FP32 on the grids less the template's offset c, the energies
+// of the centred grids (FP64; exact integers for uint16), the same combine.
 int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
-            size_t sbytes, bool certify)
+            size_t sbytes, bool certify, bool fp32 = false)
 {
-    FftLayout L = fft_layout(g);
+    if (fp32) certify = false;
+    FftLayout L = fft_layout(g, fp32);
     int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
-    C = std::min(C, 4096);
+    C = std::min(C, kChunkOther);
     if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
     char *base = sbase;
     const moco_dtype dtype = g.dtype;
@@ -644,9 +727,9 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     off += L.atab * C;
     long long *edge = L.edge ? (long long *)(base + off) : nullptr;
     off += L.edge * C;
-    double2 *s1 = (double2 *)(base + off);
+    char *s1 = base + off;
     off += L.s1 * C;
-    double2 *s2 = (double2 *)(base + off);
+    char *s2 = base + off;
     off += L.s2 * C;
     double *h = (double *)(base + off);
     off += L.h * C;
@@ -666,6 +749,11 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     // transforms form its values from the pixels)
     const bool raw_rows = g.ds <= 1;
     const bool int_energy = edge && moco::prep_grid_applicable(g);   // uint16
+    // the single-precision form's centring: c in grid units, xc in the prep
+    // kernel's integer units (box sums when downsampling)
+    const double center = fp32 ? tt.fft.center : 0.0;
+    const int xc = (int)(center * (g.ds ? 4.0 : 1.0));
+    const double *btab = fp32 ? tt.fft.btab32 : tt.btab;
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
@@ -679,24 +767,41 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             // exact integer energies only: the row transforms read the pixels
             StageTimer tm(ctx, MOCO_STAGE_PREP, st);
             HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, nullptr, atab, pm, edge,
-                                           st));
+                                           st, nullptr, xc));
         } else if (raw_rows) {
             StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
-            HIP_TRY(moco::launch_energy_px(fr, c, g, atab, pm, st));
+            HIP_TRY(moco::launch_energy_px(fr, c, g, atab, pm, st, center));
+        } else if (fp32) {
+            {
+                StageTimer tm(ctx, MOCO_STAGE_COARSE, st);
+                HIP_TRY(build_levels(fr, g.dtype, c, g, inter, coarse, st));
+            }
+            StageTimer tm(ctx, MOCO_STAGE_ENERGY, st);
+            HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st, center));
         } else {
             HIP_TRY(grid_and_energies(ctx, fr, g, c, inter, coarse, atab, pm, edge, st));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            if (raw_rows)
-                HIP_TRY(moco::launch_fft_rows_px(fr, c, g, tt.fft, s1, st));
-            else
-                HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, s1, st));
-            HIP_TRY(moco::launch_fft_corr(s1, c, g, tt.fft, s2, h, st));
+            if (fp32) {
+                if (raw_rows)
+                    HIP_TRY(moco::launch_fft32_rows_px(fr, c, g, tt.fft, (float2 *)s1, st));
+                else
+                    HIP_TRY(moco::launch_fft32_rows(coarse, c, g, tt.fft, (float2 *)s1, st));
+                HIP_TRY(moco::launch_fft32_corr((const float2 *)s1, c, g, tt.fft, (float2 *)s2,
+                                                h, st));
+            } else {
+                if (raw_rows)
+                    HIP_TRY(moco::launch_fft_rows_px(fr, c, g, tt.fft, (double2 *)s1, st));
+                else
+                    HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, (double2 *)s1, st));
+                HIP_TRY(moco::launch_fft_corr((const double2 *)s1, c, g, tt.fft, (double2 *)s2,
+                                              h, st));
+            }
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
-            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
+            HIP_TRY(moco::launch_combine(atab, btab, h, c, g, fsurf, fmin, coarse_st,
                                          out->shifts + 2 * (size_t)f0, gaps, frefine, st,
                                          nullptr, certify ? recheck : nullptr, kf, ke));
         }
@@ -736,6 +841,7 @@ size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &
     if (form == MOCO_FORM_INT8_MFMA) return int8_layout(g, tt.i8.npad).total_per_frame;
     if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED)
         return fft_layout(g).total_per_frame;
+    if (form == MOCO_FORM_FFT32) return fft_layout(g, true).total_per_frame;
     return exact_layout(g).total_per_frame;
 }
 
@@ -743,9 +849,9 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
               const moco::Geom &g, moco_form form, const moco_outputs *out, hipStream_t st,
               char *sbase, size_t sbytes)
 {
-    if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED)
+    if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED || form == MOCO_FORM_FFT32)
         return run_fft(ctx, d_frames, tt, T, g, out, st, sbase, sbytes,
-                       form == MOCO_FORM_FFT_CERTIFIED);
+                       form == MOCO_FORM_FFT_CERTIFIED, form == MOCO_FORM_FFT32);
     // the exact forms recompute nothing
     if (out->recomputed && T > 0) {
         hipError_t e = moco::launch_fill_i32(out->recomputed, T, 0, st);
@@ -800,7 +906,8 @@ bool form_applies(const moco::Tmpl &t, moco_form f)
     case MOCO_FORM_FP64_EXACT: return true;
     case MOCO_FORM_INT8_MFMA: return t.int8_ok;
     case MOCO_FORM_FFT:
-    case MOCO_FORM_FFT_CERTIFIED: return t.fft_ok;
+    case MOCO_FORM_FFT_CERTIFIED:
+    case MOCO_FORM_FFT32: return t.fft_ok;
     default: return false;
     }
 }
@@ -842,7 +949,7 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "(m=%d n=%d w=%d ds=%d dtype=%d)",
                     tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
     if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA &&
-        form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED)
+        form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED && form != MOCO_FORM_FFT32)
         return fail(MOCO_EINVAL, "unknown form %d", (int)form);
     if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
         return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
@@ -853,7 +960,8 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "the int8 matrix-core form does not apply to this template (needs uint16, "
                     "grid area below 131072, grid width at most 2048 and template values "
                     "within two base-256 digits)");
-    if ((form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED) && !tt.fft_ok)
+    if ((form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED || form == MOCO_FORM_FFT32) &&
+        !tt.fft_ok)
         return fail(MOCO_EINVAL, "the FFT form does not apply to this template (transform "
                                  "lengths above %d)", moco::kFftMaxLen);
     if (form == MOCO_FORM_AUTO) form = auto_form(tt);
@@ -975,6 +1083,7 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
         return MOCO_OK;
     case MOCO_FORM_FFT:
     case MOCO_FORM_FFT_CERTIFIED:
+    case MOCO_FORM_FFT32:
         if (!t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
         *resolved = requested;
         return MOCO_OK;

@@ -32,45 +32,63 @@ namespace {
 constexpr int kBlock = 256;
 constexpr size_t kLdsBudget = 32 * 1024;  // LDS bytes a block's two buffers may use
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+// Complex type of each working precision: FP64 (the FFT forms) and FP32 (the
+// plain single-precision form on centred grids).
+template <typename R>
+struct Cx;
+template <>
+struct Cx<double> {
+    using T = double2;
+};
+template <>
+struct Cx<float> {
+    using T = float2;
+};
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b)
 {
     return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b)
+template <typename C>
+__device__ __forceinline__ C cmulc(C a, C b)
 {
     return {fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y)};
 }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return {a.x * s, a.y * s}; }
+template <typename C, typename R>
+__device__ __forceinline__ C cscale(C a, R s) { return {a.x * s, a.y * s}; }
 // multiply by -i (forward) or +i (inverse)
-template <bool INV>
-__device__ __forceinline__ double2 rot(double2 a)
+template <bool INV, typename C>
+__device__ __forceinline__ C rot(C a)
 {
-    return INV ? double2{-a.y, a.x} : double2{a.y, -a.x};
+    return INV ? C{-a.y, a.x} : C{a.y, -a.x};
 }
 
 // Small DFTs in registers: y_k = sum_q v_q e^{-+2 pi i qk/R} (minus: forward).
-template <int R, bool INV>
+template <int R, bool INV, typename C>
 struct Dft;
 
-template <bool INV>
-struct Dft<2, INV> {
-    __device__ static void run(double2 (&v)[2])
+template <bool INV, typename C>
+struct Dft<2, INV, C> {
+    __device__ static void run(C (&v)[2])
     {
-        double2 a = v[0], b = v[1];
+        C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     }
 };
 
-template <bool INV>
-struct Dft<4, INV> {
-    __device__ static void run(double2 (&v)[4])
+template <bool INV, typename C>
+struct Dft<4, INV, C> {
+    __device__ static void run(C (&v)[4])
     {
-        double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-        double2 t2 = cadd(v[1], v[3]), t3 = rot<INV>(csub(v[1], v[3]));
+        C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        C t2 = cadd(v[1], v[3]), t3 = rot<INV>(csub(v[1], v[3]));
         v[0] = cadd(t0, t2);
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, t3);
@@ -78,20 +96,21 @@ struct Dft<4, INV> {
     }
 };
 
-template <bool INV>
-struct Dft<8, INV> {
-    __device__ static void run(double2 (&v)[8])
+template <bool INV, typename C>
+struct Dft<8, INV, C> {
+    __device__ static void run(C (&v)[8])
     {
-        constexpr double h = 0.70710678118654752440;  // sqrt(1/2)
-        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<4, INV>::run(e);
-        Dft<4, INV>::run(o);
+        using R = decltype(v[0].x);
+        constexpr R h = (R)0.70710678118654752440;  // sqrt(1/2)
+        C e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, INV, C>::run(e);
+        Dft<4, INV, C>::run(o);
         // o_k times e^{-+2 pi i k/8}
-        const double2 o1 = INV ? double2{h * (o[1].x - o[1].y), h * (o[1].x + o[1].y)}
-                               : double2{h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
-        const double2 o2 = rot<INV>(o[2]);
-        const double2 o3 = INV ? double2{-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y)}
-                               : double2{h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+        const C o1 = INV ? C{h * (o[1].x - o[1].y), h * (o[1].x + o[1].y)}
+                         : C{h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+        const C o2 = rot<INV>(o[2]);
+        const C o3 = INV ? C{-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y)}
+                         : C{h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
         v[0] = cadd(e[0], o[0]);
         v[4] = csub(e[0], o[0]);
         v[1] = cadd(e[1], o1);
@@ -103,35 +122,37 @@ struct Dft<8, INV> {
     }
 };
 
-template <bool INV>
-struct Dft<3, INV> {
-    __device__ static void run(double2 (&v)[3])
+template <bool INV, typename C>
+struct Dft<3, INV, C> {
+    __device__ static void run(C (&v)[3])
     {
-        constexpr double r3 = 0.86602540378443864676;  // sqrt(3)/2
-        const double2 t1 = cadd(v[1], v[2]);
-        const double2 t2 = {v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y};
-        const double2 d = rot<INV>(cscale(csub(v[1], v[2]), r3));
+        using R = decltype(v[0].x);
+        constexpr R r3 = (R)0.86602540378443864676;  // sqrt(3)/2
+        const C t1 = cadd(v[1], v[2]);
+        const C t2 = {v[0].x - (R)0.5 * t1.x, v[0].y - (R)0.5 * t1.y};
+        const C d = rot<INV>(cscale(csub(v[1], v[2]), r3));
         v[0] = cadd(v[0], t1);
         v[1] = cadd(t2, d);
         v[2] = csub(t2, d);
     }
 };
 
-template <bool INV>
-struct Dft<5, INV> {
-    __device__ static void run(double2 (&v)[5])
+template <bool INV, typename C>
+struct Dft<5, INV, C> {
+    __device__ static void run(C (&v)[5])
     {
-        constexpr double c1 = 0.30901699437494742410;   // cos(2 pi/5) = (sqrt 5 - 1)/4
-        constexpr double c2 = -0.80901699437494742410;  // cos(4 pi/5) = -(sqrt 5 + 1)/4
-        constexpr double s1 = 0.95105651629515357212;   // sin(2 pi/5)
-        constexpr double s2 = 0.58778525229247312917;   // sin(4 pi/5)
-        const double2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
-        const double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-        const double2 p1 = {v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y};
-        const double2 p2 = {v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y};
+        using R = decltype(v[0].x);
+        constexpr R c1 = (R)0.30901699437494742410;   // cos(2 pi/5) = (sqrt 5 - 1)/4
+        constexpr R c2 = (R)-0.80901699437494742410;  // cos(4 pi/5) = -(sqrt 5 + 1)/4
+        constexpr R s1 = (R)0.95105651629515357212;   // sin(2 pi/5)
+        constexpr R s2 = (R)0.58778525229247312917;   // sin(4 pi/5)
+        const C b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+        const C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+        const C p1 = {v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y};
+        const C p2 = {v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y};
         // -+i (s1 d1 + s2 d2) and -+i (s2 d1 - s1 d2)
-        const double2 q1 = rot<INV>(double2{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
-        const double2 q2 = rot<INV>(double2{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
+        const C q1 = rot<INV>(C{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
+        const C q2 = rot<INV>(C{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
         v[0] = cadd(v[0], cadd(b1, b2));
         v[1] = cadd(p1, q1);
         v[4] = csub(p1, q1);
@@ -149,10 +170,11 @@ __device__ __forceinline__ int divq(int x, unsigned long long mag)
 // One Stockham pass of radix R over `rows` rows of length N: butterfly j
 // (0 <= j < N/R) reads in[j + r N/R], r < R, twiddles them by w_N^{r (j mod
 // Ns) N/(Ns R)}, transforms and writes out[(j div Ns) Ns R + (j mod Ns) + r Ns].
-template <int R, bool INV>
-__device__ __forceinline__ void fft_pass(const double2 *in, double2 *out, int rows, int N, int Ns,
+// tw: the length-N twiddle table, held in LDS by the block.
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void fft_pass(const C *in, C *out, int rows, int N, int Ns,
                                          unsigned long long mag_nr, unsigned long long mag_ns,
-                                         const double2 *__restrict__ tw)
+                                         const C *tw)
 {
     const int NR = N / R;
     const int stw = N / (Ns * R);
@@ -160,18 +182,18 @@ __device__ __forceinline__ void fft_pass(const double2 *in, double2 *out, int ro
     for (int idx = threadIdx.x; idx < total; idx += kBlock) {
         const int row = divq(idx, mag_nr), j = idx - row * NR;
         const int jq = divq(j, mag_ns), jm = j - jq * Ns;
-        const double2 *src = in + row * N + j;
-        double2 v[R];
+        const C *src = in + row * N + j;
+        C v[R];
         v[0] = src[0];
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-            const double2 x = src[r * NR];
-            double2 t = tw[r * jm * stw];
+            const C x = src[r * NR];
+            C t = tw[r * jm * stw];
             if (INV) t.y = -t.y;
             v[r] = cmul(x, t);
         }
-        Dft<R, INV>::run(v);
-        double2 *dst = out + row * N + jq * Ns * R + jm;
+        Dft<R, INV, C>::run(v);
+        C *dst = out + row * N + jq * Ns * R + jm;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[r * Ns] = v[r];
     }
@@ -179,9 +201,8 @@ __device__ __forceinline__ void fft_pass(const double2 *in, double2 *out, int ro
 
 // Transform `rows` rows held in a; b is the other buffer.  Returns the buffer
 // that holds the result.  Ends with a barrier.
-template <bool INV>
-__device__ double2 *fft_lds(double2 *a, double2 *b, int rows, const FftPlan &pl,
-                            const double2 *__restrict__ tw)
+template <bool INV, typename C>
+__device__ C *fft_lds(C *a, C *b, int rows, const FftPlan &pl, const C *tw)
 {
     for (int p = 0; p < pl.npass; ++p) {
         switch (pl.radix[p]) {
@@ -192,28 +213,40 @@ __device__ double2 *fft_lds(double2 *a, double2 *b, int rows, const FftPlan &pl,
         default: fft_pass<5, INV>(a, b, rows, pl.n, pl.ns[p], pl.mag_nr[p], pl.mag_ns[p], tw); break;
         }
         __syncthreads();
-        double2 *t = a;
+        C *t = a;
         a = b;
         b = t;
     }
     return a;
 }
 
+// The block's copy of a length-n twiddle table (no barrier).
+template <typename C>
+__device__ __forceinline__ void load_twiddles(const C *__restrict__ g, int n, C *lds)
+{
+    for (int k = threadIdx.x; k < n; k += kBlock) lds[k] = g[k];
+}
+
 // Pass 1: rows.  Block (group of rp row pairs, frame).  src: the frames' grid
-// (SRC 0: mg x ng FP64) or their pixels (m x n; see grid_at).  s1:
-// [frame][qh][mg] complex.
-template <int SRC>
+// (SRC 0: mg x ng FP64) or their pixels (m x n; see grid_at).  Each grid value
+// less `center` (0 in the FP64 forms) enters the transform in precision R.
+// s1: [frame][qh][mg] complex.
+template <int SRC, typename R>
 __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ src, int m, int n,
                                                      int mg, int ng, int rp, FftPlan pq,
-                                                     const double2 *__restrict__ twq,
-                                                     double2 *__restrict__ s1)
+                                                     const typename Cx<R>::T *__restrict__ twq,
+                                                     double center,
+                                                     typename Cx<R>::T *__restrict__ s1)
 {
-    extern __shared__ double2 lds[];
+    using C = typename Cx<R>::T;
+    extern __shared__ double lds_d[];
+    C *lds = (C *)lds_d;
     const int Q = pq.n, qh = Q / 2 + 1;
     const int npairs = (mg + 1) / 2;
     const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
     const void *a = grid_frame<SRC>(src, blockIdx.y, m, n, mg, ng);
-    double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
+    C *tw = lds, *bufa = lds + Q, *bufb = bufa + (size_t)rp * Q;
+    load_twiddles(twq, Q, tw);
     for (int pr = 0; pr < np; ++pr) {
         const int r = 2 * (pair0 + pr);
         const bool two = r + 1 < mg;
@@ -222,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
             // pixel row (n a multiple of 4 keeps it aligned and ng even)
             const uint16_t *px = (const uint16_t *)a;
             for (int j = 2 * threadIdx.x; j < Q; j += 2 * kBlock) {
-                double2 v0{0.0, 0.0}, v1{0.0, 0.0};
+                C v0{0, 0}, v1{0, 0};
                 if (j < ng) {
                     int s[2][2];
 #pragma unroll
@@ -236,8 +269,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
                             s[k][1] += (int)(q.y & 0xffffu) + (int)(q.y >> 16);
                         }
                     }
-                    v0 = double2{0.25 * (double)s[0][0], 0.25 * (double)s[1][0]};
-                    v1 = double2{0.25 * (double)s[0][1], 0.25 * (double)s[1][1]};
+                    const double c1 = two ? center : 0.0;
+                    v0 = C{(R)(0.25 * (double)s[0][0] - center), (R)(0.25 * (double)s[1][0] - c1)};
+                    v1 = C{(R)(0.25 * (double)s[0][1] - center), (R)(0.25 * (double)s[1][1] - c1)};
                 }
                 bufa[pr * Q + j] = v0;
                 if (j + 1 < Q) bufa[pr * Q + j + 1] = v1;
@@ -245,57 +279,62 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
             continue;
         }
         for (int j = threadIdx.x; j < Q; j += kBlock)
-            bufa[pr * Q + j] = j < ng ? double2{grid_at<SRC>(a, n, ng, r, j),
-                                                two ? grid_at<SRC>(a, n, ng, r + 1, j) : 0.0}
-                                      : double2{0.0, 0.0};
+            bufa[pr * Q + j] =
+                j < ng ? C{(R)(grid_at<SRC>(a, n, ng, r, j) - center),
+                           two ? (R)(grid_at<SRC>(a, n, ng, r + 1, j) - center) : (R)0}
+                       : C{0, 0};
     }
     __syncthreads();
-    const double2 *z = fft_lds<false>(bufa, bufb, np, pq, twq);
+    const C *z = fft_lds<false>(bufa, bufb, np, pq, tw);
     // Z = X + iY with X, Y the spectra of the real rows r, r+1:
     // X_k = (Z_k + conj Z_{-k})/2, Y_k = (Z_k - conj Z_{-k})/(2i)
-    double2 *out = s1 + (size_t)blockIdx.y * qh * mg;
+    C *out = s1 + (size_t)blockIdx.y * qh * mg;
     for (int idx = threadIdx.x; idx < np * qh; idx += kBlock) {
         const int k = idx / np, pr = idx - k * np;
-        const double2 zk = z[pr * Q + k], zc = z[pr * Q + (k == 0 ? 0 : Q - k)];
+        const C zk = z[pr * Q + k], zc = z[pr * Q + (k == 0 ? 0 : Q - k)];
         const int r = 2 * (pair0 + pr);
-        out[(size_t)k * mg + r] = double2{0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y)};
-        if (r + 1 < mg) out[(size_t)k * mg + r + 1] = double2{0.5 * (zk.y + zc.y), 0.5 * (zc.x - zk.x)};
+        out[(size_t)k * mg + r] = C{(R)0.5 * (zk.x + zc.x), (R)0.5 * (zk.y - zc.y)};
+        if (r + 1 < mg) out[(size_t)k * mg + r + 1] = C{(R)0.5 * (zk.y + zc.y), (R)0.5 * (zc.x - zk.x)};
     }
 }
 
 // Pass 2: columns.  Block (group of kb bins, frame).  SPEC: write the full
 // column transforms to spec[k][p] (the template).  Otherwise multiply by
 // conj(spec), inverse, keep s = -(w-1) .. w-1 into s2[frame][s+w-1][k].
-template <bool SPEC>
-__global__ __launch_bounds__(kBlock) void k_fft_cols(const double2 *__restrict__ s1, int mg,
-                                                     int qh, int kb, int w, FftPlan pp,
-                                                     const double2 *__restrict__ twp,
-                                                     double2 *__restrict__ spec,
-                                                     double2 *__restrict__ s2)
+template <bool SPEC, typename R>
+__global__ __launch_bounds__(kBlock) void k_fft_cols(const typename Cx<R>::T *__restrict__ s1,
+                                                     int mg, int qh, int kb, int w, FftPlan pp,
+                                                     const typename Cx<R>::T *__restrict__ twp,
+                                                     const typename Cx<R>::T *__restrict__ spec_in,
+                                                     typename Cx<R>::T *__restrict__ spec_out,
+                                                     typename Cx<R>::T *__restrict__ s2)
 {
-    extern __shared__ double2 lds[];
+    using C = typename Cx<R>::T;
+    extern __shared__ double lds_d[];
+    C *lds = (C *)lds_d;
     const int P = pp.n;
     const int k0 = blockIdx.x * kb, nk = min(kb, qh - k0);
-    const double2 *col = s1 + (size_t)blockIdx.y * qh * mg + (size_t)k0 * mg;
-    double2 *bufa = lds, *bufb = lds + (size_t)kb * P;
+    const C *col = s1 + (size_t)blockIdx.y * qh * mg + (size_t)k0 * mg;
+    C *tw = lds, *bufa = lds + P, *bufb = bufa + (size_t)kb * P;
+    load_twiddles(twp, P, tw);
     for (int kk = 0; kk < nk; ++kk)
         for (int p = threadIdx.x; p < P; p += kBlock)
-            bufa[kk * P + p] = p < mg ? col[(size_t)kk * mg + p] : double2{0.0, 0.0};
+            bufa[kk * P + p] = p < mg ? col[(size_t)kk * mg + p] : C{0, 0};
     __syncthreads();
-    double2 *v = fft_lds<false>(bufa, bufb, nk, pp, twp);
+    C *v = fft_lds<false>(bufa, bufb, nk, pp, tw);
     if (SPEC) {
         for (int kk = 0; kk < nk; ++kk)
             for (int p = threadIdx.x; p < P; p += kBlock)
-                spec[(size_t)(k0 + kk) * P + p] = v[kk * P + p];
+                spec_out[(size_t)(k0 + kk) * P + p] = v[kk * P + p];
         return;
     }
     for (int kk = 0; kk < nk; ++kk)
         for (int p = threadIdx.x; p < P; p += kBlock)
-            v[kk * P + p] = cmulc(v[kk * P + p], spec[(size_t)(k0 + kk) * P + p]);
+            v[kk * P + p] = cmulc(v[kk * P + p], spec_in[(size_t)(k0 + kk) * P + p]);
     __syncthreads();
-    double2 *u = fft_lds<true>(v, v == bufa ? bufb : bufa, nk, pp, twp);
+    C *u = fft_lds<true>(v, v == bufa ? bufb : bufa, nk, pp, tw);
     const int W = 2 * w - 1;
-    double2 *out = s2 + (size_t)blockIdx.y * W * qh;
+    C *out = s2 + (size_t)blockIdx.y * W * qh;
     for (int idx = threadIdx.x; idx < W * nk; idx += kBlock) {
         const int si = idx / nk, kk = idx - si * nk;
         const int s = si - (w - 1);
@@ -305,53 +344,62 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(const double2 *__restrict__
 
 // Pass 3: rows back.  Block (group of rp pairs of shift rows, frame).  Rows
 // si, si+1 of s2 are half spectra of real rows; Z = X + iY over the full
-// length Q, inverse; h[si][t] = Re z_t / PQ, h[si+1][t] = Im z_t / PQ.
-__global__ __launch_bounds__(kBlock) void k_fft_rows_back(const double2 *__restrict__ s2, int qh,
-                                                          int w, int rp, double scale,
+// length Q, inverse; h[si][t] = Re z_t / PQ, h[si+1][t] = Im z_t / PQ (the
+// scale applied in FP64).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fft_rows_back(const typename Cx<R>::T *__restrict__ s2,
+                                                          int qh, int w, int rp, double scale,
                                                           FftPlan pq,
-                                                          const double2 *__restrict__ twq,
+                                                          const typename Cx<R>::T *__restrict__ twq,
                                                           double *__restrict__ h)
 {
-    extern __shared__ double2 lds[];
+    using C = typename Cx<R>::T;
+    extern __shared__ double lds_d[];
+    C *lds = (C *)lds_d;
     const int Q = pq.n, W = 2 * w - 1;
     const int npairs = (W + 1) / 2;
     const int pair0 = blockIdx.x * rp, np = min(rp, npairs - pair0);
-    const double2 *src = s2 + (size_t)blockIdx.y * W * qh;
-    double2 *bufa = lds, *bufb = lds + (size_t)rp * Q;
+    const C *src = s2 + (size_t)blockIdx.y * W * qh;
+    C *tw = lds, *bufa = lds + Q, *bufb = bufa + (size_t)rp * Q;
+    load_twiddles(twq, Q, tw);
     for (int pr = 0; pr < np; ++pr) {
         const int si = 2 * (pair0 + pr);
-        const double2 *x = src + (size_t)si * qh;
-        const double2 *y = si + 1 < W ? x + qh : nullptr;
+        const C *x = src + (size_t)si * qh;
+        const C *y = si + 1 < W ? x + qh : nullptr;
         for (int k = threadIdx.x; k < Q; k += kBlock) {
             // X_k for k >= qh is conj X_{Q-k}
             const bool lo = k < qh;
             const int kk = lo ? k : Q - k;
-            double2 X = x[kk], Y = y ? y[kk] : double2{0.0, 0.0};
+            C X = x[kk], Y = y ? y[kk] : C{0, 0};
             if (!lo) {
                 X.y = -X.y;
                 Y.y = -Y.y;
             }
-            bufa[pr * Q + k] = double2{X.x - Y.y, X.y + Y.x};
+            bufa[pr * Q + k] = C{X.x - Y.y, X.y + Y.x};
         }
     }
     __syncthreads();
-    const double2 *z = fft_lds<true>(bufa, bufb, np, pq, twq);
+    const C *z = fft_lds<true>(bufa, bufb, np, pq, tw);
     double *out = h + (size_t)blockIdx.y * W * W;
     for (int idx = threadIdx.x; idx < np * W; idx += kBlock) {
         const int pr = idx / W, ti = idx - pr * W;
         const int t = ti - (w - 1);
-        const double2 v = z[pr * Q + (t < 0 ? t + Q : t)];
+        const C v = z[pr * Q + (t < 0 ? t + Q : t)];
         const int si = 2 * (pair0 + pr);
-        out[(size_t)si * W + ti] = v.x * scale;
-        if (si + 1 < W) out[(size_t)(si + 1) * W + ti] = v.y * scale;
+        out[(size_t)si * W + ti] = (double)v.x * scale;
+        if (si + 1 < W) out[(size_t)(si + 1) * W + ti] = (double)v.y * scale;
     }
 }
 
-int rows_per_block(int n)
+// Rows of length n a block holds in its two LDS buffers (elements of `esz`
+// bytes), and the LDS bytes that takes with the length-n twiddle table.
+int rows_per_block(int n, size_t esz = sizeof(double2))
 {
-    int r = (int)(kLdsBudget / (2 * (size_t)n * sizeof(double2)));
+    int r = (int)(kLdsBudget / (2 * (size_t)n * esz));
     return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
+
+size_t block_lds(int rows, int n, size_t esz) { return (2 * (size_t)rows + 1) * n * esz; }
 
 }  // namespace
 
@@ -453,43 +501,105 @@ bool fft_applicable(const Geom &g)
     return f.P <= kFftMaxLen && f.Q <= kFftMaxLen;
 }
 
-size_t fft_s1_bytes(const Geom &g) { return (size_t)fft_geom(g).qh * g.mg * sizeof(double2); }
+size_t fft_s1_bytes(const Geom &g, size_t esz)
+{
+    return (size_t)fft_geom(g).qh * g.mg * esz;
+}
 
-size_t fft_s2_bytes(const Geom &g) { return (size_t)g.W * fft_geom(g).qh * sizeof(double2); }
+size_t fft_s2_bytes(const Geom &g, size_t esz) { return (size_t)g.W * fft_geom(g).qh * esz; }
+
+namespace {
+
+// Twiddle tables and the template spectrum of precision R.
+template <typename R>
+struct FftTabs;
+template <>
+struct FftTabs<double> {
+    static const double2 *twp(const FftTmpl &f) { return f.twp; }
+    static const double2 *twq(const FftTmpl &f) { return f.twq; }
+    static const double2 *spec(const FftTmpl &f) { return f.spec; }
+    static double center(const FftTmpl &) { return 0.0; }
+};
+template <>
+struct FftTabs<float> {
+    static const float2 *twp(const FftTmpl &f) { return f.twp32; }
+    static const float2 *twq(const FftTmpl &f) { return f.twq32; }
+    static const float2 *spec(const FftTmpl &f) { return f.spec32; }
+    static double center(const FftTmpl &f) { return f.center; }
+};
+
+template <typename R>
+hipError_t rows_grid(const double *grid, int C, const Geom &g, const FftTmpl &ft,
+                     typename Cx<R>::T *s1, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const size_t esz = sizeof(typename Cx<R>::T);
+    const int rp = rows_per_block(ft.pq.n, esz);
+    const int npairs = (g.mg + 1) / 2;
+    k_fft_rows<0, R><<<dim3((npairs + rp - 1) / rp, C), kBlock, block_lds(rp, ft.pq.n, esz), st>>>(
+        grid, g.m, g.n, g.mg, g.ng, rp, ft.pq, FftTabs<R>::twq(ft), FftTabs<R>::center(ft), s1);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
+                   typename Cx<R>::T *s1, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.ds > 1) return hipErrorInvalidValue;
+    const size_t esz = sizeof(typename Cx<R>::T);
+    const int rp = rows_per_block(ft.pq.n, esz);
+    const int npairs = (g.mg + 1) / 2;
+    const size_t lds = block_lds(rp, ft.pq.n, esz);
+    const dim3 grid((npairs + rp - 1) / rp, C);
+    const bool u16 = g.dtype == MOCO_U16;
+    const auto *tw = FftTabs<R>::twq(ft);
+    const double c = FftTabs<R>::center(ft);
+    if (u16 && g.ds)
+        k_fft_rows<1, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+    else if (u16)
+        k_fft_rows<2, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+    else if (g.ds)
+        k_fft_rows<3, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+    else
+        k_fft_rows<4, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t corr(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
+                typename Cx<R>::T *s2, double *h, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    const size_t esz = sizeof(typename Cx<R>::T);
+    const int kb = rows_per_block(ft.pp.n, esz);
+    k_fft_cols<false, R><<<dim3((ft.qh + kb - 1) / kb, C), kBlock, block_lds(kb, ft.pp.n, esz), st>>>(
+        s1, g.mg, ft.qh, kb, g.w, ft.pp, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), nullptr, s2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rp = rows_per_block(ft.pq.n, esz);
+    const int npairs = (g.W + 1) / 2;
+    const double scale = 1.0 / ((double)ft.pp.n * (double)ft.pq.n);
+    k_fft_rows_back<R><<<dim3((npairs + rp - 1) / rp, C), kBlock, block_lds(rp, ft.pq.n, esz), st>>>(
+        s2, ft.qh, g.w, rp, scale, ft.pq, FftTabs<R>::twq(ft), h);
+    return hipGetLastError();
+}
+
+}  // namespace
 
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s1, hipStream_t st)
 {
-    clear_stale_error();
-    if (C == 0) return hipSuccess;
-    const int rp = rows_per_block(ft.pq.n);
-    const int npairs = (g.mg + 1) / 2;
-    const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
-    k_fft_rows<0><<<dim3((npairs + rp - 1) / rp, C), kBlock, lds, st>>>(
-        grid, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
-    return hipGetLastError();
+    return rows_grid<double>(grid, C, g, ft, s1, st);
 }
 
 hipError_t launch_fft_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
                               double2 *s1, hipStream_t st)
 {
-    clear_stale_error();
-    if (C == 0) return hipSuccess;
-    if (g.ds > 1) return hipErrorInvalidValue;
-    const int rp = rows_per_block(ft.pq.n);
-    const int npairs = (g.mg + 1) / 2;
-    const size_t lds = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
-    const dim3 grid((npairs + rp - 1) / rp, C);
-    const bool u16 = g.dtype == MOCO_U16;
-    if (u16 && g.ds)
-        k_fft_rows<1><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
-    else if (u16)
-        k_fft_rows<2><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
-    else if (g.ds)
-        k_fft_rows<3><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
-    else
-        k_fft_rows<4><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, ft.twq, s1);
-    return hipGetLastError();
+    return rows_px<double>(frames, C, g, ft, s1, st);
 }
 
 hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
@@ -497,30 +607,34 @@ hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, 
 {
     clear_stale_error();
     const int kb = rows_per_block(ft.pp.n);
-    const size_t lds = 2 * (size_t)kb * ft.pp.n * sizeof(double2);
-    k_fft_cols<true><<<dim3((ft.qh + kb - 1) / kb, 1), kBlock, lds, st>>>(
-        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, spec, nullptr);
+    k_fft_cols<true, double><<<dim3((ft.qh + kb - 1) / kb, 1), kBlock,
+                               block_lds(kb, ft.pp.n, sizeof(double2)), st>>>(
+        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, nullptr, spec, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s2, double *h, hipStream_t st)
 {
-    clear_stale_error();
-    if (C == 0) return hipSuccess;
-    const int kb = rows_per_block(ft.pp.n);
-    const size_t ldsc = 2 * (size_t)kb * ft.pp.n * sizeof(double2);
-    k_fft_cols<false><<<dim3((ft.qh + kb - 1) / kb, C), kBlock, ldsc, st>>>(
-        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, ft.spec, s2);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int rp = rows_per_block(ft.pq.n);
-    const int npairs = (g.W + 1) / 2;
-    const size_t ldsr = 2 * (size_t)rp * ft.pq.n * sizeof(double2);
-    const double scale = 1.0 / ((double)ft.pp.n * (double)ft.pq.n);
-    k_fft_rows_back<<<dim3((npairs + rp - 1) / rp, C), kBlock, ldsr, st>>>(
-        s2, ft.qh, g.w, rp, scale, ft.pq, ft.twq, h);
-    return hipGetLastError();
+    return corr<double>(s1, C, g, ft, s2, h, st);
+}
+
+hipError_t launch_fft32_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
+                             float2 *s1, hipStream_t st)
+{
+    return rows_grid<float>(grid, C, g, ft, s1, st);
+}
+
+hipError_t launch_fft32_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
+                                float2 *s1, hipStream_t st)
+{
+    return rows_px<float>(frames, C, g, ft, s1, st);
+}
+
+hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTmpl &ft,
+                             float2 *s2, double *h, hipStream_t st)
+{
+    return corr<float>(s1, C, g, ft, s2, h, st);
 }
 
 }  // namespace moco

@@ -123,7 +123,8 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 // the grid values are written as FP64 box means (raw values without
 // downsampling) to grid [frame][mg][ng], and the energy table as FP64 in
 // grid units to atab_d (the integer sums divided by 16 when downsampling: an
-// exact scaling, the same values a FP64 pass over the grid gives).
+// exact scaling, the same values a FP64 pass over the grid gives), of the
+// values less xc (in box-sum units; the grid written is not centred).
 template <bool DS, int kMaxCol4, int NW, bool GRID>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
@@ -135,7 +136,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                                                      long long *__restrict__ edge,
                                                      double *__restrict__ grid,
                                                      double *__restrict__ atab_d,
-                                                     const int32_t *__restrict__ only)
+                                                     const int32_t *__restrict__ only,
+                                                     int xc)
 {
     // GRID with `only`: frames whose only[f] is 0 are skipped (the whole block)
     if (GRID && only && !only[blockIdx.x]) return;
@@ -211,7 +213,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                     d0p |= (d0 & 255) << (8 * q);
                     d1p |= (d1 & 255) << (8 * q);
                 }
-                long long x2 = (long long)X * X;
+                // GRID: the energies of X - xc (the single-precision FFT form's
+                // centred grid; xc = 0 otherwise); the padding columns j >= ng
+                // (X = 0) lie outside the grid and add nothing
+                const long long xd = GRID ? (j < ng ? (long long)(X - xc) : 0LL) : (long long)X;
+                long long x2 = xd * xd;
                 rpart += x2;
                 col[c][q] += x2;
                 if ((top || bot) && j < ng) {
@@ -919,24 +925,24 @@ template <bool DS, int NW, bool GRID>
 void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int nc,
                     size_t lds, int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
                     long long *edge, double *grid, double *atab_d, const int32_t *only,
-                    hipStream_t st)
+                    hipStream_t st, int xc)
 {
     if (nc <= 1)
         k_prep_u16<DS, 1, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only);
+                                                             grid, atab_d, only, xc);
     else if (nc <= 2)
         k_prep_u16<DS, 2, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only);
+                                                             grid, atab_d, only, xc);
     else if (nc <= 4)
         k_prep_u16<DS, 4, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only);
+                                                             grid, atab_d, only, xc);
     else
         k_prep_u16<DS, 8, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
                                                              npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only);
+                                                             grid, atab_d, only, xc);
 }
 
 size_t prep_lds(const Geom &g, int npad, int nw)
@@ -948,7 +954,7 @@ size_t prep_lds(const Geom &g, int npad, int nw)
 template <bool DS, bool GRID>
 void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int8_t *limbs,
                  int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, double *grid,
-                 double *atab_d, const int32_t *only, hipStream_t st)
+                 double *atab_d, const int32_t *only, hipStream_t st, int xc = 0)
 {
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
@@ -956,10 +962,10 @@ void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbi
     // frame at a fraction of the device's bandwidth)
     if (C <= 128 && prep_lds(g, npad, 16) <= 64 * 1024)
         prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, 16), limbs, nlimb,
-                                     vmax, atab, edge, grid, atab_d, only, st);
+                                     vmax, atab, edge, grid, atab_d, only, st, xc);
     else
         prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, kWaves), limbs,
-                                         nlimb, vmax, atab, edge, grid, atab_d, only, st);
+                                         nlimb, vmax, atab, edge, grid, atab_d, only, st, xc);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
@@ -991,7 +997,7 @@ size_t prep_grid_edge_bytes(const Geom &g) { return (size_t)4 * (g.w - 1) * g.w 
 
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
                             double *atab, int32_t *vmax, long long *edge, hipStream_t st,
-                            const int32_t *only)
+                            const int32_t *only, int xc)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -999,10 +1005,10 @@ hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double
     const int npad = (g.ng + kStrip - 1) / kStrip * kStrip;
     if (g.ds)
         prep_launch<true, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
-                                grid, atab, only, st);
+                                grid, atab, only, st, xc);
     else
         prep_launch<false, true>(frames, C, g, npad, 8, nullptr, nullptr, vmax, nullptr, edge,
-                                 grid, atab, only, st);
+                                 grid, atab, only, st, xc);
     return hipGetLastError();
 }
 

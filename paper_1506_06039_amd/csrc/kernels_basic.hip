@@ -223,11 +223,15 @@ __device__ void block_excl_scan(const double *v, double *out, int n, double *wsu
 // INT32_MAX when pscale is 0.
 // The grid comes from src as grid_at<SRC> reads it (an FP64 grid, or the
 // frames' pixels).
+// Every grid value enters the sums less `center` (0 but in the single-precision
+// FFT form, whose correlation is of the centred grids); the pixel bound is of
+// the values themselves.
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src, int m, int n,
                                                    int mg, int ng, int w, bool flip,
                                                    double *__restrict__ atab,
-                                                   int32_t *__restrict__ pmax, double pscale)
+                                                   int32_t *__restrict__ pmax, double pscale,
+                                                   double center)
 {
     extern __shared__ double elds[];
     const int E = w - 1, W = 2 * w - 1;
@@ -245,9 +249,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
         double cs = 0.0, cm = 0.0;
 #pragma unroll 8
         for (int i = 0; i < mg; ++i) {
-            const double x = grid_at<SRC>(a, n, ng, i, j);
+            const double v = grid_at<SRC>(a, n, ng, i, j), x = v - center;
             cs = fma(x, x, cs);
-            cm = fmax(cm, x);
+            cm = fmax(cm, v);
         }
         tot += cs;
         mx = fmax(mx, cm);
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
         const int i = rr < E ? rr : mg - 1 - (rr - E);
         double rs = 0.0;
         for (int j = lane; j < ng; j += 64) {
-            const double x = grid_at<SRC>(a, n, ng, i, j);
+            const double x = grid_at<SRC>(a, n, ng, i, j) - center;
             rs = fma(x, x, rs);
         }
 #pragma unroll
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
             if (s > 0) {
                 const int row = bottom ? mg - s : s - 1;
                 for (int j = tid; j < E; j += kBlock) {
-                    const double x = grid_at<SRC>(a, n, ng, row, right ? ng - 1 - j : j);
+                    const double x = grid_at<SRC>(a, n, ng, row, right ? ng - 1 - j : j) - center;
                     cp[j] = fma(x, x, cp[j]);
                 }
             }
@@ -1215,7 +1219,7 @@ hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, 
 }
 
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
-                         int32_t *pmax, hipStream_t st)
+                         int32_t *pmax, hipStream_t st, double center)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1229,12 +1233,12 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
     k_energy<0><<<C, kBlock, lds, st>>>(coarse, g.m, g.n, g.mg, g.ng, g.w, flip, atab, pmax,
-                                        pscale);
+                                        pscale, center);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
-                            int32_t *pmax, hipStream_t st)
+                            int32_t *pmax, hipStream_t st, double center)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1249,16 +1253,16 @@ hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *at
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
     if (u16 && g.ds)
         k_energy<1><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale);
+                                            pscale, center);
     else if (u16)
         k_energy<2><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale);
+                                            pscale, center);
     else if (g.ds)
         k_energy<3><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale);
+                                            pscale, center);
     else
         k_energy<4><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale);
+                                            pscale, center);
     return hipGetLastError();
 }
 

@@ -56,13 +56,21 @@ struct FftGeom {
     int P, Q, qh;
 };
 
-// Template side of the FFT form (device memory owned by the template).
+// Template side of the FFT forms (device memory owned by the template).
 struct FftTmpl {
     FftPlan pp, pq;                 // column (length P) and row (length Q) plans
     int qh = 0;
     double2 *twp = nullptr;         // w_P^k = exp(-2 pi i k/P), k < P
     double2 *twq = nullptr;         // w_Q^k, k < Q
     double2 *spec = nullptr;        // [qh][P] 2-D transform of the zero-padded b'
+    // the single-precision form: grids centred on `center` (the template
+    // grid's mean, an integer for uint16 data) before the transforms
+    double center = 0.0;
+    float2 *twp32 = nullptr;        // the twiddle tables rounded to FP32
+    float2 *twq32 = nullptr;
+    float2 *spec32 = nullptr;       // [qh][P] transform of the zero-padded b' - center
+                                    // (computed in FP64, rounded)
+    double *btab32 = nullptr;       // [W][W] sum of (b' - center)^2 over D_{s,t}
 };
 
 // Resident, prepared template.  All pointers are device memory owned by it.
@@ -96,14 +104,15 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 // only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g, double *coarse,
                          hipStream_t st, const int32_t *only = nullptr);
-// atab[frame][W][W]: the frame's energies over D at (s,t) ([-s][-t] when flip);
-// pmax[frame] (may be null): a pixel bound for the x2 step (uint16), else INT32_MAX
+// atab[frame][W][W]: the frame's energies over D at (s,t) ([-s][-t] when flip),
+// of the grid values less `center`; pmax[frame] (may be null): a pixel bound
+// for the x2 step (uint16), else INT32_MAX
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
-                         int32_t *pmax, hipStream_t st);
+                         int32_t *pmax, hipStream_t st, double center = 0.0);
 // the same (not flipped) from the frames' pixels, forming the grid values as
 // they are read (at most one 2x2 level): the values launch_coarse would write
 hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
-                            int32_t *pmax, hipStream_t st);
+                            int32_t *pmax, hipStream_t st, double center = 0.0);
 // only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st, const int32_t *only = nullptr);
@@ -160,9 +169,11 @@ hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, 
 // only[f] is 0 are skipped.
 bool prep_grid_applicable(const Geom &g);
 size_t prep_grid_edge_bytes(const Geom &g);
+// xc: the energies are of X - xc (X the integer grid values: box sums or
+// counts), for the single-precision FFT form's centred grids; 0 otherwise.
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
                             double *atab, int32_t *vmax, long long *edge, hipStream_t st,
-                            const int32_t *only = nullptr);
+                            const int32_t *only = nullptr, int xc = 0);
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st);
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
@@ -177,8 +188,9 @@ bool fft_applicable(const Geom &g);
 // coefficients of the certificate: |h^ - h| <= kf sqrt(m'n' Sa Sb), energy
 // errors <= ke Sa (Sa, Sb: the grids' sums of squares)
 void fft_error_coefs(const Geom &g, const FftTmpl &ft, double *kf, double *ke);
-size_t fft_s1_bytes(const Geom &g);   // per frame: [qh][mg] complex
-size_t fft_s2_bytes(const Geom &g);   // per frame: [W][qh] complex
+// per frame: [qh][mg] and [W][qh] complex elements of esz bytes
+size_t fft_s1_bytes(const Geom &g, size_t esz = sizeof(double2));
+size_t fft_s2_bytes(const Geom &g, size_t esz = sizeof(double2));
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s1, hipStream_t st);
 // the same from the frames' pixels (at most one 2x2 level), forming the
@@ -189,6 +201,14 @@ hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, 
                            hipStream_t st);
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
                            double2 *s2, double *h, hipStream_t st);
+// The single-precision form: the same passes in FP32 on the grids less
+// ft.center (ft.twp32, twq32, spec32); h (of the centred grids) in FP64.
+hipError_t launch_fft32_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
+                             float2 *s1, hipStream_t st);
+hipError_t launch_fft32_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
+                                float2 *s1, hipStream_t st);
+hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTmpl &ft,
+                             float2 *s2, double *h, hipStream_t st);
 
 // ---- the corrected stack and its mean image (apply.hip) ---------------
 // frames per chunk of the mean's partial sums (0: one chunk of [m][n] FP64

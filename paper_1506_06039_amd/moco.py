@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libmoco.so")
 
 MOCO_OK, MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE, MOCO_EBUSY, MOCO_ECANCELED = 0, -1, -2, -3, -4, -5
 MOCO_U16, MOCO_F32 = 1, 2
-FORMS = {"auto": 0, "fft": 1, "fft_cert": 2, "fp64": 3, "int8": 4}
+FORMS = {"auto": 0, "fft": 1, "fft_cert": 2, "fp64": 3, "int8": 4, "fft32": 5}
 
 
 class MocoError(RuntimeError):
