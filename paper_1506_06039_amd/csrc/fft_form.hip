@@ -401,6 +401,331 @@ int rows_per_block(int n, size_t esz = sizeof(double2))
 
 size_t block_lds(int rows, int n, size_t esz) { return (2 * (size_t)rows + 1) * n * esz; }
 
+// ---------------------------------------------------------------------------
+// Wave-level transforms for the lengths the workloads use (compile-time
+// plans).  A transform of length N is owned by T consecutive lanes of one wave
+// and lives in an LDS buffer of its own; each radix pass loads every input of
+// the lane's butterflies, transforms them in registers and stores the outputs
+// back into the same buffer.  The lanes of a wave issue each instruction
+// together and LDS operations of a wave complete in order, so a pass's loads
+// (all lanes) precede its stores: passes need no barrier, only a compiler
+// fence.  The block synchronises twice: after staging the inputs and before
+// the outputs leave, both block-cooperative and coalesced.
+
+// The same radices as fft_plan, applied in the same order.
+struct WPlan {
+    int npass;
+    int radix[kFftMaxPass];
+    int ns[kFftMaxPass];
+};
+
+constexpr WPlan make_wplan(int n)
+{
+    WPlan p{};
+    int c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int x = n;
+    while (x % 8 == 0) x /= 8, ++c[8];
+    while (x % 4 == 0) x /= 4, ++c[4];
+    while (x % 2 == 0) x /= 2, ++c[2];
+    while (x % 3 == 0) x /= 3, ++c[3];
+    while (x % 5 == 0) x /= 5, ++c[5];
+    const int order[5] = {2, 3, 4, 5, 8};
+    int ns = 1;
+    for (int o = 0; o < 5; ++o)
+        for (int k = 0; k < c[order[o]]; ++k) {
+            p.radix[p.npass] = order[o];
+            p.ns[p.npass] = ns;
+            ns *= order[o];
+            ++p.npass;
+        }
+    return p;
+}
+
+template <int N>
+struct WPlanOf {
+    static constexpr WPlan pl = make_wplan(N);
+};
+
+// Pass P and the ones after it of a length-N transform in `buf`; tl: the
+// lane's index among the transform's T lanes; tw: the length-N twiddle table.
+template <typename C, int N, int T, bool INV, int P>
+struct WPass {
+    __device__ static void run(C *buf, const C *tw, int tl)
+    {
+        constexpr WPlan pl = WPlanOf<N>::pl;
+        if constexpr (P < pl.npass) {
+            constexpr int Rr = pl.radix[P], Ns = pl.ns[P];
+            constexpr int NR = N / Rr, NB = (NR + T - 1) / T, stw = N / (Ns * Rr);
+            C v[NB][Rr];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = tl + T * b;
+                if (NR % T == 0 || j < NR) {
+#pragma unroll
+                    for (int r = 0; r < Rr; ++r) v[b][r] = buf[j + r * NR];
+                }
+            }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = tl + T * b;
+                if (NR % T == 0 || j < NR) {
+                    const int jm = j % Ns, jq = j / Ns;
+#pragma unroll
+                    for (int r = 1; r < Rr; ++r) {
+                        C t = tw[r * jm * stw];
+                        if (INV) t.y = -t.y;
+                        v[b][r] = cmul(v[b][r], t);
+                    }
+                    Dft<Rr, INV, C>::run(v[b]);
+                    C *dst = buf + jq * Ns * Rr + jm;
+#pragma unroll
+                    for (int r = 0; r < Rr; ++r) dst[r * Ns] = v[b][r];
+                }
+            }
+            asm volatile("" ::: "memory");
+            WPass<C, N, T, INV, P + 1>::run(buf, tw, tl);
+        }
+    }
+};
+
+constexpr int kWaveBlock = 256;           // four waves
+constexpr int kWPad = 0;                  // elements between transform buffers
+
+template <int N, int T>
+struct WGeom {
+    static constexpr int per_wave = 64 / T;
+    static constexpr int per_block = per_wave * (kWaveBlock / 64);
+    static constexpr int stride = N + kWPad;
+};
+
+// Rows: packed pairs of real grid rows, as k_fft_rows.
+template <int SRC, typename R, int Q, int T>
+__global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ src, int m, int n,
+                                                      int mg, int ng,
+                                                      const typename Cx<R>::T *__restrict__ twq,
+                                                      double center,
+                                                      typename Cx<R>::T *__restrict__ s1)
+{
+    using C = typename Cx<R>::T;
+    using G = WGeom<Q, T>;
+    extern __shared__ double lds_d[];
+    C *tw = (C *)lds_d, *bufs = tw + Q;
+    constexpr int qh = Q / 2 + 1;
+    const int npairs = (mg + 1) / 2;
+    const int pair0 = blockIdx.x * G::per_block, np = min(G::per_block, npairs - pair0);
+    const void *a = grid_frame<SRC>(src, blockIdx.y, m, n, mg, ng);
+    load_twiddles(twq, Q, tw);
+    for (int idx = threadIdx.x; idx < np * Q; idx += kWaveBlock) {
+        const int pr = idx / Q, j = idx - pr * Q;
+        const int r = 2 * (pair0 + pr);
+        const bool two = r + 1 < mg;
+        C v{0, 0};
+        if (j < ng) {
+            v.x = (R)(grid_at<SRC>(a, n, ng, r, j) - center);
+            if (two) v.y = (R)(grid_at<SRC>(a, n, ng, r + 1, j) - center);
+        }
+        bufs[pr * G::stride + j] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % 64, tr = (threadIdx.x / 64) * G::per_wave + lane / T;
+    if (tr < np) WPass<C, Q, T, false, 0>::run(bufs + tr * G::stride, tw, lane % T);
+    __syncthreads();
+    C *out = s1 + (size_t)blockIdx.y * qh * mg;
+    for (int idx = threadIdx.x; idx < np * qh; idx += kWaveBlock) {
+        const int k = idx / np, pr = idx - k * np;
+        const C *z = bufs + pr * G::stride;
+        const C zk = z[k], zc = z[k == 0 ? 0 : Q - k];
+        const int r = 2 * (pair0 + pr);
+        out[(size_t)k * mg + r] = C{(R)0.5 * (zk.x + zc.x), (R)0.5 * (zk.y - zc.y)};
+        if (r + 1 < mg) out[(size_t)k * mg + r + 1] = C{(R)0.5 * (zk.y + zc.y), (R)0.5 * (zc.x - zk.x)};
+    }
+}
+
+// Columns: forward, times conj(spec), inverse, the 2w-1 outputs kept, as
+// k_fft_cols<false>.
+template <typename R, int P, int T>
+__global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *__restrict__ s1,
+                                                      int mg, int qh, int w,
+                                                      const typename Cx<R>::T *__restrict__ twp,
+                                                      const typename Cx<R>::T *__restrict__ spec,
+                                                      typename Cx<R>::T *__restrict__ s2)
+{
+    using C = typename Cx<R>::T;
+    using G = WGeom<P, T>;
+    extern __shared__ double lds_d[];
+    C *tw = (C *)lds_d, *bufs = tw + P;
+    const int k0 = blockIdx.x * G::per_block, nk = min(G::per_block, qh - k0);
+    const C *col = s1 + (size_t)blockIdx.y * qh * mg + (size_t)k0 * mg;
+    load_twiddles(twp, P, tw);
+    for (int idx = threadIdx.x; idx < nk * P; idx += kWaveBlock) {
+        const int kk = idx / P, p = idx - kk * P;
+        bufs[kk * G::stride + p] = p < mg ? col[(size_t)kk * mg + p] : C{0, 0};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % 64, tr = (threadIdx.x / 64) * G::per_wave + lane / T;
+    const int tl = lane % T;
+    if (tr < nk) {
+        C *buf = bufs + tr * G::stride;
+        WPass<C, P, T, false, 0>::run(buf, tw, tl);
+        const C *sp = spec + (size_t)(k0 + tr) * P;
+#pragma unroll 4
+        for (int p = tl; p < P; p += T) buf[p] = cmulc(buf[p], sp[p]);
+        asm volatile("" ::: "memory");
+        WPass<C, P, T, true, 0>::run(buf, tw, tl);
+    }
+    __syncthreads();
+    const int W = 2 * w - 1;
+    C *out = s2 + (size_t)blockIdx.y * W * qh;
+    for (int idx = threadIdx.x; idx < W * nk; idx += kWaveBlock) {
+        const int si = idx / nk, kk = idx - si * nk;
+        const int s = si - (w - 1);
+        out[(size_t)si * qh + k0 + kk] = bufs[kk * G::stride + (s < 0 ? s + P : s)];
+    }
+}
+
+// Rows back: packed pairs of shift rows, as k_fft_rows_back.
+template <typename R, int Q, int T>
+__global__ __launch_bounds__(kWaveBlock) void k_wback(const typename Cx<R>::T *__restrict__ s2,
+                                                      int qh, int w, double scale,
+                                                      const typename Cx<R>::T *__restrict__ twq,
+                                                      double *__restrict__ h)
+{
+    using C = typename Cx<R>::T;
+    using G = WGeom<Q, T>;
+    extern __shared__ double lds_d[];
+    C *tw = (C *)lds_d, *bufs = tw + Q;
+    const int W = 2 * w - 1;
+    const int npairs = (W + 1) / 2;
+    const int pair0 = blockIdx.x * G::per_block, np = min(G::per_block, npairs - pair0);
+    const C *src = s2 + (size_t)blockIdx.y * W * qh;
+    load_twiddles(twq, Q, tw);
+    for (int idx = threadIdx.x; idx < np * Q; idx += kWaveBlock) {
+        const int pr = idx / Q, k = idx - pr * Q;
+        const int si = 2 * (pair0 + pr);
+        const bool lo = k < qh;
+        const int kk = lo ? k : Q - k;
+        C X = src[(size_t)si * qh + kk];
+        C Y = si + 1 < W ? src[(size_t)(si + 1) * qh + kk] : C{0, 0};
+        if (!lo) {
+            X.y = -X.y;
+            Y.y = -Y.y;
+        }
+        bufs[pr * G::stride + k] = C{X.x - Y.y, X.y + Y.x};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % 64, tr = (threadIdx.x / 64) * G::per_wave + lane / T;
+    if (tr < np) WPass<C, Q, T, true, 0>::run(bufs + tr * G::stride, tw, lane % T);
+    __syncthreads();
+    double *out = h + (size_t)blockIdx.y * W * W;
+    for (int idx = threadIdx.x; idx < np * W; idx += kWaveBlock) {
+        const int pr = idx / W, ti = idx - pr * W;
+        const int t = ti - (w - 1);
+        const C v = bufs[pr * G::stride + (t < 0 ? t + Q : t)];
+        const int si = 2 * (pair0 + pr);
+        out[(size_t)si * W + ti] = (double)v.x * scale;
+        if (si + 1 < W) out[(size_t)(si + 1) * W + ti] = (double)v.y * scale;
+    }
+}
+
+// Lanes per transform: a whole wave.  Measured on MI355X at 288 and 320 points
+// against 16 and 32 lanes (several transforms per wave, more registers per
+// lane, fewer waves per SIMD) and against the block-level kernels: 64 lanes
+// were fastest in both precisions (the 512x512 stack's three transform
+// kernels: FP32 1.02 ms against 1.38 for the block kernels, FP64 1.41 against
+// 2.18, per 2000 frames), with or without padding between the buffers.
+template <typename R>
+constexpr int wave_lanes() { return 64; }
+
+template <typename R, int N>
+size_t wave_lds()
+{
+    using G = WGeom<N, wave_lanes<R>()>;
+    return ((size_t)N + (size_t)G::per_block * G::stride) * sizeof(typename Cx<R>::T);
+}
+
+// The lengths with a wave-level kernel; others take the block-level kernels.
+#define MOCO_WAVE_LENGTHS(X) X(144) X(160) X(180) X(240) X(256) X(270) X(288) X(300) X(320) X(360)
+
+bool wave_length(int n)
+{
+#define MOCO_WL_CASE(L) case L:
+    switch (n) {
+        MOCO_WAVE_LENGTHS(MOCO_WL_CASE)
+        return true;
+    default:
+        return false;
+    }
+#undef MOCO_WL_CASE
+}
+
+template <typename R, int SRC, int Q>
+void wrows_launch(const void *src, int C, const Geom &g, const typename Cx<R>::T *twq,
+                  double center, typename Cx<R>::T *s1, hipStream_t st)
+{
+    constexpr int T = wave_lanes<R>();
+    const int npairs = (g.mg + 1) / 2;
+    const int pb = WGeom<Q, T>::per_block;
+    k_wrows<SRC, R, Q, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, Q>(), st>>>(
+        src, g.m, g.n, g.mg, g.ng, twq, center, s1);
+}
+
+template <typename R, int SRC>
+bool wrows(const void *src, int C, const Geom &g, const typename Cx<R>::T *twq, double center,
+           typename Cx<R>::T *s1, hipStream_t st, int Q)
+{
+#define MOCO_WL_ROWS(L) \
+    case L: wrows_launch<R, SRC, L>(src, C, g, twq, center, s1, st); return true;
+    switch (Q) {
+        MOCO_WAVE_LENGTHS(MOCO_WL_ROWS)
+    default:
+        return false;
+    }
+#undef MOCO_WL_ROWS
+}
+
+template <typename R>
+bool wcols(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
+           const typename Cx<R>::T *twp, const typename Cx<R>::T *spec, typename Cx<R>::T *s2,
+           hipStream_t st)
+{
+    constexpr int T = wave_lanes<R>();
+#define MOCO_WL_COLS(L)                                                                       \
+    case L: {                                                                                 \
+        const int pb = WGeom<L, T>::per_block;                                                \
+        k_wcols<R, L, T><<<dim3((ft.qh + pb - 1) / pb, C), kWaveBlock, wave_lds<R, L>(), st>>>( \
+            s1, g.mg, ft.qh, g.w, twp, spec, s2);                                             \
+        return true;                                                                          \
+    }
+    switch (ft.pp.n) {
+        MOCO_WAVE_LENGTHS(MOCO_WL_COLS)
+    default:
+        return false;
+    }
+#undef MOCO_WL_COLS
+}
+
+template <typename R>
+bool wback(const typename Cx<R>::T *s2, int C, const Geom &g, const FftTmpl &ft,
+           const typename Cx<R>::T *twq, double scale, double *h, hipStream_t st)
+{
+    constexpr int T = wave_lanes<R>();
+    const int npairs = (g.W + 1) / 2;
+#define MOCO_WL_BACK(L)                                                                         \
+    case L: {                                                                                   \
+        const int pb = WGeom<L, T>::per_block;                                                  \
+        k_wback<R, L, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, L>(), st>>>( \
+            s2, ft.qh, g.w, scale, twq, h);                                                     \
+        return true;                                                                            \
+    }
+    switch (ft.pq.n) {
+        MOCO_WAVE_LENGTHS(MOCO_WL_BACK)
+    default:
+        return false;
+    }
+#undef MOCO_WL_BACK
+}
+
 }  // namespace
 
 // ---- host side ------------------------------------------------------------
@@ -508,6 +833,10 @@ size_t fft_s1_bytes(const Geom &g, size_t esz)
 
 size_t fft_s2_bytes(const Geom &g, size_t esz) { return (size_t)g.W * fft_geom(g).qh * esz; }
 
+// The wave-level kernels where a length has one (on by default; the
+// block-level kernels otherwise).
+bool g_wave_fft = true;
+
 namespace {
 
 // Twiddle tables and the template spectrum of precision R.
@@ -557,6 +886,18 @@ hipError_t rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
     const bool u16 = g.dtype == MOCO_U16;
     const auto *tw = FftTabs<R>::twq(ft);
     const double c = FftTabs<R>::center(ft);
+    if (g_wave_fft) {
+        bool ok = false;
+        if (u16 && g.ds)
+            ok = wrows<R, 1>(frames, C, g, tw, c, s1, st, ft.pq.n);
+        else if (u16)
+            ok = wrows<R, 2>(frames, C, g, tw, c, s1, st, ft.pq.n);
+        else if (g.ds)
+            ok = wrows<R, 3>(frames, C, g, tw, c, s1, st, ft.pq.n);
+        else
+            ok = wrows<R, 4>(frames, C, g, tw, c, s1, st, ft.pq.n);
+        if (ok) return hipGetLastError();
+    }
     if (u16 && g.ds)
         k_fft_rows<1, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
     else if (u16)
@@ -575,16 +916,24 @@ hipError_t corr(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl
     clear_stale_error();
     if (C == 0) return hipSuccess;
     const size_t esz = sizeof(typename Cx<R>::T);
-    const int kb = rows_per_block(ft.pp.n, esz);
-    k_fft_cols<false, R><<<dim3((ft.qh + kb - 1) / kb, C), kBlock, block_lds(kb, ft.pp.n, esz), st>>>(
-        s1, g.mg, ft.qh, kb, g.w, ft.pp, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), nullptr, s2);
+    if (!g_wave_fft ||
+        !wcols<R>(s1, C, g, ft, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), s2, st)) {
+        const int kb = rows_per_block(ft.pp.n, esz);
+        k_fft_cols<false, R><<<dim3((ft.qh + kb - 1) / kb, C), kBlock,
+                               block_lds(kb, ft.pp.n, esz), st>>>(
+            s1, g.mg, ft.qh, kb, g.w, ft.pp, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), nullptr,
+            s2);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int rp = rows_per_block(ft.pq.n, esz);
-    const int npairs = (g.W + 1) / 2;
     const double scale = 1.0 / ((double)ft.pp.n * (double)ft.pq.n);
-    k_fft_rows_back<R><<<dim3((npairs + rp - 1) / rp, C), kBlock, block_lds(rp, ft.pq.n, esz), st>>>(
-        s2, ft.qh, g.w, rp, scale, ft.pq, FftTabs<R>::twq(ft), h);
+    if (!g_wave_fft || !wback<R>(s2, C, g, ft, FftTabs<R>::twq(ft), scale, h, st)) {
+        const int rp = rows_per_block(ft.pq.n, esz);
+        const int npairs = (g.W + 1) / 2;
+        k_fft_rows_back<R><<<dim3((npairs + rp - 1) / rp, C), kBlock,
+                             block_lds(rp, ft.pq.n, esz), st>>>(
+            s2, ft.qh, g.w, rp, scale, ft.pq, FftTabs<R>::twq(ft), h);
+    }
     return hipGetLastError();
 }
 
