@@ -230,6 +230,13 @@ size_t refine_steps_partial_bytes(const moco::Geom &g)
     return b;
 }
 
+// Per-frame scratch of the energy kernels: the uint16 prep kernel's integer
+// border tables (0 where it does not apply).
+size_t energy_scratch_bytes(const moco::Geom &g)
+{
+    return moco::prep_grid_applicable(g) ? moco::prep_grid_edge_bytes(g) : 0;
+}
+
 // Per-frame scratch of the FP64 exact form.
 struct ExactLayout {
     size_t coarse, inter, atab, h, cst, pm, edge, part, total_per_frame;
@@ -244,7 +251,7 @@ ExactLayout exact_layout(const moco::Geom &g)
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
-    L.edge = moco::prep_grid_applicable(g) ? align_up(moco::prep_grid_edge_bytes(g), 256) : 0;
+    L.edge = align_up(energy_scratch_bytes(g), 256);
     L.part = align_up(refine_steps_partial_bytes(g), 8);
     L.total_per_frame = L.coarse + L.inter + L.atab + L.h + L.cst + L.pm + L.edge + L.part;
     return L;
@@ -693,7 +700,7 @@ FftLayout fft_layout(const moco::Geom &g, bool fp32 = false)
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
     L.flag = sizeof(int32_t);
-    L.edge = moco::prep_grid_applicable(g) ? align_up(moco::prep_grid_edge_bytes(g), 256) : 0;
+    L.edge = align_up(energy_scratch_bytes(g), 256);
     L.part = align_up(refine_steps_partial_bytes(g), 8);
     L.total_per_frame = L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.flag +
                         L.edge + L.part;

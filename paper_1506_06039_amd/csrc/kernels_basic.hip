@@ -323,6 +323,171 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
+// k_energy_rows: the same table from one pass over the grid's rows, for grids
+// of at most 2048 columns and w <= 128 (four waves per frame; a wave takes
+// every fourth row, a lane four columns of each 256-column chunk).  Row
+// energies come from fixed-order wave sums and each lane keeps its columns'
+// energies; then the cuts (rows from the top and bottom, columns from the
+// left and right) are made cumulative, and each wave writes one quadrant of
+// the table: for s = 1..w-1 it reads the s-th border row's corner values
+// again (each lane one or two of the first or last w-1 columns), takes their
+// prefix sums over the columns with a wave scan, adds them to its running
+// corner sums, and writes row s of the quadrant.  Every sum runs in a fixed
+// order, so results are reproducible; with uint16 grids every partial sum is
+// exact, as in k_energy.
+constexpr int kErWaves = 4;
+constexpr int kErMaxChunks = 8;   // 8 x 256 grid columns
+
+// inclusive prefix sum over the 64 lanes of a wave (fixed order)
+__device__ inline double wave_incl_scan(double v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+template <int SRC, int NCH>
+__global__ __launch_bounds__(kErWaves * 64) void k_energy_rows(
+    const void *__restrict__ src, int m, int n, int mg, int ng, int w, double *__restrict__ atab,
+    int32_t *__restrict__ pmax, double pscale, double center)
+{
+    const int E = w - 1, W = 2 * w - 1, we1 = E > 0 ? E : 1;
+    // LDS: rT[w] | rB[w] | cL[w] | cR[w] | cpart[NW][2][we1] | wtot[NW] | wmax[NW]
+    extern __shared__ double erl[];
+    double *rT = erl, *rB = rT + w, *cL = rB + w, *cR = cL + w;
+    double *cpart = cR + w, *wtot = cpart + kErWaves * 2 * we1, *wmax = wtot + kErWaves;
+    const int frame = blockIdx.x, wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const void *a = grid_frame<SRC>(src, frame, m, n, mg, ng);
+    auto sq = [&](int i, int j) {
+        const double x = grid_at<SRC>(a, n, ng, i, j) - center;
+        return x * x;
+    };
+
+    double col[NCH][4];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) col[c][q] = 0.0;
+    double my_tot = 0.0, my_max = 0.0;
+    for (int i = wave; i < mg; i += kErWaves) {
+        double rpart = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = 4 * (lane + 64 * c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + q;
+                double x2 = 0.0;
+                if (j < ng) {
+                    const double v = grid_at<SRC>(a, n, ng, i, j), x = v - center;
+                    my_max = fmax(my_max, v);
+                    x2 = x * x;
+                }
+                rpart += x2;
+                col[c][q] += x2;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) rpart += __shfl_xor(rpart, off);
+        my_tot += rpart;   // the same in every lane of the wave
+        if (lane == 0) {
+            if (i < E) rT[i] = rpart;
+            if (i >= mg - E) rB[mg - 1 - i] = rpart;
+        }
+    }
+    // per-wave partials: the border columns' energies, the total, the maximum
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * (lane + 64 * c) + q;
+            if (j < ng && j < E) cpart[(size_t)wave * 2 * we1 + j] = col[c][q];
+            if (j < ng && j >= ng - E) cpart[(size_t)wave * 2 * we1 + we1 + (ng - 1 - j)] = col[c][q];
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) my_max = fmax(my_max, __shfl_xor(my_max, off));
+    if (lane == 0) {
+        wtot[wave] = my_tot;
+        wmax[wave] = my_max;
+    }
+    __syncthreads();
+    // cumulative cuts: rows from the top / bottom, columns from the left / right
+    if (threadIdx.x == 0 || threadIdx.x == 64) {
+        double *cut = threadIdx.x == 0 ? rT : rB;
+        double acc = 0.0;
+        for (int s = 0; s < w; ++s) {
+            const double v = s < E ? cut[s] : 0.0;
+            cut[s] = acc;
+            acc += v;
+        }
+    } else if (threadIdx.x == 128 || threadIdx.x == 192) {
+        const int side = threadIdx.x == 128 ? 0 : 1;
+        double *cut = side ? cR : cL;
+        double acc = 0.0;
+        for (int s = 0; s < w; ++s) {
+            cut[s] = acc;
+            if (s < E) {
+                double ce = 0.0;
+                for (int v = 0; v < kErWaves; ++v) ce += cpart[(size_t)v * 2 * we1 + side * we1 + s];
+                acc += ce;
+            }
+        }
+    }
+    __syncthreads();
+    double Etot = 0.0, mx = 0.0;
+    for (int v = 0; v < kErWaves; ++v) {
+        Etot += wtot[v];
+        mx = fmax(mx, wmax[v]);
+    }
+    if (pmax && threadIdx.x == 0) {
+        const double b = ceil(pscale * mx);
+        pmax[frame] = (pscale > 0.0 && b < 2147483647.0) ? (int32_t)b : INT32_MAX;
+    }
+    double *A = atab + (size_t)frame * W * W;
+    // the row s = 0 and the column t = 0: no corner
+    for (int tt = threadIdx.x; tt < W; tt += blockDim.x) {
+        const int t = tt - E, at = t < 0 ? -t : t;
+        A[(size_t)E * W + tt] = Etot - (t > 0 ? cL[at] : (t < 0 ? cR[at] : 0.0));
+        if (tt != E) {
+            const int si = tt, sv = si - E, as = sv < 0 ? -sv : sv;
+            A[(size_t)si * W + E] = Etot - (sv > 0 ? rT[as] : rB[as]);
+        }
+    }
+    // quadrant (side, lr) of wave side * 2 + lr: side 0 s > 0 (rows cut at the
+    // top), 1 s < 0 (bottom); lr 0 t > 0 (columns cut at the left), 1 t < 0
+    // (right).  Lane l holds column offsets l and l + 64 of the band.
+    const int side = wave >> 1, lr = wave & 1;
+    const double *rx = side ? rB : rT, *cx = lr ? cR : cL;
+    double acc0 = 0.0, acc1 = 0.0;
+    // unrolled so that several band rows' loads are in flight at once
+#pragma unroll 8
+    for (int s = 1; s < w; ++s) {
+        const int i = side ? mg - s : s - 1;
+        // squares of the band row at column offsets 0..E-1 from the cut edge
+        const int o0 = lane, o1 = lane + 64;
+        double v0 = o0 < E ? sq(i, lr ? ng - 1 - o0 : o0) : 0.0;
+        double v1 = o1 < E ? sq(i, lr ? ng - 1 - o1 : o1) : 0.0;
+        // prefix over offsets: corner(s, t) adds the sums over offsets < |t|
+        const double p0 = wave_incl_scan(v0, lane);
+        const double p1 = wave_incl_scan(v1, lane) + __shfl(p0, 63);
+        acc0 += p0;   // corner sums for |t| = lane + 1
+        acc1 += p1;   // and |t| = lane + 65
+        const double base = Etot - rx[s];
+        const int si = side ? E - s : E + s;
+        for (int k = 0; k < 2; ++k) {
+            const int at = lane + 1 + 64 * k;
+            if (at <= E) {
+                const int tt = lr ? E - at : E + at;
+                A[(size_t)si * W + tt] = (base - cx[at]) + (k ? acc1 : acc0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Direct FP64 correlation.  Block (frame, s-block): lanes_per_s threads per
 // shift row s, each owning TB consecutive t; a ring of s_per_blk zero-padded
 // frame rows sits in LDS and advances by one row per template row i, so that
@@ -1218,6 +1383,34 @@ hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, 
     return hipGetLastError();
 }
 
+bool energy_rows_applicable(const Geom &g)
+{
+    return g.ng <= 256 * kErMaxChunks && g.w <= 128;
+}
+
+static size_t energy_rows_lds(const Geom &g)
+{
+    const int we1 = g.w > 1 ? g.w - 1 : 1;
+    return ((size_t)kErWaves * 2 * we1 + 4 * (size_t)g.w + 2 * kErWaves) * sizeof(double);
+}
+
+template <int SRC>
+static void energy_rows_launch(const void *src, int C, const Geom &g, double *atab, int32_t *pmax,
+                               double pscale, double center, hipStream_t st)
+{
+    const int nch = (g.ng + 255) / 256;
+    const size_t lds = energy_rows_lds(g);
+    const dim3 grid(C), blk(kErWaves * 64);
+    if (nch <= 1)
+        k_energy_rows<SRC, 1><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+    else if (nch <= 2)
+        k_energy_rows<SRC, 2><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+    else if (nch <= 4)
+        k_energy_rows<SRC, 4><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+    else
+        k_energy_rows<SRC, 8><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+}
+
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
                          int32_t *pmax, hipStream_t st, double center)
 {
@@ -1229,6 +1422,10 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
     if (g.dtype == MOCO_U16) {
         const int b = 1 << g.ds;   // a level-L grid value is the mean of a b x b block
         if (g.m % b == 0 && g.n % b == 0) pscale = (double)b * b;
+    }
+    if (!flip && energy_rows_applicable(g)) {
+        energy_rows_launch<0>(coarse, C, g, atab, pmax, pscale, center, st);
+        return hipGetLastError();
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
@@ -1248,6 +1445,17 @@ hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *at
     if (u16) {
         const int b = 1 << g.ds;
         if (g.m % b == 0 && g.n % b == 0) pscale = (double)b * b;
+    }
+    if (energy_rows_applicable(g)) {
+        if (u16 && g.ds)
+            energy_rows_launch<1>(frames, C, g, atab, pmax, pscale, center, st);
+        else if (u16)
+            energy_rows_launch<2>(frames, C, g, atab, pmax, pscale, center, st);
+        else if (g.ds)
+            energy_rows_launch<3>(frames, C, g, atab, pmax, pscale, center, st);
+        else
+            energy_rows_launch<4>(frames, C, g, atab, pmax, pscale, center, st);
+        return hipGetLastError();
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);

@@ -106,13 +106,15 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
                          hipStream_t st, const int32_t *only = nullptr);
 // atab[frame][W][W]: the frame's energies over D at (s,t) ([-s][-t] when flip),
 // of the grid values less `center`; pmax[frame] (may be null): a pixel bound
-// for the x2 step (uint16), else INT32_MAX
+// for the x2 step (uint16), else INT32_MAX.  Not flipped, grids where
+// energy_rows_applicable take the one-pass row kernel.
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
                          int32_t *pmax, hipStream_t st, double center = 0.0);
 // the same (not flipped) from the frames' pixels, forming the grid values as
 // they are read (at most one 2x2 level): the values launch_coarse would write
 hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
                             int32_t *pmax, hipStream_t st, double center = 0.0);
+bool energy_rows_applicable(const Geom &g);
 // only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st, const int32_t *only = nullptr);
