@@ -619,6 +619,100 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     return MOCO_OK;
 }
 
+// Device tables of a multi-template int8 run: F frames, the i-th against the
+// template of tmpls[i] (one geometry, digit base and plane count for all).
+struct Int8MultiTables {
+    const int8_t **btp;          // [F] per correlation block-column (at most F used)
+    int *bf0, *bfe;              // [F]
+    const uint16_t **traws;      // [F] per frame
+    int32_t *tmaxs;              // [F]
+    const long long **btabs;     // [F]
+    static size_t bytes(int F) { return (size_t)F * (8 + 4 + 4 + 8 + 4 + 8) + 6 * 8; }
+    // lay the tables out in `base` (8-byte aligned), F entries each
+    void place(char *base, int F)
+    {
+        size_t o = 0;
+        auto take = [&](size_t sz) { char *p = base + o; o = align_up(o + sz, 8); return p; };
+        btp = (const int8_t **)take((size_t)F * 8);
+        traws = (const uint16_t **)take((size_t)F * 8);
+        btabs = (const long long **)take((size_t)F * 8);
+        bf0 = (int *)take((size_t)F * 4);
+        bfe = (int *)take((size_t)F * 4);
+        tmaxs = (int32_t *)take((size_t)F * 4);
+    }
+};
+
+// Fill the host copy of a multi-template run's tables for frames whose
+// templates are tmpls[0..F-1] (frames of one template consecutive); returns
+// the number of correlation block-columns (at most four frames each, of one
+// template).
+int fill_int8_multi(const moco::Tmpl *const *tmpls, int F, Int8MultiTables &h)
+{
+    int nb = 0;
+    for (int f = 0; f < F;) {
+        int e = f;
+        while (e < F && tmpls[e] == tmpls[f]) ++e;
+        for (int k = f; k < e; k += 4) {
+            h.btp[nb] = tmpls[f]->i8.tp;
+            h.bf0[nb] = k;
+            h.bfe[nb] = std::min(k + 4, e);
+            ++nb;
+        }
+        f = e;
+    }
+    for (int f = 0; f < F; ++f) {
+        h.traws[f] = (const uint16_t *)tmpls[f]->raw;
+        h.tmaxs[f] = tmpls[f]->i8.vmax;
+        h.btabs[f] = tmpls[f]->i8.atab;
+    }
+    return nb;
+}
+
+// Whether frames of these templates can share one multi-template int8 run:
+// the int8 form with the same geometry, digit base and planes, and the
+// rolling refine (uint16, even rows, aligned buffers) when downsampling.
+bool int8_multi_key_equal(const moco::Tmpl &a, const moco::Tmpl &b)
+{
+    const moco::Geom &x = a.g, &y = b.g;
+    return x.m == y.m && x.n == y.n && x.w == y.w && x.ds == y.ds && x.dtype == y.dtype &&
+           a.i8.npad == b.i8.npad && a.i8.trow == b.i8.trow && a.i8.padl == b.i8.padl &&
+           a.i8.dbits == b.i8.dbits && a.i8.nq == b.i8.nq;
+}
+
+// The int8 pipeline over F frames of several templates (device tables `dt`
+// already on the device), in one launch per stage; the frames must fit one
+// chunk of `sbytes` of scratch.  Outputs as run_int8 (no surface).
+int run_int8_multi(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tref, int F, int nblocks,
+                   const Int8MultiTables &dt, const moco_outputs *out, hipStream_t st, char *sbase,
+                   size_t sbytes)
+{
+    const moco::Geom &g = tref.g;
+    const int npad = tref.i8.npad;
+    Int8Layout L = int8_layout(g, npad);
+    if ((size_t)F * L.total_per_frame > sbytes)
+        return fail(MOCO_ENOMEM, "multi-template run of %d frames exceeds its scratch", F);
+    char *base = sbase;
+    int8_t *limbs = (int8_t *)base;
+    int32_t *nl = (int32_t *)(base + L.limbs * F);
+    int32_t *vm = nl + F;
+    long long *atab = (long long *)(base + (L.limbs + L.nlimb) * F);
+    long long *edge = (long long *)(base + (L.limbs + L.nlimb + L.atab) * F);
+    long long *h = (long long *)(base + (L.limbs + L.nlimb + L.atab + L.edge) * F);
+    int32_t *cst = (int32_t *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h) * F);
+    double *part = (double *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst) * F);
+    const uint16_t *fr = (const uint16_t *)d_frames;
+    int32_t *coarse = out->coarse ? out->coarse : cst;
+    const moco::Int8Multi mm{nblocks, dt.btp, dt.bf0, dt.bfe};
+    HIP_TRY(moco::launch_prep_u16(fr, F, g, npad, tref.i8.dbits, limbs, nl, vm, atab, edge, st));
+    HIP_TRY(moco::launch_corr_int8(limbs, nl, tref.i8, F, g, h, st, &mm));
+    HIP_TRY(moco::launch_combine_i64(atab, nullptr, h, F, g, nullptr, out->fmin, coarse,
+                                     out->shifts, out->gaps, out->frefine, st, dt.btabs));
+    if (g.ds)
+        HIP_TRY(moco::launch_refine_multi(fr, dt.traws, dt.tmaxs, F, g, coarse, out->shifts,
+                                          out->frefine, out->gaps, part, st, vm));
+    return MOCO_OK;
+}
+
 // The FP64 exact pipeline over one stack, in chunks that fit `sbytes` of
 // scratch at `sbase`; every launch goes to stream st.
 int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
@@ -1573,6 +1667,8 @@ struct SrvLane {
     double *d_fmin = nullptr, *d_frefine = nullptr, *d_gaps = nullptr;
     int32_t *h_shifts = nullptr, *h_coarse = nullptr;
     double *h_fmin = nullptr, *h_frefine = nullptr, *h_gaps = nullptr;
+    char *d_meta = nullptr, *h_meta = nullptr;   // multi-template tables of a batch
+    size_t meta_bytes = 0;
     std::vector<SrvRequest> reqs;
     bool active = false;
     int status = MOCO_OK;
@@ -1610,10 +1706,18 @@ void lane_free(SrvLane &L)
     if (L.d_scratch) (void)hipFree(L.d_scratch);
     if (L.d_shifts) (void)hipFree(L.d_shifts);
     if (L.h_shifts) (void)hipHostFree(L.h_shifts);
+    if (L.d_meta) (void)hipFree(L.d_meta);
+    if (L.h_meta) (void)hipHostFree(L.h_meta);
     L.d_frames = L.d_scratch = nullptr;
     L.d_shifts = nullptr;
     L.h_shifts = nullptr;
+    L.d_meta = L.h_meta = nullptr;
 }
+
+// Bytes of a batch's multi-template tables: a group of F frames takes
+// Int8MultiTables::bytes(F) rounded up to 256, there are at most max_slots
+// frames and as many groups.
+size_t srv_meta_bytes(size_t ns) { return ns * (Int8MultiTables::bytes(1) + 256) + 256; }
 
 // (Re)size the slot staging and both lanes for max_slots frames of slot_bytes
 // with pf_max scratch each.  Called with no batch in flight.
@@ -1632,10 +1736,14 @@ int server_size_buffers(moco_server *srv, size_t slot_bytes, size_t pf_max)
     if (e != hipSuccess) return fail(MOCO_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
     for (auto &L : srv->lane) {
         lane_free(L);
+        L.meta_bytes = srv_meta_bytes(ns);
         if ((e = hipMalloc(&L.d_frames, ns * slot_bytes)) != hipSuccess ||
             (e = hipMalloc(&L.d_scratch, ns * pf_max)) != hipSuccess ||
             (e = hipMalloc(&L.d_shifts, res_i32 + res_f64)) != hipSuccess ||
             (e = hipHostMalloc((void **)&L.h_shifts, res_i32 + res_f64, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipMalloc(&L.d_meta, L.meta_bytes)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&L.h_meta, L.meta_bytes, hipHostMallocDefault)) !=
                 hipSuccess)
             return fail(MOCO_ENOMEM, "server buffers: %s", hipGetErrorString(e));
         L.scratch_bytes = ns * pf_max;
@@ -1653,34 +1761,82 @@ int server_size_buffers(moco_server *srv, size_t slot_bytes, size_t pf_max)
     return MOCO_OK;
 }
 
-// Enqueue one batch on its lane: frames host -> device, the search per source
-// group, results device -> host, completion event.  The source groups run side
-// by side on the lane's sub-streams (a group's launches do not fill the device
-// when it holds a few frames), each on its own slice of the lane's scratch
-// (max_slots frames of the largest per-frame scratch, so a group of b - a
-// frames starting at request a owns frames a .. b-1 of it).
+// Enqueue one batch on its lane: frames host -> device, the search per group,
+// results device -> host, completion event.  Requests of the int8 form whose
+// templates share a geometry (and digit base) form one group, run as one
+// launch per stage over every source's frames (run_int8_multi, its template
+// tables staged with the frames); the others form one group per source (a
+// run_stack each).  Groups run side by side on the lane's sub-streams, each on
+// its own slice of the lane's scratch (max_slots frames of the largest
+// per-frame scratch, so a group of requests a .. b-1 owns frames a .. b-1 of
+// it).
 int server_enqueue(moco_server *srv, SrvLane &L)
 {
+    auto key = [](const SrvRequest &q) {
+        const moco::Tmpl &t = *q.tmpl;
+        return std::make_tuple((int)q.form, t.g.m, t.g.n, t.g.w, t.g.ds, (int)t.g.dtype,
+                               t.i8.npad, t.i8.trow, t.i8.padl, t.i8.dbits, t.i8.nq, q.source);
+    };
     std::stable_sort(L.reqs.begin(), L.reqs.end(),
-                     [](const SrvRequest &x, const SrvRequest &y) { return x.source < y.source; });
+                     [&](const SrvRequest &x, const SrvRequest &y) { return key(x) < key(y); });
     const size_t nb = L.reqs.size();
     std::vector<size_t> off(nb);
     size_t o = 0;
     for (size_t k = 0; k < nb; ++k) {
-        const SrvRequest &q = L.reqs[k];
         off[k] = o;
-        HIP_TRY(hipMemcpyAsync(L.d_frames + o, srv->h_slots + (size_t)q.slot * srv->slot_bytes,
-                               q.fbytes, hipMemcpyHostToDevice, L.stream));
-        o += q.fbytes;
+        o += L.reqs[k].fbytes;
     }
+    // the groups, and the multi-template tables of the int8 ones
+    struct Group {
+        size_t a, b;
+        bool multi;
+        int nblocks;
+        size_t meta_off;
+    };
+    std::vector<Group> groups;
+    size_t meta_used = 0;
+    std::vector<const moco::Tmpl *> tl;
+    for (size_t a = 0; a < nb;) {
+        const SrvRequest &q = L.reqs[a];
+        size_t b = a + 1;
+        const bool multi =
+            q.form == MOCO_FORM_INT8_MFMA &&
+            (q.g.ds == 0 || moco::refine_rolling(q.g, L.d_frames + off[a], q.tmpl->raw));
+        if (multi) {
+            while (b < nb && L.reqs[b].form == MOCO_FORM_INT8_MFMA &&
+                   int8_multi_key_equal(*L.reqs[b].tmpl, *q.tmpl))
+                ++b;
+        } else {
+            while (b < nb && L.reqs[b].source == q.source) ++b;
+        }
+        Group gr{a, b, multi, 0, meta_used};
+        if (multi) {
+            const int F = (int)(b - a);
+            tl.resize(F);
+            for (int f = 0; f < F; ++f) tl[f] = L.reqs[a + f].tmpl;
+            Int8MultiTables ht;
+            ht.place(L.h_meta + meta_used, F);
+            gr.nblocks = fill_int8_multi(tl.data(), F, ht);
+            meta_used = align_up(meta_used + Int8MultiTables::bytes(F), 256);
+            if (meta_used > L.meta_bytes) return fail(MOCO_ENOMEM, "server tables overflow");
+        }
+        groups.push_back(gr);
+        a = b;
+    }
+    for (size_t k = 0; k < nb; ++k) {
+        const SrvRequest &q = L.reqs[k];
+        HIP_TRY(hipMemcpyAsync(L.d_frames + off[k], srv->h_slots + (size_t)q.slot * srv->slot_bytes,
+                               q.fbytes, hipMemcpyHostToDevice, L.stream));
+    }
+    if (meta_used)
+        HIP_TRY(hipMemcpyAsync(L.d_meta, L.h_meta, meta_used, hipMemcpyHostToDevice, L.stream));
     HIP_TRY(hipEventRecord(L.staged, L.stream));
     bool used[kSrvSubStreams] = {};
-    int grp = 0;
-    for (size_t a = 0; a < nb; ++grp) {
-        size_t b = a;
-        while (b < nb && L.reqs[b].source == L.reqs[a].source) ++b;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group &gr = groups[gi];
+        const size_t a = gr.a, b = gr.b;
         const SrvRequest &q = L.reqs[a];
-        const int k = grp % kSrvSubStreams;
+        const int k = (int)(gi % kSrvSubStreams);
         if (!used[k]) {
             HIP_TRY(hipStreamWaitEvent(L.sub[k], L.staged, 0));
             used[k] = true;
@@ -1691,10 +1847,18 @@ int server_enqueue(moco_server *srv, SrvLane &L)
         out.fmin = L.d_fmin + a;
         out.frefine = L.d_frefine + 9 * a;
         out.gaps = L.d_gaps + 2 * a;
-        int rc = run_stack(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), q.g, q.form,
+        int rc;
+        if (gr.multi) {
+            Int8MultiTables dt;
+            dt.place(L.d_meta + gr.meta_off, (int)(b - a));
+            rc = run_int8_multi(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), gr.nblocks, dt,
+                                &out, L.sub[k], L.d_scratch + a * srv->pf_max,
+                                (b - a) * srv->pf_max);
+        } else {
+            rc = run_stack(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), q.g, q.form,
                            &out, L.sub[k], L.d_scratch + a * srv->pf_max, (b - a) * srv->pf_max);
+        }
         if (rc) return rc;
-        a = b;
     }
     for (int k = 0; k < kSrvSubStreams; ++k)
         if (used[k]) {

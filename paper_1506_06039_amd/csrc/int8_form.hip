@@ -407,11 +407,18 @@ __device__ __forceinline__ void wait_barrier()
 // so every LDS read provably targets a buffer other than the ones being
 // filled) and two free ring slots; one wait for every transfer and one
 // barrier per pair.
+//
+// Frames of several templates (same geometry) in one launch: btp (nullable)
+// gives each block-column x its template rows, and its frames run from
+// bf0[x] to bfe[x] - 1 (at most four, all of that template); without btp,
+// block-column x takes frames 4x .. 4x+3 of the one template tp.
 template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
-    const int8_t *__restrict__ tp, const int8_t *__restrict__ zsrc, int C, int mg, int npad,
-    int trow, int padl, int w, int tgroups, int nslice, long long *__restrict__ hout)
+    const int8_t *__restrict__ tp_one, const int8_t *__restrict__ zsrc_one, int C, int mg,
+    int npad, int trow, int padl, int w, int tgroups, int nslice, long long *__restrict__ hout,
+    const int8_t *const *__restrict__ btp, const int *__restrict__ bf0,
+    const int *__restrict__ bfe)
 {
     constexpr int RING = 32 * NS;     // frame rows an iteration reads
     constexpr int RS = RING + 3;      // ring slots: a pair of rows reads RING + 1, the next
@@ -433,7 +440,12 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int rho = lane % 32, h = lane / 32;
-    const int frame = blockIdx.x * kWaves + wave;
+    // this block-column's template and frames
+    const int8_t *tp = btp ? btp[blockIdx.x] : tp_one;
+    const int8_t *zsrc = btp ? tp + (size_t)mg * TQ * kPhases * trow : zsrc_one;  // zero tail
+    const int fb0 = btp ? bf0[blockIdx.x] : (int)blockIdx.x * kWaves;
+    const int fbe = btp ? bfe[blockIdx.x] : C;
+    const int frame = fb0 + wave;
     const int sg = blockIdx.y / tgroups, tg = blockIdx.y % tgroups;
     const int W = 2 * w - 1;
     const int s_lo = -(w - 1) + 32 * NS * sg;
@@ -449,14 +461,14 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const size_t plane = (size_t)mg * npad;
 
     // does this wave's frame take part in this pass?
-    bool live = frame < C;
+    bool live = frame < fbe;
     if (PA0 > 0) live = live && nlimb[frame] > 2;
     if (PA0 > 0) {
         // skip the whole block when no frame of it needs the extra digit plane
         int any = 0;
         for (int k = 0; k < kWaves; ++k) {
-            int f = blockIdx.x * kWaves + k;
-            if (f < C && nlimb[f] > 2) any = 1;
+            int f = fb0 + k;
+            if (f < fbe && nlimb[f] > 2) any = 1;
         }
         if (!any) return;
     }
@@ -734,9 +746,12 @@ __device__ inline bool precedes_i(double f1, int s1, int t1, double f2, int s2, 
     return t1 < t2;
 }
 
+// btabs (nullable): each frame's own template table (frames of several
+// templates in one launch), else btab_one for every frame.
 template <int TB>
 __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict__ atab,
-                                                        const long long *__restrict__ btab_t,
+                                                        const long long *__restrict__ btab_one,
+                                                        const long long *const *__restrict__ btabs,
                                                         const long long *__restrict__ hbuf,
                                                         int mg, int ng, int w, int ds,
                                                         double scale, double *__restrict__ fsurf,
@@ -750,6 +765,7 @@ __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict_
     const int frame = blockIdx.x;
     const long long *A = atab + (size_t)frame * W * W;
     const long long *Hh = hbuf + (size_t)frame * W * W;
+    const long long *btab_t = btabs ? btabs[frame] : btab_one;
     CandI c{INFINITY, INT32_MIN, 0, INFINITY};
     for (int k = threadIdx.x; k < W * W; k += blockDim.x) {
         int si = k / W, ti = k % W;
@@ -811,50 +827,54 @@ __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict_
 // tile groups and the row slices.
 template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
 hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                            const Geom &g, int nslice, long long *h, hipStream_t st)
+                            const Geom &g, int nslice, long long *h, hipStream_t st,
+                            const Int8Multi *mm)
 {
     const int tgroups = (g.W + 32 * NT - 1) / (32 * NT);
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
-    dim3 grid((C + kWaves - 1) / kWaves, sgroups * tgroups, nslice);
+    dim3 grid(mm ? mm->nblocks : (C + kWaves - 1) / kWaves, sgroups * tgroups, nslice);
     const int8_t *zsrc = tt.tp + (size_t)g.mg * tt.nq * kPhases * tt.trow;  // zero tail
     k_corr_int8<NS, NT, NPA, PA0, NDMA, KB><<<grid, kBlock, 0, st>>>(
-        limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, nslice, h);
+        limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, nslice, h,
+        mm ? mm->btp : nullptr, mm ? mm->bf0 : nullptr, mm ? mm->bfe : nullptr);
     return hipGetLastError();
 }
 
 template <int NS, int NT, int NPA, int PA0, bool KB>
 hipError_t launch_corr_nq(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                          const Geom &g, int nslice, long long *h, hipStream_t st)
+                          const Geom &g, int nslice, long long *h, hipStream_t st,
+                          const Int8Multi *mm)
 {
     // transfers per wave for a quarter of a template row (nq * 2 * trow bytes);
     // the buffer bound 3 quarters + NDMA KB <= nq * 8 * max row holds for every
     // trow up to that maximum
     switch ((tt.nq * 2 * tt.trow + 1023) / 1024) {
-    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
-    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4, KB>(limbs, nlimb, tt, C, g, nslice, h, st);
+    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int NS, int NT, int NPA, int PA0>
 hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
-                               int C, const Geom &g, int nslice, long long *h, hipStream_t st)
+                               int C, const Geom &g, int nslice, long long *h, hipStream_t st,
+                               const Int8Multi *mm)
 {
     // base-128 digits with a digit-sum plane (three products), or base-256 (four)
     if (tt.nq == 3) {
         if (tt.trow > kMaxTrowSum) return hipErrorInvalidValue;
-        return launch_corr_nq<NS, NT, NPA, PA0, true>(limbs, nlimb, tt, C, g, nslice, h, st);
+        return launch_corr_nq<NS, NT, NPA, PA0, true>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     }
     if (tt.trow > kMaxTrow) return hipErrorInvalidValue;
-    return launch_corr_nq<NS, NT, NPA, PA0, false>(limbs, nlimb, tt, C, g, nslice, h, st);
+    return launch_corr_nq<NS, NT, NPA, PA0, false>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
 }
 
 // Row slices per block group: with fewer blocks than compute units (a few
 // frames), enough slices to cover the device twice over, each slice at least 4
 // template rows (a slice first fills its ring with 32 NS + 1 frame rows).
-int corr_slices(int C, const Geom &g, int NS, int NT)
+int corr_slices(int C, const Geom &g, int NS, int NT, int nblocks = -1)
 {
     static int cus = 0;
     if (cus == 0) {
@@ -868,7 +888,7 @@ int corr_slices(int C, const Geom &g, int NS, int NT)
     }
     const long long groups = (long long)((g.W + 32 * NS - 1) / (32 * NS)) *
                              ((g.W + 32 * NT - 1) / (32 * NT));
-    const long long blocks = (long long)(C + kWaves - 1) / kWaves * groups;
+    const long long blocks = (long long)(nblocks >= 0 ? nblocks : (C + kWaves - 1) / kWaves) * groups;
     if (blocks >= cus) return 1;
     const long long want = (2LL * cus + blocks - 1) / blocks;
     const int most = max(1, g.mg / 4);
@@ -1021,43 +1041,47 @@ hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, 
 }
 
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                            const Geom &g, long long *h, hipStream_t st)
+                            const Geom &g, long long *h, hipStream_t st, const Int8Multi *mm)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     hipError_t e;
     const bool small = g.W <= 32;
-    const int nslice = small ? corr_slices(C, g, 1, 1) : corr_slices(C, g, 2, 2);
+    const int nb = mm ? mm->nblocks : -1;
+    const int nslice = small ? corr_slices(C, g, 1, 1, nb) : corr_slices(C, g, 2, 2, nb);
     if (nslice > 1) {
         // the slices add into a zeroed table
         if ((e = launch_fill_i32((int32_t *)h, 2 * C * g.W * g.W, 0, st)) != hipSuccess) return e;
     }
     if (small) {
-        if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st)) !=
+        if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st, mm)) !=
             hipSuccess)
             return e;
-        return launch_corr_variant<1, 1, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
+        return launch_corr_variant<1, 1, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     }
-    if ((e = launch_corr_variant<2, 2, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st)) != hipSuccess)
+    if ((e = launch_corr_variant<2, 2, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st, mm)) !=
+        hipSuccess)
         return e;
-    return launch_corr_variant<2, 2, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st);
+    return launch_corr_variant<2, 2, 1, 2>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
 }
 
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
                               int C, const Geom &g, double *fsurf, double *fmin,
                               int32_t *coarse_st, int32_t *shifts, double *gaps, double *frefine,
-                              hipStream_t st)
+                              hipStream_t st, const long long *const *btabs)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     const double scale = g.ds ? 0.0625 : 1.0;
     // a few frames: four times the threads per frame
     if (C <= 128)
-        k_combine_i64<1024><<<C, 1024, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale,
-                                                 fsurf, fmin, coarse_st, shifts, gaps, frefine);
+        k_combine_i64<1024><<<C, 1024, 0, st>>>(atab, btab_t, btabs, h, g.mg, g.ng, g.w, g.ds,
+                                                 scale, fsurf, fmin, coarse_st, shifts, gaps,
+                                                 frefine);
     else
-        k_combine_i64<kBlock><<<C, kBlock, 0, st>>>(atab, btab_t, h, g.mg, g.ng, g.w, g.ds, scale, fsurf, fmin,
-                                        coarse_st, shifts, gaps, frefine);
+        k_combine_i64<kBlock><<<C, kBlock, 0, st>>>(atab, btab_t, btabs, h, g.mg, g.ng, g.w,
+                                                    g.ds, scale, fsurf, fmin, coarse_st, shifts,
+                                                    gaps, frefine);
     return hipGetLastError();
 }
 

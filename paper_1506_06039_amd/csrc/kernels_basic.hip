@@ -1248,29 +1248,41 @@ __device__ __forceinline__ void roll_unit(const uint16_t *__restrict__ frames,
 }
 
 // Fast kernel: one wave per (frame, unit); waves of frames in the slow mode
-// return at once.
+// return at once.  MULTI: each frame's own template and pixel bound come from
+// tmpls, tmaxs (frames of several templates in one launch), else tmpl_one and
+// tmax_one serve every frame.  (A separate instantiation: a template pointer
+// loaded from memory, even when unused, cost the one-template kernel 18% on
+// MI355X, 289 -> 341 us per 2000 frames of 512x512.)
+template <bool MULTI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_refine_roll(
-    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl, int m, int n, int br,
-    int nbr, int ncw, int C, const int32_t *__restrict__ coarse_st,
-    const int32_t *__restrict__ pmax, int tmax, double *__restrict__ partial)
+    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl_one, int m, int n,
+    int br, int nbr, int ncw, int C, const int32_t *__restrict__ coarse_st,
+    const int32_t *__restrict__ pmax, int tmax_one, double *__restrict__ partial,
+    const uint16_t *const *__restrict__ tmpls, const int32_t *__restrict__ tmaxs)
 {
     const int units = nbr * ncw;
     const long long wid =
         (long long)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     if (wid >= (long long)C * units) return;
     const int frame = (int)(wid / units), unit = (int)(wid % units);
+    const uint16_t *tmpl = MULTI ? tmpls[frame] : tmpl_one;
+    const int tmax = MULTI ? tmaxs[frame] : tmax_one;
     roll_unit<false>(frames, tmpl, m, n, br, ncw, frame, unit, roll_flush(pmax, tmax, frame),
                      coarse_st, partial, units);
 }
 
 // Slow kernel: one block per frame, its waves take the units the fast kernel
 // left (none for most workloads).
+template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_refine_roll_slow(
-    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl, int m, int n, int br,
-    int nbr, int ncw, const int32_t *__restrict__ coarse_st, const int32_t *__restrict__ pmax,
-    int tmax, double *__restrict__ partial)
+    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl_one, int m, int n,
+    int br, int nbr, int ncw, const int32_t *__restrict__ coarse_st,
+    const int32_t *__restrict__ pmax, int tmax_one, double *__restrict__ partial,
+    const uint16_t *const *__restrict__ tmpls, const int32_t *__restrict__ tmaxs)
 {
     const int units = nbr * ncw, frame = blockIdx.x;
+    const uint16_t *tmpl = MULTI ? tmpls[frame] : tmpl_one;
+    const int tmax = MULTI ? tmaxs[frame] : tmax_one;
     const int flush = roll_flush(pmax, tmax, frame);
     if (flush >= br) return;  // every band of this frame was done by the fast kernel
     for (int unit = __builtin_amdgcn_readfirstlane(threadIdx.x / 64); unit < units;
@@ -1509,15 +1521,15 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
         const long long waves = (long long)C * units;
         const long long blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
         if (blocks > INT32_MAX) return hipErrorInvalidValue;
-        k_refine_roll<<<(unsigned)blocks, kBlock, 0, st>>>((const uint16_t *)frames,
+        k_refine_roll<false><<<(unsigned)blocks, kBlock, 0, st>>>((const uint16_t *)frames,
                                                           (const uint16_t *)traw, g.m, g.n, br,
                                                           nbr, ncw, C, coarse_st, pmax, tmax,
-                                                          partial);
+                                                          partial, nullptr, nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_refine_roll_slow<<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
+        k_refine_roll_slow<false><<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
                                                  g.m, g.n, br, nbr, ncw, coarse_st, pmax, tmax,
-                                                 partial);
+                                                 partial, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         launch_finish(partial, C, units, g, coarse_st, shifts, frefine, gaps, st);
@@ -1558,6 +1570,35 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
     else
         k_refine<float><<<C, kBlock, 0, st>>>((const float *)frames, (const float *)traw, g.m,
                                               g.n, coarse_st, shifts, frefine, gaps);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_multi(const uint16_t *frames, const uint16_t *const *traws,
+                               const int32_t *tmaxs, int C, const Geom &g,
+                               const int32_t *coarse_st, int32_t *shifts, double *frefine,
+                               double *gaps, double *partial, hipStream_t st,
+                               const int32_t *pmax)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.dtype != MOCO_U16 || g.n % 2 != 0 || ((uintptr_t)frames & 3) != 0)
+        return hipErrorInvalidValue;
+    const int br = roll_band_rows(g, C);
+    const int nbr = (g.m + br - 1) / br, ncw = ((g.n + 3) / 4 + 63) / 64;
+    const int units = nbr * ncw;
+    const long long waves = (long long)C * units;
+    const long long blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    k_refine_roll<true><<<(unsigned)blocks, kBlock, 0, st>>>(frames, nullptr, g.m, g.n, br, nbr,
+                                                            ncw, C, coarse_st, pmax, -1, partial,
+                                                            traws, tmaxs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_refine_roll_slow<true><<<C, kBlock, 0, st>>>(frames, nullptr, g.m, g.n, br, nbr, ncw,
+                                                   coarse_st, pmax, -1, partial, traws, tmaxs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_finish(partial, C, units, g, coarse_st, shifts, frefine, gaps, st);
     return hipGetLastError();
 }
 

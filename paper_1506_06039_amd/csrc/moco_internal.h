@@ -132,6 +132,15 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, double *partial, hipStream_t st,
                          const int32_t *pmax = nullptr, int tmax = -1);
+// The same for frames of several templates (uint16 rolling kernel only:
+// refine_rolling must hold for the frames and every template): traws[f] and
+// tmaxs[f] (device arrays) are frame f's template pixels and pixel bound (-1:
+// none).
+hipError_t launch_refine_multi(const uint16_t *frames, const uint16_t *const *traws,
+                               const int32_t *tmaxs, int C, const Geom &g,
+                               const int32_t *coarse_st, int32_t *shifts, double *frefine,
+                               double *gaps, double *partial, hipStream_t st,
+                               const int32_t *pmax);
 // one more pyramid level: in C x m x n FP64 -> out C x (m/2) x (n/2)
 hipError_t launch_half(const double *in, int C, int m, int n, double *out, hipStream_t st);
 // the +-1 step at an intermediate pyramid level (FP64 images of that level):
@@ -176,12 +185,24 @@ size_t prep_grid_edge_bytes(const Geom &g);
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
                             double *atab, int32_t *vmax, long long *edge, hipStream_t st,
                             const int32_t *only = nullptr, int xc = 0);
+// Frames of several templates of one geometry in one correlation launch
+// (device arrays): block-column x takes frames bf0[x] .. bfe[x]-1 (at most
+// four, consecutive) against the template rows btp[x].
+struct Int8Multi {
+    int nblocks;
+    const int8_t *const *btp;
+    const int *bf0, *bfe;
+};
+// mm (nullable): the frames' templates as above; tt then gives the geometry
+// (npad, trow, padl, digit base), which every template of the launch shares
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                            const Geom &g, long long *h, hipStream_t st);
+                            const Geom &g, long long *h, hipStream_t st,
+                            const Int8Multi *mm = nullptr);
+// btabs (nullable, device array): each frame's own template table
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
                               int C, const Geom &g, double *fsurf, double *fmin,
                               int32_t *coarse_st, int32_t *shifts, double *gaps, double *frefine,
-                              hipStream_t st);
+                              hipStream_t st, const long long *const *btabs = nullptr);
 
 // ---- FFT form (fft_form.hip) --------------------------------------------
 bool fft_plan(int n, FftPlan *pl);

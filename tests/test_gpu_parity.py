@@ -434,6 +434,44 @@ def test_server_results_equal_alone_and_in_the_mix(gpu_lib):
         assert r.fmin == orc.fmin[k]
 
 
+def test_server_sources_of_one_geometry_share_launches(gpu_lib):
+    # five 512x512 sources (one geometry: their frames go through the int8
+    # form as one multi-template run per batch) and two 256x256 ones, requests
+    # interleaved; every result equals moco_align on that frame alone and the
+    # oracle on the first frames
+    ctx = gpu_lib.Context(0)
+    srcs = {}
+    for k in range(5):
+        srcs[k] = (synth.PoissonScene(512, 512, 10, seed=60 + k), 32, True)
+    for k in (5, 6):
+        srcs[k] = (synth.PoissonScene(256, 256, 10, seed=60 + k), 16, False)
+    srv = gpu_lib.Server(ctx, max_slots=16)
+    frames = {}
+    for sid, (sc, w, ds) in srcs.items():
+        srv.add_source(sid, sc.template, w, ds)
+        frames[sid] = sc.frames(1, 7)
+    reqs = [(sid, frames[sid][k], sid * 100 + k) for k in range(6) for sid in srcs]
+    _say("case server multi-template batches: 7 sources x 6 frames")
+    out, _ = _serve_all(srv, reqs)
+    assert srv.close() == 0
+    for sid, (sc, w, ds) in srcs.items():
+        alone = _run(gpu_lib, frames[sid], sc.template, w, ds)
+        assert gpu_lib.resolved_form(ctx, gpu_lib.Template(ctx, _to_dev(sc.template), w, ds),
+                                     "auto") == "int8"
+        for k in range(6):
+            r = out[sid * 100 + k]
+            assert r.status == 0 and r.source == sid
+            assert list(r.shift) == alone["shifts"][k].tolist(), (sid, k)
+            assert list(r.coarse) == alone["coarse"][k].tolist(), (sid, k)
+            assert r.fmin == alone["fmin"][k], (sid, k)
+            assert np.array_equal(np.array(list(r.frefine)), alone["frefine"][k], equal_nan=True)
+            assert np.array_equal(np.array(list(r.gaps)), alone["gaps"][k])
+        orc = oracle.align(frames[sid][:2], sc.template, w, ds)
+        for k in range(2):
+            assert list(out[sid * 100 + k].shift) == orc.shifts[k].tolist()
+            assert out[sid * 100 + k].fmin == orc.fmin[k]
+
+
 def test_server_add_source_while_another_thread_submits(gpu_lib):
     # sources of growing frame size are added while requests of another source
     # flow (each addition replaces the slot and lane buffers once nothing holds
