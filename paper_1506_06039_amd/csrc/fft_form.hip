@@ -645,7 +645,11 @@ size_t wave_lds()
 }
 
 // The lengths with a wave-level kernel; others take the block-level kernels.
-#define MOCO_WAVE_LENGTHS(X) X(144) X(160) X(180) X(240) X(256) X(270) X(288) X(300) X(320) X(360)
+// Measured on MI355X against the block kernels: faster at 144, 288, 300 and
+// 320 points; slower at 360 (3,3,5,8: the radix-8 pass keeps 45 of 64 lanes
+// busy), so 360 keeps the block kernels (transforms of the 256x256 grid at
+// w = 85: FP32 2.58 -> 1.92 ms, FP64 3.70 -> 3.29 ms per 2000 frames).
+#define MOCO_WAVE_LENGTHS(X) X(144) X(160) X(180) X(240) X(256) X(270) X(288) X(300) X(320)
 
 bool wave_length(int n)
 {
