@@ -964,19 +964,23 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame time models of the two fast forms (seconds), from their kernels'
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
-// issues 64x64-shift tiles of three digit products (base-128 digits with their
-// sums) at about 2.4e15 ops/s or four (base 256) at about 2.8e15, beside 0.35
+// issues 64x64-shift tile groups (one 32x32 tile when 2w-1 <= 32) of three
+// digit products (base-128 digits with their
+// sums) at about 2.7e15 ops/s or four (base 256) at about 2.8e15, beside 0.31
 // us of prep, combine and refine per 512x512 frame; the FFT form's three
-// transform passes took 1.15 us at 288x288 and scale with P Q log2(P Q),
-// beside 0.28 us of energies, combine and refine per 512x512 frame (those
-// parts scale with the frame's pixels).
+// transform passes took 0.72 us at 288x288 (FP64, wave-level kernels) and
+// scale with P Q log2(P Q), beside 0.28 us of energies, combine and refine per
+// 512x512 frame (those parts scale with the frame's pixels).  At that
+// workload the models give 0.91 and 1.00 us per frame; measured 0.92 and 1.01.
 double int8_model_s(const moco::Tmpl &t)
 {
     const moco::Geom &g = t.g;
-    const double groups = std::ceil(g.W / 64.0);
-    const double macs = groups * groups * 64.0 * 64.0 * g.mg * (double)t.i8.npad;
+    // tile groups of 64x64 shifts, or one 32x32 tile when 2w-1 <= 32
+    const double tile = g.W <= 32 ? 32.0 : 64.0;
+    const double groups = std::ceil(g.W / tile);
+    const double macs = groups * groups * tile * tile * g.mg * (double)t.i8.npad;
     const double ops = macs * 2.0 * (t.i8.nq == 3 ? 3.0 : 4.0);
-    return 0.35e-6 * ((double)g.m * g.n / 262144.0) + ops / (t.i8.nq == 3 ? 2.4e15 : 2.8e15);
+    return 0.31e-6 * ((double)g.m * g.n / 262144.0) + ops / (t.i8.nq == 3 ? 2.7e15 : 2.8e15);
 }
 
 double fft_model_s(const moco::Tmpl &t)
@@ -984,7 +988,7 @@ double fft_model_s(const moco::Tmpl &t)
     const moco::Geom &g = t.g;
     const double pq = (double)t.fft.pp.n * t.fft.pq.n;
     const double ref = 288.0 * 288.0 * std::log2(288.0 * 288.0);
-    return 0.28e-6 * ((double)g.m * g.n / 262144.0) + 1.15e-6 * pq * std::log2(pq) / ref;
+    return 0.28e-6 * ((double)g.m * g.n / 262144.0) + 0.72e-6 * pq * std::log2(pq) / ref;
 }
 
 // Forms chosen by measurement (moco_tune) or set by the caller, per search
