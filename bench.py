@@ -35,7 +35,28 @@ STAGES = ["coarse", "energy", "prep", "corr", "combine", "refine", "apply"]
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_INT8_TOPS = 5000.0
+
+
+def fft_flops(P: int, Q: int) -> float:
+    """Algorithmic flops of the FFT form's correlation per frame: a forward and
+    an inverse complex transform of P x Q points at 5 PQ log2(PQ) each, plus
+    the spectrum product over the P (Q/2+1) half-spectrum bins (6 each)."""
+    import math
+    return 2.0 * 2.5 * P * Q * math.log2(P * Q) + 6.0 * P * (Q // 2 + 1)
+
+
+def next_smooth(x: int) -> int:
+    """Smallest 5-smooth integer >= x (the FFT form's transform lengths)."""
+    while True:
+        y = x
+        for p in (2, 3, 5):
+            while y % p == 0:
+                y //= p
+        if y == 1:
+            return x
+        x += 1
 
 
 def useful_macs(mg: int, ng: int, w: int) -> int:
@@ -69,9 +90,11 @@ def kernel_source_sha(fname: str, kernel: str) -> str:
     return hashlib.sha256(text).hexdigest()[:16]
 
 
-def load_traffic(kernel: str, source: str, frames_per_launch: float):
+def load_traffic(kernel: str, source: str, frames_per_launch: float, kernels=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+    None when the kernel source changed since the counters were taken.  A
+    record may cover several kernels (`kernels`): its hash then joins each
+    one's, in order."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -79,7 +102,9 @@ def load_traffic(kernel: str, source: str, frames_per_launch: float):
         rec = json.load(open(path)).get(kernel)
     except (ValueError, OSError):
         return None
-    if not rec or rec.get("source_sha256_16") != kernel_source_sha(source, kernel):
+    sha = kernel_source_sha(source, kernel) if kernels is None else \
+        hashlib.sha256("".join(kernel_source_sha(source, k) for k in kernels).encode()).hexdigest()[:16]
+    if not rec or rec.get("source_sha256_16") != sha:
         return None
     per_frame = (rec["fetch_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) / \
         rec["frames_per_dispatch"]
@@ -636,13 +661,35 @@ def main():
         steps = args.steps if fm != "fp64" else max(1, min(args.steps, 3))
         moco.moco_align(ctx, frames, tp, form=fm, out=alt)
         torch.cuda.synchronize(dev)
+        moco.profile_enable(ctx, True)
+        moco.profile_read(ctx)
         t = time.perf_counter()
         for _ in range(steps):
             moco.moco_align(ctx, frames, tp, form=fm, out=alt)
         torch.cuda.synchronize(dev)
         dt = time.perf_counter() - t
+        moco.profile_enable(ctx, False)
+        fms, fla = moco.profile_read(ctx)
         forms[fm] = {"frames_per_s": round(T * steps / dt, 2),
-                     "ms_per_step": round(1000.0 * dt / steps, 4), "steps": steps}
+                     "ms_per_step": round(1000.0 * dt / steps, 4), "steps": steps,
+                     "stage_ms_per_step": {STAGES[k]: round(fms[k] / steps, 4)
+                                           for k in range(len(STAGES)) if fla[k]}}
+        if fm in ("fft", "fft32") and fla[corr]:
+            # the transform kernels (rows, columns with the product, rows back)
+            # are the form's correlation stage
+            P = next_smooth(mg + W_WIN - 1)
+            Q = next_smooth(ng + W_WIN - 1)
+            t_launch = fms[corr] / 1000.0 / fla[corr]
+            ach = fft_flops(P, Q) * (T * steps / fla[corr]) / t_launch / 1e12
+            peak = PEAK_FP32_TFLOPS if fm == "fft32" else PEAK_FP64_TFLOPS
+            forms[fm]["roofline"] = {
+                "bound": "alu", "kernels": "k_wrows, k_wcols, k_wback", "P": P, "Q": Q,
+                "flops_per_frame": round(fft_flops(P, Q)), "achieved": round(ach, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                "ms_per_launch": round(1000 * t_launch, 4),
+                "traffic": load_traffic("fft_transforms_" + fm, "fft_form.hip",
+                                        T * steps / fla[corr],
+                                        kernels=("k_wrows", "k_wcols", "k_wback"))}
         if fm == "fft_cert":
             # frames whose argmin the transforms' error bound left uncertified
             chk = moco.moco_align(ctx, frames, tp, form=fm)
