@@ -63,11 +63,13 @@ typedef enum {
 /* How the correlation sum of a[i+s][j+t]*b[i][j] (the third term of the
  * energy split of sec. 2) is computed.  Every form computes the same f. */
 typedef enum {
-    MOCO_FORM_AUTO = 0,       /* library choice: of MOCO_FORM_INT8_MFMA (uint16) and
-                                 MOCO_FORM_FFT_CERTIFIED the one a per-frame time model of
-                                 the template's geometry ranks faster among those that
-                                 apply (int8 for small windows, the FFT for wide ones),
-                                 else MOCO_FORM_FP64_EXACT */
+    MOCO_FORM_AUTO = 0,       /* library choice: a form recorded for the search key
+                                 (moco_tune, moco_tune_set) where it applies; for uint16
+                                 data, of MOCO_FORM_INT8_MFMA and MOCO_FORM_FFT_CERTIFIED
+                                 the one a per-frame time model of the template's
+                                 geometry ranks faster among those that apply (int8 for
+                                 small windows, the FFT for wide ones); for float32 data
+                                 MOCO_FORM_FFT32_CERTIFIED; else MOCO_FORM_FP64_EXACT */
     MOCO_FORM_FFT = 1,        /* h from FP64 complex transforms of the zero-padded grids
                                  (sec. 2, the FFT construction of h), transform lengths
                                  5-smooth and at most 2048; f to about 1e-12 relative */
@@ -88,7 +90,7 @@ typedef enum {
                                  cores (balanced base-128 digits and three products per
                                  term when the template allows, else base-256 and four:
                                  moco_template_int8_products); bit-exact f */
-    MOCO_FORM_FFT32 = 5       /* the plain single-precision form: h from FP32 complex
+    MOCO_FORM_FFT32 = 5,      /* the plain single-precision form: h from FP32 complex
                                  transforms (sec. 2, the FFT construction of h) of the
                                  grids less a common offset c (the template grid's mean,
                                  rounded to an integer for uint16 data), with the overlap
@@ -99,7 +101,24 @@ typedef enum {
                                  f are closer than that.  Never chosen by AUTO; the
                                  single-precision comparator of the other forms.  Same
                                  applicability as MOCO_FORM_FFT */
+    MOCO_FORM_FFT32_CERTIFIED = 6 /* MOCO_FORM_FFT32 with a certified argmin: the
+                                 argmin of the searched grid is certified when the gap to
+                                 the second-best f exceeds twice an a-posteriori bound of
+                                 the FP32 correlation's error (first order in 2^-24, from
+                                 the centred grids' 2-norms and the largest magnitudes of
+                                 the frame's and the template's spectra); a certified
+                                 frame's f at its argmin is then evaluated by its
+                                 definition (FP64 sum of squared differences over D; exact
+                                 for uint16), and the gap moves with it, while the rest
+                                 of the surface keeps its FP32 correlation.  Frames not
+                                 certified go through MOCO_FORM_FFT_CERTIFIED (FP64
+                                 transforms, then direct sums for what its bound leaves)
+                                 and equal its results.  Same applicability as
+                                 MOCO_FORM_FFT */
 } moco_form;
+
+/* Number of moco_form values (the length of moco_tune's seconds_per_frame). */
+#define MOCO_FORM_COUNT 7
 
 typedef struct moco_ctx moco_ctx;
 typedef struct moco_tmpl moco_tmpl;
@@ -115,7 +134,10 @@ typedef struct moco_tmpl moco_tmpl;
  *                          second-best minus best of the nine; +inf when n/a)
  *   recomputed T int32    1 where MOCO_FORM_FFT_CERTIFIED recomputed the frame's
  *                          correlation by direct sums (its argmin was not
- *                          certified), else 0 (every other form writes 0)
+ *                          certified); for MOCO_FORM_FFT32_CERTIFIED the number
+ *                          of passes after the FP32 one: 1 FP64 transforms, 2
+ *                          FP64 transforms and direct sums; else 0 (every other
+ *                          form writes 0)
  * f is in squared intensity units of the searched grid (box-mean units when
  * downsampled). */
 typedef struct {
@@ -246,13 +268,15 @@ int moco_apply(moco_ctx *ctx, const void *d_frames, const int32_t *d_shifts, int
 /* The correlation form a call with `requested` runs for this template.
  * MOCO_FORM_INT8_MFMA applies to uint16 templates with a searched grid of fewer
  * than 131072 pixels and at most 2048 columns, w <= 512, and grid values within
- * two balanced base-256 digits (|value| <= 32639); MOCO_FORM_FFT and
- * MOCO_FORM_FFT_CERTIFIED apply when the transform lengths (5-smooth, at least
- * m'+w-1 by n'+w-1) are at most 2048.  MOCO_FORM_AUTO resolves to whichever of
- * MOCO_FORM_INT8_MFMA and MOCO_FORM_FFT_CERTIFIED applies, the one a per-frame
- * time model ranks faster when both do (the int8 form's work grows with the
- * (2w-1)^2 shifts, the FFT's with P Q log(P Q): at a 256x256 grid the int8
- * form for w <= 32, the FFT above), else to MOCO_FORM_FP64_EXACT.
+ * two balanced base-256 digits (|value| <= 32639); the four FFT forms apply
+ * when the transform lengths (5-smooth, at least m'+w-1 by n'+w-1) are at most
+ * 2048.  MOCO_FORM_AUTO resolves to a form recorded for the key where it
+ * applies; else, for uint16 data, to whichever of MOCO_FORM_INT8_MFMA and
+ * MOCO_FORM_FFT_CERTIFIED applies, the one a per-frame time model ranks faster
+ * when both do (the int8 form's work grows with the (2w-1)^2 shifts, the FFT's
+ * with P Q log(P Q): at a 256x256 grid the int8 form for w <= 32, the FFT
+ * above); for float32 data to MOCO_FORM_FFT32_CERTIFIED; else to
+ * MOCO_FORM_FP64_EXACT.
  * Errors: MOCO_EINVAL (null argument, or an explicit form that does not apply). */
 int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *resolved);
 
@@ -270,8 +294,8 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
  * HIP events on hip_stream, and record the fastest for the template's key.
  * The forms rank differently with the stack length (a few frames take the
  * int8 form's row-sliced launch), so `frames` should be the length of the
- * stacks the key will serve; 0 means 1024, the many-frame regime.  *chosen receives it; seconds_per_frame (nullable, 5
- * doubles indexed by moco_form) receives each timed form's seconds per frame
+ * stacks the key will serve; 0 means 1024, the many-frame regime.  *chosen receives it; seconds_per_frame (nullable,
+ * MOCO_FORM_COUNT doubles indexed by moco_form) receives each timed form's seconds per frame
  * (-1 for forms not timed).  Synchronises hip_stream; allocates the frames
  * outside the context's budget for the duration of the call.
  * Errors: MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE. */
@@ -318,8 +342,11 @@ int moco_template_int8_products(const moco_tmpl *tmpl, int *products);
  * when the GPU can accept a batch (up to max_slots), runs the search of sec. 2 on
  * the batch (frames of one source share a launch), and publishes one result per
  * request.  Requests that arrive while batches are on the GPU are admitted as
- * slots free up and go in the next batch.  Each frame's result is exactly what
- * moco_align gives for that frame alone.  All server calls are thread-safe. */
+ * slots free up and go in the next batch.  A source runs the form AUTO
+ * resolves to for its template, except that float32 sources run
+ * MOCO_FORM_FFT_CERTIFIED (the certified FP32 form is not served); each
+ * frame's result is exactly what moco_align gives for that frame alone in
+ * that form.  All server calls are thread-safe. */
 typedef struct moco_server moco_server;
 
 typedef struct {

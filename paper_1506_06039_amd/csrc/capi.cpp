@@ -250,7 +250,7 @@ ExactLayout exact_layout(const moco::Geom &g)
     L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
-    L.pm = sizeof(int32_t);
+    L.pm = 2 * sizeof(int32_t);         // padded: the partials after it stay 8-byte aligned
     L.edge = align_up(energy_scratch_bytes(g), 256);
     L.part = align_up(refine_steps_partial_bytes(g), 8);
     L.total_per_frame = L.coarse + L.inter + L.atab + L.h + L.cst + L.pm + L.edge + L.part;
@@ -518,8 +518,13 @@ int prepare_fft32_template(moco::Tmpl &t, hipStream_t st)
                (e = hipStreamSynchronize(st)) != hipSuccess) {
         rc = fail(MOCO_EDEVICE, "FFT32 template preparation: %s", hipGetErrorString(e));
     } else {
-        for (size_t k = 0; k < nspec; ++k)
+        double ymax = 0.0;
+        for (size_t k = 0; k < nspec; ++k) {
             hspec32[k] = float2{(float)hspec[k].x, (float)hspec[k].y};
+            const double yx = hspec32[k].x, yy = hspec32[k].y;
+            ymax = std::max(ymax, std::sqrt(yx * yx + yy * yy));
+        }
+        f.yinf32 = ymax * (1.0 + 0x1p-50);
         e = hipMemcpy(f.spec32, hspec32.data(), nspec * sizeof(float2), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = fail(MOCO_EDEVICE, "FFT32 template: %s", hipGetErrorString(e));
     }
@@ -777,14 +782,16 @@ int run_exact(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 
 // Per-frame scratch of the FFT form.
 struct FftLayout {
-    size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, edge, part, total_per_frame;
+    size_t coarse, inter, atab, s1, s2, h, cst, pm, flag, edge, part, xmax, f1, total_per_frame;
 };
 
-// fp32: the single-precision form's half spectra (FP32 complex)
-FftLayout fft_layout(const moco::Geom &g, bool fp32 = false)
+// fp32: the single-precision form's half spectra (FP32 complex); cert32: its
+// certified variant, whose FP64 pass over uncertified frames needs FP64 half
+// spectra, the spectrum maxima, a second flag and the combine's f
+FftLayout fft_layout(const moco::Geom &g, bool fp32 = false, bool cert32 = false)
 {
     FftLayout L;
-    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+    const size_t esz = fp32 && !cert32 ? sizeof(float2) : sizeof(double2);
     L.coarse = align_up((size_t)g.mg * g.ng * sizeof(double), 256);
     L.inter = align_up(inter_elems(g) * sizeof(double), 256);
     L.atab = align_up((size_t)g.W * g.W * sizeof(double), 256);
@@ -793,11 +800,16 @@ FftLayout fft_layout(const moco::Geom &g, bool fp32 = false)
     L.h = align_up((size_t)g.W * g.W * sizeof(double), 256);
     L.cst = 3 * 2 * sizeof(int32_t);   // the searched grid's argmin, two x2-step buffers
     L.pm = sizeof(int32_t);
-    L.flag = sizeof(int32_t);
+    // two flags for cert32, padded so that the refine partials after them stay
+    // 8-byte aligned for any chunk length
+    L.flag = cert32 ? 3 * sizeof(int32_t) : sizeof(int32_t);
     L.edge = align_up(energy_scratch_bytes(g), 256);
     L.part = align_up(refine_steps_partial_bytes(g), 8);
+    // at most one column block per bin
+    L.xmax = cert32 ? align_up((size_t)moco::fft_geom(g).qh * sizeof(float), 256) : 0;
+    L.f1 = cert32 ? sizeof(double) : 0;
     L.total_per_frame = L.coarse + L.inter + L.atab + L.s1 + L.s2 + L.h + L.cst + L.pm + L.flag +
-                        L.edge + L.part;
+                        L.edge + L.part + L.xmax + L.f1;
     return L;
 }
 
@@ -805,15 +817,19 @@ FftLayout fft_layout(const moco::Geom &g, bool fp32 = false)
 // and refine around the transform-based correlation.  With `certify`, frames
 // whose argmin the error bound of the transforms does not certify get their
 // correlation recomputed by direct FP64 sums and are combined again before the
-// x2 steps.  With `fp32` (never certified), the single-precision form: the
-// transforms in FP32 on the grids less the template's offset c, the energies
-// of the centred grids (FP64; exact integers for uint16), the same combine.
+// x2 steps.  With `fp32`, the single-precision form: the transforms in FP32 on
+// the grids less the template's offset c, the energies of the centred grids
+// (FP64; exact integers for uint16), the same combine.  Both: the FP32 form
+// certified by the a-posteriori bound of Cert32; certified frames get f at
+// their argmin by its definition (k_polish), the others go through the
+// certified FP64 form (uncentred energies, FP64 transforms, then direct sums
+// for what that leaves), and recomputed[f] counts the passes they took.
 int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             const moco::Geom &g, const moco_outputs *out, hipStream_t st, char *sbase,
             size_t sbytes, bool certify, bool fp32 = false)
 {
-    if (fp32) certify = false;
-    FftLayout L = fft_layout(g, fp32);
+    const bool cert32 = certify && fp32;
+    FftLayout L = fft_layout(g, fp32, cert32);
     int C = (int)std::min<size_t>((size_t)T, sbytes / L.total_per_frame);
     C = std::min(C, kChunkOther);
     if (C < 1) return fail(MOCO_ENOMEM, "scratch slice too small for one frame");
@@ -834,18 +850,30 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     off += L.s2 * C;
     double *h = (double *)(base + off);
     off += L.h * C;
+    float *xmax = L.xmax ? (float *)(base + off) : nullptr;   // 256-aligned, as all above
+    off += L.xmax * C;
+    double *f1buf = L.f1 ? (double *)(base + off) : nullptr;
+    off += L.f1 * C;
     int32_t *cst = (int32_t *)(base + off);
     int32_t *shA = cst + 2 * (size_t)C, *shB = cst + 4 * (size_t)C;
     off += L.cst * C;
     int32_t *pm = (int32_t *)(base + off);
     off += L.pm * C;
     int32_t *flag = (int32_t *)(base + off);
+    int32_t *flag2 = flag + C;
     off += L.flag * C;
     double *part = (double *)(base + align_up(off, 8));
     const size_t fbytes = (size_t)g.m * g.n * dtype_size(dtype);
     const int W = g.W;
     double kf = 0.0, ke = 0.0;
     if (certify) moco::fft_error_coefs(g, tt.fft, &kf, &ke);
+    moco::Cert32 c32;
+    if (cert32) {
+        moco::fft32_cert_coefs(tt.fft, &c32.e1, &c32.e2);
+        c32.yinf = tt.fft.yinf32;
+        c32.sqrtpq = std::sqrt((double)tt.fft.pp.n * (double)tt.fft.pq.n);
+        c32.xmax = xmax;
+    }
     // at most one 2x2 level: no FP64 grid in HBM (the energies and the row
     // transforms form its values from the pixels)
     const bool raw_rows = g.ds <= 1;
@@ -861,7 +889,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int32_t *coarse_st = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         int32_t *recheck = out->recomputed ? out->recomputed + f0 : flag;
         double *fsurf = out->fsurf ? out->fsurf + (size_t)f0 * W * W : nullptr;
-        double *fmin = out->fmin ? out->fmin + f0 : nullptr;
+        double *fmin = out->fmin ? out->fmin + f0 : f1buf;
         double *gaps = out->gaps ? out->gaps + 2 * (size_t)f0 : nullptr;
         double *frefine = out->frefine ? out->frefine + 9 * (size_t)f0 : nullptr;
         if (raw_rows && int_energy) {
@@ -890,7 +918,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
                 else
                     HIP_TRY(moco::launch_fft32_rows(coarse, c, g, tt.fft, (float2 *)s1, st));
                 HIP_TRY(moco::launch_fft32_corr((const float2 *)s1, c, g, tt.fft, (float2 *)s2,
-                                                h, st));
+                                                h, st, xmax, &c32.nxb));
             } else {
                 if (raw_rows)
                     HIP_TRY(moco::launch_fft_rows_px(fr, c, g, tt.fft, (double2 *)s1, st));
@@ -904,9 +932,48 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
             HIP_TRY(moco::launch_combine(atab, btab, h, c, g, fsurf, fmin, coarse_st,
                                          out->shifts + 2 * (size_t)f0, gaps, frefine, st,
-                                         nullptr, certify ? recheck : nullptr, kf, ke));
+                                         nullptr, certify ? recheck : nullptr, kf, ke,
+                                         cert32 ? &c32 : nullptr));
         }
-        if (certify) {
+        if (cert32) {
+            {
+                // certified frames: f at the argmin by its definition
+                StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+                HIP_TRY(moco::launch_polish(raw_rows ? (const void *)fr : (const void *)coarse,
+                                            raw_rows, c, g, tt.coarse, coarse_st, recheck, fmin,
+                                            fsurf, gaps, st));
+            }
+            StageTimer tm(ctx, MOCO_STAGE_CORR, st);
+            // the others: uncentred energies, FP64 transforms, the FP64 certificate
+            if (raw_rows && int_energy)
+                HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, nullptr, atab, pm, edge,
+                                               st, recheck));
+            else if (raw_rows)
+                HIP_TRY(moco::launch_energy_px(fr, c, g, atab, pm, st, 0.0, recheck));
+            else
+                HIP_TRY(moco::launch_energy(coarse, c, g, false, atab, pm, st, 0.0, recheck));
+            if (raw_rows)
+                HIP_TRY(moco::launch_fft_rows_px(fr, c, g, tt.fft, (double2 *)s1, st, recheck));
+            else
+                HIP_TRY(moco::launch_fft_rows(coarse, c, g, tt.fft, (double2 *)s1, st, recheck));
+            HIP_TRY(moco::launch_fft_corr((const double2 *)s1, c, g, tt.fft, (double2 *)s2, h, st,
+                                          recheck));
+            HIP_TRY(moco::launch_fill_i32(flag2, c, 0, st));
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
+                                         out->shifts + 2 * (size_t)f0, gaps, frefine, st,
+                                         recheck, flag2, kf, ke));
+            // and what the FP64 bound leaves: direct sums
+            if (raw_rows && int_energy)
+                HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, coarse, atab, pm, edge,
+                                               st, flag2));
+            else if (raw_rows)
+                HIP_TRY(moco::launch_coarse(fr, dtype, c, g, coarse, st, flag2));
+            HIP_TRY(moco::launch_corr_fp64(coarse, tt.coarse, c, g, h, st, flag2));
+            HIP_TRY(moco::launch_combine(atab, tt.btab, h, c, g, fsurf, fmin, coarse_st,
+                                         out->shifts + 2 * (size_t)f0, gaps, frefine, st,
+                                         flag2));
+            HIP_TRY(moco::launch_add_i32(recheck, flag2, c, st));
+        } else if (certify) {
             // the frames left uncertified: direct sums, combined again (their
             // FP64 grid first, when the row transforms read the pixels)
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
@@ -935,6 +1002,12 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     return MOCO_OK;
 }
 
+bool is_fft_form(moco_form f)
+{
+    return f == MOCO_FORM_FFT || f == MOCO_FORM_FFT_CERTIFIED || f == MOCO_FORM_FFT32 ||
+           f == MOCO_FORM_FFT32_CERTIFIED;
+}
+
 int chunk_cap(moco_form form) { return form == MOCO_FORM_INT8_MFMA ? kChunkInt8 : kChunkOther; }
 
 size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &tt)
@@ -943,6 +1016,7 @@ size_t per_frame_scratch(const moco::Geom &g, moco_form form, const moco::Tmpl &
     if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED)
         return fft_layout(g).total_per_frame;
     if (form == MOCO_FORM_FFT32) return fft_layout(g, true).total_per_frame;
+    if (form == MOCO_FORM_FFT32_CERTIFIED) return fft_layout(g, true, true).total_per_frame;
     return exact_layout(g).total_per_frame;
 }
 
@@ -950,9 +1024,10 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
               const moco::Geom &g, moco_form form, const moco_outputs *out, hipStream_t st,
               char *sbase, size_t sbytes)
 {
-    if (form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED || form == MOCO_FORM_FFT32)
+    if (is_fft_form(form))
         return run_fft(ctx, d_frames, tt, T, g, out, st, sbase, sbytes,
-                       form == MOCO_FORM_FFT_CERTIFIED, form == MOCO_FORM_FFT32);
+                       form == MOCO_FORM_FFT_CERTIFIED || form == MOCO_FORM_FFT32_CERTIFIED,
+                       form == MOCO_FORM_FFT32 || form == MOCO_FORM_FFT32_CERTIFIED);
     // the exact forms recompute nothing
     if (out->recomputed && T > 0) {
         hipError_t e = moco::launch_fill_i32(out->recomputed, T, 0, st);
@@ -1012,15 +1087,17 @@ bool form_applies(const moco::Tmpl &t, moco_form f)
     case MOCO_FORM_INT8_MFMA: return t.int8_ok;
     case MOCO_FORM_FFT:
     case MOCO_FORM_FFT_CERTIFIED:
-    case MOCO_FORM_FFT32: return t.fft_ok;
+    case MOCO_FORM_FFT32:
+    case MOCO_FORM_FFT32_CERTIFIED: return t.fft_ok;
     default: return false;
     }
 }
 
 // The form AUTO runs: a form recorded for the template's key (moco_tune,
 // moco_tune_set) when it applies; else the faster of the exact int8 form and
-// the FFT form by the models above when both apply, else whichever applies,
-// else direct FP64 sums.  The FFT form runs with its argmin certificate.
+// the FFT form by the models above when both apply, else whichever applies
+// (for float32 data the FFT in FP32), else direct FP64 sums.  The FFT forms
+// run with their argmin certificates.
 moco_form auto_form(const moco::Tmpl &t)
 {
     {
@@ -1031,6 +1108,7 @@ moco_form auto_form(const moco::Tmpl &t)
     if (t.int8_ok && t.fft_ok)
         return int8_model_s(t) <= fft_model_s(t) ? MOCO_FORM_INT8_MFMA : MOCO_FORM_FFT_CERTIFIED;
     if (t.int8_ok) return MOCO_FORM_INT8_MFMA;
+    if (t.fft_ok && t.g.dtype == MOCO_F32) return MOCO_FORM_FFT32_CERTIFIED;
     if (t.fft_ok) return MOCO_FORM_FFT_CERTIFIED;
     return MOCO_FORM_FP64_EXACT;
 }
@@ -1054,7 +1132,7 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "(m=%d n=%d w=%d ds=%d dtype=%d)",
                     tg.m, tg.n, tg.w, tg.ds, (int)tg.dtype, m, n, w, downsample, (int)dtype);
     if (form != MOCO_FORM_AUTO && form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA &&
-        form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED && form != MOCO_FORM_FFT32)
+        !is_fft_form(form))
         return fail(MOCO_EINVAL, "unknown form %d", (int)form);
     if (form == MOCO_FORM_INT8_MFMA && dtype != MOCO_U16)
         return fail(MOCO_EINVAL, "the int8 matrix-core form needs uint16 data");
@@ -1065,7 +1143,7 @@ int check_stack(const moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl
                     "the int8 matrix-core form does not apply to this template (needs uint16, "
                     "grid area below 131072, grid width at most 2048 and template values "
                     "within two base-256 digits)");
-    if ((form == MOCO_FORM_FFT || form == MOCO_FORM_FFT_CERTIFIED || form == MOCO_FORM_FFT32) &&
+    if (is_fft_form(form) &&
         !tt.fft_ok)
         return fail(MOCO_EINVAL, "the FFT form does not apply to this template (transform "
                                  "lengths above %d)", moco::kFftMaxLen);
@@ -1189,6 +1267,7 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
     case MOCO_FORM_FFT:
     case MOCO_FORM_FFT_CERTIFIED:
     case MOCO_FORM_FFT32:
+    case MOCO_FORM_FFT32_CERTIFIED:
         if (!t.fft_ok) return fail(MOCO_EINVAL, "the FFT form does not apply");
         *resolved = requested;
         return MOCO_OK;
@@ -1225,10 +1304,13 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     const int T = frames > 0 ? frames : 1024;
     hipStream_t st = (hipStream_t)hip_stream;
     if (seconds_per_frame)
-        for (int k = 0; k < 5; ++k) seconds_per_frame[k] = -1.0;
+        for (int k = 0; k < MOCO_FORM_COUNT; ++k) seconds_per_frame[k] = -1.0;
     std::vector<moco_form> cand;
     if (t.int8_ok) cand.push_back(MOCO_FORM_INT8_MFMA);
     if (t.fft_ok) cand.push_back(MOCO_FORM_FFT_CERTIFIED);
+    // (copies of the template pass the FP32 bound at once, which says little of
+    // uint16 frames whose gaps are a few per cent of f: timed for float32 only)
+    if (t.fft_ok && g.dtype == MOCO_F32) cand.push_back(MOCO_FORM_FFT32_CERTIFIED);
     if (cand.empty()) cand.push_back(MOCO_FORM_FP64_EXACT);
     DeviceGuard dg(ctx->device);
     // T copies of the template (its own frame: a realistic image, the shift at
@@ -1285,8 +1367,7 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
 
 int moco_tune_set(int m, int n, int w, int downsample, moco_dtype dtype, moco_form form)
 {
-    if (form != MOCO_FORM_FFT && form != MOCO_FORM_FFT_CERTIFIED && form != MOCO_FORM_FP64_EXACT &&
-        form != MOCO_FORM_INT8_MFMA)
+    if (form != MOCO_FORM_FP64_EXACT && form != MOCO_FORM_INT8_MFMA && !is_fft_form(form))
         return fail(MOCO_EINVAL, "moco_tune_set: form %d is not a concrete form", (int)form);
     if (dtype != MOCO_U16 && dtype != MOCO_F32)
         return fail(MOCO_EINVAL, "moco_tune_set: unknown dtype %d", (int)dtype);
@@ -2033,6 +2114,8 @@ int moco_server_add_source(moco_server *srv, int source, const void *h_template,
     sc.g = g;
     moco_form resolved = MOCO_FORM_AUTO;
     (void)moco_template_form(tp, MOCO_FORM_AUTO, &resolved);
+    // the certified FP32 form is not served: float32 sources run the FP64 one
+    if (resolved == MOCO_FORM_FFT32_CERTIFIED) resolved = MOCO_FORM_FFT_CERTIFIED;
     sc.form = resolved;
     sc.fbytes = fbytes;
     sc.pf = per_frame_scratch(g, resolved, tp->t);

@@ -220,6 +220,22 @@ __device__ C *fft_lds(C *a, C *b, int rows, const FftPlan &pl, const C *tw)
     return a;
 }
 
+// Largest of one value per thread of the block, stored by thread 0 (every
+// thread calls it; it synchronises the block).
+template <typename R>
+__device__ void block_max_store(R v, R *dst)
+{
+    __shared__ R wm[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if (threadIdx.x % 64 == 0) wm[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        R m = wm[0];
+        for (int k = 1; k < (int)(blockDim.x / 64); ++k) m = fmax(m, wm[k]);
+        *dst = m;
+    }
+}
+
 // The block's copy of a length-n twiddle table (no barrier).
 template <typename C>
 __device__ __forceinline__ void load_twiddles(const C *__restrict__ g, int n, C *lds)
@@ -236,9 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
                                                      int mg, int ng, int rp, FftPlan pq,
                                                      const typename Cx<R>::T *__restrict__ twq,
                                                      double center,
-                                                     typename Cx<R>::T *__restrict__ s1)
+                                                     typename Cx<R>::T *__restrict__ s1,
+                                                     const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *lds = (C *)lds_d;
     const int Q = pq.n, qh = Q / 2 + 1;
@@ -301,15 +319,20 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(const void *__restrict__ sr
 // Pass 2: columns.  Block (group of kb bins, frame).  SPEC: write the full
 // column transforms to spec[k][p] (the template).  Otherwise multiply by
 // conj(spec), inverse, keep s = -(w-1) .. w-1 into s2[frame][s+w-1][k].
+// xmax (may be null): the largest |X_k|^2 of the frame's spectrum over the
+// block's bins, at xmax[frame][block].
 template <bool SPEC, typename R>
 __global__ __launch_bounds__(kBlock) void k_fft_cols(const typename Cx<R>::T *__restrict__ s1,
                                                      int mg, int qh, int kb, int w, FftPlan pp,
                                                      const typename Cx<R>::T *__restrict__ twp,
                                                      const typename Cx<R>::T *__restrict__ spec_in,
                                                      typename Cx<R>::T *__restrict__ spec_out,
-                                                     typename Cx<R>::T *__restrict__ s2)
+                                                     typename Cx<R>::T *__restrict__ s2,
+                                                     const int32_t *__restrict__ only,
+                                                     R *__restrict__ xmax)
 {
     using C = typename Cx<R>::T;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *lds = (C *)lds_d;
     const int P = pp.n;
@@ -328,9 +351,14 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(const typename Cx<R>::T *__
                 spec_out[(size_t)(k0 + kk) * P + p] = v[kk * P + p];
         return;
     }
+    R m2 = 0;
     for (int kk = 0; kk < nk; ++kk)
-        for (int p = threadIdx.x; p < P; p += kBlock)
-            v[kk * P + p] = cmulc(v[kk * P + p], spec_in[(size_t)(k0 + kk) * P + p]);
+        for (int p = threadIdx.x; p < P; p += kBlock) {
+            const C x = v[kk * P + p];
+            m2 = fmax(m2, x.x * x.x + x.y * x.y);
+            v[kk * P + p] = cmulc(x, spec_in[(size_t)(k0 + kk) * P + p]);
+        }
+    if (xmax) block_max_store(m2, xmax + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
     __syncthreads();
     C *u = fft_lds<true>(v, v == bufa ? bufb : bufa, nk, pp, tw);
     const int W = 2 * w - 1;
@@ -351,9 +379,11 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows_back(const typename Cx<R>::
                                                           int qh, int w, int rp, double scale,
                                                           FftPlan pq,
                                                           const typename Cx<R>::T *__restrict__ twq,
-                                                          double *__restrict__ h)
+                                                          double *__restrict__ h,
+                                                          const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *lds = (C *)lds_d;
     const int Q = pq.n, W = 2 * w - 1;
@@ -505,10 +535,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ s
                                                       int mg, int ng,
                                                       const typename Cx<R>::T *__restrict__ twq,
                                                       double center,
-                                                      typename Cx<R>::T *__restrict__ s1)
+                                                      typename Cx<R>::T *__restrict__ s1,
+                                                      const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
     using G = WGeom<Q, T>;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + Q;
     constexpr int qh = Q / 2 + 1;
@@ -542,17 +574,20 @@ __global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ s
     }
 }
 
-// Columns: forward, times conj(spec), inverse, the 2w-1 outputs kept, as
-// k_fft_cols<false>.
+// Columns: forward, times conj(spec), inverse, the 2w-1 outputs kept, and
+// the block's largest |X_k|^2 when xmax is given, as k_fft_cols<false>.
 template <typename R, int P, int T>
 __global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *__restrict__ s1,
                                                       int mg, int qh, int w,
                                                       const typename Cx<R>::T *__restrict__ twp,
                                                       const typename Cx<R>::T *__restrict__ spec,
-                                                      typename Cx<R>::T *__restrict__ s2)
+                                                      typename Cx<R>::T *__restrict__ s2,
+                                                      const int32_t *__restrict__ only,
+                                                      R *__restrict__ xmax)
 {
     using C = typename Cx<R>::T;
     using G = WGeom<P, T>;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + P;
     const int k0 = blockIdx.x * G::per_block, nk = min(G::per_block, qh - k0);
@@ -565,15 +600,21 @@ __global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *_
     __syncthreads();
     const int lane = threadIdx.x % 64, tr = (threadIdx.x / 64) * G::per_wave + lane / T;
     const int tl = lane % T;
+    R m2 = 0;
     if (tr < nk) {
         C *buf = bufs + tr * G::stride;
         WPass<C, P, T, false, 0>::run(buf, tw, tl);
         const C *sp = spec + (size_t)(k0 + tr) * P;
 #pragma unroll 4
-        for (int p = tl; p < P; p += T) buf[p] = cmulc(buf[p], sp[p]);
+        for (int p = tl; p < P; p += T) {
+            const C x = buf[p];
+            m2 = fmax(m2, x.x * x.x + x.y * x.y);
+            buf[p] = cmulc(x, sp[p]);
+        }
         asm volatile("" ::: "memory");
         WPass<C, P, T, true, 0>::run(buf, tw, tl);
     }
+    if (xmax) block_max_store(m2, xmax + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
     __syncthreads();
     const int W = 2 * w - 1;
     C *out = s2 + (size_t)blockIdx.y * W * qh;
@@ -589,10 +630,12 @@ template <typename R, int Q, int T>
 __global__ __launch_bounds__(kWaveBlock) void k_wback(const typename Cx<R>::T *__restrict__ s2,
                                                       int qh, int w, double scale,
                                                       const typename Cx<R>::T *__restrict__ twq,
-                                                      double *__restrict__ h)
+                                                      double *__restrict__ h,
+                                                      const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
     using G = WGeom<Q, T>;
+    if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + Q;
     const int W = 2 * w - 1;
@@ -665,21 +708,21 @@ bool wave_length(int n)
 
 template <typename R, int SRC, int Q>
 void wrows_launch(const void *src, int C, const Geom &g, const typename Cx<R>::T *twq,
-                  double center, typename Cx<R>::T *s1, hipStream_t st)
+                  double center, typename Cx<R>::T *s1, hipStream_t st, const int32_t *only)
 {
     constexpr int T = wave_lanes<R>();
     const int npairs = (g.mg + 1) / 2;
     const int pb = WGeom<Q, T>::per_block;
     k_wrows<SRC, R, Q, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, Q>(), st>>>(
-        src, g.m, g.n, g.mg, g.ng, twq, center, s1);
+        src, g.m, g.n, g.mg, g.ng, twq, center, s1, only);
 }
 
 template <typename R, int SRC>
 bool wrows(const void *src, int C, const Geom &g, const typename Cx<R>::T *twq, double center,
-           typename Cx<R>::T *s1, hipStream_t st, int Q)
+           typename Cx<R>::T *s1, hipStream_t st, int Q, const int32_t *only)
 {
 #define MOCO_WL_ROWS(L) \
-    case L: wrows_launch<R, SRC, L>(src, C, g, twq, center, s1, st); return true;
+    case L: wrows_launch<R, SRC, L>(src, C, g, twq, center, s1, st, only); return true;
     switch (Q) {
         MOCO_WAVE_LENGTHS(MOCO_WL_ROWS)
     default:
@@ -691,14 +734,15 @@ bool wrows(const void *src, int C, const Geom &g, const typename Cx<R>::T *twq, 
 template <typename R>
 bool wcols(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
            const typename Cx<R>::T *twp, const typename Cx<R>::T *spec, typename Cx<R>::T *s2,
-           hipStream_t st)
+           hipStream_t st, const int32_t *only, R *xmax, int *nxb)
 {
     constexpr int T = wave_lanes<R>();
 #define MOCO_WL_COLS(L)                                                                       \
     case L: {                                                                                 \
         const int pb = WGeom<L, T>::per_block;                                                \
-        k_wcols<R, L, T><<<dim3((ft.qh + pb - 1) / pb, C), kWaveBlock, wave_lds<R, L>(), st>>>( \
-            s1, g.mg, ft.qh, g.w, twp, spec, s2);                                             \
+        *nxb = (ft.qh + pb - 1) / pb;                                                         \
+        k_wcols<R, L, T><<<dim3(*nxb, C), kWaveBlock, wave_lds<R, L>(), st>>>(                 \
+            s1, g.mg, ft.qh, g.w, twp, spec, s2, only, xmax);                                 \
         return true;                                                                          \
     }
     switch (ft.pp.n) {
@@ -711,7 +755,8 @@ bool wcols(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
 
 template <typename R>
 bool wback(const typename Cx<R>::T *s2, int C, const Geom &g, const FftTmpl &ft,
-           const typename Cx<R>::T *twq, double scale, double *h, hipStream_t st)
+           const typename Cx<R>::T *twq, double scale, double *h, hipStream_t st,
+           const int32_t *only)
 {
     constexpr int T = wave_lanes<R>();
     const int npairs = (g.W + 1) / 2;
@@ -719,7 +764,7 @@ bool wback(const typename Cx<R>::T *s2, int C, const Geom &g, const FftTmpl &ft,
     case L: {                                                                                   \
         const int pb = WGeom<L, T>::per_block;                                                  \
         k_wback<R, L, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, L>(), st>>>( \
-            s2, ft.qh, g.w, scale, twq, h);                                                     \
+            s2, ft.qh, g.w, scale, twq, h, only);                                               \
         return true;                                                                            \
     }
     switch (ft.pq.n) {
@@ -815,6 +860,23 @@ void fft_error_coefs(const Geom &g, const FftTmpl &ft, double *kf, double *ke)
     *ke = (4.0 * (g.mg + g.ng + 2.0 * g.w + 16.0) + 6.0) * u;
 }
 
+// The single-precision form's factors, the same pass terms in u32 = 2^-24:
+// e1 = eps + u32 for the frame's transform (its centred values rounded to
+// FP32 once), e2 = eps + 7 u32 for the inverse, the template spectrum rounded
+// from FP64 (2 u32), the complex product (4 u32) and the scale.
+void fft32_cert_coefs(const FftTmpl &ft, double *e1, double *e2)
+{
+    const double u = 0x1p-24;
+    double eps = 2.0 * u;
+    for (const FftPlan *pl : {&ft.pp, &ft.pq})
+        for (int p = 0; p < pl->npass; ++p) {
+            const int r = pl->radix[p];
+            eps += (5.0 + (r == 2 ? 1.0 : r == 4 ? 2.0 : r == 8 ? 6.0 : r == 3 ? 10.0 : 18.0)) * u;
+        }
+    *e1 = eps + u;
+    *e2 = eps + 7.0 * u;
+}
+
 FftGeom fft_geom(const Geom &g)
 {
     FftGeom f{};
@@ -863,7 +925,7 @@ struct FftTabs<float> {
 
 template <typename R>
 hipError_t rows_grid(const double *grid, int C, const Geom &g, const FftTmpl &ft,
-                     typename Cx<R>::T *s1, hipStream_t st)
+                     typename Cx<R>::T *s1, hipStream_t st, const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -871,13 +933,14 @@ hipError_t rows_grid(const double *grid, int C, const Geom &g, const FftTmpl &ft
     const int rp = rows_per_block(ft.pq.n, esz);
     const int npairs = (g.mg + 1) / 2;
     k_fft_rows<0, R><<<dim3((npairs + rp - 1) / rp, C), kBlock, block_lds(rp, ft.pq.n, esz), st>>>(
-        grid, g.m, g.n, g.mg, g.ng, rp, ft.pq, FftTabs<R>::twq(ft), FftTabs<R>::center(ft), s1);
+        grid, g.m, g.n, g.mg, g.ng, rp, ft.pq, FftTabs<R>::twq(ft), FftTabs<R>::center(ft), s1,
+        only);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
-                   typename Cx<R>::T *s1, hipStream_t st)
+                   typename Cx<R>::T *s1, hipStream_t st, const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -893,50 +956,59 @@ hipError_t rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
     if (g_wave_fft) {
         bool ok = false;
         if (u16 && g.ds)
-            ok = wrows<R, 1>(frames, C, g, tw, c, s1, st, ft.pq.n);
+            ok = wrows<R, 1>(frames, C, g, tw, c, s1, st, ft.pq.n, only);
         else if (u16)
-            ok = wrows<R, 2>(frames, C, g, tw, c, s1, st, ft.pq.n);
+            ok = wrows<R, 2>(frames, C, g, tw, c, s1, st, ft.pq.n, only);
         else if (g.ds)
-            ok = wrows<R, 3>(frames, C, g, tw, c, s1, st, ft.pq.n);
+            ok = wrows<R, 3>(frames, C, g, tw, c, s1, st, ft.pq.n, only);
         else
-            ok = wrows<R, 4>(frames, C, g, tw, c, s1, st, ft.pq.n);
+            ok = wrows<R, 4>(frames, C, g, tw, c, s1, st, ft.pq.n, only);
         if (ok) return hipGetLastError();
     }
     if (u16 && g.ds)
-        k_fft_rows<1, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+        k_fft_rows<1, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1,
+                                                  only);
     else if (u16)
-        k_fft_rows<2, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+        k_fft_rows<2, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1,
+                                                  only);
     else if (g.ds)
-        k_fft_rows<3, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+        k_fft_rows<3, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1,
+                                                  only);
     else
-        k_fft_rows<4, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1);
+        k_fft_rows<4, R><<<grid, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, rp, ft.pq, tw, c, s1,
+                                                  only);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t corr(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
-                typename Cx<R>::T *s2, double *h, hipStream_t st)
+                typename Cx<R>::T *s2, double *h, hipStream_t st, const int32_t *only, R *xmax,
+                int *nxb)
 {
     clear_stale_error();
+    int nb = 0;
+    if (nxb) *nxb = 0;
     if (C == 0) return hipSuccess;
     const size_t esz = sizeof(typename Cx<R>::T);
     if (!g_wave_fft ||
-        !wcols<R>(s1, C, g, ft, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), s2, st)) {
+        !wcols<R>(s1, C, g, ft, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), s2, st, only, xmax,
+                  &nb)) {
         const int kb = rows_per_block(ft.pp.n, esz);
-        k_fft_cols<false, R><<<dim3((ft.qh + kb - 1) / kb, C), kBlock,
-                               block_lds(kb, ft.pp.n, esz), st>>>(
+        nb = (ft.qh + kb - 1) / kb;
+        k_fft_cols<false, R><<<dim3(nb, C), kBlock, block_lds(kb, ft.pp.n, esz), st>>>(
             s1, g.mg, ft.qh, kb, g.w, ft.pp, FftTabs<R>::twp(ft), FftTabs<R>::spec(ft), nullptr,
-            s2);
+            s2, only, xmax);
     }
+    if (nxb) *nxb = nb;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)ft.pp.n * (double)ft.pq.n);
-    if (!g_wave_fft || !wback<R>(s2, C, g, ft, FftTabs<R>::twq(ft), scale, h, st)) {
+    if (!g_wave_fft || !wback<R>(s2, C, g, ft, FftTabs<R>::twq(ft), scale, h, st, only)) {
         const int rp = rows_per_block(ft.pq.n, esz);
         const int npairs = (g.W + 1) / 2;
         k_fft_rows_back<R><<<dim3((npairs + rp - 1) / rp, C), kBlock,
                              block_lds(rp, ft.pq.n, esz), st>>>(
-            s2, ft.qh, g.w, rp, scale, ft.pq, FftTabs<R>::twq(ft), h);
+            s2, ft.qh, g.w, rp, scale, ft.pq, FftTabs<R>::twq(ft), h, only);
     }
     return hipGetLastError();
 }
@@ -944,15 +1016,15 @@ hipError_t corr(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl
 }  // namespace
 
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
-                           double2 *s1, hipStream_t st)
+                           double2 *s1, hipStream_t st, const int32_t *only)
 {
-    return rows_grid<double>(grid, C, g, ft, s1, st);
+    return rows_grid<double>(grid, C, g, ft, s1, st, only);
 }
 
 hipError_t launch_fft_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
-                              double2 *s1, hipStream_t st)
+                              double2 *s1, hipStream_t st, const int32_t *only)
 {
-    return rows_px<double>(frames, C, g, ft, s1, st);
+    return rows_px<double>(frames, C, g, ft, s1, st, only);
 }
 
 hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
@@ -962,32 +1034,39 @@ hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, 
     const int kb = rows_per_block(ft.pp.n);
     k_fft_cols<true, double><<<dim3((ft.qh + kb - 1) / kb, 1), kBlock,
                                block_lds(kb, ft.pp.n, sizeof(double2)), st>>>(
-        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, nullptr, spec, nullptr);
+        s1, g.mg, ft.qh, kb, g.w, ft.pp, ft.twp, nullptr, spec, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
-                           double2 *s2, double *h, hipStream_t st)
+                           double2 *s2, double *h, hipStream_t st, const int32_t *only)
 {
-    return corr<double>(s1, C, g, ft, s2, h, st);
+    return corr<double>(s1, C, g, ft, s2, h, st, only, nullptr, nullptr);
 }
 
 hipError_t launch_fft32_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                              float2 *s1, hipStream_t st)
 {
-    return rows_grid<float>(grid, C, g, ft, s1, st);
+    return rows_grid<float>(grid, C, g, ft, s1, st, nullptr);
 }
 
 hipError_t launch_fft32_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
                                 float2 *s1, hipStream_t st)
 {
-    return rows_px<float>(frames, C, g, ft, s1, st);
+    return rows_px<float>(frames, C, g, ft, s1, st, nullptr);
 }
 
 hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTmpl &ft,
-                             float2 *s2, double *h, hipStream_t st)
+                             float2 *s2, double *h, hipStream_t st, float *xmax, int *nxb)
 {
-    return corr<float>(s1, C, g, ft, s2, h, st);
+    return corr<float>(s1, C, g, ft, s2, h, st, nullptr, xmax, nxb);
+}
+
+int fft_cols_blocks(const Geom &g, const FftTmpl &ft, size_t esz)
+{
+    if (g_wave_fft && wave_length(ft.pp.n)) return (ft.qh + 3) / 4;
+    const int kb = rows_per_block(ft.pp.n, esz);
+    return (ft.qh + kb - 1) / kb;
 }
 
 }  // namespace moco

@@ -231,8 +231,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
                                                    int mg, int ng, int w, bool flip,
                                                    double *__restrict__ atab,
                                                    int32_t *__restrict__ pmax, double pscale,
-                                                   double center)
+                                                   double center, const int32_t *__restrict__ only)
 {
+    if (only && !only[blockIdx.x]) return;
     extern __shared__ double elds[];
     const int E = w - 1, W = 2 * w - 1;
     double *colL = elds, *colR = colL + (E + 1), *rowT = colR + (E + 1), *rowB = rowT + (E + 1);
@@ -352,8 +353,9 @@ __device__ inline double wave_incl_scan(double v, int lane)
 template <int SRC, int NCH>
 __global__ __launch_bounds__(kErWaves * 64) void k_energy_rows(
     const void *__restrict__ src, int m, int n, int mg, int ng, int w, double *__restrict__ atab,
-    int32_t *__restrict__ pmax, double pscale, double center)
+    int32_t *__restrict__ pmax, double pscale, double center, const int32_t *__restrict__ only)
 {
+    if (only && !only[blockIdx.x]) return;
     const int E = w - 1, W = 2 * w - 1, we1 = E > 0 ? E : 1;
     // LDS: rT[w] | rB[w] | cL[w] | cR[w] | cpart[NW][2][we1] | wtot[NW] | wmax[NW]
     extern __shared__ double erl[];
@@ -595,6 +597,38 @@ __device__ bool certified(const double *At, const double *btab, int mg, int ng, 
     return margin > 2.0 * delta / amin;
 }
 
+// The single-precision form's certificate: the same rule with the
+// correlation's error bound hb of Cert32 (first order in u32 = 2^-24, doubled)
+// in place of kf sqrt(m'n' Sa Sb).  Its norms are those of the centred grids:
+// |x|_2 = sqrt(Sa), |y|_2 = sqrt(Sb); |X|_inf is the largest magnitude of the
+// frame's computed spectrum (its square formed in FP32, three roundings) and
+// |Y|_inf that of the template's FP32 spectrum.  The bound holds in 2-norm
+// over the whole P x Q output (frame transform error e1 sqrt(PQ) |x|_2 times
+// |Y|_inf; template spectrum, product and inverse errors times |X|_inf
+// sqrt(PQ) |y|_2; the 1/(PQ) scale), hence for every shift.
+__device__ __forceinline__ bool certified32(const double *At, const double *btab, int mg, int ng,
+                                            int w, double f1, double f2, double ke,
+                                            const float *xmax, int nxb, double e1, double e2,
+                                            double yinf, double sqrtpq, int frame)
+{
+    const double u = 0x1p-53, u32 = 0x1p-24;
+    if (!(f1 == f1) || isinf(f1)) return false;
+    if (isinf(f2)) return true;
+    const int W = 2 * w - 1, c0 = (w - 1) * W + (w - 1);
+    const double sa = fmax(At[c0], 0.0), sb = fmax(btab[c0], 0.0);
+    const float *xm = xmax + (size_t)frame * nxb;
+    float x2 = 0.0f;
+    for (int k = 0; k < nxb; ++k) x2 = fmaxf(x2, xm[k]);
+    if (!(x2 <= 3.0e38f)) return false;
+    const double xinf = sqrt((double)x2) * (1.0 + 4.0 * u32);
+    const double na = sqrt(sa), nb = sqrt(sb);
+    const double hb = 2.0 * (e1 * na * yinf + e2 * (xinf + e1 * sqrtpq * na) * nb);
+    const double delta = 1.01 * ((ke + 4.0 * u) * (sa + sb) + 2.0 * u * na * nb + 2.0 * hb);
+    const double amin = (double)(mg - (w - 1)) * (double)(ng - (w - 1));
+    const double margin = (f2 - f1) - 1.01 * u * (fabs(f1) + fabs(f2));
+    return margin > 2.0 * delta / amin;
+}
+
 __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ atab,
                                                     const double *__restrict__ btab,
                                                     const double *__restrict__ hbuf, int mg,
@@ -607,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ a
                                                     double *__restrict__ frefine,
                                                     const int32_t *__restrict__ only,
                                                     int32_t *__restrict__ recheck, double kf,
-                                                    double ke)
+                                                    double ke, Cert32 c32)
 {
     const int W = 2 * w - 1;
     const int frame = blockIdx.x;
@@ -634,15 +668,71 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ a
             shifts[2 * frame + 1] = r.t;
             if (gaps) gaps[2 * frame + 1] = INFINITY;
         }
-        if (recheck) recheck[frame] = certified(At, btab, mg, ng, w, r.f, r.second, kf, ke) ? 0 : 1;
+        if (recheck) {
+            const bool ok = c32.xmax
+                                ? certified32(At, btab, mg, ng, w, r.f, r.second, ke, c32.xmax,
+                                              c32.nxb, c32.e1, c32.e2, c32.yinf, c32.sqrtpq,
+                                              frame)
+                                : certified(At, btab, mg, ng, w, r.f, r.second, kf, ke);
+            recheck[frame] = ok ? 0 : 1;
+        }
     }
     if (!ds && frefine && threadIdx.x < 9) frefine[(size_t)frame * 9 + threadIdx.x] = NAN;
+}
+
+// f at the coarse argmin by its definition (eq. (f)): the FP64 sum of squared
+// differences of the searched grids over D, in a fixed order (exact for uint16
+// grids: multiples of 1/16 below 2^32 per term).  One block per frame.
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src, int m, int n,
+                                                   int mg, int ng, int w,
+                                                   const double *__restrict__ tcoarse,
+                                                   const int32_t *__restrict__ coarse_st,
+                                                   const int32_t *__restrict__ skip,
+                                                   double *__restrict__ fmin,
+                                                   double *__restrict__ fsurf,
+                                                   double *__restrict__ gaps)
+{
+    const int frame = blockIdx.x;
+    if (skip && skip[frame]) return;
+    const int s = coarse_st[2 * frame], t = coarse_st[2 * frame + 1];
+    const void *a = grid_frame<SRC>(src, frame, m, n, mg, ng);
+    const int i0 = max(0, -s), i1 = min(mg, mg - s), j0 = max(0, -t), j1 = min(ng, ng - t);
+    const int nr = i1 - i0, nc = j1 - j0;
+    double acc = 0.0;
+    for (long long p = threadIdx.x; p < (long long)nr * nc; p += kBlock) {
+        const int i = i0 + (int)(p / nc), j = j0 + (int)(p % nc);
+        const double d = grid_at<SRC>(a, n, ng, i + s, j + t) - tcoarse[(size_t)i * ng + j];
+        acc = fma(d, d, acc);
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+        const double f = red[0] / area;
+        const double f0 = fmin[frame];
+        if (gaps) gaps[2 * frame] += f0 - f;
+        fmin[frame] = f;
+        const int W = 2 * w - 1;
+        if (fsurf) fsurf[(size_t)frame * W * W + (size_t)(s + w - 1) * W + (t + w - 1)] = f;
+    }
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int count, int32_t v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
+}
+
+__global__ void k_add_i32(int32_t *__restrict__ p, const int32_t *__restrict__ q, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] += q[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1408,23 +1498,23 @@ static size_t energy_rows_lds(const Geom &g)
 
 template <int SRC>
 static void energy_rows_launch(const void *src, int C, const Geom &g, double *atab, int32_t *pmax,
-                               double pscale, double center, hipStream_t st)
+                               double pscale, double center, hipStream_t st, const int32_t *only)
 {
     const int nch = (g.ng + 255) / 256;
     const size_t lds = energy_rows_lds(g);
     const dim3 grid(C), blk(kErWaves * 64);
     if (nch <= 1)
-        k_energy_rows<SRC, 1><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+        k_energy_rows<SRC, 1><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center, only);
     else if (nch <= 2)
-        k_energy_rows<SRC, 2><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+        k_energy_rows<SRC, 2><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center, only);
     else if (nch <= 4)
-        k_energy_rows<SRC, 4><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+        k_energy_rows<SRC, 4><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center, only);
     else
-        k_energy_rows<SRC, 8><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center);
+        k_energy_rows<SRC, 8><<<grid, blk, lds, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, atab, pmax, pscale, center, only);
 }
 
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
-                         int32_t *pmax, hipStream_t st, double center)
+                         int32_t *pmax, hipStream_t st, double center, const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1436,18 +1526,18 @@ hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, 
         if (g.m % b == 0 && g.n % b == 0) pscale = (double)b * b;
     }
     if (!flip && energy_rows_applicable(g)) {
-        energy_rows_launch<0>(coarse, C, g, atab, pmax, pscale, center, st);
+        energy_rows_launch<0>(coarse, C, g, atab, pmax, pscale, center, st, only);
         return hipGetLastError();
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
     k_energy<0><<<C, kBlock, lds, st>>>(coarse, g.m, g.n, g.mg, g.ng, g.w, flip, atab, pmax,
-                                        pscale, center);
+                                        pscale, center, only);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
-                            int32_t *pmax, hipStream_t st, double center)
+                            int32_t *pmax, hipStream_t st, double center, const int32_t *only)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1460,41 +1550,71 @@ hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *at
     }
     if (energy_rows_applicable(g)) {
         if (u16 && g.ds)
-            energy_rows_launch<1>(frames, C, g, atab, pmax, pscale, center, st);
+            energy_rows_launch<1>(frames, C, g, atab, pmax, pscale, center, st, only);
         else if (u16)
-            energy_rows_launch<2>(frames, C, g, atab, pmax, pscale, center, st);
+            energy_rows_launch<2>(frames, C, g, atab, pmax, pscale, center, st, only);
         else if (g.ds)
-            energy_rows_launch<3>(frames, C, g, atab, pmax, pscale, center, st);
+            energy_rows_launch<3>(frames, C, g, atab, pmax, pscale, center, st, only);
         else
-            energy_rows_launch<4>(frames, C, g, atab, pmax, pscale, center, st);
+            energy_rows_launch<4>(frames, C, g, atab, pmax, pscale, center, st, only);
         return hipGetLastError();
     }
     const int E = g.w - 1;
     const size_t lds = ((size_t)10 * (E + 1) + 1 + 2 * kBlock) * sizeof(double);
     if (u16 && g.ds)
         k_energy<1><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale, center);
+                                            pscale, center, only);
     else if (u16)
         k_energy<2><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale, center);
+                                            pscale, center, only);
     else if (g.ds)
         k_energy<3><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale, center);
+                                            pscale, center, only);
     else
         k_energy<4><<<C, kBlock, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w, false, atab, pmax,
-                                            pscale, center);
+                                            pscale, center, only);
     return hipGetLastError();
 }
 
 hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st,
-                          const int32_t *only, int32_t *recheck, double kf, double ke)
+                          const int32_t *only, int32_t *recheck, double kf, double ke,
+                          const Cert32 *c32)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     k_combine<<<C, kBlock, 0, st>>>(atab, btab, h, g.mg, g.ng, g.w, g.ds, fsurf, fmin, coarse_st,
-                                    shifts, gaps, frefine, only, recheck, kf, ke);
+                                    shifts, gaps, frefine, only, recheck, kf, ke,
+                                    c32 ? *c32 : Cert32{});
+    return hipGetLastError();
+}
+
+hipError_t launch_polish(const void *src, bool raw, int C, const Geom &g, const double *tcoarse,
+                         const int32_t *coarse_st, const int32_t *skip, double *fmin,
+                         double *fsurf, double *gaps, hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (!fmin) return hipErrorInvalidValue;
+    const bool u16 = g.dtype == MOCO_U16;
+    if (!raw)
+        k_polish<0><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
+                                          fmin, fsurf, gaps);
+    else if (g.ds > 1)
+        return hipErrorInvalidValue;
+    else if (u16 && g.ds)
+        k_polish<1><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
+                                          fmin, fsurf, gaps);
+    else if (u16)
+        k_polish<2><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
+                                          fmin, fsurf, gaps);
+    else if (g.ds)
+        k_polish<3><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
+                                          fmin, fsurf, gaps);
+    else
+        k_polish<4><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
+                                          fmin, fsurf, gaps);
     return hipGetLastError();
 }
 
@@ -1503,6 +1623,14 @@ hipError_t launch_fill_i32(int32_t *p, int count, int32_t v, hipStream_t st)
     clear_stale_error();
     if (count <= 0) return hipSuccess;
     k_fill_i32<<<(count + kBlock - 1) / kBlock, kBlock, 0, st>>>(p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_i32(int32_t *p, const int32_t *q, int count, hipStream_t st)
+{
+    clear_stale_error();
+    if (count <= 0) return hipSuccess;
+    k_add_i32<<<(count + kBlock - 1) / kBlock, kBlock, 0, st>>>(p, q, count);
     return hipGetLastError();
 }
 

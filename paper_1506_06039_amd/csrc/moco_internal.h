@@ -71,6 +71,19 @@ struct FftTmpl {
     float2 *spec32 = nullptr;       // [qh][P] transform of the zero-padded b' - center
                                     // (computed in FP64, rounded)
     double *btab32 = nullptr;       // [W][W] sum of (b' - center)^2 over D_{s,t}
+    double yinf32 = 0.0;            // largest |spec32| (the certificate's |Y|_inf)
+};
+
+// The single-precision form's certificate: a bound on the FP32 correlation's
+// error from the norms of the centred grids and the largest magnitudes of
+// their spectra (the frame's measured by the column kernel):
+// |h^ - h| <= hb = 2 (e1 |x|_2 |Y|_inf + e2 (|X|_inf + e1 sqrt(PQ) |x|_2) |y|_2).
+struct Cert32 {
+    const float *xmax = nullptr;    // [frame][nxb] block maxima of |X_k|^2
+    int nxb = 0;
+    double e1 = 0.0, e2 = 0.0;      // frame transform; inverse, template and product
+    double yinf = 0.0;
+    double sqrtpq = 0.0;
 };
 
 // Resident, prepared template.  All pointers are device memory owned by it.
@@ -109,25 +122,36 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
 // for the x2 step (uint16), else INT32_MAX.  Not flipped, grids where
 // energy_rows_applicable take the one-pass row kernel.
 hipError_t launch_energy(const double *coarse, int C, const Geom &g, bool flip, double *atab,
-                         int32_t *pmax, hipStream_t st, double center = 0.0);
+                         int32_t *pmax, hipStream_t st, double center = 0.0,
+                         const int32_t *only = nullptr);
 // the same (not flipped) from the frames' pixels, forming the grid values as
 // they are read (at most one 2x2 level): the values launch_coarse would write
 hipError_t launch_energy_px(const void *frames, int C, const Geom &g, double *atab,
-                            int32_t *pmax, hipStream_t st, double center = 0.0);
+                            int32_t *pmax, hipStream_t st, double center = 0.0,
+                            const int32_t *only = nullptr);
 bool energy_rows_applicable(const Geom &g);
 // only (may be null): frames whose only[f] is 0 are skipped
 hipError_t launch_corr_fp64(const double *coarse, const double *tcoarse, int C, const Geom &g,
                             double *h, hipStream_t st, const int32_t *only = nullptr);
 // only (may be null): frames whose only[f] is 0 are skipped.  recheck (may be
 // null): recheck[f] = 0 when the argmin is certified against a correlation
-// error of at most kf sqrt(m'n' Sa Sb) and energy errors of at most ke (Sa or
-// Sb), else 1.
+// error of at most kf sqrt(m'n' Sa Sb) (or the bound of c32, when given) and
+// energy errors of at most ke (Sa or Sb), else 1.
 hipError_t launch_combine(const double *atab, const double *btab, const double *h, int C,
                           const Geom &g, double *fsurf, double *fmin, int32_t *coarse_st,
                           int32_t *shifts, double *gaps, double *frefine, hipStream_t st,
                           const int32_t *only = nullptr, int32_t *recheck = nullptr,
-                          double kf = 0.0, double ke = 0.0);
+                          double kf = 0.0, double ke = 0.0, const Cert32 *c32 = nullptr);
+// f at each frame's coarse argmin by its definition (FP64 sum of squared
+// differences of the searched grids over D), for frames whose skip[f] is 0:
+// fmin[f] and fsurf at the argmin get that value and gaps[2f] moves with it.
+// fmin holds the combine's value on entry.
+hipError_t launch_polish(const void *src, bool raw, int C, const Geom &g, const double *tcoarse,
+                         const int32_t *coarse_st, const int32_t *skip, double *fmin,
+                         double *fsurf, double *gaps, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int count, int32_t v, hipStream_t st);
+// p[i] += q[i], i < count
+hipError_t launch_add_i32(int32_t *p, const int32_t *q, int count, hipStream_t st);
 hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom &g,
                          const int32_t *coarse_st, int32_t *shifts, double *frefine,
                          double *gaps, double *partial, hipStream_t st,
@@ -211,27 +235,34 @@ bool fft_applicable(const Geom &g);
 // coefficients of the certificate: |h^ - h| <= kf sqrt(m'n' Sa Sb), energy
 // errors <= ke Sa (Sa, Sb: the grids' sums of squares)
 void fft_error_coefs(const Geom &g, const FftTmpl &ft, double *kf, double *ke);
+// e1, e2 of Cert32 for the template's transform lengths
+void fft32_cert_coefs(const FftTmpl &ft, double *e1, double *e2);
 // per frame: [qh][mg] and [W][qh] complex elements of esz bytes
 size_t fft_s1_bytes(const Geom &g, size_t esz = sizeof(double2));
 size_t fft_s2_bytes(const Geom &g, size_t esz = sizeof(double2));
+// only (may be null) on the FFT passes: frames whose only[f] is 0 are skipped
 hipError_t launch_fft_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
-                           double2 *s1, hipStream_t st);
+                           double2 *s1, hipStream_t st, const int32_t *only = nullptr);
 // the same from the frames' pixels (at most one 2x2 level), forming the
 // grid's FP64 values (box means, or the pixels) as the rows are read
 hipError_t launch_fft_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
-                              double2 *s1, hipStream_t st);
+                              double2 *s1, hipStream_t st, const int32_t *only = nullptr);
 hipError_t launch_fft_spec(const double2 *s1, const Geom &g, const FftTmpl &ft, double2 *spec,
                            hipStream_t st);
 hipError_t launch_fft_corr(const double2 *s1, int C, const Geom &g, const FftTmpl &ft,
-                           double2 *s2, double *h, hipStream_t st);
+                           double2 *s2, double *h, hipStream_t st, const int32_t *only = nullptr);
 // The single-precision form: the same passes in FP32 on the grids less
 // ft.center (ft.twp32, twq32, spec32); h (of the centred grids) in FP64.
 hipError_t launch_fft32_rows(const double *grid, int C, const Geom &g, const FftTmpl &ft,
                              float2 *s1, hipStream_t st);
 hipError_t launch_fft32_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
                                 float2 *s1, hipStream_t st);
+// xmax (may be null): [frame][fft_cols_blocks] maxima of |X_k|^2 over the
+// frame's spectrum, one per column block (*nxb, may be null, gets their count)
 hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTmpl &ft,
-                             float2 *s2, double *h, hipStream_t st);
+                             float2 *s2, double *h, hipStream_t st, float *xmax = nullptr,
+                             int *nxb = nullptr);
+int fft_cols_blocks(const Geom &g, const FftTmpl &ft, size_t esz);
 
 // ---- the corrected stack and its mean image (apply.hip) ---------------
 // frames per chunk of the mean's partial sums (0: one chunk of [m][n] FP64

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_PKG, "libmoco.so")
 
 MOCO_OK, MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE, MOCO_EBUSY, MOCO_ECANCELED = 0, -1, -2, -3, -4, -5
 MOCO_U16, MOCO_F32 = 1, 2
-FORMS = {"auto": 0, "fft": 1, "fft_cert": 2, "fp64": 3, "int8": 4, "fft32": 5}
+FORMS = {"auto": 0, "fft": 1, "fft_cert": 2, "fp64": 3, "int8": 4, "fft32": 5,
+         "fft32_cert": 6}
+FORM_COUNT = 7
 
 
 class MocoError(RuntimeError):
@@ -452,10 +454,10 @@ def tune(ctx: Context, tmpl: Template, frames: int = 0):
     of it (0: 1024) and record the fastest for its key; AUTO then picks it.
     Returns (form, {form: s/frame})."""
     chosen = _i()
-    sec = (ctypes.c_double * 5)()
+    sec = (ctypes.c_double * FORM_COUNT)()
     _check(_lib.moco_tune(ctx.handle, tmpl.handle, frames, _stream_handle(ctx.device),
                           ctypes.byref(chosen), sec))
-    times = {_FORM_NAMES[k]: sec[k] for k in range(5) if k in _FORM_NAMES and sec[k] >= 0}
+    times = {_FORM_NAMES[k]: sec[k] for k in range(FORM_COUNT) if k in _FORM_NAMES and sec[k] >= 0}
     return _FORM_NAMES[chosen.value], times
 
 

@@ -147,11 +147,154 @@ def test_fft32_chunked_equals_unchunked(gpu_lib):
 
 
 def test_fft32_never_chosen_by_auto(gpu_lib):
-    for args in ((synth.poisson512_u16(T=2).template, 32, 1),
-                 (synth.lowsnr256_f32().template, 64, 0)):
+    # the plain form never; the certified one for float32 data
+    for args, auto in (((synth.poisson512_u16(T=2).template, 32, 1), "int8"),
+                       ((synth.lowsnr256_f32().template, 64, 0), "fft32_cert")):
         ctx = gpu_lib.Context(0)
         tp = gpu_lib.Template(ctx, _to_dev(args[0]), args[1], args[2])
         assert gpu_lib.resolved_form(ctx, tp, "fft32") == "fft32"
-        assert gpu_lib.resolved_form(ctx, tp, "auto") != "fft32"
+        assert gpu_lib.resolved_form(ctx, tp, "auto") == auto
         tp.close()
         ctx.close()
+
+
+# ---- the certified single-precision form ----------------------------------
+# An argmin certified by the FP32 bound is exact, and its f is then evaluated
+# by its definition in FP64 (bit-exact on uint16); frames left uncertified go
+# through the certified FP64 form and equal its results.  So f at the argmin
+# meets the search's 1e-5 bar on every frame; the rest of the surface keeps
+# the FP32 correlation (held to F32_RTOL).
+
+
+def _cert32(moco, fr, tm, w, ds, label, aba=None):
+    """aba: (A+B)/Area scale for the rule's floor on noise-free frames."""
+    f_floor = 1e-12 if aba is None else 1e-9 * aba
+    res = _run(moco, fr, tm, w, ds, form="fft32_cert")
+    ref = _run(moco, fr, tm, w, ds, form="fft_cert")
+    orc = oracle.align(fr, tm, w, ds, want_surface=True)
+    rec = res["recomputed"]
+    assert set(np.unique(rec).tolist()) <= {0, 1, 2}, label
+    st = check(res, orc, bool(ds), exact=False, label=label, f_floor=f_floor)
+    # an argmin certified by either bound is the exact argmin of the grid
+    cert = rec < 2
+    assert np.array_equal(res["coarse"][cert], orc.coarse[cert]), label
+    # frames the FP32 bound left: the certified FP64 form's results, bit for bit
+    re = rec > 0
+    for k in ("shifts", "coarse", "fmin", "frefine", "gaps", "fsurf"):
+        assert np.array_equal(res[k][re], ref[k][re], equal_nan=True), (label, k)
+    assert np.array_equal(ref["recomputed"][re], (rec[re] == 2).astype(np.int32)), label
+    # the FP32 surfaces (the others were compared with the FP64 form's above)
+    ok = rec == 0
+    err = check_surface(res["fsurf"][ok], orc.surf[ok], A_plus_B_over_area=aba, rtol=F32_RTOL,
+                        label=label + " surface") if ok.any() else 0.0
+    _say(label, st, "recomputed", np.bincount(rec, minlength=3).tolist(),
+         "surface max rel err %.3g" % err)
+    return res, orc
+
+
+def test_fft32_cert_lowsnr256_f32_w64(gpu_lib):
+    sc = synth.lowsnr256_f32()
+    res, orc = _cert32(gpu_lib, sc.frames(0, 8), sc.template, 64, 0, "cert32 lowsnr256")
+    assert (res["recomputed"] == 0).mean() >= 0.75
+
+
+def test_fft32_cert_blobs128_meets_the_bar(gpu_lib):
+    # the high-SNR stack where the plain FP32 form's f misses 1e-5 (kappa ~350)
+    sc = synth.blobs128_f32()
+    fr = sc.frames(0, 100)
+    res, orc = _cert32(gpu_lib, fr, sc.template, 10, 0, "cert32 blobs128")
+    assert np.array_equal(res["shifts"], sc.shifts(0, 100))
+    ok = res["recomputed"] == 0
+    assert ok.mean() >= 0.75
+    rel = np.abs(res["fmin"][ok] - orc.fmin[ok]) / orc.fmin[ok]
+    assert rel.max() < 1e-12, rel.max()
+
+
+def test_fft32_cert_poisson512_u16_ds(gpu_lib):
+    # gaps of a few per cent of f: some frames certified, the others recomputed
+    sc = synth.poisson512_u16(T=2000)
+    fr = sc.frames(1, 25)
+    res, orc = _cert32(gpu_lib, fr, sc.template, 32, 1, "cert32 poisson512")
+    ok = res["recomputed"] == 0
+    # the definition's f is exact on uint16 grids (multiples of 1/16)
+    assert np.array_equal(res["fmin"][ok], orc.fmin[ok])
+    ex = _run(gpu_lib, fr, sc.template, 32, 1, form="int8", surface=False)
+    assert np.array_equal(res["shifts"], ex["shifts"])
+
+
+def test_fft32_cert_exact_ties_are_recomputed(gpu_lib):
+    # rows of period two and exact rolls: many shifts tie exactly
+    tmpl, fr, _ = synth.row_periodic(96, 100, 12, "f32", max_shift=4, noisy_every=3, seed=3)
+    # noise-free frames have f = 0 at their shift: the rule's floor, 1e-9 of
+    # (A+B)/Area, about twice the grid's mean square
+    aba = 2 * float(np.mean(tmpl.astype(np.float64) ** 2))
+    res, orc = _cert32(gpu_lib, fr, tmpl, 6, 0, "cert32 ties", aba=aba)
+    tie = orc.gap_c == 0
+    assert tie.any()
+    assert np.all(res["recomputed"][tie] == 2)
+
+
+def test_fft32_cert_chunked_equals_unchunked(gpu_lib):
+    sc = synth.poisson512_u16(T=40)
+    fr = sc.frames(1, 9)
+    big = _run(gpu_lib, fr, sc.template, 32, 1, form="fft32_cert")
+    ctx = gpu_lib.Context(0, scratch_budget=3 * 1024 * 1024)
+    small = _run(gpu_lib, fr, sc.template, 32, 1, form="fft32_cert", ctx=ctx)
+    ctx.close()
+    for k in big:
+        assert np.array_equal(big[k], small[k], equal_nan=True), k
+
+
+def _centred_bound_terms(fr_grid, t_grid, c, P, Q):
+    """Norms of the centred grids and the largest magnitudes of their
+    zero-padded spectra (numpy FFT in FP64)."""
+    x, y = fr_grid - c, t_grid - c
+    X = np.abs(np.fft.rfft2(x, (P, Q))).max()
+    Y = np.abs(np.fft.rfft2(y, (P, Q))).max()
+    return np.sqrt((x * x).sum()), np.sqrt((y * y).sum()), X, Y
+
+
+def _plan_eps(n, u):
+    c = {2: 1, 4: 2, 8: 6, 3: 10, 5: 18}
+    e = 0.0
+    for r in (8, 4, 2, 3, 5):
+        while n % r == 0:
+            n //= r
+            e += (5 + c[r]) * u
+    assert n == 1
+    return e
+
+
+def test_fft32_error_within_the_certificate_bound(gpu_lib):
+    # the plain FP32 surface against the oracle: on every shift, the observed
+    # error of Area*f is within 2 hb, the certificate's bound on 2|h^ - h|
+    u = 2.0 ** -24
+    for sc, w, T in ((synth.blobs128_f32(), 10, 6), (synth.lowsnr256_f32(), 64, 3)):
+        fr = sc.frames(0, T)
+        tm = sc.template.astype(np.float64)
+        m, n = tm.shape
+        P = next(k for k in range(m + w - 1, 4 * m) if _smooth(k))
+        Q = next(k for k in range(n + w - 1, 4 * n) if _smooth(k))
+        eps = _plan_eps(P, u) + _plan_eps(Q, u) + 2 * u
+        e1, e2 = eps + u, eps + 7 * u
+        res = _run(gpu_lib, fr, sc.template, w, 0, form="fft32")
+        orc = oracle.align(fr, sc.template, w, False, want_surface=True)
+        c = tm.mean()
+        W = 2 * w - 1
+        s = np.arange(W) - (w - 1)
+        area = np.outer(m - np.abs(s), n - np.abs(s)).astype(np.float64)
+        worst = 0.0
+        for k in range(T):
+            na, nb, X, Y = _centred_bound_terms(fr[k].astype(np.float64), tm, c, P, Q)
+            hb = 2 * (e1 * na * Y + e2 * (X + e1 * np.sqrt(P * Q) * na) * nb)
+            obs = np.max(np.abs(res["fsurf"][k] - orc.surf[k]) * area)
+            assert obs <= 2 * hb, (k, obs, hb)
+            worst = max(worst, obs / (2 * hb))
+        _say("observed error / bound, worst frame: %.3g" % worst)
+
+
+def _smooth(k):
+    for p in (2, 3, 5):
+        while k % p == 0:
+            k //= p
+    return k == 1

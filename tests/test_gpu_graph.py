@@ -25,7 +25,7 @@ def _host(r):
 
 
 @pytest.mark.parametrize("form,T", [("int8", 1), ("int8", 24), ("fft_cert", 5), ("fp64", 3),
-                                    ("auto", 2)])
+                                    ("fft32_cert", 6), ("auto", 2)])
 def test_graph_replays_equal_eager_calls(gpu_lib, form, T):
     sc = synth.poisson512_u16(T=2000)
     pool = torch.from_numpy(sc.frames(0, 4 * T)).cuda()

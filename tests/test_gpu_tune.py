@@ -76,7 +76,7 @@ def test_recorded_form_overrides_the_model(gpu_lib):
         # a recorded form that does not apply is ignored (float32: no int8 form)
         t32 = gpu_lib.Template(ctx, torch.from_numpy(sc.template.astype(np.float32)).cuda(), 32, True)
         gpu_lib.tune_set(512, 512, 32, 1, "f32", "int8")
-        assert gpu_lib.resolved_form(ctx, t32, "auto") == "fft_cert"
+        assert gpu_lib.resolved_form(ctx, t32, "auto") == "fft32_cert"
         gpu_lib.tune_clear()
         assert gpu_lib.resolved_form(ctx, tp, "auto") == "int8"
         t32.close()

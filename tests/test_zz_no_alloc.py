@@ -52,6 +52,7 @@ CASES = [
     # (label, scene factory, w, ds, form, first T, second T)
     ("poisson512_int8", lambda: synth.poisson512_u16(T=64), 32, True, "int8", 40, 3),
     ("poisson512_fft_cert", lambda: synth.poisson512_u16(T=64), 32, True, "fft_cert", 60, 5),
+    ("poisson512_fft32_cert", lambda: synth.poisson512_u16(T=64), 32, True, "fft32_cert", 30, 4),
     ("blobs128_fft", lambda: synth.blobs128_f32(), 10, False, "fft", 100, 7),
     ("blobs128_fp64", lambda: synth.blobs128_f32(), 10, False, "fp64", 20, 2),
 ]
