@@ -636,9 +636,13 @@ def main():
     # time model; the table is cleared again)
     moco.tune_clear()
     tuned_form, tuned_times = moco.tune(ctx, tp, frames=T)
+    # the int8 form's faster shift tile (32x32 tiles or 2x2 groups of them)
+    tuned_tile = moco.int8_tile(tp) if form_ran == "int8" else None
     moco.tune_clear()
     tuned = {"form": tuned_form,
              "us_per_frame": {k: round(v * 1e6, 4) for k, v in tuned_times.items()}}
+    if tuned_tile is not None:
+        tuned["int8_tile"] = tuned_tile
     if peaks and form_ran == "int8" and "int8_mfma_tops" in peaks:
         roof["frac_of_measured_peak"] = roof["achieved"] / peaks["int8_mfma_tops"]
         if "int8_mfma_tops_random_operands" in peaks:

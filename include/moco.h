@@ -246,6 +246,20 @@ typedef struct {
 int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
                      int lanes, void *hip_stream);
 
+/* moco_align_batch captured as one HIP graph, for callers that repeat the same
+ * batch (buffers refilled between calls): the stacks' launch sequences, spread
+ * over `lanes` streams as moco_align_batch spreads them (forked from and
+ * joined to one origin inside the capture), replay with a single launch
+ * (moco_graph_launch) over whatever the frame buffers then hold, into the
+ * same outputs.  The graph has its own scratch (lanes x the slice
+ * moco_align_batch would use, allocated here) and captures on streams of its
+ * own, with stage timing off; it refers to every stack's frames, template and
+ * outputs, which must outlive it.  Arguments and errors are
+ * moco_align_batch's; a batch with no frame is MOCO_EINVAL.  Release with
+ * moco_graph_destroy. */
+int moco_graph_create_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
+                            int lanes, moco_graph **graph);
+
 /* Apply the correction (sec. 2: each frame moved by the translation found for
  * it is the motion-corrected video; sec. 3, fig. 1 and 2: corrected frames are
  * black outside their overlap with the template, and the mean of the
@@ -288,16 +302,21 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
  * moco_template_form decides.  The table starts empty, so AUTO is the model's
  * choice until a form is tuned or set. */
 
-/* Time the forms that apply to `tmpl` (of MOCO_FORM_INT8_MFMA and
- * MOCO_FORM_FFT_CERTIFIED; MOCO_FORM_FP64_EXACT when neither does) on
- * `frames` copies of the template, one warm-up and three timed calls each with
- * HIP events on hip_stream, and record the fastest for the template's key.
- * The forms rank differently with the stack length (a few frames take the
- * int8 form's row-sliced launch), so `frames` should be the length of the
- * stacks the key will serve; 0 means 1024, the many-frame regime.  *chosen receives it; seconds_per_frame (nullable,
- * MOCO_FORM_COUNT doubles indexed by moco_form) receives each timed form's seconds per frame
- * (-1 for forms not timed).  Synchronises hip_stream; allocates the frames
- * outside the context's budget for the duration of the call.
+/* Time the forms that apply to `tmpl` (of MOCO_FORM_INT8_MFMA,
+ * MOCO_FORM_FFT_CERTIFIED and, for float32 data, MOCO_FORM_FFT32_CERTIFIED;
+ * MOCO_FORM_FP64_EXACT when none does) on `frames` copies of the template, one
+ * warm-up and three timed calls each with HIP events on hip_stream, and record
+ * the fastest for the template's key.  The int8 form is timed with each of its
+ * shift-tile shapes that applies (one 32x32 tile per block, or 2x2 tiles of
+ * 32 when 2w-1 > 32) and keeps the faster for the key whichever form wins
+ * (moco_template_int8_tile).  The forms rank differently with the stack length
+ * (a few frames take the int8 form's row-sliced launch), so `frames` should be
+ * the length of the stacks the key will serve; 0 means 1024, the many-frame
+ * regime.  *chosen receives the form; seconds_per_frame (nullable,
+ * MOCO_FORM_COUNT doubles indexed by moco_form) receives each timed form's
+ * seconds per frame, the int8 form's with its faster tile (-1 for forms not
+ * timed).  Synchronises hip_stream; allocates the frames outside the context's
+ * budget for the duration of the call.
  * Errors: MOCO_EINVAL, MOCO_ENOMEM, MOCO_EDEVICE. */
 int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream,
               moco_form *chosen, double *seconds_per_frame);
@@ -309,7 +328,14 @@ int moco_tune_set(int m, int n, int w, int downsample, moco_dtype dtype, moco_fo
 /* The form recorded for the key.  Errors: MOCO_EINVAL (none recorded). */
 int moco_tune_get(int m, int n, int w, int downsample, moco_dtype dtype, moco_form *form);
 
-/* Forget every recorded form. */
+/* Record the int8 form's shift tile for the key (uint16 data): 32 (one 32x32
+ * tile per block, ceil((2w-1)/32)^2 blocks per frame) or 64 (2x2 tiles of 32,
+ * ceil((2w-1)/64)^2 blocks; not when 2w-1 <= 32).  Without a recorded tile the
+ * form takes 32 when 2w-1 <= 32, else 64.  Both give the same exact results.
+ * Host only.  Errors: MOCO_EINVAL. */
+int moco_tune_set_tile(int m, int n, int w, int downsample, moco_dtype dtype, int tile);
+
+/* Forget every recorded form and tile. */
 void moco_tune_clear(void);
 
 /* Error bound of the FFT forms for this template (sec. 2, the FFT construction
@@ -332,6 +358,11 @@ int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke);
  * second pass.  Host only.
  * Errors: MOCO_EINVAL (null argument, or the int8 form does not apply). */
 int moco_template_int8_products(const moco_tmpl *tmpl, int *products);
+
+/* The shift tile (32 or 64) the int8 form uses for this template's key now:
+ * the recorded one, else the model's.  Host only.
+ * Errors: MOCO_EINVAL (null argument, or the int8 form does not apply). */
+int moco_template_int8_tile(const moco_tmpl *tmpl, int *tile);
 
 /* ---- Serving: single frames from many sources, continuous batching ----
  *

@@ -570,6 +570,10 @@ int prepare_fft_template(moco::Tmpl &t, hipStream_t st)
     return MOCO_OK;
 }
 
+// The int8 correlation's shift tile for a template's key: a tile recorded by
+// moco_tune (or moco_tune_set_tile), else the model's (int8_model_tile).
+int int8_tile(const moco::Tmpl &t);
+
 // The int8 pipeline over one stack, in chunks that fit `sbytes` of scratch at
 // `sbase`; every launch goes to stream st.
 int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
@@ -592,6 +596,7 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     double *part = (double *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst) * C);
     const size_t fbytes = (size_t)g.m * g.n * sizeof(uint16_t);
     const int W = g.W;
+    const int tile = int8_tile(tt);
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const uint16_t *fr = (const uint16_t *)((const char *)d_frames + (size_t)f0 * fbytes);
@@ -603,7 +608,7 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            HIP_TRY(moco::launch_corr_int8(limbs, nl, tt.i8, c, g, h, st));
+            HIP_TRY(moco::launch_corr_int8(limbs, nl, tt.i8, c, g, h, st, nullptr, tile));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
@@ -709,7 +714,7 @@ int run_int8_multi(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tref, 
     int32_t *coarse = out->coarse ? out->coarse : cst;
     const moco::Int8Multi mm{nblocks, dt.btp, dt.bf0, dt.bfe};
     HIP_TRY(moco::launch_prep_u16(fr, F, g, npad, tref.i8.dbits, limbs, nl, vm, atab, edge, st));
-    HIP_TRY(moco::launch_corr_int8(limbs, nl, tref.i8, F, g, h, st, &mm));
+    HIP_TRY(moco::launch_corr_int8(limbs, nl, tref.i8, F, g, h, st, &mm, int8_tile(tref)));
     HIP_TRY(moco::launch_combine_i64(atab, nullptr, h, F, g, nullptr, out->fmin, coarse,
                                      out->shifts, out->gaps, out->frefine, st, dt.btabs));
     if (g.ds)
@@ -1037,9 +1042,23 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     return run_exact(ctx, d_frames, tt, T, g, out, st, sbase, sbytes);
 }
 
+// MFMA tiles of 32x32 shifts a frame's correlation issues with each tile
+// shape: ceil(W/32)^2 one-tile blocks, or ceil(W/64)^2 blocks of 2x2 tiles.
+double int8_tiles(const moco::Geom &g, int tile)
+{
+    const double gs = std::ceil(g.W / (double)tile);
+    return tile == 32 ? gs * gs : 4.0 * gs * gs;
+}
+
+// One 32x32 tile when 2w-1 <= 32, else 2x2 groups: a group reads each frame
+// and template operand once for two tiles, and at 2w-1 = 79 on a 256x256 grid
+// the groups (16 tiles) ran faster than single tiles (9 tiles).  moco_tune
+// times both shapes.
+int int8_model_tile(const moco::Geom &g) { return g.W <= 32 ? 32 : 64; }
+
 // Per-frame time models of the two fast forms (seconds), from their kernels'
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
-// issues 64x64-shift tile groups (one 32x32 tile when 2w-1 <= 32) of three
+// issues the MFMA tiles of its tile shape (int8_tiles) of three
 // digit products (base-128 digits with their
 // sums) at about 2.7e15 ops/s or four (base 256) at about 2.8e15, beside 0.31
 // us of prep, combine and refine per 512x512 frame; the FFT form's three
@@ -1050,10 +1069,7 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 double int8_model_s(const moco::Tmpl &t)
 {
     const moco::Geom &g = t.g;
-    // tile groups of 64x64 shifts, or one 32x32 tile when 2w-1 <= 32
-    const double tile = g.W <= 32 ? 32.0 : 64.0;
-    const double groups = std::ceil(g.W / tile);
-    const double macs = groups * groups * tile * tile * g.mg * (double)t.i8.npad;
+    const double macs = int8_tiles(g, int8_tile(t)) * 1024.0 * g.mg * (double)t.i8.npad;
     const double ops = macs * 2.0 * (t.i8.nq == 3 ? 3.0 : 4.0);
     return 0.31e-6 * ((double)g.m * g.n / 262144.0) + ops / (t.i8.nq == 3 ? 2.7e15 : 2.8e15);
 }
@@ -1077,8 +1093,19 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, moco_form> g_tune;
+std::map<TuneKey, int> g_tune_tile;   // the int8 form's shift tile, 32 or 64
 
 TuneKey tune_key(const moco::Geom &g) { return TuneKey{g.m, g.n, g.w, g.ds, (int)g.dtype}; }
+
+int int8_tile(const moco::Tmpl &t)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_tile.find(tune_key(t.g));
+        if (it != g_tune_tile.end()) return it->second;
+    }
+    return int8_model_tile(t.g);
+}
 
 bool form_applies(const moco::Tmpl &t, moco_form f)
 {
@@ -1305,13 +1332,18 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     hipStream_t st = (hipStream_t)hip_stream;
     if (seconds_per_frame)
         for (int k = 0; k < MOCO_FORM_COUNT; ++k) seconds_per_frame[k] = -1.0;
-    std::vector<moco_form> cand;
-    if (t.int8_ok) cand.push_back(MOCO_FORM_INT8_MFMA);
-    if (t.fft_ok) cand.push_back(MOCO_FORM_FFT_CERTIFIED);
+    // (form, int8 tile) candidates: the int8 form with each tile shape that
+    // applies (32 only when 2w-1 <= 32)
+    std::vector<std::pair<moco_form, int>> cand;
+    if (t.int8_ok) {
+        cand.push_back({MOCO_FORM_INT8_MFMA, 32});
+        if (g.W > 32) cand.push_back({MOCO_FORM_INT8_MFMA, 64});
+    }
+    if (t.fft_ok) cand.push_back({MOCO_FORM_FFT_CERTIFIED, 0});
     // (copies of the template pass the FP32 bound at once, which says little of
     // uint16 frames whose gaps are a few per cent of f: timed for float32 only)
-    if (t.fft_ok && g.dtype == MOCO_F32) cand.push_back(MOCO_FORM_FFT32_CERTIFIED);
-    if (cand.empty()) cand.push_back(MOCO_FORM_FP64_EXACT);
+    if (t.fft_ok && g.dtype == MOCO_F32) cand.push_back({MOCO_FORM_FFT32_CERTIFIED, 0});
+    if (cand.empty()) cand.push_back({MOCO_FORM_FP64_EXACT, 0});
     DeviceGuard dg(ctx->device);
     // T copies of the template (its own frame: a realistic image, the shift at
     // zero) and a shift output
@@ -1326,12 +1358,25 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int rc = e == hipSuccess ? MOCO_OK : fail(MOCO_ENOMEM, "moco_tune: %s", hipGetErrorString(e));
-    moco_form best = cand[0];
-    double best_s = INFINITY;
+    moco_form best = cand[0].first;
+    int int8_tile_best = 0;
+    double best_s = INFINITY, int8_best_s = INFINITY;
     moco_outputs out{};
     out.shifts = d_shifts;
+    const TuneKey key = tune_key(g);
+    int prev_tile = 0;   // a tile recorded before the call, restored if int8 is not timed
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_tile.find(key);
+        if (it != g_tune_tile.end()) prev_tile = it->second;
+    }
     for (size_t c = 0; c < cand.size() && rc == MOCO_OK; ++c) {
-        const moco_form f = cand[c];
+        const moco_form f = cand[c].first;
+        if (cand[c].second) {
+            // the tile the int8 runs below take
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_tile[key] = cand[c].second;
+        }
         rc = moco_align(ctx, d_frames, tmpl, T, g.m, g.n, g.w, g.ds, g.dtype, f, &out, st);
         const int reps = 3;
         if (rc == MOCO_OK && (e = hipEventRecord(e0, st)) != hipSuccess)
@@ -1345,7 +1390,12 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
             rc = fail(MOCO_EDEVICE, "moco_tune: %s", hipGetErrorString(e));
         if (rc != MOCO_OK) break;
         const double sec = ms / 1000.0 / reps / T;
-        if (seconds_per_frame) seconds_per_frame[(int)f] = sec;
+        if (f == MOCO_FORM_INT8_MFMA && sec < int8_best_s) {
+            int8_best_s = sec;
+            int8_tile_best = cand[c].second;
+        }
+        if (seconds_per_frame && (f != MOCO_FORM_INT8_MFMA || sec <= int8_best_s))
+            seconds_per_frame[(int)f] = sec;
         if (sec < best_s) {
             best_s = sec;
             best = f;
@@ -1356,12 +1406,35 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     (void)hipStreamSynchronize(st);
     if (d_frames) (void)hipFree(d_frames);
     if (d_shifts) (void)hipFree(d_shifts);
-    if (rc != MOCO_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[tune_key(g)] = best;
+        // the int8 form keeps its faster tile whichever form won
+        if (rc == MOCO_OK && int8_tile_best) g_tune_tile[key] = int8_tile_best;
+        else if (prev_tile) g_tune_tile[key] = prev_tile;
+        else g_tune_tile.erase(key);
+        if (rc == MOCO_OK) g_tune[key] = best;
     }
+    if (rc != MOCO_OK) return rc;
     *chosen = best;
+    return MOCO_OK;
+}
+
+int moco_tune_set_tile(int m, int n, int w, int downsample, moco_dtype dtype, int tile)
+{
+    if (tile != 32 && tile != 64) return fail(MOCO_EINVAL, "moco_tune_set_tile: tile %d", tile);
+    if (dtype != MOCO_U16) return fail(MOCO_EINVAL, "moco_tune_set_tile: the int8 form is uint16 only");
+    if (tile == 64 && 2 * w - 1 <= 32)
+        return fail(MOCO_EINVAL, "moco_tune_set_tile: 2w-1 = %d takes one 32x32 tile", 2 * w - 1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_tile[TuneKey{m, n, w, downsample, (int)dtype}] = tile;
+    return MOCO_OK;
+}
+
+int moco_template_int8_tile(const moco_tmpl *tmpl, int *tile)
+{
+    if (!tmpl || !tile) return fail(MOCO_EINVAL, "moco_template_int8_tile: null argument");
+    if (!tmpl->t.int8_ok) return fail(MOCO_EINVAL, "the int8 form does not apply");
+    *tile = int8_tile(tmpl->t);
     return MOCO_OK;
 }
 
@@ -1390,6 +1463,7 @@ void moco_tune_clear(void)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+    g_tune_tile.clear();
 }
 
 int moco_profile_enable(moco_ctx *ctx, int enable)
@@ -1540,6 +1614,99 @@ int moco_align_noalloc(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmp
     return rc;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A batch's validated stacks, lanes, lane slice and the stacks of each lane.
+struct BatchPlan {
+    std::vector<moco::Geom> geo;
+    std::vector<moco_form> forms;
+    int nl = 0;                       // lanes; 0: no frame to align
+    size_t slice = 0;                 // scratch bytes per lane
+    std::vector<std::vector<int>> plan;
+};
+
+// Validate every stack (all-or-nothing, before anything is enqueued), choose
+// the lanes and their scratch slice, and spread the stacks over the lanes
+// longest first onto the least loaded.
+int plan_batch(const moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
+               int lanes, BatchPlan *bp)
+{
+    if (lanes < 0) return fail(MOCO_EINVAL, "lanes=%d must be >= 0", lanes);
+    bp->geo.assign(nstacks, moco::Geom{});
+    bp->forms.assign(nstacks, MOCO_FORM_AUTO);
+    std::vector<double> cost(nstacks);
+    size_t pf_max = 0, slice_need = 0;
+    for (int k = 0; k < nstacks; ++k) {
+        const moco_stack &sk = stacks[k];
+        int rc = check_stack(ctx, sk.d_frames, sk.tmpl, sk.T, sk.m, sk.n, sk.w, sk.downsample,
+                             sk.dtype, form, &sk.out, &bp->geo[k], &bp->forms[k]);
+        if (rc) return fail(rc, "stack %d: %s", k, moco_last_error());
+        const size_t pf = per_frame_scratch(bp->geo[k], bp->forms[k], sk.tmpl->t);
+        if (sk.T > 0) {
+            pf_max = std::max(pf_max, pf);
+            // a lane slice never needs more than one chunk of its largest stack
+            slice_need = std::max(slice_need, pf * (size_t)std::min(sk.T, chunk_cap(bp->forms[k])));
+        }
+        const moco::Geom &g = bp->geo[k];
+        cost[k] = (double)sk.T * ((double)g.W * g.W * g.mg * g.ng + (double)g.m * g.n);
+    }
+    bp->nl = 0;
+    if (pf_max == 0) return MOCO_OK;  // nothing to align
+    if (pf_max > ctx->budget)
+        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf_max,
+                    ctx->budget);
+    int nl = lanes ? std::min(lanes, 8) : 4;
+    nl = (int)std::min<size_t>((size_t)nl, ctx->budget / pf_max);
+    nl = std::max(1, std::min(nl, nstacks));
+    // lane slices start 256-byte aligned; each must hold one frame of any stack
+    size_t lane_cap = ctx->budget / nl / 256 * 256;
+    while (nl > 1 && lane_cap < pf_max) lane_cap = ctx->budget / --nl / 256 * 256;
+    bp->slice = std::min(lane_cap, align_up(slice_need, 256));
+    bp->nl = nl;
+    std::vector<int> order(nstacks);
+    for (int k = 0; k < nstacks; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nl, 0.0);
+    bp->plan.assign(nl, {});
+    for (int k : order) {
+        if (stacks[k].T == 0) continue;
+        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bp->plan[best].push_back(k);
+        load[best] += cost[k];
+    }
+    return MOCO_OK;
+}
+
+// Enqueue a planned batch: every lane stream waits for `st`, runs its stacks
+// on its slice of `base`, and `st` waits for every lane.  ev: nl + 1 events.
+int enqueue_batch(moco_ctx *ctx, const moco_stack *stacks, const BatchPlan &bp, hipStream_t st,
+                  char *base, hipStream_t *lane_st, hipEvent_t *ev)
+{
+    const int nl = bp.nl;
+    hipEvent_t fork = ev[nl];
+    HIP_TRY(hipEventRecord(fork, st));
+    for (int l = 0; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(lane_st[l], fork, 0));
+    for (int l = 0; l < nl; ++l) {
+        for (int k : bp.plan[l]) {
+            const moco_stack &sk = stacks[k];
+            int rc = run_stack(ctx, sk.d_frames, sk.tmpl->t, sk.T, bp.geo[k], bp.forms[k], &sk.out,
+                               lane_st[l], base + bp.slice * l, bp.slice);
+            if (rc) return rc;
+        }
+    }
+    for (int l = 0; l < nl; ++l) {
+        HIP_TRY(hipEventRecord(ev[l], lane_st[l]));
+        HIP_TRY(hipStreamWaitEvent(st, ev[l], 0));
+    }
+    return MOCO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int moco_graph_create(moco_ctx *ctx, const void *d_frames, const moco_tmpl *tmpl, int T, int m,
                       int n, int w, int downsample, moco_dtype dtype, moco_form form,
                       const moco_outputs *out, moco_graph **graph)
@@ -1625,43 +1792,14 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
 {
     if (!ctx || (nstacks > 0 && !stacks) || nstacks < 0)
         return fail(MOCO_EINVAL, "moco_align_batch: null ctx or stacks, or nstacks < 0");
-    if (lanes < 0) return fail(MOCO_EINVAL, "lanes=%d must be >= 0", lanes);
-    // validate everything before enqueuing anything
-    std::vector<moco::Geom> geo(nstacks);
-    std::vector<moco_form> forms(nstacks);
-    std::vector<size_t> pf(nstacks);
-    std::vector<double> cost(nstacks);
-    size_t pf_max = 0, slice_need = 0;
-    for (int k = 0; k < nstacks; ++k) {
-        const moco_stack &sk = stacks[k];
-        int rc = check_stack(ctx, sk.d_frames, sk.tmpl, sk.T, sk.m, sk.n, sk.w, sk.downsample,
-                             sk.dtype, form, &sk.out, &geo[k], &forms[k]);
-        if (rc) return fail(rc, "stack %d: %s", k, moco_last_error());
-        pf[k] = per_frame_scratch(geo[k], forms[k], sk.tmpl->t);
-        if (sk.T > 0) {
-            pf_max = std::max(pf_max, pf[k]);
-            // a lane slice never needs more than one chunk of its largest stack
-            slice_need = std::max(
-                slice_need, pf[k] * (size_t)std::min(sk.T, chunk_cap(forms[k])));
-        }
-        const moco::Geom &g = geo[k];
-        cost[k] = (double)sk.T * ((double)g.W * g.W * g.mg * g.ng + (double)g.m * g.n);
-    }
-    if (pf_max == 0) return MOCO_OK;  // nothing to align
-    if (pf_max > ctx->budget)
-        return fail(MOCO_ENOMEM, "one frame needs %zu bytes of scratch, budget is %zu", pf_max,
-                    ctx->budget);
+    BatchPlan bp;
+    int rc = plan_batch(ctx, stacks, nstacks, form, lanes, &bp);
+    if (rc || bp.nl == 0) return rc;
     DeviceGuard dg(ctx->device);
     if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)hip_stream;
-    int nl = lanes ? std::min(lanes, 8) : 4;
-    nl = (int)std::min<size_t>((size_t)nl, ctx->budget / pf_max);
-    nl = std::max(1, std::min(nl, nstacks));
-    // lane slices start 256-byte aligned; each must hold one frame of any stack
-    size_t lane_cap = ctx->budget / nl / 256 * 256;
-    while (nl > 1 && lane_cap < pf_max) lane_cap = ctx->budget / --nl / 256 * 256;
-    const size_t slice = std::min(lane_cap, align_up(slice_need, 256));
-    int rc = ensure_scratch(ctx, slice * nl, st);
+    const int nl = bp.nl;
+    rc = ensure_scratch(ctx, bp.slice * nl, st);
     if (rc) return rc;
     while ((int)ctx->lanes.size() < nl) {
         hipStream_t l = nullptr;
@@ -1673,36 +1811,71 @@ int moco_align_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         ctx->lane_ev.push_back(e);
     }
-    // longest first onto the least loaded lane
-    std::vector<int> order(nstacks);
-    for (int k = 0; k < nstacks; ++k) order[k] = k;
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    std::vector<double> load(nl, 0.0);
-    std::vector<std::vector<int>> plan(nl);
-    for (int k : order) {
-        if (stacks[k].T == 0) continue;
-        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        plan[best].push_back(k);
-        load[best] += cost[k];
+    return enqueue_batch(ctx, stacks, bp, st, (char *)ctx->scratch, ctx->lanes.data(),
+                         ctx->lane_ev.data());
+}
+
+int moco_graph_create_batch(moco_ctx *ctx, const moco_stack *stacks, int nstacks, moco_form form,
+                            int lanes, moco_graph **graph)
+{
+    if (!ctx || !graph || (nstacks > 0 && !stacks) || nstacks < 0)
+        return fail(MOCO_EINVAL, "moco_graph_create_batch: null argument or nstacks < 0");
+    *graph = nullptr;
+    BatchPlan bp;
+    int rc = plan_batch(ctx, stacks, nstacks, form, lanes, &bp);
+    if (rc) return rc;
+    if (bp.nl == 0) return fail(MOCO_EINVAL, "moco_graph_create_batch: no frame to align");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok()) return fail(MOCO_EDEVICE, "cannot select device %d", ctx->device);
+    const int nl = bp.nl;
+    moco_graph *gr = new (std::nothrow) moco_graph;
+    if (!gr) return fail(MOCO_ENOMEM, "moco_graph_create_batch: out of host memory");
+    gr->device = ctx->device;
+    hipError_t e = hipMalloc(&gr->scratch, bp.slice * nl);
+    if (e != hipSuccess) {
+        delete gr;
+        return fail(MOCO_ENOMEM, "graph scratch of %zu bytes: %s", bp.slice * nl,
+                    hipGetErrorString(e));
     }
-    // fork: every lane waits for the caller's stream
-    hipEvent_t fork = ctx->lane_ev[nl];
-    HIP_TRY(hipEventRecord(fork, st));
-    for (int l = 0; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(ctx->lanes[l], fork, 0));
-    char *base = (char *)ctx->scratch;
-    for (int l = 0; l < nl; ++l) {
-        for (int k : plan[l]) {
-            const moco_stack &sk = stacks[k];
-            rc = run_stack(ctx, sk.d_frames, sk.tmpl->t, sk.T, geo[k], forms[k], &sk.out,
-                           ctx->lanes[l], base + slice * l, slice);
-            if (rc) return rc;
-        }
+    // capture on streams of its own: the origin stream forks to nl lane
+    // streams through events and joins them again, all inside the capture
+    std::vector<hipStream_t> ls(nl, nullptr);
+    std::vector<hipEvent_t> ev(nl + 1, nullptr);
+    hipStream_t cs = nullptr;
+    hipGraph_t graph_ = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int l = 0; l < nl && e == hipSuccess; ++l)
+        e = hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking);
+    for (int l = 0; l <= nl && e == hipSuccess; ++l)
+        e = hipEventCreateWithFlags(&ev[l], hipEventDisableTiming);
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = enqueue_batch(ctx, stacks, bp, cs, (char *)gr->scratch, ls.data(), ev.data());
+        hipError_t e2 = hipStreamEndCapture(cs, &graph_);
+        if (rc == MOCO_OK && e2 != hipSuccess)
+            rc = fail(MOCO_EDEVICE, "graph capture: %s", hipGetErrorString(e2));
+        if (rc == MOCO_OK && (e2 = hipGraphInstantiate(&gr->exec, graph_, nullptr, nullptr, 0)) !=
+                                 hipSuccess)
+            rc = fail(MOCO_EDEVICE, "graph instantiation: %s", hipGetErrorString(e2));
+    } else {
+        rc = fail(MOCO_EDEVICE, "graph capture: %s", hipGetErrorString(e));
     }
-    // join: the caller's stream waits for every lane
-    for (int l = 0; l < nl; ++l) {
-        HIP_TRY(hipEventRecord(ctx->lane_ev[l], ctx->lanes[l]));
-        HIP_TRY(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
+    ctx->profiling = prof;
+    if (graph_) (void)hipGraphDestroy(graph_);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    for (hipStream_t x : ls)
+        if (x) (void)hipStreamDestroy(x);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != MOCO_OK) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        (void)hipFree(gr->scratch);
+        delete gr;
+        return rc;
     }
+    *graph = gr;
     return MOCO_OK;
 }
 
@@ -1738,6 +1911,7 @@ struct SrvRequest {
 
 // Streams on which a lane runs the source groups of a batch side by side.
 constexpr int kSrvSubStreams = 4;
+constexpr int kSrvLanes = 2;       // batches in flight at once (four measured slower)
 
 // Device and pinned buffers of one batch in flight.
 struct SrvLane {
@@ -1771,7 +1945,7 @@ struct moco_server {
     size_t tmpl_bytes = 0;  // device bytes held by prepared templates (estimate)
     char *h_slots = nullptr;  // pinned staging, max_slots x slot_bytes
     std::vector<int> free_slots;
-    SrvLane lane[2];
+    SrvLane lane[kSrvLanes];
     hipStream_t setup = nullptr;
     std::deque<SrvRequest> pending;
     std::deque<moco_result> completed;
@@ -1812,9 +1986,9 @@ int server_size_buffers(moco_server *srv, size_t slot_bytes, size_t pf_max)
     const size_t res_i32 = ns * 4 * sizeof(int32_t);            // shifts + coarse
     const size_t res_f64 = ns * (1 + 9 + 2) * sizeof(double);   // fmin, frefine, gaps
     const size_t per_lane = ns * slot_bytes + ns * pf_max + res_i32 + res_f64 + 4096;
-    if (2 * per_lane + srv->tmpl_bytes > srv->budget)
+    if (kSrvLanes * per_lane + srv->tmpl_bytes > srv->budget)
         return fail(MOCO_ENOMEM, "server needs %zu device bytes for %d slots, budget is %zu",
-                    2 * per_lane + srv->tmpl_bytes, srv->max_slots, srv->budget);
+                    kSrvLanes * per_lane + srv->tmpl_bytes, srv->max_slots, srv->budget);
     if (srv->h_slots) (void)hipHostFree(srv->h_slots);
     srv->h_slots = nullptr;
     hipError_t e = hipHostMalloc((void **)&srv->h_slots, ns * slot_bytes, hipHostMallocDefault);
@@ -1991,13 +2165,17 @@ void server_loop(moco_server *srv)
     (void)hipSetDevice(srv->ctx->device);
     std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
-        const bool any_active = srv->lane[0].active || srv->lane[1].active;
+        bool any_active = false;
+        int fl = -1;   // a free lane
+        for (int k = 0; k < kSrvLanes; ++k) {
+            any_active = any_active || srv->lane[k].active;
+            if (fl < 0 && !srv->lane[k].active) fl = k;
+        }
         if (!any_active) {
             srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
             if (srv->stop && srv->pending.empty()) break;
         }
         // launch the waiting requests into a free lane
-        int fl = !srv->lane[0].active ? 0 : (!srv->lane[1].active ? 1 : -1);
         if (fl >= 0 && !srv->pending.empty() && !srv->stop) {
             SrvLane &L = srv->lane[fl];
             while (!srv->pending.empty() && (int)L.reqs.size() < srv->max_slots) {
@@ -2036,7 +2214,7 @@ void server_loop(moco_server *srv)
             srv->cv_done.notify_all();
             continue;
         }
-        if (srv->stop && srv->pending.empty() && !srv->lane[0].active && !srv->lane[1].active)
+        if (srv->stop && srv->pending.empty() && !any_active)
             break;
         // a batch is on the GPU: poll its event again after yielding the lock
         // and the core (a timed wait sleeps for the scheduler's timer slack:

@@ -1041,12 +1041,16 @@ hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, 
 }
 
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
-                            const Geom &g, long long *h, hipStream_t st, const Int8Multi *mm)
+                            const Geom &g, long long *h, hipStream_t st, const Int8Multi *mm,
+                            int tile)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     hipError_t e;
-    const bool small = g.W <= 32;
+    // (the template rows are padded for 2x2 tiles of 32 only when 2w-1 > 32)
+    if ((tile != 0 && tile != 32 && tile != 64) || (tile == 64 && g.W <= 32))
+        return hipErrorInvalidValue;
+    const bool small = tile == 32 || (tile == 0 && g.W <= 32);
     const int nb = mm ? mm->nblocks : -1;
     const int nslice = small ? corr_slices(C, g, 1, 1, nb) : corr_slices(C, g, 2, 2, nb);
     if (nslice > 1) {

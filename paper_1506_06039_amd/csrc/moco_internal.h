@@ -218,10 +218,12 @@ struct Int8Multi {
     const int *bf0, *bfe;
 };
 // mm (nullable): the frames' templates as above; tt then gives the geometry
-// (npad, trow, padl, digit base), which every template of the launch shares
+// (npad, trow, padl, digit base), which every template of the launch shares.
+// tile: shift tiles per block, 32 (one 32x32 tile, ceil(W/32)^2 block groups)
+// or 64 (2x2 tiles of 32, ceil(W/64)^2 groups); 0: 32 when W <= 32, else 64.
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st,
-                            const Int8Multi *mm = nullptr);
+                            const Int8Multi *mm = nullptr, int tile = 0);
 // btabs (nullable, device array): each frame's own template table
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
                               int C, const Geom &g, double *fsurf, double *fmin,

@@ -73,6 +73,9 @@ class _Stack(ctypes.Structure):
 
 _lib.moco_align_batch.argtypes = [_vp, ctypes.POINTER(_Stack), _i, _i, _i, _vp]
 _lib.moco_align_batch.restype = _i
+_lib.moco_graph_create_batch.argtypes = [_vp, ctypes.POINTER(_Stack), _i, _i, _i,
+                                         ctypes.POINTER(_vp)]
+_lib.moco_graph_create_batch.restype = _i
 class ServerResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("source", ctypes.c_int), ("status", ctypes.c_int),
                 ("shift", ctypes.c_int32 * 2), ("coarse", ctypes.c_int32 * 2),
@@ -99,6 +102,10 @@ _lib.moco_template_fft_bound.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
 _lib.moco_template_fft_bound.restype = _i
 _lib.moco_template_int8_products.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _lib.moco_template_int8_products.restype = _i
+_lib.moco_template_int8_tile.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+_lib.moco_template_int8_tile.restype = _i
+_lib.moco_tune_set_tile.argtypes = [_i, _i, _i, _i, _i, _i]
+_lib.moco_tune_set_tile.restype = _i
 _lib.moco_graph_create.argtypes = [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i,
                                    ctypes.POINTER(_Outputs), ctypes.POINTER(_vp)]
 _lib.moco_graph_create.restype = _i
@@ -385,11 +392,9 @@ def _outputs(r: Result, T: int, W: int, dev) -> "_Outputs":
                     r.recomputed.data_ptr() if r.recomputed is not None else None)
 
 
-def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
-                     surface: bool = False):
-    """Align several stacks in one call.  items: list of (frames, Template) or
-    (frames, Template, Result).  Returns the list of Results (enqueued on the
-    current stream)."""
+def _stack_records(items, surface: bool):
+    """The moco_stack records of (frames, Template[, Result]) items, their
+    Results (new where not given) and the device."""
     stacks = (_Stack * max(1, len(items)))()
     results = []
     dev = None
@@ -405,9 +410,51 @@ def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
         o = _outputs(res, T, 2 * tmpl.w - 1, dev)
         stacks[k] = _Stack(frames.data_ptr(), tmpl.handle.value, T, m, n, tmpl.w,
                            int(tmpl.downsample), _dtype_code(frames), o)
+    return stacks, results, dev
+
+
+def moco_align_batch(ctx: Context, items, form: str = "auto", lanes: int = 0,
+                     surface: bool = False):
+    """Align several stacks in one call.  items: list of (frames, Template) or
+    (frames, Template, Result).  Returns the list of Results (enqueued on the
+    current stream)."""
+    stacks, results, dev = _stack_records(items, surface)
     stream = _stream_handle(dev if dev is not None else ctx.device)
     _check(_lib.moco_align_batch(ctx.handle, stacks, len(items), FORMS[form], lanes, stream))
     return results
+
+
+class BatchGraph:
+    """moco_graph_create_batch: a moco_align_batch call captured once;
+    launch() realigns whatever the stacks' frame buffers hold then, into
+    `results` (the buffers and templates are kept alive here)."""
+
+    def __init__(self, ctx: Context, items, form: str = "auto", lanes: int = 0,
+                 surface: bool = False):
+        self.items = list(items)
+        stacks, self.results, dev = _stack_records(self.items, surface)
+        self.device = dev if dev is not None else torch.device("cuda", ctx.device)
+        h = _vp()
+        _check(_lib.moco_graph_create_batch(ctx.handle, stacks, len(self.items), FORMS[form],
+                                            lanes, ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        """Enqueue a replay on the current stream; returns the Results."""
+        _check(_lib.moco_graph_launch(self.handle, _stream_handle(self.device)))
+        return self.results
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _lib.moco_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def align(frames: torch.Tensor, template: torch.Tensor, w: int, downsample: bool,
@@ -505,6 +552,19 @@ def fft_bound(tmpl: Template):
     kf, ke = ctypes.c_double(), ctypes.c_double()
     _check(_lib.moco_template_fft_bound(tmpl.handle, ctypes.byref(kf), ctypes.byref(ke)))
     return kf.value, ke.value
+
+
+def int8_tile(tmpl: Template) -> int:
+    """moco_template_int8_tile: the int8 form's shift tile (32 or 64) for the
+    template's key now (recorded by tune or tune_set_tile, else the model's)."""
+    n = ctypes.c_int()
+    _check(_lib.moco_template_int8_tile(tmpl.handle, ctypes.byref(n)))
+    return n.value
+
+
+def tune_set_tile(m: int, n: int, w: int, downsample: int, dtype: str, tile: int):
+    """moco_tune_set_tile (dtype "u16")."""
+    _check(_lib.moco_tune_set_tile(m, n, w, int(downsample), _DTYPES[dtype], tile))
 
 
 def int8_products(tmpl: Template) -> int:

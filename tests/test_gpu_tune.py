@@ -84,3 +84,73 @@ def test_recorded_form_overrides_the_model(gpu_lib):
     finally:
         gpu_lib.tune_clear()
         ctx.close()
+
+
+# the int8 form's two tile shapes give the same exact results: shift windows
+# of one, two and five tile groups, a frame of several chunks of digits
+TILE_CASES = [
+    # (m, n, w, ds, T): 2w-1 = W
+    (256, 256, 33, 0, 4),    # W = 65: 3x3 tiles of 32 against 2x2 groups of 2x2
+    (256, 256, 64, 0, 3),    # W = 127: 4x4 against 2x2 groups
+    (416, 460, 69, 1, 3),    # W = 137, grid 208x230: 5x5 against 3x3 groups
+    (200, 136, 20, 0, 5),    # W = 39
+]
+
+
+@pytest.mark.parametrize("case", TILE_CASES, ids=lambda c: "%dx%d_w%d_ds%d" % c[:4])
+def test_int8_tile_shapes_agree_with_the_oracle(gpu_lib, case):
+    import oracle
+    from tests._parity import check, check_surface
+    m, n, w, ds, T = case
+    sc = synth.PoissonScene(m, n, T + 1, seed=m + w)
+    fr = sc.frames(1, T + 1)
+    gpu_lib.tune_clear()
+    ctx = gpu_lib.Context(0)
+    try:
+        tp = gpu_lib.Template(ctx, torch.from_numpy(sc.template).cuda(), w, ds)
+        model = gpu_lib.int8_tile(tp)
+        res = {}
+        for tile in (32, 64):
+            gpu_lib.tune_set_tile(m, n, w, ds, "u16", tile)
+            assert gpu_lib.int8_tile(tp) == tile
+            r = gpu_lib.moco_align(ctx, torch.from_numpy(fr).cuda(), tp, form="int8", surface=True)
+            torch.cuda.synchronize()
+            res[tile] = {k: getattr(r, k).cpu().numpy() for k in
+                         ("shifts", "coarse", "fmin", "frefine", "gaps", "fsurf")}
+        _say("case int8 tiles", case, "model tile", model)
+        for k in res[32]:
+            assert np.array_equal(res[32][k], res[64][k], equal_nan=True), k
+        orc = oracle.align(fr, sc.template, w, bool(ds), want_surface=True)
+        check(res[32], orc, bool(ds), exact=True, label="int8 tile 32 %s" % (case,))
+        check_surface(res[32]["fsurf"], orc.surf, exact=True, label="int8 tile 32 surface")
+        tp.close()
+    finally:
+        gpu_lib.tune_clear()
+        ctx.close()
+
+
+def test_tune_records_the_faster_tile(gpu_lib):
+    sc = synth.PoissonScene(256, 256, 4, seed=31)
+    gpu_lib.tune_clear()
+    ctx = gpu_lib.Context(0)
+    try:
+        tp = gpu_lib.Template(ctx, torch.from_numpy(sc.template).cuda(), 40, False)
+        # 79 shifts a side: the model's 2x2 groups of 2x2 tiles (16 tiles)
+        # against 3x3 single tiles (9), timed by the tuner
+        assert gpu_lib.int8_tile(tp) == 64
+        form, times = gpu_lib.tune(ctx, tp, frames=256)
+        tile = gpu_lib.int8_tile(tp)
+        _say("tuned", form, times, "int8 tile", tile)
+        assert tile in (32, 64) and "int8" in times
+        gpu_lib.tune_clear()
+        assert gpu_lib.int8_tile(tp) == 64
+        with pytest.raises(gpu_lib.MocoError):
+            gpu_lib.tune_set_tile(256, 256, 8, 0, "u16", 64)      # 2w-1 = 15: one tile
+        with pytest.raises(gpu_lib.MocoError):
+            gpu_lib.tune_set_tile(256, 256, 40, 0, "u16", 16)
+        with pytest.raises(gpu_lib.MocoError):
+            gpu_lib.tune_set_tile(256, 256, 40, 0, "f32", 32)
+        tp.close()
+    finally:
+        gpu_lib.tune_clear()
+        ctx.close()
