@@ -417,6 +417,11 @@ def measure_batch(moco, ctx, steps: int, unique: int = 8):
         return (time.perf_counter() - t) / steps
 
     dt_batch = timed(lambda: moco.moco_align_batch(ctx, items, form="auto"))
+    # the same call captured once as a graph (its own scratch), replayed
+    g = moco.BatchGraph(ctx, [(fr, tp) for fr, tp, _ in items], form="auto")
+    dt_graph = timed(g.launch)
+    g.close()
+    del g
     dt_loop = timed(lambda: [moco.moco_align(ctx, fr, tp, out=res) for fr, tp, res in items])
     # the same batch after timing the forms of every stack's key (moco_tune) at
     # that stack's length (stacks that share a key: the last one's measurement)
@@ -438,6 +443,8 @@ def measure_batch(moco, ctx, steps: int, unique: int = 8):
     return {"stacks": 64, "frames": total, "bytes": nbytes, "unique_frames_per_stack": unique,
             "forms": forms, "steps": steps,
             "batched": {"seconds": round(dt_batch, 5), "frames_per_s": round(total / dt_batch, 1)},
+            "batched_graph": {"seconds": round(dt_graph, 5),
+                              "frames_per_s": round(total / dt_graph, 1)},
             "batched_tuned": {"seconds": round(dt_tuned, 5),
                               "frames_per_s": round(total / dt_tuned, 1), "forms": tuned_forms,
                               "tuning_seconds": round(t_tune, 2)},

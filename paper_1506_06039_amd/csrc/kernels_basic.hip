@@ -125,6 +125,36 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const T *__restrict__ fr, int
     }
 }
 
+// The same for the frames whose only[f] is set: block (x, frame), the blocks
+// of unset frames exit at once (the masked passes of the certified forms
+// usually cover few frames of a chunk).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_masked(const T *__restrict__ fr, int m, int n,
+                                                          int mg, int ng, int ds,
+                                                          double *__restrict__ out,
+                                                          const int32_t *__restrict__ only)
+{
+    const int f = blockIdx.y;
+    if (!only[f]) return;
+    const size_t plane = (size_t)mg * ng;
+    const T *a = fr + (size_t)f * m * n;
+    double *o = out + (size_t)f * plane;
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < plane;
+         r += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(r / ng), j = (int)(r - (r / ng) * ng);
+        double v;
+        if (ds) {
+            const T *p = a + (size_t)(2 * i) * n + 2 * j;
+            double x00 = (double)p[0], x01 = (double)p[1];
+            double x10 = (double)p[n], x11 = (double)p[n + 1];
+            v = (((x00 + x01) + x10) + x11) / 4.0;
+        } else {
+            v = (double)a[(size_t)i * n + j];
+        }
+        o[r] = v;
+    }
+}
+
 // Same values as k_coarse with downsampling, four grid columns per thread:
 // the eight frame pixels of each of the two rows are read with 16-byte loads
 // (n a multiple of 8, 16-byte aligned frames) and summed in k_coarse's order.
@@ -326,9 +356,10 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
 // ---------------------------------------------------------------------------
 // k_energy_rows: the same table from one pass over the grid's rows, for grids
 // of at most 2048 columns and w <= 128 (four waves per frame; a wave takes
-// every fourth row, a lane four columns of each 256-column chunk).  Row
-// energies come from fixed-order wave sums and each lane keeps its columns'
-// energies; then the cuts (rows from the top and bottom, columns from the
+// every fourth row, a lane four columns of each 256-column chunk).  The
+// energies of the first and last w-1 rows come from fixed-order wave sums,
+// the total from each lane's share summed over the wave and then the waves,
+// and each lane keeps its columns' energies; then the cuts (rows from the top and bottom, columns from the
 // left and right) are made cumulative, and each wave writes one quadrant of
 // the table: for s = 1..w-1 it reads the s-th border row's corner values
 // again (each lane one or two of the first or last w-1 columns), takes their
@@ -373,33 +404,48 @@ __global__ __launch_bounds__(kErWaves * 64) void k_energy_rows(
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
         for (int q = 0; q < 4; ++q) col[c][q] = 0.0;
-    double my_tot = 0.0, my_max = 0.0;
+    // float pixels as they are, rows 16-byte aligned: four columns per load
+    const bool vec4 = SRC == 4 && (n & 3) == 0 && (((uintptr_t)a) & 15) == 0;
+    double my_tot = 0.0, my_max = 0.0;   // the lane's share of the total
     for (int i = wave; i < mg; i += kErWaves) {
         double rpart = 0.0;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int j0 = 4 * (lane + 64 * c);
+            double v[4];
+            if (vec4 && j0 + 3 < ng) {
+                const float4 f4 = *(const float4 *)((const float *)a + (size_t)i * n + j0);
+                v[0] = f4.x, v[1] = f4.y, v[2] = f4.z, v[3] = f4.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = j0 + q < ng ? grid_at<SRC>(a, n, ng, i, j0 + q) : 0.0;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int j = j0 + q;
                 double x2 = 0.0;
-                if (j < ng) {
-                    const double v = grid_at<SRC>(a, n, ng, i, j), x = v - center;
-                    my_max = fmax(my_max, v);
+                if (j0 + q < ng) {
+                    const double x = v[q] - center;
+                    my_max = fmax(my_max, v[q]);
                     x2 = x * x;
                 }
                 rpart += x2;
                 col[c][q] += x2;
             }
         }
+        my_tot += rpart;
+        // the row's energy is needed only for the first and last w-1 rows (a
+        // whole wave takes the row, so the branch is uniform)
+        if (i < E || i >= mg - E) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) rpart += __shfl_xor(rpart, off);
-        my_tot += rpart;   // the same in every lane of the wave
-        if (lane == 0) {
-            if (i < E) rT[i] = rpart;
-            if (i >= mg - E) rB[mg - 1 - i] = rpart;
+            for (int off = 32; off > 0; off >>= 1) rpart += __shfl_xor(rpart, off);
+            if (lane == 0) {
+                if (i < E) rT[i] = rpart;
+                if (i >= mg - E) rB[mg - 1 - i] = rpart;
+            }
         }
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) my_tot += __shfl_xor(my_tot, off);
     // per-wave partials: the border columns' energies, the total, the maximum
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -1452,6 +1498,17 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
         else
             k_coarse_ds4<float><<<grid_for(quads), kBlock, 0, st>>>(
                 (const float *)frames, C, g.m, g.n, g.mg, g.ng, coarse);
+        return hipGetLastError();
+    }
+    if (only && C <= 65535) {
+        const size_t plane = (size_t)g.mg * g.ng;
+        const dim3 grid((unsigned)std::min<size_t>((plane + kBlock - 1) / kBlock, 64), C);
+        if (dt == MOCO_U16)
+            k_coarse_masked<uint16_t><<<grid, kBlock, 0, st>>>(
+                (const uint16_t *)frames, g.m, g.n, g.mg, g.ng, g.ds, coarse, only);
+        else
+            k_coarse_masked<float><<<grid, kBlock, 0, st>>>(
+                (const float *)frames, g.m, g.n, g.mg, g.ng, g.ds, coarse, only);
         return hipGetLastError();
     }
     if (dt == MOCO_U16)
