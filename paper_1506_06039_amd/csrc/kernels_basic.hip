@@ -744,13 +744,13 @@ __global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src,
     const int s = coarse_st[2 * frame], t = coarse_st[2 * frame + 1];
     const void *a = grid_frame<SRC>(src, frame, m, n, mg, ng);
     const int i0 = max(0, -s), i1 = min(mg, mg - s), j0 = max(0, -t), j1 = min(ng, ng - t);
-    const int nr = i1 - i0, nc = j1 - j0;
+    // thread k takes columns j0 + k, j0 + k + 256, ... of every row of D
     double acc = 0.0;
-    for (long long p = threadIdx.x; p < (long long)nr * nc; p += kBlock) {
-        const int i = i0 + (int)(p / nc), j = j0 + (int)(p % nc);
-        const double d = grid_at<SRC>(a, n, ng, i + s, j + t) - tcoarse[(size_t)i * ng + j];
-        acc = fma(d, d, acc);
-    }
+    for (int i = i0; i < i1; ++i)
+        for (int j = j0 + threadIdx.x; j < j1; j += kBlock) {
+            const double d = grid_at<SRC>(a, n, ng, i + s, j + t) - tcoarse[(size_t)i * ng + j];
+            acc = fma(d, d, acc);
+        }
     __shared__ double red[kBlock];
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -1502,7 +1502,8 @@ hipError_t launch_coarse(const void *frames, moco_dtype dt, int C, const Geom &g
     }
     if (only && C <= 65535) {
         const size_t plane = (size_t)g.mg * g.ng;
-        const dim3 grid((unsigned)std::min<size_t>((plane + kBlock - 1) / kBlock, 64), C);
+        // few blocks per frame: most frames of a masked pass are unset
+        const dim3 grid((unsigned)std::min<size_t>((plane + kBlock - 1) / kBlock, 8), C);
         if (dt == MOCO_U16)
             k_coarse_masked<uint16_t><<<grid, kBlock, 0, st>>>(
                 (const uint16_t *)frames, g.m, g.n, g.mg, g.ng, g.ds, coarse, only);
