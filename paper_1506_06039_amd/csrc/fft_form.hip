@@ -225,7 +225,7 @@ __device__ C *fft_lds(C *a, C *b, int rows, const FftPlan &pl, const C *tw)
 template <typename R>
 __device__ void block_max_store(R v, R *dst)
 {
-    __shared__ R wm[kBlock / 64];
+    __shared__ R wm[1024 / 64];   // any block of at most 1024 threads
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
     if (threadIdx.x % 64 == 0) wm[threadIdx.x / 64] = v;
     __syncthreads();
@@ -519,19 +519,25 @@ struct WPass {
     }
 };
 
-constexpr int kWaveBlock = 256;           // four waves
 constexpr int kWPad = 0;                  // elements between transform buffers
 
-template <int N, int T>
+// Threads per block of the wave-level kernels: eight waves in FP32, four in
+// FP64.  Measured on MI355X (three transform kernels per 2000 frames of the
+// 512x512 stack; the 10000-frame 256x256 stack): FP32 0.94 -> 0.875 ms and
+// 5.08 -> 4.65 ms with eight waves, FP64 1.40 -> 1.47 ms.
+template <typename R>
+constexpr int wave_block() { return sizeof(R) == 4 ? 512 : 256; }
+
+template <int N, int T, int B>
 struct WGeom {
     static constexpr int per_wave = 64 / T;
-    static constexpr int per_block = per_wave * (kWaveBlock / 64);
+    static constexpr int per_block = per_wave * (B / 64);
     static constexpr int stride = N + kWPad;
 };
 
 // Rows: packed pairs of real grid rows, as k_fft_rows.
 template <int SRC, typename R, int Q, int T>
-__global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ src, int m, int n,
+__global__ __launch_bounds__(wave_block<R>()) void k_wrows(const void *__restrict__ src, int m, int n,
                                                       int mg, int ng,
                                                       const typename Cx<R>::T *__restrict__ twq,
                                                       double center,
@@ -539,7 +545,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ s
                                                       const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
-    using G = WGeom<Q, T>;
+    using G = WGeom<Q, T, wave_block<R>()>;
+    constexpr int kWaveBlock = wave_block<R>();
     if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + Q;
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_wrows(const void *__restrict__ s
 // Columns: forward, times conj(spec), inverse, the 2w-1 outputs kept, and
 // the block's largest |X_k|^2 when xmax is given, as k_fft_cols<false>.
 template <typename R, int P, int T>
-__global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *__restrict__ s1,
+__global__ __launch_bounds__(wave_block<R>()) void k_wcols(const typename Cx<R>::T *__restrict__ s1,
                                                       int mg, int qh, int w,
                                                       const typename Cx<R>::T *__restrict__ twp,
                                                       const typename Cx<R>::T *__restrict__ spec,
@@ -586,7 +593,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *_
                                                       R *__restrict__ xmax)
 {
     using C = typename Cx<R>::T;
-    using G = WGeom<P, T>;
+    using G = WGeom<P, T, wave_block<R>()>;
+    constexpr int kWaveBlock = wave_block<R>();
     if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + P;
@@ -627,14 +635,15 @@ __global__ __launch_bounds__(kWaveBlock) void k_wcols(const typename Cx<R>::T *_
 
 // Rows back: packed pairs of shift rows, as k_fft_rows_back.
 template <typename R, int Q, int T>
-__global__ __launch_bounds__(kWaveBlock) void k_wback(const typename Cx<R>::T *__restrict__ s2,
+__global__ __launch_bounds__(wave_block<R>()) void k_wback(const typename Cx<R>::T *__restrict__ s2,
                                                       int qh, int w, double scale,
                                                       const typename Cx<R>::T *__restrict__ twq,
                                                       double *__restrict__ h,
                                                       const int32_t *__restrict__ only)
 {
     using C = typename Cx<R>::T;
-    using G = WGeom<Q, T>;
+    using G = WGeom<Q, T, wave_block<R>()>;
+    constexpr int kWaveBlock = wave_block<R>();
     if (only && !only[blockIdx.y]) return;
     extern __shared__ double lds_d[];
     C *tw = (C *)lds_d, *bufs = tw + Q;
@@ -683,7 +692,7 @@ constexpr int wave_lanes() { return 64; }
 template <typename R, int N>
 size_t wave_lds()
 {
-    using G = WGeom<N, wave_lanes<R>()>;
+    using G = WGeom<N, wave_lanes<R>(), wave_block<R>()>;
     return ((size_t)N + (size_t)G::per_block * G::stride) * sizeof(typename Cx<R>::T);
 }
 
@@ -712,8 +721,9 @@ void wrows_launch(const void *src, int C, const Geom &g, const typename Cx<R>::T
 {
     constexpr int T = wave_lanes<R>();
     const int npairs = (g.mg + 1) / 2;
-    const int pb = WGeom<Q, T>::per_block;
-    k_wrows<SRC, R, Q, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, Q>(), st>>>(
+    const int pb = WGeom<Q, T, wave_block<R>()>::per_block;
+    k_wrows<SRC, R, Q, T><<<dim3((npairs + pb - 1) / pb, C), wave_block<R>(), wave_lds<R, Q>(),
+                            st>>>(
         src, g.m, g.n, g.mg, g.ng, twq, center, s1, only);
 }
 
@@ -739,9 +749,9 @@ bool wcols(const typename Cx<R>::T *s1, int C, const Geom &g, const FftTmpl &ft,
     constexpr int T = wave_lanes<R>();
 #define MOCO_WL_COLS(L)                                                                       \
     case L: {                                                                                 \
-        const int pb = WGeom<L, T>::per_block;                                                \
+        const int pb = WGeom<L, T, wave_block<R>()>::per_block;                               \
         *nxb = (ft.qh + pb - 1) / pb;                                                         \
-        k_wcols<R, L, T><<<dim3(*nxb, C), kWaveBlock, wave_lds<R, L>(), st>>>(                 \
+        k_wcols<R, L, T><<<dim3(*nxb, C), wave_block<R>(), wave_lds<R, L>(), st>>>(            \
             s1, g.mg, ft.qh, g.w, twp, spec, s2, only, xmax);                                 \
         return true;                                                                          \
     }
@@ -762,8 +772,9 @@ bool wback(const typename Cx<R>::T *s2, int C, const Geom &g, const FftTmpl &ft,
     const int npairs = (g.W + 1) / 2;
 #define MOCO_WL_BACK(L)                                                                         \
     case L: {                                                                                   \
-        const int pb = WGeom<L, T>::per_block;                                                  \
-        k_wback<R, L, T><<<dim3((npairs + pb - 1) / pb, C), kWaveBlock, wave_lds<R, L>(), st>>>( \
+        const int pb = WGeom<L, T, wave_block<R>()>::per_block;                                 \
+        k_wback<R, L, T><<<dim3((npairs + pb - 1) / pb, C), wave_block<R>(), wave_lds<R, L>(),   \
+                           st>>>(                                                                \
             s2, ft.qh, g.w, scale, twq, h, only);                                               \
         return true;                                                                            \
     }
@@ -1062,11 +1073,5 @@ hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTm
     return corr<float>(s1, C, g, ft, s2, h, st, nullptr, xmax, nxb);
 }
 
-int fft_cols_blocks(const Geom &g, const FftTmpl &ft, size_t esz)
-{
-    if (g_wave_fft && wave_length(ft.pp.n)) return (ft.qh + 3) / 4;
-    const int kb = rows_per_block(ft.pp.n, esz);
-    return (ft.qh + kb - 1) / kb;
-}
 
 }  // namespace moco

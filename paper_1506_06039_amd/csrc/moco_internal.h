@@ -259,12 +259,12 @@ hipError_t launch_fft32_rows(const double *grid, int C, const Geom &g, const Fft
                              float2 *s1, hipStream_t st);
 hipError_t launch_fft32_rows_px(const void *frames, int C, const Geom &g, const FftTmpl &ft,
                                 float2 *s1, hipStream_t st);
-// xmax (may be null): [frame][fft_cols_blocks] maxima of |X_k|^2 over the
-// frame's spectrum, one per column block (*nxb, may be null, gets their count)
+// xmax (may be null): [frame][*nxb] maxima of |X_k|^2 over the frame's
+// spectrum, one per column block (*nxb, may be null, gets their count, at most
+// the number of bins)
 hipError_t launch_fft32_corr(const float2 *s1, int C, const Geom &g, const FftTmpl &ft,
                              float2 *s2, double *h, hipStream_t st, float *xmax = nullptr,
                              int *nxb = nullptr);
-int fft_cols_blocks(const Geom &g, const FftTmpl &ft, size_t esz);
 
 // ---- the corrected stack and its mean image (apply.hip) ---------------
 // frames per chunk of the mean's partial sums (0: one chunk of [m][n] FP64
