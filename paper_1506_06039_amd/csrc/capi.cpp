@@ -234,7 +234,7 @@ size_t refine_steps_partial_bytes(const moco::Geom &g)
 // border tables (0 where it does not apply).
 size_t energy_scratch_bytes(const moco::Geom &g)
 {
-    return moco::prep_grid_applicable(g) ? moco::prep_grid_edge_bytes(g) : 0;
+    return moco::prep_grid_applicable(g) ? moco::prep_edge_bytes(g) : 0;
 }
 
 // Per-frame scratch of the FP64 exact form.
@@ -374,7 +374,7 @@ Int8Layout int8_layout(const moco::Geom &g, int npad)
     L.limbs = align_up((size_t)3 * g.mg * npad, 256);
     L.nlimb = 256;
     L.atab = align_up((size_t)g.W * g.W * sizeof(long long), 256);
-    L.edge = align_up((size_t)4 * (g.w - 1) * g.w * sizeof(long long), 256);
+    L.edge = align_up(moco::prep_edge_bytes(g), 256);
     L.h = align_up((size_t)g.W * g.W * sizeof(long long), 256);
     L.cst = 2 * sizeof(int32_t);
     L.part = align_up(moco::refine_partial_bytes(g), 8);
@@ -1912,6 +1912,7 @@ struct SrvRequest {
 // Streams on which a lane runs the source groups of a batch side by side.
 constexpr int kSrvSubStreams = 4;
 constexpr int kSrvLanes = 2;       // batches in flight at once (four measured slower)
+constexpr long kPollSpinUs = 1000;  // moco_server_poll looks for results this long before sleeping
 
 // Device and pinned buffers of one batch in flight.
 struct SrvLane {
@@ -1930,6 +1931,7 @@ struct SrvLane {
     size_t meta_bytes = 0;
     std::vector<SrvRequest> reqs;
     bool active = false;
+    bool enqueuing = false;   // its launches are being issued (completion not yet recorded)
     int status = MOCO_OK;
 };
 
@@ -1951,6 +1953,7 @@ struct moco_server {
     std::deque<moco_result> completed;
     int inflight = 0;
     int staging = 0;  // submits holding a slot while they copy into it (lock released)
+    bool launching = false;   // a batch is being enqueued (by the worker or a submit)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
@@ -2089,14 +2092,17 @@ int server_enqueue(moco_server *srv, SrvLane &L)
     }
     if (meta_used)
         HIP_TRY(hipMemcpyAsync(L.d_meta, L.h_meta, meta_used, hipMemcpyHostToDevice, L.stream));
-    HIP_TRY(hipEventRecord(L.staged, L.stream));
+    // one group runs on the lane's stream; several fork onto its sub-streams
+    const bool fork = groups.size() > 1;
+    if (fork) HIP_TRY(hipEventRecord(L.staged, L.stream));
     bool used[kSrvSubStreams] = {};
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group &gr = groups[gi];
         const size_t a = gr.a, b = gr.b;
         const SrvRequest &q = L.reqs[a];
         const int k = (int)(gi % kSrvSubStreams);
-        if (!used[k]) {
+        const hipStream_t gs = fork ? L.sub[k] : L.stream;
+        if (fork && !used[k]) {
             HIP_TRY(hipStreamWaitEvent(L.sub[k], L.staged, 0));
             used[k] = true;
         }
@@ -2111,11 +2117,11 @@ int server_enqueue(moco_server *srv, SrvLane &L)
             Int8MultiTables dt;
             dt.place(L.d_meta + gr.meta_off, (int)(b - a));
             rc = run_int8_multi(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), gr.nblocks, dt,
-                                &out, L.sub[k], L.d_scratch + a * srv->pf_max,
+                                &out, gs, L.d_scratch + a * srv->pf_max,
                                 (b - a) * srv->pf_max);
         } else {
             rc = run_stack(srv->ctx, L.d_frames + off[a], *q.tmpl, (int)(b - a), q.g, q.form,
-                           &out, L.sub[k], L.d_scratch + a * srv->pf_max, (b - a) * srv->pf_max);
+                           &out, gs, L.d_scratch + a * srv->pf_max, (b - a) * srv->pf_max);
         }
         if (rc) return rc;
     }
@@ -2160,48 +2166,76 @@ void server_publish(moco_server *srv, SrvLane &L)
     L.active = false;
 }
 
+// Launch the waiting requests into the free lane L (called with srv->mu held,
+// by the worker or by a submit, never by two at once: srv->launching).  The
+// lane is marked as enqueuing meanwhile, so that the worker does not query
+// its completion event before this batch has recorded it.
+void server_launch(moco_server *srv, SrvLane &L, std::unique_lock<std::mutex> &lk)
+{
+    while (!srv->pending.empty() && (int)L.reqs.size() < srv->max_slots) {
+        L.reqs.push_back(srv->pending.front());
+        srv->pending.pop_front();
+    }
+    L.active = true;
+    L.enqueuing = true;
+    srv->launching = true;
+    lk.unlock();
+    int rc;
+    {
+        DeviceGuard dg(srv->ctx->device);
+        rc = dg.ok() ? server_enqueue(srv, L) : fail(MOCO_EDEVICE, "server: cannot select the device");
+    }
+    if (rc != MOCO_OK) {
+        // the batch never reached the GPU in full: wait for what did, then fail it
+        (void)hipStreamSynchronize(L.stream);
+        for (int k = 0; k < kSrvSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
+    }
+    lk.lock();
+    L.status = rc;
+    L.enqueuing = false;
+    srv->launching = false;
+    if (rc != MOCO_OK) server_publish(srv, L);
+    srv->cv_work.notify_all();   // the worker polls the lane, or launches what waits
+    srv->cv_done.notify_all();
+}
+
+bool server_any_active(const moco_server *srv)
+{
+    for (const auto &L : srv->lane)
+        if (L.active) return true;
+    return false;
+}
+
 void server_loop(moco_server *srv)
 {
     (void)hipSetDevice(srv->ctx->device);
     std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
-        bool any_active = false;
-        int fl = -1;   // a free lane
-        for (int k = 0; k < kSrvLanes; ++k) {
-            any_active = any_active || srv->lane[k].active;
-            if (fl < 0 && !srv->lane[k].active) fl = k;
-        }
-        if (!any_active) {
-            srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
-            if (srv->stop && srv->pending.empty()) break;
+        if (!server_any_active(srv)) {
+            srv->cv_work.wait(lk, [&] {
+                return srv->stop || !srv->pending.empty() || server_any_active(srv);
+            });
+            if (srv->stop && srv->pending.empty() && !server_any_active(srv)) break;
         }
         // launch the waiting requests into a free lane
-        if (fl >= 0 && !srv->pending.empty() && !srv->stop) {
-            SrvLane &L = srv->lane[fl];
-            while (!srv->pending.empty() && (int)L.reqs.size() < srv->max_slots) {
-                L.reqs.push_back(srv->pending.front());
-                srv->pending.pop_front();
+        if (!srv->launching && !srv->pending.empty() && !srv->stop) {
+            SrvLane *fl = nullptr;
+            for (auto &L : srv->lane)
+                if (!L.active) {
+                    fl = &L;
+                    break;
+                }
+            if (fl) {
+                server_launch(srv, *fl, lk);
+                continue;
             }
-            L.active = true;
-            lk.unlock();
-            int rc = server_enqueue(srv, L);
-            lk.lock();
-            L.status = rc;
-            if (rc != MOCO_OK) {
-                // the batch never reached the GPU in full: wait for what did, then fail it
-                lk.unlock();
-                (void)hipStreamSynchronize(L.stream);
-                for (int k = 0; k < kSrvSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
-                lk.lock();
-                server_publish(srv, L);
-                srv->cv_done.notify_all();
-            }
-            continue;
         }
-        // finish lanes whose batch has completed, oldest first
+        // finish lanes whose batch has completed, oldest first (only this
+        // thread publishes a lane whose launches were all issued, so the lane
+        // keeps its state while the lock is released for the query)
         bool progressed = false;
         for (auto &L : srv->lane) {
-            if (!L.active) continue;
+            if (!L.active || L.enqueuing) continue;
             lk.unlock();
             hipError_t q = hipEventQuery(L.done);
             lk.lock();
@@ -2214,7 +2248,7 @@ void server_loop(moco_server *srv)
             srv->cv_done.notify_all();
             continue;
         }
-        if (srv->stop && srv->pending.empty() && !any_active)
+        if (srv->stop && srv->pending.empty() && !server_any_active(srv))
             break;
         // a batch is on the GPU: poll its event again after yielding the lock
         // and the core (a timed wait sleeps for the scheduler's timer slack:
@@ -2350,6 +2384,14 @@ int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64
     }
     srv->pending.push_back(q);
     srv->inflight += 1;
+    // a free lane and no launch in progress: start the batch from here, so
+    // that it does not wait for the worker thread to wake up
+    if (!srv->launching)
+        for (auto &L : srv->lane)
+            if (!L.active) {
+                server_launch(srv, L, lk);
+                break;
+            }
     srv->cv_work.notify_one();
     srv->cv_done.notify_all();
     return MOCO_OK;
@@ -2361,10 +2403,27 @@ int moco_server_poll(moco_server *srv, moco_result *results, int max, int timeou
         return fail(MOCO_EINVAL, "moco_server_poll: bad arguments");
     std::unique_lock<std::mutex> lk(srv->mu);
     auto ready = [&] { return !srv->completed.empty(); };
-    if (timeout_us < 0)
-        srv->cv_done.wait(lk, [&] { return ready() || srv->inflight == 0; });
-    else if (timeout_us > 0)
-        srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+    auto idle = [&] { return timeout_us < 0 && srv->inflight == 0; };
+    if (timeout_us != 0 && !ready() && !idle()) {
+        // results usually follow within a batch's time: look for them, yielding
+        // the lock and the core, for up to kPollSpinUs before sleeping, so that
+        // a result is not held up by this thread's wake-up
+        const auto t0 = Clock::now();
+        const long spin = timeout_us < 0 ? kPollSpinUs : std::min<long>(timeout_us, kPollSpinUs);
+        const auto until = t0 + std::chrono::microseconds(spin);
+        while (!ready() && !idle() && Clock::now() < until) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        }
+        if (timeout_us < 0) {
+            srv->cv_done.wait(lk, [&] { return ready() || srv->inflight == 0; });
+        } else if (!ready()) {
+            const auto left = std::chrono::microseconds(timeout_us) -
+                              std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0);
+            if (left.count() > 0) srv->cv_done.wait_for(lk, left, ready);
+        }
+    }
     int k = 0;
     while (k < max && !srv->completed.empty()) {
         results[k++] = srv->completed.front();
@@ -2387,8 +2446,9 @@ int moco_server_destroy(moco_server *srv)
     {
         std::unique_lock<std::mutex> lk(srv->mu);
         srv->stop = true;
-        // submits still copying into their slots finish (and cancel themselves)
-        srv->cv_done.wait(lk, [&] { return srv->staging == 0; });
+        // submits still copying into their slots finish (and cancel themselves),
+        // and a batch being launched by a submit is fully enqueued
+        srv->cv_done.wait(lk, [&] { return srv->staging == 0 && !srv->launching; });
         cancelled = (int)srv->pending.size();
         for (auto &q : srv->pending) srv->free_slots.push_back(q.slot);
         srv->inflight -= cancelled;

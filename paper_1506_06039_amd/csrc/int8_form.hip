@@ -24,6 +24,8 @@
 // per MFMA).
 #include <math.h>
 
+#include <algorithm>
+
 #include "moco_internal.h"
 
 namespace moco {
@@ -67,7 +69,8 @@ __device__ inline unsigned byte_add(unsigned x, unsigned y)
 }
 
 // ---------------------------------------------------------------------------
-// k_prep_u16: one block per frame.
+// k_prep_u16: one block per frame (a few frames: one per band of rows, and
+// k_prep_finish per frame).
 //   limbs  [frame][3][mg][npad] int8 balanced digits of base 2^dbits (128 or
 //          256), plane 2 written only when needed
 //   nlimb  [frame]               2, or 3 when some X needs a third digit
@@ -125,7 +128,93 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 // grid units to atab_d (the integer sums divided by 16 when downsampling: an
 // exact scaling, the same values a FP64 pass over the grid gives), of the
 // values less xc (in box-sum units; the grid written is not centred).
-template <bool DS, int kMaxCol4, int NW, bool GRID>
+//
+// With BAND, a few frames are split over bands of band_rows grid rows, one
+// block per (band, frame) (grid.x bands, grid.y frames): each band writes its
+// digit planes (or grid rows) and the edge prefix rows it owns, and leaves
+// in bandp the sums the energy table needs from it; k_prep_finish then forms
+// the table per frame.  bandp [frame][prep_band_longs]: the 2(w-1) border
+// row energies (top rows 0..w-2, then bottom rows mg-1 down), then per band
+// {energies of the first w-1 and of the last w-1 columns (from the right),
+// total energy, third-digit flag, largest grid value}.
+
+// Energies of the border columns, rows and the whole grid -> the energy
+// table, the third digit plane (when needed) and the per-frame flags.  On
+// entry cL[s], cR[s], rT[s], rB[s] (s < w-1) hold the energies of column s,
+// column ng-1-s, row s and row mg-1-s; they are turned into prefix sums over
+// s = 0..w-1 here.  Every thread of the block (256) calls it.
+template <bool DS, bool GRID>
+__device__ inline void prep_tables(const uint16_t *a, int m, int n, int mg, int ng, int w,
+                                   int npad, int dbits, int frame, long long *cL, long long *cR,
+                                   long long *rT, long long *rB, long long Etot, int need3,
+                                   int xmax, const long long *E, int8_t *L0, int32_t *nlimb,
+                                   int32_t *vmax, long long *atab, double *atab_d)
+{
+    const int W = 2 * w - 1, we = w - 1;
+    auto eidx = [&](int tb, int lr, int e, int q) { return ((size_t)(tb * 2 + lr) * we + e) * w + q; };
+    // prefix sums: rows excluded from the top / bottom, columns from left / right
+    if (threadIdx.x % 64 == 0) {
+        long long *v = threadIdx.x == 0 ? cL : threadIdx.x == 64 ? cR : threadIdx.x == 128 ? rT : rB;
+        long long acc = 0;
+        for (int s = 0; s < w; ++s) {
+            const long long x = s < we ? v[s] : 0;
+            v[s] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    auto put = [&](size_t k, long long v) {
+        if (GRID)
+            atab_d[(size_t)frame * W * W + k] = DS ? 0.0625 * (double)v : (double)v;
+        else
+            atab[(size_t)frame * W * W + k] = v;
+    };
+    // one thread per (column shift t, sign of the row shift); the corner sums
+    // run down the rows, their loads unrolled so that several are in flight
+    for (int idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+        const int tt = idx % W, side = idx / W;
+        const int t = tt - we, at = t < 0 ? -t : t;
+        const int lr = t > 0 ? 0 : 1;
+        const long long colex = t > 0 ? cL[at] : (t < 0 ? cR[at] : 0);
+        const long long base = Etot - colex;
+        if (side == 0) put((size_t)we * W + tt, base);
+        const long long *rx = side ? rB : rT;   // rows excluded at the top (+s) or bottom (-s)
+        long long c = 0;
+#pragma unroll 8
+        for (int s = 1; s < w; ++s) {
+            if (t != 0) c += E[eidx(side, lr, s - 1, at)];
+            put((size_t)(side ? we - s : we + s) * W + tt, base - rx[s] + c);
+        }
+    }
+    // third digit plane, only for frames that need it
+    if (!GRID && need3) {
+        const size_t plane = (size_t)mg * npad;
+        int8_t *L2 = L0 + 2 * plane;
+        const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+        for (int i = wave; i < mg; i += nw)
+            for (int j0 = 4 * lane; j0 < npad; j0 += 256) {
+                int d2p = 0;
+                for (int q = 0; q < 4; ++q) {
+                    int j = j0 + q;
+                    int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
+                    int d0 = bdigit(X, dbits);
+                    int x1 = (X - d0) >> dbits;
+                    int d1 = bdigit(x1, dbits);
+                    int d2 = (x1 - d1) >> dbits;
+                    d2p |= (d2 & 255) << (8 * q);
+                }
+                *(int *)(L2 + (size_t)i * npad + j0) = d2p;
+            }
+    }
+    if (threadIdx.x == 0) {
+        if (!GRID) nlimb[frame] = need3 ? 3 : 2;
+        // every pixel is a term of some grid value unless a side is odd when downsampling
+        const bool covers = !DS || ((m % 2) == 0 && (n % 2) == 0);
+        vmax[frame] = covers ? xmax : INT32_MAX;
+    }
+}
+
+template <bool DS, int kMaxCol4, int NW, bool GRID, bool BAND>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_prep_u16(const uint16_t *__restrict__ raw, int m,
                                                      int n, int mg, int ng, int w, int npad,
                                                      int dbits,
@@ -137,10 +226,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                                                      double *__restrict__ grid,
                                                      double *__restrict__ atab_d,
                                                      const int32_t *__restrict__ only,
-                                                     int xc)
+                                                     int xc, int band_rows,
+                                                     long long *__restrict__ bandp)
 {
+    const int frame = BAND ? blockIdx.y : blockIdx.x;
     // GRID with `only`: frames whose only[f] is 0 are skipped (the whole block)
-    if (GRID && only && !only[blockIdx.x]) return;
+    if (GRID && only && !only[frame]) return;
     // dynamic LDS: colE[npad] | rowbuf[NW][2][we1] | rT[w] | rB[w] | cL[w] | cR[w] | etot | need3
     extern __shared__ long long lds_prep[];
     const int we1 = w > 1 ? w - 1 : 1;
@@ -155,7 +246,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     int &xmax = *((int *)(cR + w + 1) + 1);
     auto rowbuf = [&](int wv, int side) { return rowbuf_base + ((size_t)wv * 2 + side) * we1; };
 
-    const int frame = blockIdx.x;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const uint16_t *a = raw + (size_t)frame * m * n;
     // vector raw reads need aligned rows: 16 bytes (box sums) or 8 bytes
@@ -164,10 +254,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     const size_t plane = (size_t)mg * npad;
     int8_t *L0 = limbs + (size_t)frame * 3 * plane;
     int8_t *L1 = L0 + plane;
-    const int W = 2 * w - 1, we = w - 1;
+    const int we = w - 1;
     long long *E = edge + (size_t)frame * 4 * we * w;
     // E layout: [tb][lr][e][q]: tb 0 top / 1 bottom, lr 0 LP / 1 RS
     auto eidx = [&](int tb, int lr, int e, int q) { return ((size_t)(tb * 2 + lr) * we + e) * w + q; };
+    long long *bp = BAND ? bandp + (size_t)frame * prep_band_longs(w) : nullptr;
+    const int i_lo = BAND ? blockIdx.x * band_rows : 0;
+    const int i_hi = BAND ? min(mg, i_lo + band_rows) : mg;
 
     for (int j = threadIdx.x; j < npad; j += blockDim.x) colE[j] = 0;
     if (threadIdx.x == 0) {
@@ -186,7 +279,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     long long my_etot = 0;
     int my_need3 = 0;
 
-    for (int i = wave; i < mg; i += NW) {
+    for (int i = i_lo + wave; i < i_hi; i += NW) {
         const bool top = i < we, bot = i >= mg - we;
         long long rpart = 0;
 #pragma unroll
@@ -234,8 +327,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
         my_etot += r;
         if (top || bot) {
             if (lane == 0) {
-                if (top) rT[i] = r;
-                if (bot) rB[mg - 1 - i] = r;
+                long long *tT = BAND ? bp : rT, *tB = BAND ? bp + we : rB;
+                if (top) tT[i] = r;
+                if (bot) tB[mg - 1 - i] = r;
             }
             // prefix sums of this row's X^2 over the first / last q columns
             for (int q = lane; q < w; q += 64) {
@@ -268,74 +362,76 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     if (my_need3) need3 = 1;
     atomicMax(&xmax, my_xmax);
     __syncthreads();
-    // cumulative border tables: rows excluded from the top / bottom, columns from left / right
-    if (threadIdx.x == 0) {
-        long long acc = 0;
-        for (int s = 0; s < w; ++s) { cL[s] = acc; if (s < we) acc += colE[s]; }
-    }
-    if (threadIdx.x == 64) {
-        long long acc = 0;
-        for (int s = 0; s < w; ++s) { cR[s] = acc; if (s < we) acc += colE[ng - 1 - s]; }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // rT/rB become cumulative: rT[s] = sum of the first s row energies
-        long long acc = 0;
-        for (int s = 0; s < w; ++s) { long long v = (s < we) ? rT[s] : 0; rT[s] = acc; acc += v; }
-    }
-    if (threadIdx.x == 64) {
-        long long acc = 0;
-        for (int s = 0; s < w; ++s) { long long v = (s < we) ? rB[s] : 0; rB[s] = acc; acc += v; }
-    }
-    __syncthreads();
-    const long long Etot = etot;
-    auto put = [&](size_t k, long long v) {
-        if (GRID)
-            atab_d[(size_t)frame * W * W + k] = DS ? 0.0625 * (double)v : (double)v;
-        else
-            atab[(size_t)frame * W * W + k] = v;
-    };
-    // one thread per (column shift t, sign of the row shift); the corner sums
-    // run down the rows, their loads unrolled so that several are in flight
-    for (int idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
-        const int tt = idx % W, side = idx / W;
-        const int t = tt - we, at = t < 0 ? -t : t;
-        const int lr = t > 0 ? 0 : 1;
-        const long long colex = t > 0 ? cL[at] : (t < 0 ? cR[at] : 0);
-        const long long base = Etot - colex;
-        if (side == 0) put((size_t)we * W + tt, base);
-        const long long *rx = side ? rB : rT;   // rows excluded at the top (+s) or bottom (-s)
-        long long c = 0;
-#pragma unroll 8
-        for (int s = 1; s < w; ++s) {
-            if (t != 0) c += E[eidx(side, lr, s - 1, at)];
-            put((size_t)(side ? we - s : we + s) * W + tt, base - rx[s] + c);
+    if (BAND) {
+        // this band's share of the border-column, total and flag reductions
+        long long *P = bp + 2 * we + (size_t)blockIdx.x * (2 * we + 3);
+        for (int s = threadIdx.x; s < we; s += blockDim.x) {
+            P[s] = colE[s];
+            P[we + s] = colE[ng - 1 - s];
         }
+        if (threadIdx.x == 0) {
+            P[2 * we] = etot;
+            P[2 * we + 1] = need3;
+            P[2 * we + 2] = xmax;
+        }
+        return;
     }
-    // third digit plane, only for frames that need it
-    if (!GRID && need3) {
-        int8_t *L2 = L0 + 2 * plane;
-        for (int i = wave; i < mg; i += NW)
-            for (int j0 = 4 * lane; j0 < npad; j0 += 256) {
-                int d2p = 0;
-                for (int q = 0; q < 4; ++q) {
-                    int j = j0 + q;
-                    int X = (j < ng) ? grid_value<DS>(a, n, i, j) : 0;
-                    int d0 = bdigit(X, dbits);
-                    int x1 = (X - d0) >> dbits;
-                    int d1 = bdigit(x1, dbits);
-                    int d2 = (x1 - d1) >> dbits;
-                    d2p |= (d2 & 255) << (8 * q);
-                }
-                *(int *)(L2 + (size_t)i * npad + j0) = d2p;
-            }
+    for (int s = threadIdx.x; s < we; s += blockDim.x) {
+        cL[s] = colE[s];
+        cR[s] = colE[ng - 1 - s];
+    }
+    __syncthreads();
+    prep_tables<DS, GRID>(a, m, n, mg, ng, w, npad, dbits, frame, cL, cR, rT, rB, etot, need3,
+                          xmax, E, L0, nlimb, vmax, atab, atab_d);
+}
+
+// The energy table of each frame from its bands' sums (one block per frame).
+template <bool DS, bool GRID>
+__global__ __launch_bounds__(256) void k_prep_finish(const uint16_t *__restrict__ raw, int m, int n,
+                                                     int mg, int ng, int w, int npad, int dbits,
+                                                     int nbands, int8_t *__restrict__ limbs,
+                                                     int32_t *__restrict__ nlimb,
+                                                     int32_t *__restrict__ vmax,
+                                                     long long *__restrict__ atab,
+                                                     const long long *__restrict__ edge,
+                                                     double *__restrict__ atab_d,
+                                                     const int32_t *__restrict__ only,
+                                                     const long long *__restrict__ bandp)
+{
+    const int frame = blockIdx.x;
+    if (GRID && only && !only[frame]) return;
+    extern __shared__ long long lds_fin[];   // cL[w] | cR[w] | rT[w] | rB[w]
+    long long *cL = lds_fin, *cR = cL + w, *rT = cR + w, *rB = rT + w;
+    __shared__ long long s_etot;
+    __shared__ int s_need3, s_xmax;
+    const int we = w - 1;
+    const long long *bp = bandp + (size_t)frame * prep_band_longs(w);
+    const int rec = 2 * we + 3;
+    for (int s = threadIdx.x; s < 2 * we; s += blockDim.x) {
+        long long acc = 0;
+        for (int b = 0; b < nbands; ++b) acc += bp[2 * we + (size_t)b * rec + s];
+        (s < we ? cL[s] : cR[s - we]) = acc;
+        (s < we ? rT[s] : rB[s - we]) = bp[s];
     }
     if (threadIdx.x == 0) {
-        if (!GRID) nlimb[frame] = need3 ? 3 : 2;
-        // every pixel is a term of some grid value unless a side is odd when downsampling
-        const bool covers = !DS || ((m % 2) == 0 && (n % 2) == 0);
-        vmax[frame] = covers ? xmax : INT32_MAX;
+        long long e = 0;
+        int n3 = 0, xm = 0;
+        for (int b = 0; b < nbands; ++b) {
+            const long long *P = bp + 2 * we + (size_t)b * rec;
+            e += P[2 * we];
+            n3 |= (int)P[2 * we + 1];
+            xm = max(xm, (int)P[2 * we + 2]);
+        }
+        s_etot = e;
+        s_need3 = n3;
+        s_xmax = xm;
     }
+    __syncthreads();
+    const size_t plane = (size_t)mg * npad;
+    int8_t *L0 = GRID ? nullptr : limbs + (size_t)frame * 3 * plane;
+    prep_tables<DS, GRID>(raw + (size_t)frame * m * n, m, n, mg, ng, w, npad, dbits, frame, cL, cR,
+                          rT, rB, s_etot, s_need3, s_xmax, edge + (size_t)frame * 4 * we * w, L0,
+                          nlimb, vmax, atab, atab_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -941,28 +1037,38 @@ size_t int8_template_bytes(const Geom &g, int nq)
     return (size_t)g.mg * nq * kPhases * int8_geom(g).trow + kInt8ZeroTail;
 }
 
-template <bool DS, int NW, bool GRID>
-void prep_launch_nw(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int nc,
-                    size_t lds, int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
-                    long long *edge, double *grid, double *atab_d, const int32_t *only,
-                    hipStream_t st, int xc)
+// Bands per frame for a launch of C frames: one block per frame once the
+// frames alone fill the device; fewer frames are split over bands of rows
+// (at least one row per wave) so that about 512 blocks stream them.
+int prep_bands(int C, int mg)
 {
-    if (nc <= 1)
-        k_prep_u16<DS, 1, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only, xc);
-    else if (nc <= 2)
-        k_prep_u16<DS, 2, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only, xc);
-    else if (nc <= 4)
-        k_prep_u16<DS, 4, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only, xc);
-    else
-        k_prep_u16<DS, 8, NW, GRID><<<C, NW * 64, lds, st>>>(frames, g.m, g.n, g.mg, g.ng, g.w,
-                                                             npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                                             grid, atab_d, only, xc);
+    if (C >= 256) return 1;
+    const int want = (512 + C - 1) / C;
+    return std::max(1, std::min(std::min(want, kPrepMaxBands), mg / kWaves));
+}
+
+template <bool DS, int kMaxCol4, bool GRID>
+void prep_launch_c(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, size_t lds,
+                   int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge,
+                   double *grid, double *atab_d, const int32_t *only, hipStream_t st, int xc)
+{
+    const int nb = prep_bands(C, g.mg);
+    if (nb <= 1) {
+        k_prep_u16<DS, kMaxCol4, kWaves, GRID, false><<<C, kWaves * 64, lds, st>>>(
+            frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, limbs, nlimb, vmax, atab, edge, grid,
+            atab_d, only, xc, 0, nullptr);
+        return;
+    }
+    const int rows = (g.mg + nb - 1) / nb;
+    const int nbu = (g.mg + rows - 1) / rows;   // bands that hold rows (<= nb)
+    // the bands' sums follow the C frames' border prefix tables
+    long long *bandp = edge + (size_t)C * 4 * (g.w - 1) * g.w;
+    k_prep_u16<DS, kMaxCol4, kWaves, GRID, true><<<dim3(nbu, C), kWaves * 64, lds, st>>>(
+        frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, limbs, nlimb, vmax, atab, edge, grid,
+        atab_d, only, xc, rows, bandp);
+    k_prep_finish<DS, GRID><<<C, 256, 4 * (size_t)g.w * sizeof(long long), st>>>(
+        frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, nbu, limbs, nlimb, vmax, atab, edge, atab_d,
+        only, bandp);
 }
 
 size_t prep_lds(const Geom &g, int npad, int nw)
@@ -978,14 +1084,19 @@ void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbi
 {
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
-    // a few frames: sixteen waves per frame (one block of four waves streams a
-    // frame at a fraction of the device's bandwidth)
-    if (C <= 128 && prep_lds(g, npad, 16) <= 64 * 1024)
-        prep_launch_nw<DS, 16, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, 16), limbs, nlimb,
-                                     vmax, atab, edge, grid, atab_d, only, st, xc);
+    const size_t lds = prep_lds(g, npad, kWaves);
+    if (nc <= 1)
+        prep_launch_c<DS, 1, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
+                                   grid, atab_d, only, st, xc);
+    else if (nc <= 2)
+        prep_launch_c<DS, 2, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
+                                   grid, atab_d, only, st, xc);
+    else if (nc <= 4)
+        prep_launch_c<DS, 4, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
+                                   grid, atab_d, only, st, xc);
     else
-        prep_launch_nw<DS, kWaves, GRID>(frames, C, g, npad, dbits, nc, prep_lds(g, npad, kWaves), limbs,
-                                         nlimb, vmax, atab, edge, grid, atab_d, only, st, xc);
+        prep_launch_c<DS, 8, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
+                                   grid, atab_d, only, st, xc);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
@@ -1013,7 +1124,6 @@ bool prep_grid_applicable(const Geom &g)
     return prep_lds(g, npad, kWaves) <= 64 * 1024;
 }
 
-size_t prep_grid_edge_bytes(const Geom &g) { return (size_t)4 * (g.w - 1) * g.w * sizeof(long long); }
 
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
                             double *atab, int32_t *vmax, long long *edge, hipStream_t st,

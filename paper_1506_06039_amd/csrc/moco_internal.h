@@ -192,18 +192,32 @@ constexpr size_t kInt8ZeroTail = 1024;
 // vmax[frame]: an upper bound of the frame's pixel values (its largest grid
 // value), or INT32_MAX when the grid does not cover every pixel (odd sides when
 // downsampling)
+// edge: prep_edge_bytes(g) scratch per frame.
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
                            int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
                            long long *edge, hipStream_t st);
+// A few frames are split over at most kPrepMaxBands bands of rows each (one
+// block per band); the bands' partial sums take prep_band_longs(w) int64 per
+// frame, after the C frames' edge prefix tables.
+constexpr int kPrepMaxBands = 32;
+__host__ __device__ inline size_t prep_band_longs(int w)
+{
+    return 2 * (size_t)(w - 1) + (size_t)kPrepMaxBands * (2 * (size_t)(w - 1) + 3);
+}
+// Per-frame scratch of the prep pass: the border prefix tables
+// [2][2][w-1][w] int64 and the bands' partial sums.
+inline size_t prep_edge_bytes(const Geom &g)
+{
+    return ((size_t)4 * (g.w - 1) * g.w + prep_band_longs(g.w)) * sizeof(long long);
+}
 hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, hipStream_t st);
 // The FP64 forms' grid and energies for uint16 frames with at most one 2x2
 // level, in one pass over the raw frames (the prep kernel without digit
 // planes): grid [frame][mg][ng] FP64 (may be null: energies only), atab
 // [frame][W][W] FP64 in grid units, vmax as launch_prep_u16; edge:
-// prep_grid_edge_bytes scratch per frame; only (may be null): frames whose
+// prep_edge_bytes scratch per frame; only (may be null): frames whose
 // only[f] is 0 are skipped.
 bool prep_grid_applicable(const Geom &g);
-size_t prep_grid_edge_bytes(const Geom &g);
 // xc: the energies are of X - xc (X the integer grid values: box sums or
 // counts), for the single-precision FFT form's centred grids; 0 otherwise.
 hipError_t launch_prep_grid(const uint16_t *frames, int C, const Geom &g, double *grid,
