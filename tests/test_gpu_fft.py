@@ -103,6 +103,11 @@ FFT_SHAPES = [
     (60, 220, 46, False, "f32", 2),   # 108 x 270 (2*3^3*5)
     (40, 1030, 6, True, "u16", 2),    # grid 20x515: 25 x 540
     (276, 200, 85, False, "f32", 2),  # 360 x 288 (radices 3,3,5,8 and 3,3,4,8)
+    (512, 796, 48, True, "u16", 2),   # grid 256x398: 320 x 450 (2,3,3,5,5)
+    (512, 796, 32, True, "f32", 2),   # grid 256x398: 288 x 432 (2,3,3,3,8)
+    (350, 350, 30, False, "u16", 2),  # 384 x 384 (2,3,8,8)
+    (380, 140, 16, False, "f32", 2),  # 400 x 160 (5,5,2,8)
+    (460, 100, 16, False, "u16", 2),  # 480 x 120 (3,4,5,8)
 ]
 
 

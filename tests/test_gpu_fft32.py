@@ -116,6 +116,9 @@ FFT32_SHAPES = [
     (130, 262, 40, 0, "u16", 2),    # 262 columns: one partial prep strip, no downsampling
     (300, 17, 8, 1, "f32", 3),      # tall and narrow
     (9, 9, 1, 0, "u16", 3),         # w = 1
+    (512, 796, 48, 1, "u16", 2),    # 320 x 450
+    (350, 350, 30, 0, "f32", 2),    # 384 x 384
+    (460, 100, 16, 0, "f32", 2),    # 480 x 120
 ]
 
 

@@ -523,6 +523,66 @@ def test_server_add_source_while_another_thread_submits(gpu_lib):
         assert list(r.shift) == one["shifts"][0].tolist() and r.fmin == one["fmin"][0]
 
 
+@pytest.mark.parametrize("form", ["int8", "fft", "fft32", "fft_cert"])
+def test_prep_bands_equal_one_block_per_frame(gpu_lib, form):
+    # a launch of fewer than 256 frames splits each frame's prep over bands of
+    # rows (partial sums finished per frame); 260 frames take one block per
+    # frame: the first 40 frames' results are identical either way
+    sc = synth.PoissonScene(512, 512, 261, seed=91)
+    frames = sc.frames(1, 261)
+    _say("case prep bands vs one block per frame, form %s" % form)
+    many = _run(gpu_lib, frames, sc.template, 32, True, form=form)
+    few = _run(gpu_lib, frames[:40], sc.template, 32, True, form=form)
+    for k in ("shifts", "coarse", "fmin", "frefine", "gaps"):
+        assert np.array_equal(many[k][:40], few[k], equal_nan=True), k
+
+
+def test_server_submitters_on_several_threads(gpu_lib):
+    # four threads submit frames of their own sources at once (a submit that
+    # finds a lane free launches the batch itself, one launch at a time); the
+    # main thread collects the results; every one equals moco_align on that
+    # frame alone
+    import threading
+    import time
+    ctx = gpu_lib.Context(0)
+    srv = gpu_lib.Server(ctx, max_slots=8)
+    scenes = {k: synth.PoissonScene(256, 256, 21, seed=80 + k) for k in range(4)}
+    for k, sc in scenes.items():
+        srv.add_source(k, sc.template, 16, k % 2 == 1)
+    frames = {k: sc.frames(1, 21) for k, sc in scenes.items()}
+    errors = []
+
+    def submitter(k):
+        try:
+            for j in range(20):
+                while not srv.submit(k, frames[k][j], k * 100 + j):
+                    time.sleep(0.0002)
+        except Exception as e:   # surfaced by the main thread
+            errors.append(e)
+
+    _say("case server submits from four threads")
+    ths = [threading.Thread(target=submitter, args=(k,)) for k in range(4)]
+    for t in ths:
+        t.start()
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < 80 and time.time() < deadline:
+        for r in srv.poll(64, timeout_us=1000):
+            out[r.tag] = r
+    for t in ths:
+        t.join(timeout=60)
+    assert not errors, errors
+    assert len(out) == 80
+    assert srv.close() == 0
+    for k, sc in scenes.items():
+        alone = _run(gpu_lib, frames[k], sc.template, 16, k % 2 == 1)
+        for j in range(20):
+            r = out[k * 100 + j]
+            assert r.status == 0 and r.source == k
+            assert list(r.shift) == alone["shifts"][j].tolist(), (k, j)
+            assert r.fmin == alone["fmin"][j], (k, j)
+
+
 def test_server_rejects_bad_use_and_cancels_on_destroy(gpu_lib):
     ctx = gpu_lib.Context(0)
     srv = gpu_lib.Server(ctx, max_slots=3)
