@@ -601,14 +601,16 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
         int c = std::min(C, T - f0);
         const uint16_t *fr = (const uint16_t *)((const char *)d_frames + (size_t)f0 * fbytes);
         int32_t *coarse = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
+        // a correlation over row slices adds into a table the prep launch clears
+        const bool zero_h = moco::int8_corr_adds_slices(c, g, tile);
         {
             StageTimer tm(ctx, MOCO_STAGE_PREP, st);
             HIP_TRY(moco::launch_prep_u16(fr, c, g, npad, tt.i8.dbits, limbs, nl, vm, atab, edge,
-                                          st));
+                                          st, zero_h ? (int32_t *)h : nullptr));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            HIP_TRY(moco::launch_corr_int8(limbs, nl, tt.i8, c, g, h, st, nullptr, tile));
+            HIP_TRY(moco::launch_corr_int8(limbs, nl, tt.i8, c, g, h, st, nullptr, tile, zero_h));
         }
         {
             StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
@@ -713,8 +715,11 @@ int run_int8_multi(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tref, 
     const uint16_t *fr = (const uint16_t *)d_frames;
     int32_t *coarse = out->coarse ? out->coarse : cst;
     const moco::Int8Multi mm{nblocks, dt.btp, dt.bf0, dt.bfe};
-    HIP_TRY(moco::launch_prep_u16(fr, F, g, npad, tref.i8.dbits, limbs, nl, vm, atab, edge, st));
-    HIP_TRY(moco::launch_corr_int8(limbs, nl, tref.i8, F, g, h, st, &mm, int8_tile(tref)));
+    const int tile = int8_tile(tref);
+    const bool zero_h = moco::int8_corr_adds_slices(F, g, tile, mm.nblocks);
+    HIP_TRY(moco::launch_prep_u16(fr, F, g, npad, tref.i8.dbits, limbs, nl, vm, atab, edge, st,
+                                  zero_h ? (int32_t *)h : nullptr));
+    HIP_TRY(moco::launch_corr_int8(limbs, nl, tref.i8, F, g, h, st, &mm, tile, zero_h));
     HIP_TRY(moco::launch_combine_i64(atab, nullptr, h, F, g, nullptr, out->fmin, coarse,
                                      out->shifts, out->gaps, out->frefine, st, dt.btabs));
     if (g.ds)

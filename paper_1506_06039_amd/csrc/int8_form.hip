@@ -227,7 +227,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                                                      double *__restrict__ atab_d,
                                                      const int32_t *__restrict__ only,
                                                      int xc, int band_rows,
-                                                     long long *__restrict__ bandp)
+                                                     long long *__restrict__ bandp,
+                                                     int32_t *__restrict__ hz)
 {
     const int frame = BAND ? blockIdx.y : blockIdx.x;
     // GRID with `only`: frames whose only[f] is 0 are skipped (the whole block)
@@ -380,12 +381,19 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
         cL[s] = colE[s];
         cR[s] = colE[ng - 1 - s];
     }
+    if (hz) {
+        const int W = 2 * w - 1;
+        int32_t *hf = hz + (size_t)frame * 2 * W * W;
+        for (int k = threadIdx.x; k < 2 * W * W; k += blockDim.x) hf[k] = 0;
+    }
     __syncthreads();
     prep_tables<DS, GRID>(a, m, n, mg, ng, w, npad, dbits, frame, cL, cR, rT, rB, etot, need3,
                           xmax, E, L0, nlimb, vmax, atab, atab_d);
 }
 
-// The energy table of each frame from its bands' sums (one block per frame).
+// The energy table of each frame from its bands' sums (one block per frame);
+// with hz, the frame's 2 W^2 int32 correlation table is zeroed too (for a
+// correlation launch that adds row slices into it).
 template <bool DS, bool GRID>
 __global__ __launch_bounds__(256) void k_prep_finish(const uint16_t *__restrict__ raw, int m, int n,
                                                      int mg, int ng, int w, int npad, int dbits,
@@ -396,42 +404,52 @@ __global__ __launch_bounds__(256) void k_prep_finish(const uint16_t *__restrict_
                                                      const long long *__restrict__ edge,
                                                      double *__restrict__ atab_d,
                                                      const int32_t *__restrict__ only,
-                                                     const long long *__restrict__ bandp)
+                                                     const long long *__restrict__ bandp,
+                                                     int32_t *__restrict__ hz)
 {
     const int frame = blockIdx.x;
     if (GRID && only && !only[frame]) return;
-    extern __shared__ long long lds_fin[];   // cL[w] | cR[w] | rT[w] | rB[w]
-    long long *cL = lds_fin, *cR = cL + w, *rT = cR + w, *rB = rT + w;
-    __shared__ long long s_etot;
+    // dynamic LDS: cL[w] | cR[w] | rT[w] | rB[w] | acc[2(w-1) + 1]
+    extern __shared__ long long lds_fin[];
+    long long *cL = lds_fin, *cR = cL + w, *rT = cR + w, *rB = rT + w, *acc = rB + w;
     __shared__ int s_need3, s_xmax;
-    const int we = w - 1;
+    const int we = w - 1, W = 2 * w - 1;
     const long long *bp = bandp + (size_t)frame * prep_band_longs(w);
     const int rec = 2 * we + 3;
-    for (int s = threadIdx.x; s < 2 * we; s += blockDim.x) {
-        long long acc = 0;
-        for (int b = 0; b < nbands; ++b) acc += bp[2 * we + (size_t)b * rec + s];
-        (s < we ? cL[s] : cR[s - we]) = acc;
-        (s < we ? rT[s] : rB[s - we]) = bp[s];
-    }
+    for (int s = threadIdx.x; s <= 2 * we; s += blockDim.x) acc[s] = 0;
     if (threadIdx.x == 0) {
-        long long e = 0;
-        int n3 = 0, xm = 0;
-        for (int b = 0; b < nbands; ++b) {
-            const long long *P = bp + 2 * we + (size_t)b * rec;
-            e += P[2 * we];
-            n3 |= (int)P[2 * we + 1];
-            xm = max(xm, (int)P[2 * we + 2]);
+        s_need3 = 0;
+        s_xmax = 0;
+    }
+    if (hz) {
+        int32_t *hf = hz + (size_t)frame * 2 * W * W;
+        for (int k = threadIdx.x; k < 2 * W * W; k += blockDim.x) hf[k] = 0;
+    }
+    __syncthreads();
+    // every band record at once: column sums and the total added, flags merged
+    for (int idx = threadIdx.x; idx < nbands * rec; idx += blockDim.x) {
+        const int b = idx / rec, s = idx - b * rec;
+        const long long v = bp[2 * we + idx];
+        if (s <= 2 * we)
+            atomicAdd((unsigned long long *)&acc[s], (unsigned long long)v);
+        else if (s == 2 * we + 1) {
+            if (v) atomicOr(&s_need3, 1);
+        } else {
+            atomicMax(&s_xmax, (int)v);
         }
-        s_etot = e;
-        s_need3 = n3;
-        s_xmax = xm;
+    }
+    for (int s = threadIdx.x; s < 2 * we; s += blockDim.x) (s < we ? rT[s] : rB[s - we]) = bp[s];
+    __syncthreads();
+    for (int s = threadIdx.x; s < we; s += blockDim.x) {
+        cL[s] = acc[s];
+        cR[s] = acc[we + s];
     }
     __syncthreads();
     const size_t plane = (size_t)mg * npad;
     int8_t *L0 = GRID ? nullptr : limbs + (size_t)frame * 3 * plane;
     prep_tables<DS, GRID>(raw + (size_t)frame * m * n, m, n, mg, ng, w, npad, dbits, frame, cL, cR,
-                          rT, rB, s_etot, s_need3, s_xmax, edge + (size_t)frame * 4 * we * w, L0,
-                          nlimb, vmax, atab, atab_d);
+                          rT, rB, acc[2 * we], s_need3, s_xmax, edge + (size_t)frame * 4 * we * w,
+                          L0, nlimb, vmax, atab, atab_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,13 +1068,14 @@ int prep_bands(int C, int mg)
 template <bool DS, int kMaxCol4, bool GRID>
 void prep_launch_c(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, size_t lds,
                    int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge,
-                   double *grid, double *atab_d, const int32_t *only, hipStream_t st, int xc)
+                   double *grid, double *atab_d, const int32_t *only, hipStream_t st, int xc,
+                   int32_t *hz)
 {
     const int nb = prep_bands(C, g.mg);
     if (nb <= 1) {
         k_prep_u16<DS, kMaxCol4, kWaves, GRID, false><<<C, kWaves * 64, lds, st>>>(
             frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, limbs, nlimb, vmax, atab, edge, grid,
-            atab_d, only, xc, 0, nullptr);
+            atab_d, only, xc, 0, nullptr, hz);
         return;
     }
     const int rows = (g.mg + nb - 1) / nb;
@@ -1065,10 +1084,10 @@ void prep_launch_c(const uint16_t *frames, int C, const Geom &g, int npad, int d
     long long *bandp = edge + (size_t)C * 4 * (g.w - 1) * g.w;
     k_prep_u16<DS, kMaxCol4, kWaves, GRID, true><<<dim3(nbu, C), kWaves * 64, lds, st>>>(
         frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, limbs, nlimb, vmax, atab, edge, grid,
-        atab_d, only, xc, rows, bandp);
-    k_prep_finish<DS, GRID><<<C, 256, 4 * (size_t)g.w * sizeof(long long), st>>>(
+        atab_d, only, xc, rows, bandp, nullptr);
+    k_prep_finish<DS, GRID><<<C, 256, (6 * (size_t)g.w - 1) * sizeof(long long), st>>>(
         frames, g.m, g.n, g.mg, g.ng, g.w, npad, dbits, nbu, limbs, nlimb, vmax, atab, edge, atab_d,
-        only, bandp);
+        only, bandp, hz);
 }
 
 size_t prep_lds(const Geom &g, int npad, int nw)
@@ -1080,38 +1099,39 @@ size_t prep_lds(const Geom &g, int npad, int nw)
 template <bool DS, bool GRID>
 void prep_launch(const uint16_t *frames, int C, const Geom &g, int npad, int dbits, int8_t *limbs,
                  int32_t *nlimb, int32_t *vmax, long long *atab, long long *edge, double *grid,
-                 double *atab_d, const int32_t *only, hipStream_t st, int xc = 0)
+                 double *atab_d, const int32_t *only, hipStream_t st, int xc = 0,
+                 int32_t *hz = nullptr)
 {
     // 256 grid columns per chunk (64 lanes x 4 columns)
     const int nc = (npad + 255) / 256;
     const size_t lds = prep_lds(g, npad, kWaves);
     if (nc <= 1)
         prep_launch_c<DS, 1, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
-                                   grid, atab_d, only, st, xc);
+                                   grid, atab_d, only, st, xc, hz);
     else if (nc <= 2)
         prep_launch_c<DS, 2, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
-                                   grid, atab_d, only, st, xc);
+                                   grid, atab_d, only, st, xc, hz);
     else if (nc <= 4)
         prep_launch_c<DS, 4, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
-                                   grid, atab_d, only, st, xc);
+                                   grid, atab_d, only, st, xc, hz);
     else
         prep_launch_c<DS, 8, GRID>(frames, C, g, npad, dbits, lds, limbs, nlimb, vmax, atab, edge,
-                                   grid, atab_d, only, st, xc);
+                                   grid, atab_d, only, st, xc, hz);
 }
 
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
                            int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
-                           long long *edge, hipStream_t st)
+                           long long *edge, hipStream_t st, int32_t *hz)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
     if (dbits != 7 && dbits != 8) return hipErrorInvalidValue;
     if (g.ds)
         prep_launch<true, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                 nullptr, nullptr, nullptr, st);
+                                 nullptr, nullptr, nullptr, st, 0, hz);
     else
         prep_launch<false, false>(frames, C, g, npad, dbits, limbs, nlimb, vmax, atab, edge,
-                                  nullptr, nullptr, nullptr, st);
+                                  nullptr, nullptr, nullptr, st, 0, hz);
     return hipGetLastError();
 }
 
@@ -1150,9 +1170,15 @@ hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, 
     return hipGetLastError();
 }
 
+bool int8_corr_adds_slices(int C, const Geom &g, int tile, int nblocks)
+{
+    const bool small = tile == 32 || (tile == 0 && g.W <= 32);
+    return (small ? corr_slices(C, g, 1, 1, nblocks) : corr_slices(C, g, 2, 2, nblocks)) > 1;
+}
+
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st, const Int8Multi *mm,
-                            int tile)
+                            int tile, bool h_zeroed)
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
@@ -1163,7 +1189,7 @@ hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int
     const bool small = tile == 32 || (tile == 0 && g.W <= 32);
     const int nb = mm ? mm->nblocks : -1;
     const int nslice = small ? corr_slices(C, g, 1, 1, nb) : corr_slices(C, g, 2, 2, nb);
-    if (nslice > 1) {
+    if (nslice > 1 && !h_zeroed) {
         // the slices add into a zeroed table
         if ((e = launch_fill_i32((int32_t *)h, 2 * C * g.W * g.W, 0, st)) != hipSuccess) return e;
     }

@@ -192,10 +192,12 @@ constexpr size_t kInt8ZeroTail = 1024;
 // vmax[frame]: an upper bound of the frame's pixel values (its largest grid
 // value), or INT32_MAX when the grid does not cover every pixel (odd sides when
 // downsampling)
-// edge: prep_edge_bytes(g) scratch per frame.
+// edge: prep_edge_bytes(g) scratch per frame.  hz (nullable): the C frames'
+// correlation tables ([frame][2 W^2] int32), zeroed by the same launch for a
+// correlation that adds row slices (int8_corr_adds_slices).
 hipError_t launch_prep_u16(const uint16_t *frames, int C, const Geom &g, int npad, int dbits,
                            int8_t *limbs, int32_t *nlimb, int32_t *vmax, long long *atab,
-                           long long *edge, hipStream_t st);
+                           long long *edge, hipStream_t st, int32_t *hz = nullptr);
 // A few frames are split over at most kPrepMaxBands bands of rows each (one
 // block per band); the bands' partial sums take prep_band_longs(w) int64 per
 // frame, after the C frames' edge prefix tables.
@@ -235,9 +237,14 @@ struct Int8Multi {
 // (npad, trow, padl, digit base), which every template of the launch shares.
 // tile: shift tiles per block, 32 (one 32x32 tile, ceil(W/32)^2 block groups)
 // or 64 (2x2 tiles of 32, ceil(W/64)^2 groups); 0: 32 when W <= 32, else 64.
+// h_zeroed: the table h is already zero (the prep launch cleared it), so a
+// launch that adds row slices into it does not clear it first.
 hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, long long *h, hipStream_t st,
-                            const Int8Multi *mm = nullptr, int tile = 0);
+                            const Int8Multi *mm = nullptr, int tile = 0, bool h_zeroed = false);
+// Whether that launch (C frames, tile, nblocks = mm->nblocks or -1) splits the
+// template rows over blocks that add into a zeroed table.
+bool int8_corr_adds_slices(int C, const Geom &g, int tile, int nblocks = -1);
 // btabs (nullable, device array): each frame's own template table
 hipError_t launch_combine_i64(const long long *atab, const long long *btab_t, const long long *h,
                               int C, const Geom &g, double *fsurf, double *fmin,
