@@ -2389,14 +2389,11 @@ int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64
     }
     srv->pending.push_back(q);
     srv->inflight += 1;
-    // a free lane and no launch in progress: start the batch from here, so
-    // that it does not wait for the worker thread to wake up
-    if (!srv->launching)
-        for (auto &L : srv->lane)
-            if (!L.active) {
-                server_launch(srv, L, lk);
-                break;
-            }
+    // an idle server (no batch in flight, so the worker may be asleep): start
+    // the batch from here, so that it does not wait for the worker to wake
+    // up; while batches run, the worker is awake and gathers what waits into
+    // the next one
+    if (!srv->launching && !server_any_active(srv)) server_launch(srv, srv->lane[0], lk);
     srv->cv_work.notify_one();
     srv->cv_done.notify_all();
     return MOCO_OK;
