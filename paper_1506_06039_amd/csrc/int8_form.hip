@@ -90,20 +90,34 @@ __device__ inline int grid_value(const uint16_t *a, int n, int i, int j)
 }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-// Four consecutive grid values j0..j0+3 of grid row i (zero beyond ng).  With
-// `vec`, the raw rows are read as 16-byte (box sums) or 8-byte vectors.
+// Four consecutive grid values j0..j0+3 of grid row i (zero beyond ng).  vec:
+// 0 scalar reads; 1 the raw rows read as 8-byte vectors (rows 8-byte
+// aligned: n a multiple of 4); 2 (box sums only) as 16-byte vectors (n a
+// multiple of 8).
 template <bool DS>
-__device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int j0, bool vec,
+__device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int j0, int vec,
                                     int (&X)[4])
 {
     if (vec && j0 + 3 < ng) {
         if (DS) {
             // streamed once: non-temporal loads keep the frames out of the caches
-            const u32x4 r0 = __builtin_nontemporal_load((const u32x4 *)(a + (size_t)(2 * i) * n + 2 * j0));
-            const u32x4 r1 =
-                __builtin_nontemporal_load((const u32x4 *)(a + (size_t)(2 * i + 1) * n + 2 * j0));
-            const unsigned u0[4] = {r0.x, r0.y, r0.z, r0.w}, u1[4] = {r1.x, r1.y, r1.z, r1.w};
+            const uint16_t *p0 = a + (size_t)(2 * i) * n + 2 * j0, *p1 = p0 + n;
+            unsigned u0[4], u1[4];
+            if (vec == 2) {
+                const u32x4 r0 = __builtin_nontemporal_load((const u32x4 *)p0);
+                const u32x4 r1 = __builtin_nontemporal_load((const u32x4 *)p1);
+                u0[0] = r0.x, u0[1] = r0.y, u0[2] = r0.z, u0[3] = r0.w;
+                u1[0] = r1.x, u1[1] = r1.y, u1[2] = r1.z, u1[3] = r1.w;
+            } else {
+                const u32x2 r0a = __builtin_nontemporal_load((const u32x2 *)p0);
+                const u32x2 r0b = __builtin_nontemporal_load((const u32x2 *)p0 + 1);
+                const u32x2 r1a = __builtin_nontemporal_load((const u32x2 *)p1);
+                const u32x2 r1b = __builtin_nontemporal_load((const u32x2 *)p1 + 1);
+                u0[0] = r0a.x, u0[1] = r0a.y, u0[2] = r0b.x, u0[3] = r0b.y;
+                u1[0] = r1a.x, u1[1] = r1a.y, u1[2] = r1b.x, u1[3] = r1b.y;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 X[q] = (int)(u0[q] & 0xffff) + (int)(u0[q] >> 16) + (int)(u1[q] & 0xffff) +
@@ -250,8 +264,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const uint16_t *a = raw + (size_t)frame * m * n;
     // vector raw reads need aligned rows: 16 bytes (box sums) or 8 bytes
-    const bool vec = DS ? ((n % 8) == 0 && (((uintptr_t)a) & 15) == 0)
-                        : ((n % 4) == 0 && (((uintptr_t)a) & 7) == 0);
+    const bool al8 = (n % 4) == 0 && (((uintptr_t)a) & 7) == 0;
+    const int vec = DS && al8 && (n % 8) == 0 && (((uintptr_t)a) & 15) == 0 ? 2 : (al8 ? 1 : 0);
     const size_t plane = (size_t)mg * npad;
     int8_t *L0 = limbs + (size_t)frame * 3 * plane;
     int8_t *L1 = L0 + plane;

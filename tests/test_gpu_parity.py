@@ -78,6 +78,7 @@ RAGGED = [
     (2, 2, 1, True, "f32", 3),        # smallest downsampled image
     (48, 1100, 8, True, "u16", 3),    # wide rows: interior waves of the refine need no masks
     (40, 1030, 6, True, "u16", 3),    # n % 4 == 2: a template column group half past the edge
+    (512, 796, 8, True, "u16", 2),    # n % 8 == 4: box sums from 8-byte row reads
 ]
 
 
