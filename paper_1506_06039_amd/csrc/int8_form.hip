@@ -157,7 +157,10 @@ __device__ inline void grid_values4(const uint16_t *a, int n, int ng, int i, int
 // entry cL[s], cR[s], rT[s], rB[s] (s < w-1) hold the energies of column s,
 // column ng-1-s, row s and row mg-1-s; they are turned into prefix sums over
 // s = 0..w-1 here.  Every thread of the block (256) calls it.
-template <bool DS, bool GRID>
+//
+// KU: corner-sum loads each thread issues before using them (a larger KU
+// takes more registers and fewer round trips to memory).
+template <bool DS, bool GRID, int KU>
 __device__ inline void prep_tables(const uint16_t *a, int m, int n, int mg, int ng, int w,
                                    int npad, int dbits, int frame, long long *cL, long long *cR,
                                    long long *rT, long long *rB, long long Etot, int need3,
@@ -194,10 +197,19 @@ __device__ inline void prep_tables(const uint16_t *a, int m, int n, int mg, int 
         if (side == 0) put((size_t)we * W + tt, base);
         const long long *rx = side ? rB : rT;   // rows excluded at the top (+s) or bottom (-s)
         long long c = 0;
-#pragma unroll 8
-        for (int s = 1; s < w; ++s) {
-            if (t != 0) c += E[eidx(side, lr, s - 1, at)];
-            put((size_t)(side ? we - s : we + s) * W + tt, base - rx[s] + c);
+        for (int s0 = 1; s0 < w; s0 += KU) {
+            long long ev[KU];
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+                ev[u] = (t != 0 && s0 + u < w) ? E[eidx(side, lr, s0 + u - 1, at)] : 0;
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int s = s0 + u;
+                if (s < w) {
+                    c += ev[u];
+                    put((size_t)(side ? we - s : we + s) * W + tt, base - rx[s] + c);
+                }
+            }
         }
     }
     // third digit plane, only for frames that need it
@@ -401,8 +413,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
         for (int k = threadIdx.x; k < 2 * W * W; k += blockDim.x) hf[k] = 0;
     }
     __syncthreads();
-    prep_tables<DS, GRID>(a, m, n, mg, ng, w, npad, dbits, frame, cL, cR, rT, rB, etot, need3,
-                          xmax, E, L0, nlimb, vmax, atab, atab_d);
+    prep_tables<DS, GRID, 8>(a, m, n, mg, ng, w, npad, dbits, frame, cL, cR, rT, rB, etot, need3,
+                             xmax, E, L0, nlimb, vmax, atab, atab_d);
 }
 
 // The energy table of each frame from its bands' sums (one block per frame);
@@ -440,16 +452,29 @@ __global__ __launch_bounds__(256) void k_prep_finish(const uint16_t *__restrict_
         for (int k = threadIdx.x; k < 2 * W * W; k += blockDim.x) hf[k] = 0;
     }
     __syncthreads();
-    // every band record at once: column sums and the total added, flags merged
-    for (int idx = threadIdx.x; idx < nbands * rec; idx += blockDim.x) {
-        const int b = idx / rec, s = idx - b * rec;
-        const long long v = bp[2 * we + idx];
-        if (s <= 2 * we)
-            atomicAdd((unsigned long long *)&acc[s], (unsigned long long)v);
-        else if (s == 2 * we + 1) {
-            if (v) atomicOr(&s_need3, 1);
-        } else {
-            atomicMax(&s_xmax, (int)v);
+    // every band record at once: column sums and the total added, flags
+    // merged; each thread's loads are all issued before their first use
+    constexpr int PER = 16;
+    const int total = nbands * rec;
+    for (int i0 = 0; i0 < total; i0 += PER * (int)blockDim.x) {
+        long long v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+            v[u] = idx < total ? bp[2 * we + idx] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+            if (idx >= total) continue;
+            const int s = idx % rec;
+            if (s <= 2 * we)
+                atomicAdd((unsigned long long *)&acc[s], (unsigned long long)v[u]);
+            else if (s == 2 * we + 1) {
+                if (v[u]) atomicOr(&s_need3, 1);
+            } else {
+                atomicMax(&s_xmax, (int)v[u]);
+            }
         }
     }
     for (int s = threadIdx.x; s < 2 * we; s += blockDim.x) (s < we ? rT[s] : rB[s - we]) = bp[s];
@@ -461,9 +486,9 @@ __global__ __launch_bounds__(256) void k_prep_finish(const uint16_t *__restrict_
     __syncthreads();
     const size_t plane = (size_t)mg * npad;
     int8_t *L0 = GRID ? nullptr : limbs + (size_t)frame * 3 * plane;
-    prep_tables<DS, GRID>(raw + (size_t)frame * m * n, m, n, mg, ng, w, npad, dbits, frame, cL, cR,
-                          rT, rB, acc[2 * we], s_need3, s_xmax, edge + (size_t)frame * 4 * we * w,
-                          L0, nlimb, vmax, atab, atab_d);
+    prep_tables<DS, GRID, 16>(raw + (size_t)frame * m * n, m, n, mg, ng, w, npad, dbits, frame, cL,
+                              cR, rT, rB, acc[2 * we], s_need3, s_xmax,
+                              edge + (size_t)frame * 4 * we * w, L0, nlimb, vmax, atab, atab_d);
 }
 
 // ---------------------------------------------------------------------------
