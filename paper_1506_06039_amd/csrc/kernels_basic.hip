@@ -370,14 +370,29 @@ __global__ __launch_bounds__(kBlock) void k_energy(const void *__restrict__ src,
 constexpr int kErWaves = 4;
 constexpr int kErMaxChunks = 8;   // 8 x 256 grid columns
 
-// inclusive prefix sum over the 64 lanes of a wave (fixed order)
-__device__ inline double wave_incl_scan(double v, int lane)
+// v of another lane by a data-parallel-primitives move of both 32-bit halves;
+// lanes without a source (outside the row, or of a masked row) get 0
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double u = __shfl_up(v, off);
-        if (lane >= off) v += u;
-    }
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// inclusive prefix sum over the 64 lanes of a wave (fixed order): within each
+// row of 16 lanes by shifts of 1, 2, 4 and 8 lanes, then lane 15's sum added
+// to rows 1 and 3 and lane 31's to rows 2 and 3 (moves within the VALU, not
+// through the LDS crossbar)
+__device__ inline double wave_incl_scan(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31
     return v;
 }
 
@@ -519,8 +534,9 @@ __global__ __launch_bounds__(kErWaves * 64) void k_energy_rows(
         double v0 = o0 < E ? sq(i, lr ? ng - 1 - o0 : o0) : 0.0;
         double v1 = o1 < E ? sq(i, lr ? ng - 1 - o1 : o1) : 0.0;
         // prefix over offsets: corner(s, t) adds the sums over offsets < |t|
-        const double p0 = wave_incl_scan(v0, lane);
-        const double p1 = wave_incl_scan(v1, lane) + __shfl(p0, 63);
+        const double p0 = wave_incl_scan(v0);
+        // offsets past 63 exist only for w > 65 (the branch is uniform)
+        const double p1 = E > 64 ? wave_incl_scan(v1) + __shfl(p0, 63) : 0.0;
         acc0 += p0;   // corner sums for |t| = lane + 1
         acc1 += p1;   // and |t| = lane + 65
         const double base = Etot - rx[s];
