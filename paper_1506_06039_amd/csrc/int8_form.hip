@@ -350,9 +350,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
                 *(int *)(L1 + (size_t)i * npad + j0) = d1p;
             }
         }
-        long long r = wave_sum_i64(rpart);
-        my_etot += r;
+        my_etot += rpart;   // the lane's share, summed over the wave once at the end
         if (top || bot) {
+            // a border row's energy (the branch is uniform: a wave takes the row)
+            const long long r = wave_sum_i64(rpart);
             if (lane == 0) {
                 long long *tT = BAND ? bp : rT, *tB = BAND ? bp + we : rB;
                 if (top) tT[i] = r;
@@ -385,7 +386,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
         for (int q = 0; q < 4; ++q)
             if (j0 + q < ng) atomicAdd((unsigned long long *)&colE[j0 + q], (unsigned long long)col[c][q]);
     }
-    if (lane == 0) atomicAdd((unsigned long long *)&etot, (unsigned long long)my_etot);
+    {
+        const long long wt = wave_sum_i64(my_etot);
+        if (lane == 0) atomicAdd((unsigned long long *)&etot, (unsigned long long)wt);
+    }
     if (my_need3) need3 = 1;
     atomicMax(&xmax, my_xmax);
     __syncthreads();
