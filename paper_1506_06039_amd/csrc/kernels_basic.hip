@@ -745,6 +745,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(const double *__restrict__ a
 // f at the coarse argmin by its definition (eq. (f)): the FP64 sum of squared
 // differences of the searched grids over D, in a fixed order (exact for uint16
 // grids: multiples of 1/16 below 2^32 per term).  One block per frame.
+constexpr int kPolishRows = 8;   // rows whose loads a thread issues together
+
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src, int m, int n,
                                                    int mg, int ng, int w,
@@ -760,12 +762,24 @@ __global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src,
     const int s = coarse_st[2 * frame], t = coarse_st[2 * frame + 1];
     const void *a = grid_frame<SRC>(src, frame, m, n, mg, ng);
     const int i0 = max(0, -s), i1 = min(mg, mg - s), j0 = max(0, -t), j1 = min(ng, ng - t);
-    // thread k takes columns j0 + k, j0 + k + 256, ... of every row of D
+    // thread k takes columns j0 + k, j0 + k + 256, ... of every row of D,
+    // kPolishRows rows at a time with every load of a batch issued before
+    // the first is used (a fixed order of the terms)
     double acc = 0.0;
-    for (int i = i0; i < i1; ++i)
-        for (int j = j0 + threadIdx.x; j < j1; j += kBlock) {
-            const double d = grid_at<SRC>(a, n, ng, i + s, j + t) - tcoarse[(size_t)i * ng + j];
-            acc = fma(d, d, acc);
+    for (int j = j0 + threadIdx.x; j < j1; j += kBlock)
+        for (int i = i0; i < i1; i += kPolishRows) {
+            double fv[kPolishRows], tv[kPolishRows];
+#pragma unroll
+            for (int u = 0; u < kPolishRows; ++u) {
+                const bool in = i + u < i1;
+                fv[u] = in ? grid_at<SRC>(a, n, ng, i + u + s, j + t) : 0.0;
+                tv[u] = in ? tcoarse[(size_t)(i + u) * ng + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kPolishRows; ++u) {
+                const double d = fv[u] - tv[u];
+                acc = fma(d, d, acc);
+            }
         }
     __shared__ double red[kBlock];
     red[threadIdx.x] = acc;
