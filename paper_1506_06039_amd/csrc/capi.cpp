@@ -572,7 +572,7 @@ int prepare_fft_template(moco::Tmpl &t, hipStream_t st)
 
 // The int8 correlation's shift tile for a template's key: a tile recorded by
 // moco_tune (or moco_tune_set_tile), else the model's (int8_model_tile).
-int int8_tile(const moco::Tmpl &t);
+int int8_tile(const moco::Tmpl &t, int C);
 
 // The int8 pipeline over one stack, in chunks that fit `sbytes` of scratch at
 // `sbase`; every launch goes to stream st.
@@ -596,9 +596,9 @@ int run_int8(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     double *part = (double *)(base + (L.limbs + L.nlimb + L.atab + L.edge + L.h + L.cst) * C);
     const size_t fbytes = (size_t)g.m * g.n * sizeof(uint16_t);
     const int W = g.W;
-    const int tile = int8_tile(tt);
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
+        const int tile = int8_tile(tt, c);
         const uint16_t *fr = (const uint16_t *)((const char *)d_frames + (size_t)f0 * fbytes);
         int32_t *coarse = out->coarse ? out->coarse + 2 * (size_t)f0 : cst;
         // a correlation over row slices adds into a table the prep launch clears
@@ -715,7 +715,7 @@ int run_int8_multi(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tref, 
     const uint16_t *fr = (const uint16_t *)d_frames;
     int32_t *coarse = out->coarse ? out->coarse : cst;
     const moco::Int8Multi mm{nblocks, dt.btp, dt.bf0, dt.bfe};
-    const int tile = int8_tile(tref);
+    const int tile = int8_tile(tref, F);
     const bool zero_h = moco::int8_corr_adds_slices(F, g, tile, mm.nblocks);
     HIP_TRY(moco::launch_prep_u16(fr, F, g, npad, tref.i8.dbits, limbs, nl, vm, atab, edge, st,
                                   zero_h ? (int32_t *)h : nullptr));
@@ -1055,11 +1055,22 @@ double int8_tiles(const moco::Geom &g, int tile)
     return tile == 32 ? gs * gs : 4.0 * gs * gs;
 }
 
+// Launches of at most this many frames form the small size class of the
+// int8 tile choice (their correlation splits the template rows over blocks).
+constexpr int kInt8SmallBatch = 64;
+int tile_class(int C) { return C <= kInt8SmallBatch ? 0 : 1; }
+
 // One 32x32 tile when 2w-1 <= 32, else 2x2 groups: a group reads each frame
 // and template operand once for two tiles, and at 2w-1 = 79 on a 256x256 grid
-// the groups (16 tiles) ran faster than single tiles (9 tiles).  moco_tune
-// times both shapes.
-int int8_model_tile(const moco::Geom &g) { return g.W <= 32 ? 32 : 64; }
+// the groups (16 tiles) ran faster than single tiles (9 tiles).  A launch of
+// at most kInt8SmallBatch frames takes single tiles up to 2w-1 = 64: four
+// times the blocks fill more of the device (512x512 frames, w = 32:
+// correlation 21 against 35 us for one frame, 109 against 128 us for 64,
+// 176 against 165 us for 128).  moco_tune times both shapes.
+int int8_model_tile(const moco::Geom &g, int cls)
+{
+    return g.W <= 32 || (cls == 0 && g.W <= 64) ? 32 : 64;
+}
 
 // Per-frame time models of the two fast forms (seconds), from their kernels'
 // rates measured on MI355X at the 512x512, w = 32 workload: the int8 form
@@ -1074,7 +1085,8 @@ int int8_model_tile(const moco::Geom &g) { return g.W <= 32 ? 32 : 64; }
 double int8_model_s(const moco::Tmpl &t)
 {
     const moco::Geom &g = t.g;
-    const double macs = int8_tiles(g, int8_tile(t)) * 1024.0 * g.mg * (double)t.i8.npad;
+    const double macs =
+        int8_tiles(g, int8_tile(t, kInt8SmallBatch + 1)) * 1024.0 * g.mg * (double)t.i8.npad;
     const double ops = macs * 2.0 * (t.i8.nq == 3 ? 3.0 : 4.0);
     return 0.31e-6 * ((double)g.m * g.n / 262144.0) + ops / (t.i8.nq == 3 ? 2.7e15 : 2.8e15);
 }
@@ -1098,18 +1110,20 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, moco_form> g_tune;
-std::map<TuneKey, int> g_tune_tile;   // the int8 form's shift tile, 32 or 64
+// the int8 form's shift tile (32 or 64) per key and launch size class
+std::map<std::pair<TuneKey, int>, int> g_tune_tile;
 
 TuneKey tune_key(const moco::Geom &g) { return TuneKey{g.m, g.n, g.w, g.ds, (int)g.dtype}; }
 
-int int8_tile(const moco::Tmpl &t)
+int int8_tile(const moco::Tmpl &t, int C)
 {
+    const int cls = tile_class(C);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_tile.find(tune_key(t.g));
+        auto it = g_tune_tile.find({tune_key(t.g), cls});
         if (it != g_tune_tile.end()) return it->second;
     }
-    return int8_model_tile(t.g);
+    return int8_model_tile(t.g, cls);
 }
 
 bool form_applies(const moco::Tmpl &t, moco_form f)
@@ -1369,10 +1383,11 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     moco_outputs out{};
     out.shifts = d_shifts;
     const TuneKey key = tune_key(g);
+    const std::pair<TuneKey, int> tkey{key, tile_class(T)};   // the tile for launches of T frames
     int prev_tile = 0;   // a tile recorded before the call, restored if int8 is not timed
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_tile.find(key);
+        auto it = g_tune_tile.find(tkey);
         if (it != g_tune_tile.end()) prev_tile = it->second;
     }
     for (size_t c = 0; c < cand.size() && rc == MOCO_OK; ++c) {
@@ -1380,7 +1395,7 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
         if (cand[c].second) {
             // the tile the int8 runs below take
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_tile[key] = cand[c].second;
+            g_tune_tile[tkey] = cand[c].second;
         }
         rc = moco_align(ctx, d_frames, tmpl, T, g.m, g.n, g.w, g.ds, g.dtype, f, &out, st);
         const int reps = 3;
@@ -1414,9 +1429,9 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         // the int8 form keeps its faster tile whichever form won
-        if (rc == MOCO_OK && int8_tile_best) g_tune_tile[key] = int8_tile_best;
-        else if (prev_tile) g_tune_tile[key] = prev_tile;
-        else g_tune_tile.erase(key);
+        if (rc == MOCO_OK && int8_tile_best) g_tune_tile[tkey] = int8_tile_best;
+        else if (prev_tile) g_tune_tile[tkey] = prev_tile;
+        else g_tune_tile.erase(tkey);
         if (rc == MOCO_OK) g_tune[key] = best;
     }
     if (rc != MOCO_OK) return rc;
@@ -1431,7 +1446,7 @@ int moco_tune_set_tile(int m, int n, int w, int downsample, moco_dtype dtype, in
     if (tile == 64 && 2 * w - 1 <= 32)
         return fail(MOCO_EINVAL, "moco_tune_set_tile: 2w-1 = %d takes one 32x32 tile", 2 * w - 1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_tile[TuneKey{m, n, w, downsample, (int)dtype}] = tile;
+    for (int cls = 0; cls < 2; ++cls) g_tune_tile[{TuneKey{m, n, w, downsample, (int)dtype}, cls}] = tile;
     return MOCO_OK;
 }
 
@@ -1439,7 +1454,7 @@ int moco_template_int8_tile(const moco_tmpl *tmpl, int *tile)
 {
     if (!tmpl || !tile) return fail(MOCO_EINVAL, "moco_template_int8_tile: null argument");
     if (!tmpl->t.int8_ok) return fail(MOCO_EINVAL, "the int8 form does not apply");
-    *tile = int8_tile(tmpl->t);
+    *tile = int8_tile(tmpl->t, kInt8SmallBatch + 1);
     return MOCO_OK;
 }
 

@@ -556,7 +556,8 @@ def fft_bound(tmpl: Template):
 
 def int8_tile(tmpl: Template) -> int:
     """moco_template_int8_tile: the int8 form's shift tile (32 or 64) for the
-    template's key now (recorded by tune or tune_set_tile, else the model's)."""
+    template's key now, in launches of more than 64 frames (recorded by tune
+    or tune_set_tile, else the model's)."""
     n = ctypes.c_int()
     _check(_lib.moco_template_int8_tile(tmpl.handle, ctypes.byref(n)))
     return n.value
