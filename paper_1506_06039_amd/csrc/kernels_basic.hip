@@ -1324,7 +1324,8 @@ __device__ __forceinline__ void roll_rows(const uint16_t *__restrict__ fb,
 }
 
 // Per-frame mode: narrow and a single flush at the end of a band of `rows`
-// rows (the fast kernel), else narrow with flushes or wide (the slow kernel).
+// rows (the fast kernel), else narrow with flushes or wide (the slow units,
+// run by k_refine_slow_finish).
 __device__ __forceinline__ int roll_flush(const int32_t *pmax, int tmax, int frame)
 {
     if (!pmax || tmax < 0) return -1;  // wide
@@ -1437,36 +1438,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                      coarse_st, partial, units);
 }
 
-// Slow kernel: one block per frame, its waves take the units the fast kernel
-// left (none for most workloads).
-template <bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_refine_roll_slow(
-    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl_one, int m, int n,
-    int br, int nbr, int ncw, const int32_t *__restrict__ coarse_st,
-    const int32_t *__restrict__ pmax, int tmax_one, double *__restrict__ partial,
-    const uint16_t *const *__restrict__ tmpls, const int32_t *__restrict__ tmaxs)
+// The nine full-resolution sums of one frame from its units' partials (one
+// wave: lanes take every 64th partial, then a fixed tree), and the argmin.
+__device__ __forceinline__ void refine_finish_wave(const double *__restrict__ partial, int frame,
+                                                   int nband, int m, int n,
+                                                   const int32_t *__restrict__ coarse_st,
+                                                   int32_t *__restrict__ shifts,
+                                                   double *__restrict__ frefine,
+                                                   double *__restrict__ gaps)
 {
-    const int units = nbr * ncw, frame = blockIdx.x;
-    const uint16_t *tmpl = MULTI ? tmpls[frame] : tmpl_one;
-    const int tmax = MULTI ? tmaxs[frame] : tmax_one;
-    const int flush = roll_flush(pmax, tmax, frame);
-    if (flush >= br) return;  // every band of this frame was done by the fast kernel
-    for (int unit = __builtin_amdgcn_readfirstlane(threadIdx.x / 64); unit < units;
-         unit += kBlock / 64)
-        roll_unit<true>(frames, tmpl, m, n, br, ncw, frame, unit, flush, coarse_st, partial, units);
-}
-
-__global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restrict__ partial,
-                                                          int C, int nband, int m, int n,
-                                                          const int32_t *__restrict__ coarse_st,
-                                                          int32_t *__restrict__ shifts,
-                                                          double *__restrict__ frefine,
-                                                          double *__restrict__ gaps)
-{
-    // one wave per frame: lanes take every 64th partial, then a fixed tree
     const int lane = threadIdx.x % 64;
-    const int frame = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
-    if (frame >= C) return;
     double e9[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) e9[q] = 0.0;
@@ -1495,6 +1476,48 @@ __global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restri
     shifts[2 * frame] = c.s;
     shifts[2 * frame + 1] = c.t;
     if (gaps) gaps[2 * frame + 1] = c.second - c.f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_finish(const double *__restrict__ partial,
+                                                          int C, int nband, int m, int n,
+                                                          const int32_t *__restrict__ coarse_st,
+                                                          int32_t *__restrict__ shifts,
+                                                          double *__restrict__ frefine,
+                                                          double *__restrict__ gaps)
+{
+    // one wave per frame
+    const int frame = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    if (frame >= C) return;
+    refine_finish_wave(partial, frame, nband, m, n, coarse_st, shifts, frefine, gaps);
+}
+
+// The rolling refine's slow units and its finish in one launch, one wave per
+// frame: a frame in the slow mode (sums too wide for the fast kernel's
+// 32-bit flushes) runs its units here first (none for most workloads), then
+// the wave forms the frame's nine sums and argmin as k_refine_finish.
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_refine_slow_finish(
+    const uint16_t *__restrict__ frames, const uint16_t *__restrict__ tmpl_one, int m, int n,
+    int br, int nbr, int ncw, int C, const int32_t *__restrict__ coarse_st,
+    const int32_t *__restrict__ pmax, int tmax_one, double *__restrict__ partial,
+    const uint16_t *const *__restrict__ tmpls, const int32_t *__restrict__ tmaxs,
+    int32_t *__restrict__ shifts, double *__restrict__ frefine, double *__restrict__ gaps)
+{
+    const int frame =
+        blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    if (frame >= C) return;
+    const int units = nbr * ncw;
+    const uint16_t *tmpl = MULTI ? tmpls[frame] : tmpl_one;
+    const int tmax = MULTI ? tmaxs[frame] : tmax_one;
+    const int flush = roll_flush(pmax, tmax, frame);
+    if (flush < br) {
+        for (int unit = 0; unit < units; ++unit)
+            roll_unit<true>(frames, tmpl, m, n, br, ncw, frame, unit, flush, coarse_st, partial,
+                            units);
+        // the units' partials (stored by lane 0) before the wave reads them
+        __threadfence();
+    }
+    refine_finish_wave(partial, frame, units, m, n, coarse_st, shifts, frefine, gaps);
 }
 
 void launch_finish(const double *partial, int C, int nunits, const Geom &g,
@@ -1743,12 +1766,9 @@ hipError_t launch_refine(const void *frames, const void *traw, int C, const Geom
                                                           partial, nullptr, nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_refine_roll_slow<false><<<C, kBlock, 0, st>>>((const uint16_t *)frames, (const uint16_t *)traw,
-                                                 g.m, g.n, br, nbr, ncw, coarse_st, pmax, tmax,
-                                                 partial, nullptr, nullptr);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        launch_finish(partial, C, units, g, coarse_st, shifts, frefine, gaps, st);
+        k_refine_slow_finish<false><<<(C + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
+            (const uint16_t *)frames, (const uint16_t *)traw, g.m, g.n, br, nbr, ncw, C,
+            coarse_st, pmax, tmax, partial, nullptr, nullptr, shifts, frefine, gaps);
         return hipGetLastError();
     }
     int br = refine_band_rows(g);
@@ -1810,11 +1830,9 @@ hipError_t launch_refine_multi(const uint16_t *frames, const uint16_t *const *tr
                                                             traws, tmaxs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_refine_roll_slow<true><<<C, kBlock, 0, st>>>(frames, nullptr, g.m, g.n, br, nbr, ncw,
-                                                   coarse_st, pmax, -1, partial, traws, tmaxs);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    launch_finish(partial, C, units, g, coarse_st, shifts, frefine, gaps, st);
+    k_refine_slow_finish<true><<<(C + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
+        frames, nullptr, g.m, g.n, br, nbr, ncw, C, coarse_st, pmax, -1, partial, traws, tmaxs,
+        shifts, frefine, gaps);
     return hipGetLastError();
 }
 
