@@ -891,11 +891,25 @@ void fft32_cert_coefs(const FftTmpl &ft, double *e1, double *e2)
     *e2 = eps + 7.0 * u;
 }
 
+// The transform length for x = grid side + w - 1 points: the next length
+// with a wave-level kernel when it is at most 10% longer than the next
+// 2,3,5-smooth length, else that length (384 points in place of 360: the
+// wave-level kernels ran the 384-point transforms 30% faster than the block
+// kernels, more than the 14% more points cost).
+static int transform_length(int x)
+{
+    const int n0 = next_smooth(x);
+    if (wave_length(n0)) return n0;
+    for (int n = n0 + 1; n <= n0 + n0 / 10; ++n)
+        if (wave_length(n)) return n;
+    return n0;
+}
+
 FftGeom fft_geom(const Geom &g)
 {
     FftGeom f{};
-    f.P = next_smooth(g.mg + g.w - 1);
-    f.Q = next_smooth(g.ng + g.w - 1);
+    f.P = transform_length(g.mg + g.w - 1);
+    f.Q = transform_length(g.ng + g.w - 1);
     f.qh = f.Q / 2 + 1;
     return f;
 }

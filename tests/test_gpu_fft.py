@@ -102,7 +102,7 @@ FFT_SHAPES = [
     (300, 17, 8, True, "f32", 3),     # grid 150x8: 160 x 15
     (60, 220, 46, False, "f32", 2),   # 108 x 270 (2*3^3*5)
     (40, 1030, 6, True, "u16", 2),    # grid 20x515: 25 x 540
-    (276, 200, 85, False, "f32", 2),  # 360 x 288 (radices 3,3,5,8 and 3,3,4,8)
+    (276, 200, 85, False, "f32", 2),  # 384 x 288 (2,3,8,8 and 3,3,4,8): 384 in place of 360
     (512, 796, 48, True, "u16", 2),   # grid 256x398: 320 x 450 (2,3,3,5,5)
     (512, 796, 32, True, "f32", 2),   # grid 256x398: 288 x 432 (2,3,3,3,8)
     (350, 350, 30, False, "u16", 2),  # 384 x 384 (2,3,8,8)
@@ -176,7 +176,8 @@ def test_wide_window_paper_shape_auto_picks_fft(gpu_lib):
 
 # The paper's own setting (sec. 3): downsample once iff a side exceeds 256 and
 # a window of a third of the searched grid's side, here w = 85 on 256x256
-# grids: transform lengths 360 x 360 (the stack shapes of its timing table).
+# grids: transform lengths 384 x 384 (the stack shapes of its timing table;
+# a wave-level length in place of the 2,3,5-smooth 360).
 PAPER_W85 = [(512, 512, 3, 11), (256, 256, 3, 12)]
 
 
