@@ -697,14 +697,15 @@ size_t wave_lds()
 }
 
 // The lengths with a wave-level kernel; others take the block-level kernels.
-// Measured on MI355X against the block kernels: faster at 144, 288, 300, 320
-// and 384 points (384 x 384, 1000 frames: FP64 1.86 -> 1.30 ms, FP32 1.22 ->
-// 0.72 ms); slower at 360 (3,3,5,8: the radix-8 pass keeps 45 of 64 lanes
+// Measured on MI355X against the block kernels: faster at 144, 288, 300, 320,
+// 384 and 512 points (384 x 384, 1000 frames: FP64 1.86 -> 1.30 ms, FP32 1.22
+// -> 0.72 ms; 512 x 512: FP64 3.47 -> 2.42 ms, FP32 1.89 -> 1.21 ms, three
+// radix-8 passes with every lane busy); slower at 360 (3,3,5,8: the radix-8 pass keeps 45 of 64 lanes
 // busy; transforms of the 256x256 grid at w = 85: FP32 2.58 -> 1.92 ms, FP64
 // 3.70 -> 3.29 ms per 2000 frames with the block kernels), 400, 432, 450 and
 // 480 (5-18% slower: passes that leave lanes idle), which keep the block
 // kernels.
-#define MOCO_WAVE_LENGTHS(X) X(144) X(160) X(180) X(240) X(256) X(270) X(288) X(300) X(320) X(384)
+#define MOCO_WAVE_LENGTHS(X) X(144) X(160) X(180) X(240) X(256) X(270) X(288) X(300) X(320) X(384) X(512)
 
 bool wave_length(int n)
 {

@@ -108,6 +108,7 @@ FFT_SHAPES = [
     (350, 350, 30, False, "u16", 2),  # 384 x 384 (2,3,8,8)
     (380, 140, 16, False, "f32", 2),  # 400 x 160 (5,5,2,8)
     (460, 100, 16, False, "u16", 2),  # 480 x 120 (3,4,5,8)
+    (480, 100, 32, False, "u16", 2),  # 512 x 144: the wave-level 512 (8,8,8)
 ]
 
 

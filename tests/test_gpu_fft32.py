@@ -119,6 +119,7 @@ FFT32_SHAPES = [
     (512, 796, 48, 1, "u16", 2),    # 320 x 450
     (350, 350, 30, 0, "f32", 2),    # 384 x 384
     (460, 100, 16, 0, "f32", 2),    # 480 x 120
+    (470, 80, 16, 0, "f32", 2),     # 512 (in place of the smooth 486) x 96
 ]
 
 
