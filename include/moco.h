@@ -409,13 +409,16 @@ int moco_server_add_source(moco_server *srv, int source, const void *h_template,
                            moco_dtype dtype, int m, int n, int w, int downsample);
 
 /* Submit one frame (host memory of the source's size and dtype, copied during
- * the call).  Returns MOCO_OK when admitted, MOCO_EBUSY when no slot is free
+ * the call).  When no batch is in flight the call also enqueues the batch
+ * (this request and any others waiting) itself, instead of waking the worker
+ * thread.  Returns MOCO_OK when admitted, MOCO_EBUSY when no slot is free
  * (back-pressure: poll, then retry), MOCO_EINVAL for an unknown source. */
 int moco_server_submit(moco_server *srv, int source, const void *h_frame, uint64_t tag);
 
 /* Wait up to timeout_us (0: do not wait, < 0: wait without limit) for finished
  * requests and copy up to `max` results into `results` (host), oldest first.
- * Returns the number copied (>= 0) or a negative status. */
+ * The first millisecond of a wait polls (yielding the core) rather than
+ * sleeping.  Returns the number copied (>= 0) or a negative status. */
 int moco_server_poll(moco_server *srv, moco_result *results, int max, int timeout_us);
 
 /* Requests admitted and not yet published (queued or on the GPU). */
