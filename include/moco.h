@@ -307,8 +307,9 @@ int moco_template_form(const moco_tmpl *tmpl, moco_form requested, moco_form *re
  * MOCO_FORM_FP64_EXACT when none does) on `frames` copies of the template, one
  * warm-up and three timed calls each with HIP events on hip_stream, and record
  * the fastest for the template's key.  The int8 form is timed with each of its
- * shift-tile shapes that applies (one 32x32 tile per block, or 2x2 tiles of
- * 32 when 2w-1 > 32) and keeps the faster for the key and for launches of
+ * shift-tile shapes that applies (two 16x16 tiles in one 32x32 product when
+ * 2w-1 <= 16, one 32x32 tile per block, or 2x2 tiles of 32 when 2w-1 > 32)
+ * and keeps the fastest for the key and for launches of
  * that size class (at most 64 frames, or more) whichever form wins
  * (moco_template_int8_tile).  The forms rank differently with the stack length
  * (a few frames take the int8 form's row-sliced launch), so `frames` should be
@@ -330,11 +331,14 @@ int moco_tune_set(int m, int n, int w, int downsample, moco_dtype dtype, moco_fo
 int moco_tune_get(int m, int n, int w, int downsample, moco_dtype dtype, moco_form *form);
 
 /* Record the int8 form's shift tile for the key (uint16 data), for launches
- * of any size: 32 (one 32x32 tile per block, ceil((2w-1)/32)^2 blocks per
- * frame) or 64 (2x2 tiles of 32, ceil((2w-1)/64)^2 blocks; not when 2w-1 <=
- * 32).  Without a recorded tile the form takes 32 when 2w-1 <= 32, or when
- * 2w-1 <= 64 and a launch holds at most 64 frames; else 64.  Both give the
- * same exact results.  Host only.  Errors: MOCO_EINVAL. */
+ * of any size: 16 (two 16x16 tiles on the diagonal of one 32x32 MFMA product,
+ * over the two halves of each 128-column strip; only when 2w-1 <= 16), 32
+ * (one 32x32 tile per block, ceil((2w-1)/32)^2 blocks per frame) or 64 (2x2
+ * tiles of 32, ceil((2w-1)/64)^2 blocks; not when 2w-1 <= 32).  Without a
+ * recorded tile the form takes 16 when 2w-1 <= 16 and the template takes
+ * three digit products, else 32 when 2w-1 <= 32, or when 2w-1 <= 64 and a
+ * launch holds at most 64 frames; else 64.  All give the same exact results.
+ * Host only.  Errors: MOCO_EINVAL. */
 int moco_tune_set_tile(int m, int n, int w, int downsample, moco_dtype dtype, int tile);
 
 /* Forget every recorded form and tile. */
@@ -361,7 +365,7 @@ int moco_template_fft_bound(const moco_tmpl *tmpl, double *kf, double *ke);
  * Errors: MOCO_EINVAL (null argument, or the int8 form does not apply). */
 int moco_template_int8_products(const moco_tmpl *tmpl, int *products);
 
-/* The shift tile (32 or 64) the int8 form uses for this template's key now,
+/* The shift tile (16, 32 or 64) the int8 form uses for this template's key now,
  * in launches of more than 64 frames: the recorded one, else the model's.
  * Host only.
  * Errors: MOCO_EINVAL (null argument, or the int8 form does not apply). */

@@ -1048,9 +1048,11 @@ int run_stack(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
 }
 
 // MFMA tiles of 32x32 shifts a frame's correlation issues with each tile
-// shape: ceil(W/32)^2 one-tile blocks, or ceil(W/64)^2 blocks of 2x2 tiles.
+// shape: half a tile (16), ceil(W/32)^2 one-tile blocks, or ceil(W/64)^2
+// blocks of 2x2 tiles.
 double int8_tiles(const moco::Geom &g, int tile)
 {
+    if (tile == 16) return 0.5;   // one tile's MFMAs over half the K-chunks
     const double gs = std::ceil(g.W / (double)tile);
     return tile == 32 ? gs * gs : 4.0 * gs * gs;
 }
@@ -1060,15 +1062,22 @@ double int8_tiles(const moco::Geom &g, int tile)
 constexpr int kInt8SmallBatch = 64;
 int tile_class(int C) { return C <= kInt8SmallBatch ? 0 : 1; }
 
-// One 32x32 tile when 2w-1 <= 32, else 2x2 groups: a group reads each frame
+// Two 16x16 tiles on the diagonal of one 32x32 MFMA product when 2w-1 <= 16
+// with three digit products (half the MFMAs of a single tile: 256x256 frames
+// at w = 8, correlation 0.19 against 0.33 us per frame; with four products,
+// whose LDS reads per MFMA are more, it gained nothing at 512x796, 0.58
+// against 0.56); one 32x32 tile when 2w-1 <= 32, else 2x2 groups: a group
+// reads each frame
 // and template operand once for two tiles, and at 2w-1 = 79 on a 256x256 grid
 // the groups (16 tiles) ran faster than single tiles (9 tiles).  A launch of
 // at most kInt8SmallBatch frames takes single tiles up to 2w-1 = 64: four
 // times the blocks fill more of the device (512x512 frames, w = 32:
 // correlation 21 against 35 us for one frame, 109 against 128 us for 64,
 // 176 against 165 us for 128).  moco_tune times both shapes.
-int int8_model_tile(const moco::Geom &g, int cls)
+int int8_model_tile(const moco::Tmpl &t, int cls)
 {
+    const moco::Geom &g = t.g;
+    if (g.W <= 16 && t.i8.nq == 3) return 16;
     return g.W <= 32 || (cls == 0 && g.W <= 64) ? 32 : 64;
 }
 
@@ -1123,7 +1132,7 @@ int int8_tile(const moco::Tmpl &t, int C)
         auto it = g_tune_tile.find({tune_key(t.g), cls});
         if (it != g_tune_tile.end()) return it->second;
     }
-    return int8_model_tile(t.g, cls);
+    return int8_model_tile(t, cls);
 }
 
 bool form_applies(const moco::Tmpl &t, moco_form f)
@@ -1355,6 +1364,7 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
     // applies (32 only when 2w-1 <= 32)
     std::vector<std::pair<moco_form, int>> cand;
     if (t.int8_ok) {
+        if (g.W <= 16) cand.push_back({MOCO_FORM_INT8_MFMA, 16});
         cand.push_back({MOCO_FORM_INT8_MFMA, 32});
         if (g.W > 32) cand.push_back({MOCO_FORM_INT8_MFMA, 64});
     }
@@ -1441,7 +1451,10 @@ int moco_tune(moco_ctx *ctx, const moco_tmpl *tmpl, int frames, void *hip_stream
 
 int moco_tune_set_tile(int m, int n, int w, int downsample, moco_dtype dtype, int tile)
 {
-    if (tile != 32 && tile != 64) return fail(MOCO_EINVAL, "moco_tune_set_tile: tile %d", tile);
+    if (tile != 16 && tile != 32 && tile != 64)
+        return fail(MOCO_EINVAL, "moco_tune_set_tile: tile %d", tile);
+    if (tile == 16 && 2 * w - 1 > 16)
+        return fail(MOCO_EINVAL, "moco_tune_set_tile: 2w-1 = %d exceeds a 16x16 tile", 2 * w - 1);
     if (dtype != MOCO_U16) return fail(MOCO_EINVAL, "moco_tune_set_tile: the int8 form is uint16 only");
     if (tile == 64 && 2 * w - 1 <= 32)
         return fail(MOCO_EINVAL, "moco_tune_set_tile: 2w-1 = %d takes one 32x32 tile", 2 * w - 1);

@@ -569,7 +569,13 @@ __device__ __forceinline__ void wait_barrier()
 // gives each block-column x its template rows, and its frames run from
 // bf0[x] to bfe[x] - 1 (at most four, all of that template); without btp,
 // block-column x takes frames 4x .. 4x+3 of the one template tp.
-template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
+//
+// HALF (one tile, 2w-1 <= 16): the 32x32 MFMA product holds two 16x16 shift
+// tiles on its diagonal, rows and columns 0-15 over the first 64 columns of
+// each strip and rows and columns 16-31 over the last 64, so a strip takes two
+// K-chunks instead of four; the tile is the sum of the two diagonal blocks
+// (the off-diagonal ones mix the halves and are dropped).
+template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB, bool HALF = false>
 __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *__restrict__ limbs, const int32_t *__restrict__ nlimb,
     const int8_t *__restrict__ tp_one, const int8_t *__restrict__ zsrc_one, int C, int mg,
@@ -577,7 +583,8 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     const int8_t *const *__restrict__ btp, const int *__restrict__ bf0,
     const int *__restrict__ bfe)
 {
-    constexpr int RING = 32 * NS;     // frame rows an iteration reads
+    static_assert(!HALF || (NS == 1 && NT == 1), "the half tile is one tile");
+    constexpr int RING = HALF ? 16 : 32 * NS;   // frame rows an iteration reads
     constexpr int RS = RING + 3;      // ring slots: a pair of rows reads RING + 1, the next
                                       // pair's two arrive meanwhile
     constexpr bool SUMP = KB && PA0 == 0;        // three-product main pass
@@ -588,7 +595,8 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
     constexpr int TQ = KB ? 3 : 2;               // template planes held
     constexpr int MAXT = KB ? kMaxTrowSum : kMaxTrow;
     constexpr int SLOT = (SUMP ? 3 : 2) * kStrip + 16;   // LDS bytes per ring slot (+ bank offset)
-    constexpr int KC = kStrip / 32;   // MFMA K-chunks per strip (npad is a multiple of kStrip)
+    // MFMA K-chunks per strip (npad is a multiple of kStrip)
+    constexpr int KC = HALF ? kStrip / 64 : kStrip / 32;
     __shared__ __attribute__((aligned(16))) int8_t s_ring[kWaves * RS * SLOT];
     __shared__ __attribute__((aligned(16))) int8_t s_tA[TQ * kPhases * MAXT];
     __shared__ __attribute__((aligned(16))) int8_t s_tB[TQ * kPhases * MAXT];
@@ -714,19 +722,23 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
         auto rowmma = [&](int i, const int8_t *tcur) {
             // operand addresses of K-chunk 0; chunk kc adds kc*32 bytes.  The byte
             // phase of a template read does not depend on kc (32 is a multiple of 8).
+            // HALF: operand row / column rho takes shift rho % 16 over the
+            // strip's half rho / 16
+            const int rs = HALF ? (rho & 15) : rho;
+            const int ch = HALF ? 64 * (rho >> 4) : 0;
             const int8_t *abase[NS][NA];
 #pragma unroll
             for (int st = 0; st < NS; ++st)
 #pragma unroll
                 for (int p = 0; p < NA; ++p)
-                    abase[st][p] = my_ring + (size_t)((i + 32 * st + rho) % RS) * SLOT +
-                                   p * kStrip + 16 * h;
+                    abase[st][p] = my_ring + (size_t)((i + 32 * st + rs) % RS) * SLOT +
+                                   p * kStrip + 16 * h + ch;
             const int8_t *bbase[NT][NB];
 #pragma unroll
             for (int tt = 0; tt < NT; ++tt) {
                 // template bytes B[i][k - t] for k = ks + kc*32 + 16h + e, t = t_lo + 32 tt + rho,
                 // read from the phase copy that makes them 8-byte aligned
-                int x0 = ks + 16 * h - (t_lo + 32 * tt + rho) + padl;
+                int x0 = ks + 16 * h + ch - (t_lo + 32 * tt + rs) + padl;
                 int phi = x0 & (kPhases - 1);
 #pragma unroll
                 for (int q = 0; q < NB; ++q)
@@ -850,6 +862,46 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
 
     if (!live) return;
     long long *H = hout + (size_t)frame * W * W;
+    // accumulator r of lane (rho, h): row 8 (r / 4) + 4 h + r % 4, column rho
+    auto tile_value = [&](int st, int tt, int r) {
+        long long v = 0;
+        if constexpr (SUMP) {
+            const long long h00 = acc[st][tt][0][r], sum = acc[st][tt][1][r];
+            const long long h11 = acc[st][tt][NACC - 1][r];
+            v = h00 + (sum - h00 - h11) * 128 + h11 * 16384;
+        } else {
+#pragma unroll
+            for (int p = 0; p < NPA; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    v += (long long)acc[st][tt][p * 2 + q][r] * (1LL << (DB * (PA0 + p + q)));
+        }
+        return v;
+    };
+    auto put = [&](int s, int t, long long v) {
+        size_t k = (size_t)(s + w - 1) * W + (t + w - 1);
+        if (nslice > 1)
+            atomicAdd((unsigned long long *)&H[k], (unsigned long long)v);
+        else if (PA0 == 0)
+            H[k] = v;
+        else
+            H[k] += v;
+    };
+    if constexpr (HALF) {
+        // rows 0-15 are r < 8; row + 16 is r + 8, whose column + 16 sits 16
+        // lanes up (every lane takes part in the exchange)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const long long up = tile_value(0, 0, r + 8);
+            const unsigned ulo = (unsigned)__shfl_down((int)(unsigned)up, 16);
+            const unsigned uhi = (unsigned)__shfl_down((int)(unsigned)((unsigned long long)up >> 32), 16);
+            const long long v = tile_value(0, 0, r) + (long long)(((unsigned long long)uhi << 32) | ulo);
+            const int s = s_lo + 8 * (r / 4) + 4 * h + (r % 4);
+            const int t = t_lo + rho;
+            if (rho < 16 && s <= w - 1 && t <= w - 1) put(s, t, v);
+        }
+        return;
+    }
 #pragma unroll
     for (int st = 0; st < NS; ++st)
 #pragma unroll
@@ -859,26 +911,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_corr_int8(
                 int s = s_lo + 32 * st + 8 * (r / 4) + 4 * h + (r % 4);
                 int t = t_lo + 32 * tt + rho;
                 if (s > w - 1 || t > w - 1) continue;
-                long long v = 0;
-                if constexpr (SUMP) {
-                    const long long h00 = acc[st][tt][0][r], sum = acc[st][tt][1][r];
-                    const long long h11 = acc[st][tt][NACC - 1][r];
-                    v = h00 + (sum - h00 - h11) * 128 + h11 * 16384;
-                } else {
-#pragma unroll
-                    for (int p = 0; p < NPA; ++p)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-                            v += (long long)acc[st][tt][p * 2 + q][r] *
-                                 (1LL << (DB * (PA0 + p + q)));
-                }
-                size_t k = (size_t)(s + w - 1) * W + (t + w - 1);
-                if (nslice > 1)
-                    atomicAdd((unsigned long long *)&H[k], (unsigned long long)v);
-                else if (PA0 == 0)
-                    H[k] = v;
-                else
-                    H[k] += v;
+                put(s, t, tile_value(st, tt, r));
             }
 }
 
@@ -982,7 +1015,7 @@ __global__ __launch_bounds__(TB) void k_combine_i64(const long long *__restrict_
 // ---------------------------------------------------------------------------
 // Launch shapes of k_corr_int8: the operand-transfer count per wave, the
 // tile groups and the row slices.
-template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB>
+template <int NS, int NT, int NPA, int PA0, int NDMA, bool KB, bool HALF>
 hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                             const Geom &g, int nslice, long long *h, hipStream_t st,
                             const Int8Multi *mm)
@@ -991,13 +1024,13 @@ hipError_t launch_corr_ndma(const int8_t *limbs, const int32_t *nlimb, const Int
     const int sgroups = (g.W + 32 * NS - 1) / (32 * NS);
     dim3 grid(mm ? mm->nblocks : (C + kWaves - 1) / kWaves, sgroups * tgroups, nslice);
     const int8_t *zsrc = tt.tp + (size_t)g.mg * tt.nq * kPhases * tt.trow;  // zero tail
-    k_corr_int8<NS, NT, NPA, PA0, NDMA, KB><<<grid, kBlock, 0, st>>>(
+    k_corr_int8<NS, NT, NPA, PA0, NDMA, KB, HALF><<<grid, kBlock, 0, st>>>(
         limbs, nlimb, tt.tp, zsrc, C, g.mg, tt.npad, tt.trow, tt.padl, g.w, tgroups, nslice, h,
         mm ? mm->btp : nullptr, mm ? mm->bf0 : nullptr, mm ? mm->bfe : nullptr);
     return hipGetLastError();
 }
 
-template <int NS, int NT, int NPA, int PA0, bool KB>
+template <int NS, int NT, int NPA, int PA0, bool KB, bool HALF>
 hipError_t launch_corr_nq(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt, int C,
                           const Geom &g, int nslice, long long *h, hipStream_t st,
                           const Int8Multi *mm)
@@ -1006,15 +1039,15 @@ hipError_t launch_corr_nq(const int8_t *limbs, const int32_t *nlimb, const Int8T
     // the buffer bound 3 quarters + NDMA KB <= nq * 8 * max row holds for every
     // trow up to that maximum
     switch ((tt.nq * 2 * tt.trow + 1023) / 1024) {
-    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
-    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
-    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
-    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4, KB>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 1: return launch_corr_ndma<NS, NT, NPA, PA0, 1, KB, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 2: return launch_corr_ndma<NS, NT, NPA, PA0, 2, KB, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 3: return launch_corr_ndma<NS, NT, NPA, PA0, 3, KB, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    case 4: return launch_corr_ndma<NS, NT, NPA, PA0, 4, KB, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int NS, int NT, int NPA, int PA0>
+template <int NS, int NT, int NPA, int PA0, bool HALF = false>
 hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const Int8Tmpl &tt,
                                int C, const Geom &g, int nslice, long long *h, hipStream_t st,
                                const Int8Multi *mm)
@@ -1022,10 +1055,10 @@ hipError_t launch_corr_variant(const int8_t *limbs, const int32_t *nlimb, const 
     // base-128 digits with a digit-sum plane (three products), or base-256 (four)
     if (tt.nq == 3) {
         if (tt.trow > kMaxTrowSum) return hipErrorInvalidValue;
-        return launch_corr_nq<NS, NT, NPA, PA0, true>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+        return launch_corr_nq<NS, NT, NPA, PA0, true, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     }
     if (tt.trow > kMaxTrow) return hipErrorInvalidValue;
-    return launch_corr_nq<NS, NT, NPA, PA0, false>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
+    return launch_corr_nq<NS, NT, NPA, PA0, false, HALF>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
 }
 
 // Row slices per block group: with fewer blocks than compute units (a few
@@ -1215,7 +1248,7 @@ hipError_t launch_tpad(const int8_t *tlimbs, const Geom &g, const Int8Tmpl &tt, 
 
 bool int8_corr_adds_slices(int C, const Geom &g, int tile, int nblocks)
 {
-    const bool small = tile == 32 || (tile == 0 && g.W <= 32);
+    const bool small = tile == 16 || tile == 32 || (tile == 0 && g.W <= 32);
     return (small ? corr_slices(C, g, 1, 1, nblocks) : corr_slices(C, g, 2, 2, nblocks)) > 1;
 }
 
@@ -1227,14 +1260,22 @@ hipError_t launch_corr_int8(const int8_t *limbs, const int32_t *nlimb, const Int
     if (C == 0) return hipSuccess;
     hipError_t e;
     // (the template rows are padded for 2x2 tiles of 32 only when 2w-1 > 32)
-    if ((tile != 0 && tile != 32 && tile != 64) || (tile == 64 && g.W <= 32))
+    if ((tile != 0 && tile != 16 && tile != 32 && tile != 64) || (tile == 64 && g.W <= 32) ||
+        (tile == 16 && g.W > 16))
         return hipErrorInvalidValue;
-    const bool small = tile == 32 || (tile == 0 && g.W <= 32);
+    const bool half = tile == 16 || (tile == 0 && g.W <= 16);
+    const bool small = half || tile == 32 || (tile == 0 && g.W <= 32);
     const int nb = mm ? mm->nblocks : -1;
     const int nslice = small ? corr_slices(C, g, 1, 1, nb) : corr_slices(C, g, 2, 2, nb);
     if (nslice > 1 && !h_zeroed) {
         // the slices add into a zeroed table
         if ((e = launch_fill_i32((int32_t *)h, 2 * C * g.W * g.W, 0, st)) != hipSuccess) return e;
+    }
+    if (half) {
+        if ((e = launch_corr_variant<1, 1, 2, 0, true>(limbs, nlimb, tt, C, g, nslice, h, st,
+                                                        mm)) != hipSuccess)
+            return e;
+        return launch_corr_variant<1, 1, 1, 2, true>(limbs, nlimb, tt, C, g, nslice, h, st, mm);
     }
     if (small) {
         if ((e = launch_corr_variant<1, 1, 2, 0>(limbs, nlimb, tt, C, g, nslice, h, st, mm)) !=

@@ -555,7 +555,7 @@ def fft_bound(tmpl: Template):
 
 
 def int8_tile(tmpl: Template) -> int:
-    """moco_template_int8_tile: the int8 form's shift tile (32 or 64) for the
+    """moco_template_int8_tile: the int8 form's shift tile (16, 32 or 64) for the
     template's key now, in launches of more than 64 frames (recorded by tune
     or tune_set_tile, else the model's)."""
     n = ctypes.c_int()

@@ -129,6 +129,52 @@ def test_int8_tile_shapes_agree_with_the_oracle(gpu_lib, case):
         ctx.close()
 
 
+HALF_CASES = [
+    # (m, n, w, ds, T): 2w-1 <= 16, two 16x16 tiles on the diagonal of one MFMA
+    # product against one 32x32 tile
+    (256, 256, 8, 0, 5),     # W = 15
+    (512, 796, 8, 1, 3),     # W = 15, grid 256x398
+    (130, 262, 1, 0, 4),     # W = 1
+    (200, 136, 6, 1, 70),    # W = 11, 70 frames (more than the small-launch class)
+]
+
+
+@pytest.mark.parametrize("case", HALF_CASES, ids=lambda c: "%dx%d_w%d_ds%d" % c[:4])
+def test_int8_half_tile_agrees_with_the_single_tile_and_the_oracle(gpu_lib, case):
+    import oracle
+    from tests._parity import check, check_surface
+    m, n, w, ds, T = case
+    sc = synth.PoissonScene(m, n, T + 1, seed=m + 3 * w)
+    fr = sc.frames(1, T + 1)
+    gpu_lib.tune_clear()
+    ctx = gpu_lib.Context(0)
+    try:
+        tp = gpu_lib.Template(ctx, torch.from_numpy(sc.template).cuda(), w, ds)
+        # the model's half tile goes with three digit products
+        assert gpu_lib.int8_tile(tp) == (16 if gpu_lib.int8_products(tp) == 3 else 32)
+        res = {}
+        for tile in (16, 32):
+            gpu_lib.tune_set_tile(m, n, w, ds, "u16", tile)
+            r = gpu_lib.moco_align(ctx, torch.from_numpy(fr).cuda(), tp, form="int8", surface=True)
+            torch.cuda.synchronize()
+            res[tile] = {k: getattr(r, k).cpu().numpy() for k in
+                         ("shifts", "coarse", "fmin", "frefine", "gaps", "fsurf")}
+        _say("case int8 half tile", case)
+        for k in res[16]:
+            assert np.array_equal(res[16][k], res[32][k], equal_nan=True), k
+        nchk = min(T, 6)
+        orc = oracle.align(fr[:nchk], sc.template, w, bool(ds), want_surface=True)
+        sub = {k: v[:nchk] for k, v in res[16].items()}
+        check(sub, orc, bool(ds), exact=True, label="int8 half tile %s" % (case,))
+        check_surface(sub["fsurf"], orc.surf, exact=True, label="int8 half tile surface")
+        with pytest.raises(gpu_lib.MocoError):
+            gpu_lib.tune_set_tile(256, 256, 9, 0, "u16", 16)   # 2w-1 = 17
+        tp.close()
+    finally:
+        gpu_lib.tune_clear()
+        ctx.close()
+
+
 def test_tune_records_the_faster_tile(gpu_lib):
     sc = synth.PoissonScene(256, 256, 4, seed=31)
     gpu_lib.tune_clear()
