@@ -478,6 +478,45 @@ def test_server_sources_of_one_geometry_share_launches(gpu_lib):
             assert out[sid * 100 + k].fmin == orc.fmin[k]
 
 
+def test_server_small_window_sources_share_half_tile_launches(gpu_lib):
+    # four 256x256 sources at w = 8 (2w - 1 = 15 shifts per axis: their batches
+    # run the multi-template correlation with two 16x16 shift tiles on the
+    # diagonal of each product) beside one at w = 16 (a group of its own);
+    # every result equals moco_align on that frame alone and the oracle on the
+    # first frames (no recorded tile: the tile model decides)
+    gpu_lib.tune_clear()
+    ctx = gpu_lib.Context(0)
+    srcs = {k: (synth.PoissonScene(256, 256, 10, seed=80 + k), 8, False) for k in range(4)}
+    srcs[4] = (synth.PoissonScene(256, 256, 10, seed=84), 16, False)
+    for sid in range(4):
+        sc, w, ds = srcs[sid]
+        tp = gpu_lib.Template(ctx, _to_dev(sc.template), w, ds)
+        assert gpu_lib.resolved_form(ctx, tp, "auto") == "int8"
+        assert gpu_lib.int8_products(tp) == 3 and gpu_lib.int8_tile(tp) == 16
+    srv = gpu_lib.Server(ctx, max_slots=16)
+    frames = {}
+    for sid, (sc, w, ds) in srcs.items():
+        srv.add_source(sid, sc.template, w, ds)
+        frames[sid] = sc.frames(1, 7)
+    reqs = [(sid, frames[sid][k], sid * 100 + k) for k in range(6) for sid in srcs]
+    _say("case server half-tile batches: 5 sources x 6 frames, w = 8 and 16")
+    out, _ = _serve_all(srv, reqs)
+    assert srv.close() == 0
+    for sid, (sc, w, ds) in srcs.items():
+        alone = _run(gpu_lib, frames[sid], sc.template, w, ds)
+        for k in range(6):
+            r = out[sid * 100 + k]
+            assert r.status == 0 and r.source == sid
+            assert list(r.shift) == alone["shifts"][k].tolist(), (sid, k)
+            assert list(r.coarse) == alone["coarse"][k].tolist(), (sid, k)
+            assert r.fmin == alone["fmin"][k], (sid, k)
+            assert np.array_equal(np.array(list(r.gaps)), alone["gaps"][k])
+        orc = oracle.align(frames[sid][:2], sc.template, w, ds)
+        for k in range(2):
+            assert list(out[sid * 100 + k].shift) == orc.shifts[k].tolist()
+            assert out[sid * 100 + k].fmin == orc.fmin[k]
+
+
 def test_server_add_source_while_another_thread_submits(gpu_lib):
     # sources of growing frame size are added while requests of another source
     # flow (each addition replaces the slot and lane buffers once nothing holds
