@@ -51,6 +51,9 @@ def _pair(moco, ctx, frames, tp, form, surface):
 CASES = [
     # (label, scene factory, w, ds, form, first T, second T)
     ("poisson512_int8", lambda: synth.poisson512_u16(T=64), 32, True, "int8", 40, 3),
+    # 2w - 1 = 15: the int8 correlation's half tile (two 16x16 shift tiles per product)
+    ("poisson256_int8_w8", lambda: synth.PoissonScene(256, 256, 41, seed=5), 8, False, "int8",
+     40, 3),
     ("poisson512_fft_cert", lambda: synth.poisson512_u16(T=64), 32, True, "fft_cert", 60, 5),
     ("poisson512_fft32_cert", lambda: synth.poisson512_u16(T=64), 32, True, "fft32_cert", 30, 4),
     ("blobs128_fft", lambda: synth.blobs128_f32(), 10, False, "fft", 100, 7),
