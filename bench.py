@@ -705,13 +705,14 @@ def main():
                                         kernels=("k_wrows", "k_wcols", "k_wback"))}
         if fm in ("fft_cert", "fft32_cert"):
             # frames whose argmin the transforms' error bound left uncertified
-            # (the FP32 form: by pass, FP64 transforms / direct sums)
+            # (the FP32 form: by pass, FP64 transforms / direct sums / exact
+            # sums over the nine shifts around the argmin)
             chk = moco.moco_align(ctx, frames, tp, form=fm)
             torch.cuda.synchronize(dev)
             forms[fm]["recomputed_frames"] = int((chk.recomputed > 0).sum().item())
             if fm == "fft32_cert":
                 forms[fm]["recomputed_by_pass"] = [int((chk.recomputed == k).sum().item())
-                                                   for k in (1, 2)]
+                                                   for k in (1, 2, 3)]
             forms[fm]["shifts_equal_headline"] = bool(torch.equal(chk.shifts, out.shifts))
             del chk
         print("[bench] form %s: %.3f ms/step" % (fm, 1000.0 * dt / steps), file=sys.stderr,

@@ -136,8 +136,12 @@ typedef struct moco_tmpl moco_tmpl;
  *                          correlation by direct sums (its argmin was not
  *                          certified); for MOCO_FORM_FFT32_CERTIFIED the number
  *                          of passes after the FP32 one: 1 FP64 transforms, 2
- *                          FP64 transforms and direct sums; else 0 (every other
- *                          form writes 0)
+ *                          FP64 transforms and direct sums, or 3 where exact
+ *                          integer sums over the nine shifts around the
+ *                          computed argmin settled it (uint16 frames with at
+ *                          most one 2x2 level, when every shift the bound
+ *                          leaves open is among those nine); else 0 (every
+ *                          other form writes 0)
  * f is in squared intensity units of the searched grid (box-mean units when
  * downsampled). */
 typedef struct {

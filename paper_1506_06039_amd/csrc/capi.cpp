@@ -893,6 +893,11 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     const double center = fp32 ? tt.fft.center : 0.0;
     const int xc = (int)(center * (g.ds ? 4.0 : 1.0));
     const double *btab = fp32 ? tt.fft.btab32 : tt.btab;
+    // the candidate pass of the single-precision certificate: its largest
+    // squared difference is (4 x 65535)^2 with 2x2 box sums, 65535^2 without
+    const double term_max = g.ds ? 262140.0 * 262140.0 : 65535.0 * 65535.0;
+    const bool cand32 = cert32 && raw_rows && int_energy &&
+                        (double)g.mg * (double)g.ng * term_max < 0x1p53;
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);
         const char *fr = (const char *)d_frames + (size_t)f0 * fbytes;
@@ -953,8 +958,19 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
                                             raw_rows, c, g, tt.coarse, coarse_st, recheck, fmin,
                                             fsurf, gaps, st));
             }
+            // the others: first their candidates, where exact integer sums
+            // settle them (uint16 pixels, one 2x2 level or none, sums of
+            // squared differences below 2^53 so that f is exact)
+            int32_t *resolved = flag + 2 * (size_t)C;
+            if (cand32) {
+                StageTimer tm(ctx, MOCO_STAGE_COMBINE, st);
+                HIP_TRY(moco::launch_cand32(fr, c, g, atab, btab, h, tt.coarse, ke, c32,
+                                            coarse_st, fmin, fsurf, gaps,
+                                            out->shifts + 2 * (size_t)f0, recheck, resolved,
+                                            st));
+            }
             StageTimer tm(ctx, MOCO_STAGE_CORR, st);
-            // the others: uncentred energies, FP64 transforms, the FP64 certificate
+            // then uncentred energies, FP64 transforms, the FP64 certificate
             if (raw_rows && int_energy)
                 HIP_TRY(moco::launch_prep_grid((const uint16_t *)fr, c, g, nullptr, atab, pm, edge,
                                                st, recheck));
@@ -983,6 +999,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
                                          out->shifts + 2 * (size_t)f0, gaps, frefine, st,
                                          flag2));
             HIP_TRY(moco::launch_add_i32(recheck, flag2, c, st));
+            if (cand32) HIP_TRY(moco::launch_add_i32(recheck, resolved, c, st));
         } else if (certify) {
             // the frames left uncertified: direct sums, combined again (their
             // FP64 grid first, when the row transforms read the pixels)

@@ -668,14 +668,15 @@ __device__ bool certified(const double *At, const double *btab, int mg, int ng, 
 // over the whole P x Q output (frame transform error e1 sqrt(PQ) |x|_2 times
 // |Y|_inf; template spectrum, product and inverse errors times |X|_inf
 // sqrt(PQ) |y|_2; the 1/(PQ) scale), hence for every shift.
-__device__ __forceinline__ bool certified32(const double *At, const double *btab, int mg, int ng,
-                                            int w, double f1, double f2, double ke,
-                                            const float *xmax, int nxb, double e1, double e2,
-                                            double yinf, double sqrtpq, int frame)
+// Delta of the single-precision certificate for one frame (false when the
+// frame's spectrum maximum is not finite): every computed f of the frame is
+// within Delta/Area + u|f^| of the exact f.
+__device__ __forceinline__ bool cert32_delta(const double *At, const double *btab, int w,
+                                             double ke, const float *xmax, int nxb, double e1,
+                                             double e2, double yinf, double sqrtpq, int frame,
+                                             double *delta)
 {
     const double u = 0x1p-53, u32 = 0x1p-24;
-    if (!(f1 == f1) || isinf(f1)) return false;
-    if (isinf(f2)) return true;
     const int W = 2 * w - 1, c0 = (w - 1) * W + (w - 1);
     const double sa = fmax(At[c0], 0.0), sb = fmax(btab[c0], 0.0);
     const float *xm = xmax + (size_t)frame * nxb;
@@ -685,7 +686,21 @@ __device__ __forceinline__ bool certified32(const double *At, const double *btab
     const double xinf = sqrt((double)x2) * (1.0 + 4.0 * u32);
     const double na = sqrt(sa), nb = sqrt(sb);
     const double hb = 2.0 * (e1 * na * yinf + e2 * (xinf + e1 * sqrtpq * na) * nb);
-    const double delta = 1.01 * ((ke + 4.0 * u) * (sa + sb) + 2.0 * u * na * nb + 2.0 * hb);
+    *delta = 1.01 * ((ke + 4.0 * u) * (sa + sb) + 2.0 * u * na * nb + 2.0 * hb);
+    return true;
+}
+
+__device__ __forceinline__ bool certified32(const double *At, const double *btab, int mg, int ng,
+                                            int w, double f1, double f2, double ke,
+                                            const float *xmax, int nxb, double e1, double e2,
+                                            double yinf, double sqrtpq, int frame)
+{
+    const double u = 0x1p-53;
+    if (!(f1 == f1) || isinf(f1)) return false;
+    if (isinf(f2)) return true;
+    double delta;
+    if (!cert32_delta(At, btab, w, ke, xmax, nxb, e1, e2, yinf, sqrtpq, frame, &delta))
+        return false;
     const double amin = (double)(mg - (w - 1)) * (double)(ng - (w - 1));
     const double margin = (f2 - f1) - 1.01 * u * (fabs(f1) + fabs(f2));
     return margin > 2.0 * delta / amin;
@@ -797,6 +812,162 @@ __global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src,
         const int W = 2 * w - 1;
         if (fsurf) fsurf[(size_t)frame * W * W + (size_t)(s + w - 1) * W + (t + w - 1)] = f;
     }
+}
+
+// An argmin that the single-precision certificate leaves open, settled from
+// its candidates (uint16 pixels; the grid is their 2x2 box means, or the
+// pixels themselves).  Every computed f of the frame is within
+// delta = Delta/Area + u|f^| of the exact f (the certificate's bound), so a
+// shift with f^ - delta above U = min over all shifts of (f^ + delta) has an
+// exact f above the exact minimum: it is not the argmin and does not tie with
+// it.  When every other shift lies in the 3 x 3 neighbourhood of the computed
+// argmin, the exact f of those nine shifts (integer sums of squared
+// differences of the box sums, i.e. 16 times the box-mean units, or of the
+// pixels) settle the exact argmin under the tie order: the frame's coarse
+// argmin, f there, its gap (the second-best of the nine, or the least
+// computed f outside them) and the nine surface values are written, recheck
+// is cleared and resolved set to 3.  Otherwise the frame keeps recheck for
+// the FP64 pass.  resolved is written for every frame.  One block per frame.
+constexpr int kCandRows = 8;   // template rows whose frame loads a thread issues together
+
+template <int SRC>   // 1: 2x2 box sums of uint16 pixels; 2: uint16 pixels
+__global__ __launch_bounds__(kBlock) void k_cand32(
+    const uint16_t *__restrict__ frames, int m, int n, int mg, int ng, int w, int ds,
+    const double *__restrict__ atab, const double *__restrict__ btab,
+    const double *__restrict__ hbuf, const double *__restrict__ tcoarse, double ke, Cert32 c32,
+    int32_t *__restrict__ coarse_st, double *__restrict__ fmin_out, double *__restrict__ fsurf,
+    double *__restrict__ gaps, int32_t *__restrict__ shifts, int32_t *__restrict__ recheck,
+    int32_t *__restrict__ resolved)
+{
+    const int frame = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid == 0) resolved[frame] = 0;
+    if (!recheck[frame]) return;
+    const int W = 2 * w - 1, WW = W * W;
+    const double u = 0x1p-53;
+    const double *At = atab + (size_t)frame * WW;
+    const double *h = hbuf + (size_t)frame * WW;
+    double delta;
+    if (!cert32_delta(At, btab, w, ke, c32.xmax, c32.nxb, c32.e1, c32.e2, c32.yinf, c32.sqrtpq,
+                      frame, &delta))
+        return;
+    const int s0 = coarse_st[2 * frame], t0 = coarse_st[2 * frame + 1];
+    __shared__ double red[kBlock];
+    auto block_min = [&](double v) {
+        red[tid] = v;
+        __syncthreads();
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
+            if (tid < off) red[tid] = fmin(red[tid], red[tid + off]);
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    // U, and the least computed f outside the neighbourhood (as the combine forms f)
+    double up = INFINITY, fout = INFINITY;
+    bool bad = false;
+    for (int k = tid; k < WW; k += kBlock) {
+        const int s = k / W - (w - 1), t = k % W - (w - 1);
+        const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+        const double f = (At[k] + btab[k] - 2.0 * h[k]) / area;
+        if (!isfinite(f)) bad = true;
+        up = fmin(up, f + delta / area + 1.01 * u * fabs(f));
+        if (abs(s - s0) > 1 || abs(t - t0) > 1) fout = fmin(fout, f);
+    }
+    if (__syncthreads_or(bad)) return;
+    const double U = block_min(up);
+    fout = block_min(fout);
+    bool far = false;
+    for (int k = tid; k < WW; k += kBlock) {
+        const int s = k / W - (w - 1), t = k % W - (w - 1);
+        if (abs(s - s0) <= 1 && abs(t - t0) <= 1) continue;
+        const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+        const double f = (At[k] + btab[k] - 2.0 * h[k]) / area;
+        if (f - delta / area - 1.01 * u * fabs(f) <= U) far = true;
+    }
+    if (__syncthreads_or(far)) return;
+
+    // exact sums for the nine shifts (s0 + du - 1, t0 + dv - 1); a frame value
+    // outside the grid is -1 (its terms are outside D)
+    const uint16_t *fb = frames + (size_t)frame * m * n;
+    auto fval = [&](int r, int c) -> int {
+        if (r < 0 || r >= mg || c < 0 || c >= ng) return -1;
+        if (SRC == 1) {
+            const uint16_t *p = fb + (size_t)(2 * r) * n + 2 * c;
+            return (int)p[0] + (int)p[1] + (int)p[n] + (int)p[n + 1];
+        }
+        return (int)fb[(size_t)r * n + c];
+    };
+    const double tscale = SRC == 1 ? 4.0 : 1.0;
+    long long acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0;
+    for (int j = tid; j < ng; j += kBlock) {
+        for (int i0 = 0; i0 < mg; i0 += kCandRows) {
+            int fv[kCandRows + 2][3], tv[kCandRows];
+#pragma unroll
+            for (int r = 0; r < kCandRows + 2; ++r)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) fv[r][v] = fval(i0 + s0 - 1 + r, j + t0 + v - 1);
+#pragma unroll
+            for (int q = 0; q < kCandRows; ++q)
+                tv[q] = i0 + q < mg ? (int)(tcoarse[(size_t)(i0 + q) * ng + j] * tscale) : 0;
+#pragma unroll
+            for (int q = 0; q < kCandRows; ++q) {
+                if (i0 + q >= mg) break;
+#pragma unroll
+                for (int du = 0; du < 3; ++du)
+#pragma unroll
+                    for (int dv = 0; dv < 3; ++dv) {
+                        const int a = fv[q + du][dv];
+                        if (a >= 0) {
+                            const long long d = (long long)(a - tv[q]);
+                            acc[3 * du + dv] += d * d;
+                        }
+                    }
+            }
+        }
+    }
+    __shared__ long long wsum[kBlock / 64][9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        unsigned long long v = (unsigned long long)acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+            lo = __shfl_xor(lo, off);
+            hi = __shfl_xor(hi, off);
+            v += ((unsigned long long)hi << 32) | lo;
+        }
+        if (tid % 64 == 0) wsum[tid / 64][q] = (long long)v;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double escale = SRC == 1 ? 0.0625 : 1.0;
+    Cand c{INFINITY, INT32_MIN, 0, INFINITY};
+    for (int q = 0; q < 9; ++q) {
+        const int s = s0 + q / 3 - 1, t = t0 + q % 3 - 1;
+        if (abs(s) > w - 1 || abs(t) > w - 1) continue;
+        long long e = 0;
+        for (int k = 0; k < kBlock / 64; ++k) e += wsum[k][q];
+        const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+        const double f = ((double)e * escale) / area;
+        if (fsurf) fsurf[(size_t)frame * WW + (size_t)(s + w - 1) * W + (t + w - 1)] = f;
+        cand_add(c, f, s, t);
+    }
+    c.second = fmin(c.second, fout);
+    coarse_st[2 * frame] = c.s;
+    coarse_st[2 * frame + 1] = c.t;
+    fmin_out[frame] = c.f;
+    if (gaps) gaps[2 * frame] = c.second - c.f;
+    if (!ds) {
+        shifts[2 * frame] = c.s;
+        shifts[2 * frame + 1] = c.t;
+        if (gaps) gaps[2 * frame + 1] = INFINITY;
+    }
+    recheck[frame] = 0;
+    resolved[frame] = 3;
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int count, int32_t v)
@@ -1726,6 +1897,27 @@ hipError_t launch_polish(const void *src, bool raw, int C, const Geom &g, const 
     else
         k_polish<4><<<C, kBlock, 0, st>>>(src, g.m, g.n, g.mg, g.ng, g.w, tcoarse, coarse_st, skip,
                                           fmin, fsurf, gaps);
+    return hipGetLastError();
+}
+
+hipError_t launch_cand32(const void *frames, int C, const Geom &g, const double *atab,
+                         const double *btab, const double *h, const double *tcoarse, double ke,
+                         const Cert32 &c32, int32_t *coarse_st, double *fmin, double *fsurf,
+                         double *gaps, int32_t *shifts, int32_t *recheck, int32_t *resolved,
+                         hipStream_t st)
+{
+    clear_stale_error();
+    if (C == 0) return hipSuccess;
+    if (g.dtype != MOCO_U16 || g.ds > 1 || !fmin || !shifts || !recheck || !resolved || !c32.xmax)
+        return hipErrorInvalidValue;
+    if (g.ds)
+        k_cand32<1><<<C, kBlock, 0, st>>>((const uint16_t *)frames, g.m, g.n, g.mg, g.ng, g.w,
+                                          g.ds, atab, btab, h, tcoarse, ke, c32, coarse_st, fmin,
+                                          fsurf, gaps, shifts, recheck, resolved);
+    else
+        k_cand32<2><<<C, kBlock, 0, st>>>((const uint16_t *)frames, g.m, g.n, g.mg, g.ng, g.w,
+                                          g.ds, atab, btab, h, tcoarse, ke, c32, coarse_st, fmin,
+                                          fsurf, gaps, shifts, recheck, resolved);
     return hipGetLastError();
 }
 

@@ -149,6 +149,17 @@ hipError_t launch_combine(const double *atab, const double *btab, const double *
 hipError_t launch_polish(const void *src, bool raw, int C, const Geom &g, const double *tcoarse,
                          const int32_t *coarse_st, const int32_t *skip, double *fmin,
                          double *fsurf, double *gaps, hipStream_t st);
+// Frames the single-precision certificate left (recheck[f] != 0) whose open
+// shifts all lie in the 3 x 3 neighbourhood of the computed argmin: exact f
+// there by integer sums (uint16 pixels, at most one 2x2 level), the argmin,
+// gap and surface values rewritten, recheck cleared and resolved[f] = 3;
+// resolved[f] = 0 for every other frame.  atab, btab, h: the tables the
+// combine formed f from.
+hipError_t launch_cand32(const void *frames, int C, const Geom &g, const double *atab,
+                         const double *btab, const double *h, const double *tcoarse, double ke,
+                         const Cert32 &c32, int32_t *coarse_st, double *fmin, double *fsurf,
+                         double *gaps, int32_t *shifts, int32_t *recheck, int32_t *resolved,
+                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int count, int32_t v, hipStream_t st);
 // p[i] += q[i], i < count
 hipError_t launch_add_i32(int32_t *p, const int32_t *q, int count, hipStream_t st);
