@@ -888,59 +888,71 @@ __global__ __launch_bounds__(kBlock) void k_cand32(
     }
     if (__syncthreads_or(far)) return;
 
-    // exact sums for the nine shifts (s0 + du - 1, t0 + dv - 1); a frame value
-    // outside the grid is -1 (its terms are outside D)
+    // exact sums for the nine shifts (s0 + du - 1, t0 + dv - 1).  Every load
+    // is made, at an index clamped into the grid, and a term whose frame value
+    // lies outside the grid counts zero (it is outside D): no branch around a
+    // load, and all of a batch's loads are issued before the first is used.
+    // The terms are integers (16 times the box-mean units, or pixel units) and
+    // the sums stay below 2^53, so FP64 FMAs add them exactly.
     const uint16_t *fb = frames + (size_t)frame * m * n;
-    auto fval = [&](int r, int c) -> int {
-        if (r < 0 || r >= mg || c < 0 || c >= ng) return -1;
-        if (SRC == 1) {
-            const uint16_t *p = fb + (size_t)(2 * r) * n + 2 * c;
-            return (int)p[0] + (int)p[1] + (int)p[n] + (int)p[n + 1];
-        }
-        return (int)fb[(size_t)r * n + c];
-    };
     const double tscale = SRC == 1 ? 4.0 : 1.0;
-    long long acc[9];
+    double acc[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0;
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
     for (int j = tid; j < ng; j += kBlock) {
         for (int i0 = 0; i0 < mg; i0 += kCandRows) {
-            int fv[kCandRows + 2][3], tv[kCandRows];
+            // the batch's loads: two pixel pairs per box (its two rows), or
+            // one pixel, and the template values
+            uint32_t top[kCandRows + 2][3], bot[kCandRows + 2][3];
+            double tv[kCandRows];
 #pragma unroll
             for (int r = 0; r < kCandRows + 2; ++r)
 #pragma unroll
-                for (int v = 0; v < 3; ++v) fv[r][v] = fval(i0 + s0 - 1 + r, j + t0 + v - 1);
+                for (int v = 0; v < 3; ++v) {
+                    const int rr = min(max(i0 + s0 - 1 + r, 0), mg - 1);
+                    const int cc = min(max(j + t0 + v - 1, 0), ng - 1);
+                    if (SRC == 1) {
+                        const char *pb = (const char *)(fb + (size_t)(2 * rr) * n + 2 * cc);
+                        top[r][v] = *(const uint32_t *)pb;
+                        bot[r][v] = *(const uint32_t *)(pb + 2 * (size_t)n);
+                    } else {
+                        top[r][v] = fb[(size_t)rr * n + cc];
+                        bot[r][v] = 0;
+                    }
+                }
 #pragma unroll
             for (int q = 0; q < kCandRows; ++q)
-                tv[q] = i0 + q < mg ? (int)(tcoarse[(size_t)(i0 + q) * ng + j] * tscale) : 0;
+                tv[q] = tcoarse[(size_t)min(i0 + q, mg - 1) * ng + j] * tscale;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < kCandRows; ++q) {
-                if (i0 + q >= mg) break;
+                const bool row_in = i0 + q < mg;
 #pragma unroll
-                for (int du = 0; du < 3; ++du)
+                for (int du = 0; du < 3; ++du) {
+                    const int fr = i0 + s0 - 1 + q + du;
+                    const bool fr_in = row_in && fr >= 0 && fr < mg;
 #pragma unroll
                     for (int dv = 0; dv < 3; ++dv) {
-                        const int a = fv[q + du][dv];
-                        if (a >= 0) {
-                            const long long d = (long long)(a - tv[q]);
-                            acc[3 * du + dv] += d * d;
-                        }
+                        const int fc = j + t0 + dv - 1;
+                        const uint32_t x = top[q + du][dv], y = bot[q + du][dv];
+                        const int a = SRC == 1 ? (int)((x & 0xffffu) + (x >> 16) + (y & 0xffffu) +
+                                                       (y >> 16))
+                                               : (int)x;
+                        const double d =
+                            fr_in && fc >= 0 && fc < ng ? (double)a - tv[q] : 0.0;
+                        acc[3 * du + dv] = fma(d, d, acc[3 * du + dv]);
                     }
+                }
             }
         }
     }
-    __shared__ long long wsum[kBlock / 64][9];
+    __shared__ double wsum[kBlock / 64][9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        unsigned long long v = (unsigned long long)acc[q];
+        double v = acc[q];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-            lo = __shfl_xor(lo, off);
-            hi = __shfl_xor(hi, off);
-            v += ((unsigned long long)hi << 32) | lo;
-        }
-        if (tid % 64 == 0) wsum[tid / 64][q] = (long long)v;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (tid % 64 == 0) wsum[tid / 64][q] = v;
     }
     __syncthreads();
     if (tid != 0) return;
@@ -949,10 +961,10 @@ __global__ __launch_bounds__(kBlock) void k_cand32(
     for (int q = 0; q < 9; ++q) {
         const int s = s0 + q / 3 - 1, t = t0 + q % 3 - 1;
         if (abs(s) > w - 1 || abs(t) > w - 1) continue;
-        long long e = 0;
+        double e = 0.0;
         for (int k = 0; k < kBlock / 64; ++k) e += wsum[k][q];
         const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
-        const double f = ((double)e * escale) / area;
+        const double f = (e * escale) / area;
         if (fsurf) fsurf[(size_t)frame * WW + (size_t)(s + w - 1) * W + (t + w - 1)] = f;
         cand_add(c, f, s, t);
     }
