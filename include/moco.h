@@ -139,8 +139,8 @@ typedef struct moco_tmpl moco_tmpl;
  *                          FP64 transforms and direct sums, or 3 where exact
  *                          integer sums over the nine shifts around the
  *                          computed argmin settled it (uint16 frames with at
- *                          most one 2x2 level, when every shift the bound
- *                          leaves open is among those nine); else 0 (every
+ *                          most one 2x2 level and w <= 32, when every shift
+ *                          the bound leaves open is among those nine); else 0 (every
  *                          other form writes 0)
  * f is in squared intensity units of the searched grid (box-mean units when
  * downsampled). */

@@ -896,7 +896,7 @@ int run_fft(moco_ctx *ctx, const void *d_frames, const moco::Tmpl &tt, int T,
     // the candidate pass of the single-precision certificate: its largest
     // squared difference is (4 x 65535)^2 with 2x2 box sums, 65535^2 without
     const double term_max = g.ds ? 262140.0 * 262140.0 : 65535.0 * 65535.0;
-    const bool cand32 = cert32 && raw_rows && int_energy &&
+    const bool cand32 = cert32 && raw_rows && int_energy && g.W * g.W <= moco::kCand32MaxShifts &&
                         (double)g.mg * (double)g.ng * term_max < 0x1p53;
     for (int f0 = 0; f0 < T; f0 += C) {
         int c = std::min(C, T - f0);

@@ -671,23 +671,31 @@ __device__ bool certified(const double *At, const double *btab, int mg, int ng, 
 // Delta of the single-precision certificate for one frame (false when the
 // frame's spectrum maximum is not finite): every computed f of the frame is
 // within Delta/Area + u|f^| of the exact f.
-__device__ __forceinline__ bool cert32_delta(const double *At, const double *btab, int w,
-                                             double ke, const float *xmax, int nxb, double e1,
-                                             double e2, double yinf, double sqrtpq, int frame,
-                                             double *delta)
+// x2: the largest |X_k|^2 of the frame's computed spectrum
+__device__ __forceinline__ bool cert32_delta_x2(const double *At, const double *btab, int w,
+                                                double ke, float x2, double e1, double e2,
+                                                double yinf, double sqrtpq, double *delta)
 {
     const double u = 0x1p-53, u32 = 0x1p-24;
     const int W = 2 * w - 1, c0 = (w - 1) * W + (w - 1);
     const double sa = fmax(At[c0], 0.0), sb = fmax(btab[c0], 0.0);
-    const float *xm = xmax + (size_t)frame * nxb;
-    float x2 = 0.0f;
-    for (int k = 0; k < nxb; ++k) x2 = fmaxf(x2, xm[k]);
     if (!(x2 <= 3.0e38f)) return false;
     const double xinf = sqrt((double)x2) * (1.0 + 4.0 * u32);
     const double na = sqrt(sa), nb = sqrt(sb);
     const double hb = 2.0 * (e1 * na * yinf + e2 * (xinf + e1 * sqrtpq * na) * nb);
     *delta = 1.01 * ((ke + 4.0 * u) * (sa + sb) + 2.0 * u * na * nb + 2.0 * hb);
     return true;
+}
+
+__device__ __forceinline__ bool cert32_delta(const double *At, const double *btab, int w,
+                                             double ke, const float *xmax, int nxb, double e1,
+                                             double e2, double yinf, double sqrtpq, int frame,
+                                             double *delta)
+{
+    const float *xm = xmax + (size_t)frame * nxb;
+    float x2 = 0.0f;
+    for (int k = 0; k < nxb; ++k) x2 = fmaxf(x2, xm[k]);
+    return cert32_delta_x2(At, btab, w, ke, x2, e1, e2, yinf, sqrtpq, delta);
 }
 
 __device__ __forceinline__ bool certified32(const double *At, const double *btab, int mg, int ng,
@@ -829,6 +837,8 @@ __global__ __launch_bounds__(kBlock) void k_polish(const void *__restrict__ src,
 // is cleared and resolved set to 3.  Otherwise the frame keeps recheck for
 // the FP64 pass.  resolved is written for every frame.  One block per frame.
 constexpr int kCandRows = 8;   // template rows whose frame loads a thread issues together
+constexpr int kCandBatch = 4;  // shifts whose table loads a thread issues together
+constexpr int kCandMaxShifts = kCand32MaxShifts;
 
 template <int SRC>   // 1: 2x2 box sums of uint16 pixels; 2: uint16 pixels
 __global__ __launch_bounds__(kBlock) void k_cand32(
@@ -844,13 +854,10 @@ __global__ __launch_bounds__(kBlock) void k_cand32(
     if (tid == 0) resolved[frame] = 0;
     if (!recheck[frame]) return;
     const int W = 2 * w - 1, WW = W * W;
+    if (WW > kCandMaxShifts) return;   // the launcher refuses such windows
     const double u = 0x1p-53;
     const double *At = atab + (size_t)frame * WW;
     const double *h = hbuf + (size_t)frame * WW;
-    double delta;
-    if (!cert32_delta(At, btab, w, ke, c32.xmax, c32.nxb, c32.e1, c32.e2, c32.yinf, c32.sqrtpq,
-                      frame, &delta))
-        return;
     const int s0 = coarse_st[2 * frame], t0 = coarse_st[2 * frame + 1];
     __shared__ double red[kBlock];
     auto block_min = [&](double v) {
@@ -864,16 +871,41 @@ __global__ __launch_bounds__(kBlock) void k_cand32(
         __syncthreads();
         return r;
     };
-    // U, and the least computed f outside the neighbourhood (as the combine forms f)
+    // Delta, from the frame's spectrum maximum taken over the block
+    float x2 = 0.0f;
+    for (int k = tid; k < c32.nxb; k += kBlock)
+        x2 = fmaxf(x2, c32.xmax[(size_t)frame * c32.nxb + k]);
+    x2 = (float)-block_min(-(double)x2);
+    double delta;
+    if (!cert32_delta_x2(At, btab, w, ke, x2, c32.e1, c32.e2, c32.yinf, c32.sqrtpq, &delta))
+        return;
+    // every computed f (as the combine forms it) into LDS, kCandBatch shifts'
+    // table loads at a time; U, and the least computed f outside the
+    // neighbourhood
+    __shared__ double sf[kCandMaxShifts];
     double up = INFINITY, fout = INFINITY;
     bool bad = false;
-    for (int k = tid; k < WW; k += kBlock) {
-        const int s = k / W - (w - 1), t = k % W - (w - 1);
-        const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
-        const double f = (At[k] + btab[k] - 2.0 * h[k]) / area;
-        if (!isfinite(f)) bad = true;
-        up = fmin(up, f + delta / area + 1.01 * u * fabs(f));
-        if (abs(s - s0) > 1 || abs(t - t0) > 1) fout = fmin(fout, f);
+    for (int k0 = tid; k0 < WW; k0 += kCandBatch * kBlock) {
+        double a[kCandBatch], b[kCandBatch], c[kCandBatch];
+#pragma unroll
+        for (int q = 0; q < kCandBatch; ++q) {
+            const int k = min(k0 + q * kBlock, WW - 1);
+            a[q] = At[k];
+            b[q] = btab[k];
+            c[q] = h[k];
+        }
+#pragma unroll
+        for (int q = 0; q < kCandBatch; ++q) {
+            const int k = k0 + q * kBlock;
+            if (k >= WW) break;
+            const int s = k / W - (w - 1), t = k % W - (w - 1);
+            const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
+            const double f = (a[q] + b[q] - 2.0 * c[q]) / area;
+            sf[k] = f;
+            if (!isfinite(f)) bad = true;
+            up = fmin(up, f + delta / area + 1.01 * u * fabs(f));
+            if (abs(s - s0) > 1 || abs(t - t0) > 1) fout = fmin(fout, f);
+        }
     }
     if (__syncthreads_or(bad)) return;
     const double U = block_min(up);
@@ -883,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_cand32(
         const int s = k / W - (w - 1), t = k % W - (w - 1);
         if (abs(s - s0) <= 1 && abs(t - t0) <= 1) continue;
         const double area = (double)(mg - abs(s)) * (double)(ng - abs(t));
-        const double f = (At[k] + btab[k] - 2.0 * h[k]) / area;
+        const double f = sf[k];
         if (f - delta / area - 1.01 * u * fabs(f) <= U) far = true;
     }
     if (__syncthreads_or(far)) return;
@@ -1920,7 +1952,8 @@ hipError_t launch_cand32(const void *frames, int C, const Geom &g, const double 
 {
     clear_stale_error();
     if (C == 0) return hipSuccess;
-    if (g.dtype != MOCO_U16 || g.ds > 1 || !fmin || !shifts || !recheck || !resolved || !c32.xmax)
+    if (g.dtype != MOCO_U16 || g.ds > 1 || g.W * g.W > kCand32MaxShifts || !fmin || !shifts ||
+        !recheck || !resolved || !c32.xmax)
         return hipErrorInvalidValue;
     if (g.ds)
         k_cand32<1><<<C, kBlock, 0, st>>>((const uint16_t *)frames, g.m, g.n, g.mg, g.ng, g.w,

@@ -155,6 +155,7 @@ hipError_t launch_polish(const void *src, bool raw, int C, const Geom &g, const 
 // gap and surface values rewritten, recheck cleared and resolved[f] = 3;
 // resolved[f] = 0 for every other frame.  atab, btab, h: the tables the
 // combine formed f from.
+constexpr int kCand32MaxShifts = 4096;   // (2w-1)^2 at most (w <= 32) for launch_cand32
 hipError_t launch_cand32(const void *frames, int C, const Geom &g, const double *atab,
                          const double *btab, const double *h, const double *tcoarse, double ke,
                          const Cert32 &c32, int32_t *coarse_st, double *fmin, double *fsurf,
